@@ -1,0 +1,276 @@
+"""Seeded synthetic inputs for the projection-method solver.
+
+This module produces *inputs only*: projection matrices P, coefficient modes
+m with their Fourier coefficients, grid sizes N and right-hand sides.  It does
+none of the method's arithmetic (no stiffness products, preconditioner, Krylov
+solve or homogenized coefficient), so the GPU path and the CPU reference can
+both consume exactly the same arrays.  It imports only numpy.
+
+Conventions (Sec. 2.1 and Sec. 3.1 of the paper):
+
+* A quasiperiodic coefficient is a(x) = A(P^T x) with a parent function A on
+  the n-torus, A(y) = sum_m Ahat_m exp(i m.y).  A problem is given by P (d x n,
+  row-major), the integer mode list m (g x n) and the complex coefficients
+  Ahat_m (g,).  A real coefficient needs Ahat_{-m} = conj(Ahat_m).
+* Vectors of unknowns have D = N^n complex entries in the tensor-to-vector
+  order of Sec. 3.1.2: row-major, k_1 slowest, each index stored as k mod N
+  (FFT order).
+
+Every random draw is made from ``numpy.random.default_rng(seed)``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SQRT2 = float(np.sqrt(2.0))
+SQRT3 = float(np.sqrt(3.0))
+SQRT5 = float(np.sqrt(5.0))
+TAU = float((1.0 + np.sqrt(5.0)) / 2.0)
+TWO_PI = float(2.0 * np.pi)
+
+#: base seed of the random-coefficient workloads (the arXiv id followed by 0)
+BASE_SEED = 2404068410
+
+
+@dataclass
+class Problem:
+    """One quasiperiodic elliptic problem: P, coefficient modes and N."""
+
+    name: str
+    d: int
+    n: int
+    N: int
+    P: np.ndarray  # (d, n) float64, row-major
+    modes: np.ndarray  # (g, n) int32
+    coef: np.ndarray  # (g,) complex128
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def D(self) -> int:
+        return int(self.N) ** int(self.n)
+
+    @property
+    def g(self) -> int:
+        return int(self.modes.shape[0])
+
+    def with_N(self, N: int) -> "Problem":
+        return Problem(self.name, self.d, self.n, int(N), self.P.copy(),
+                       self.modes.copy(), self.coef.copy(), dict(self.meta))
+
+
+def _modes_from_dict(n: int, table: dict) -> tuple[np.ndarray, np.ndarray]:
+    keys = sorted(table.keys())
+    modes = np.array(keys, dtype=np.int32).reshape(len(keys), n)
+    coef = np.array([table[k] for k in keys], dtype=np.complex128)
+    return modes, coef
+
+
+def _unit(n: int, t: int, s: int = 1) -> tuple:
+    v = [0] * n
+    v[t] = s
+    return tuple(v)
+
+
+def cosine_field(n: int, mean: float, amplitudes) -> tuple[np.ndarray, np.ndarray]:
+    """A(y) = mean + sum_t amplitudes[t] cos(y_t): Ahat_{+-e_t} = amplitudes[t]/2."""
+    table = {tuple([0] * n): complex(mean)}
+    for t, c in enumerate(amplitudes):
+        if c == 0.0:
+            continue
+        table[_unit(n, t, +1)] = complex(c / 2.0)
+        table[_unit(n, t, -1)] = complex(c / 2.0)
+    return _modes_from_dict(n, table)
+
+
+# --------------------------------------------------------------------------
+# Projection matrices
+# --------------------------------------------------------------------------
+
+def eightfold_P() -> np.ndarray:
+    """Columns (1,0), (0,1), (cos pi/4, sin pi/4), (cos 3pi/4, sin 3pi/4)."""
+    c = SQRT2 / 2.0
+    return np.array([[1.0, 0.0, c, -c],
+                     [0.0, 1.0, c, c]], dtype=np.float64)
+
+
+def icosahedral_P() -> np.ndarray:
+    """Columns (1,tau,0), (-1,tau,0), (0,1,tau), (0,-1,tau), (tau,0,1), (tau,0,-1)."""
+    t = TAU
+    cols = [(1.0, t, 0.0), (-1.0, t, 0.0), (0.0, 1.0, t), (0.0, -1.0, t),
+            (t, 0.0, 1.0), (t, 0.0, -1.0)]
+    return np.array(cols, dtype=np.float64).T.copy()
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+
+def one_d_two_mode(N: int = 32, mean: float = 2.0, scale: float = 1.0) -> Problem:
+    """d=1, n=2, P = scale*(1, sqrt2), A = mean + cos y1 + cos y2.
+
+    mean=2, scale=1 is the 1024-unknown configuration at N=32 (degenerate: A
+    touches 0 at y=(pi,pi)); mean=6, scale=2*pi is the paper's first example
+    (Sec. 5.1.1).
+    """
+    P = np.array([[1.0, SQRT2]], dtype=np.float64) * scale
+    modes, coef = cosine_field(2, mean, [1.0, 1.0])
+    return Problem("1d_n2", 1, 2, int(N), P, modes, coef,
+                   {"mean": mean, "scale": scale})
+
+
+def one_d_three_mode(N: int = 16, mean: float = 6.0) -> Problem:
+    """d=1, n=3, P = 2*pi*(1, sqrt2, sqrt3), A = mean + cos y1 + cos y2 + cos y3 (Sec. 5.1.3)."""
+    P = np.array([[1.0, SQRT2, SQRT3]], dtype=np.float64) * TWO_PI
+    modes, coef = cosine_field(3, mean, [1.0, 1.0, 1.0])
+    return Problem("1d_n3", 1, 3, int(N), P, modes, coef, {"mean": mean})
+
+
+def paper_four_mode_2d(N: int = 6) -> Problem:
+    """d=2, n=4 example of Sec. 5.1.5: A = 12 + cos y1 + cos y2 + cos y3 + sin y4.
+
+    P = 2*pi*[[1, 0, sqrt3, 0], [0, sqrt2, 0, sqrt5]].  The sine term gives a
+    purely imaginary Hermitian pair, Ahat_{+-e4} = -+ i/2.
+    """
+    P = TWO_PI * np.array([[1.0, 0.0, SQRT3, 0.0],
+                           [0.0, SQRT2, 0.0, SQRT5]], dtype=np.float64)
+    n = 4
+    table = {tuple([0] * n): 12.0 + 0j}
+    for t in range(3):
+        table[_unit(n, t, 1)] = 0.5 + 0j
+        table[_unit(n, t, -1)] = 0.5 + 0j
+    table[_unit(n, 3, 1)] = -0.5j
+    table[_unit(n, 3, -1)] = 0.5j
+    modes, coef = _modes_from_dict(n, table)
+    return Problem("paper_2d_n4", 2, 4, int(N), P, modes, coef)
+
+
+def eightfold(N: int = 16, amplitude: float = 0.5, mean: float = 3.0) -> Problem:
+    """d=2, n=4 eightfold: A = mean + amplitude * sum_{j=1..4} cos(y_j).
+
+    amplitude=1 is the literal (indefinite) field 3 + sum cos; the measured
+    runs use amplitude 1/2 so that 1 <= a <= 5.
+    """
+    modes, coef = cosine_field(4, mean, [amplitude] * 4)
+    return Problem("eightfold", 2, 4, int(N), eightfold_P(), modes, coef,
+                   {"amplitude": amplitude, "mean": mean})
+
+
+def random_modes(n: int, pairs: int, radius: int, rng: np.random.Generator,
+                 max_amp: float, amp_cap: float, mean: float):
+    """Draw `pairs` distinct +-m pairs from {-radius..radius}^n \\ {0} (modulo sign)
+    with amplitudes c ~ U(0, max_amp), redrawing the amplitudes while their sum
+    exceeds amp_cap; Ahat_{+-m} = c/2, Ahat_0 = mean."""
+    side = 2 * radius + 1
+    reps = []
+    for flat in range(side ** n):
+        v = []
+        x = flat
+        for _ in range(n):
+            v.append(x % side - radius)
+            x //= side
+        v = tuple(reversed(v))
+        if any(v):
+            neg = tuple(-c for c in v)
+            if v > neg:  # one representative of each +-pair
+                reps.append(v)
+    idx = rng.choice(len(reps), size=pairs, replace=False)
+    chosen = [reps[i] for i in sorted(idx)]
+    amps = rng.uniform(0.0, max_amp, size=pairs)
+    while amps.sum() > amp_cap:
+        amps = rng.uniform(0.0, max_amp, size=pairs)
+    table = {tuple([0] * n): complex(mean)}
+    for v, c in zip(chosen, amps):
+        table[v] = complex(c / 2.0)
+        table[tuple(-x for x in v)] = complex(c / 2.0)
+    modes, coef = _modes_from_dict(n, table)
+    return modes, coef, amps
+
+
+def eightfold_random(N: int = 32, instance: int = 0, pairs: int = 8) -> Problem:
+    """Eightfold P with `pairs` seeded random +-mode pairs around mean 3.
+
+    Mode pairs come from {-2..2}^4 \\ {0}; amplitudes c_r ~ U(0, 0.4) redrawn
+    while sum c_r > 2.5, so a >= 0.5.  Seed = BASE_SEED + instance.
+    """
+    rng = np.random.default_rng(BASE_SEED + int(instance))
+    modes, coef, amps = random_modes(4, pairs, 2, rng, 0.4, 2.5, 3.0)
+    return Problem("eightfold_random", 2, 4, int(N), eightfold_P(), modes, coef,
+                   {"instance": int(instance), "amplitudes": amps.tolist()})
+
+
+def eightfold_batch(count: int = 64, seed: int = BASE_SEED,
+                    sizes=(8, 12, 16, 24, 32)) -> list:
+    """`count` eightfold_random instances with N drawn uniformly from `sizes`."""
+    rng = np.random.default_rng(int(seed))
+    Ns = rng.choice(np.array(sizes), size=count, replace=True)
+    return [eightfold_random(int(Ns[i]), instance=i) for i in range(count)]
+
+
+def icosahedral(N: int = 8, amplitude: float = 0.5, mean: float = 4.0) -> Problem:
+    """d=3, n=6 icosahedral: A = mean + amplitude * sum_{j=1..6} cos(y_j)."""
+    modes, coef = cosine_field(6, mean, [amplitude] * 6)
+    return Problem("icosahedral", 3, 6, int(N), icosahedral_P(), modes, coef,
+                   {"amplitude": amplitude, "mean": mean})
+
+
+def anisotropic_paper_example():
+    """Appendix D / Sec. 5.2 homogenization example, as two parent fields on T^4.
+
+    P = 2*pi*[[1, sqrt2, 1, sqrt2], [1, sqrt2, 0, 0]];
+    alpha(x) = 4 + cos(2*pi(x1+x2)) + cos(2*pi*sqrt2(x1+x2)) -> parent 4 + cos y1 + cos y2,
+    beta(x)  = 6 + sin^2(2*pi x1) + sin^2(2*pi*sqrt2 x1)       -> parent 7 - cos(2 y3)/2 - cos(2 y4)/2.
+    Returns (P, (modes_alpha, coef_alpha), (modes_beta, coef_beta)).
+    """
+    P = TWO_PI * np.array([[1.0, SQRT2, 1.0, SQRT2],
+                           [1.0, SQRT2, 0.0, 0.0]], dtype=np.float64)
+    n = 4
+    ta = {tuple([0] * n): 4.0 + 0j,
+          _unit(n, 0, 1): 0.5 + 0j, _unit(n, 0, -1): 0.5 + 0j,
+          _unit(n, 1, 1): 0.5 + 0j, _unit(n, 1, -1): 0.5 + 0j}
+    tb = {tuple([0] * n): 7.0 + 0j,
+          _unit(n, 2, 2): -0.25 + 0j, _unit(n, 2, -2): -0.25 + 0j,
+          _unit(n, 3, 2): -0.25 + 0j, _unit(n, 3, -2): -0.25 + 0j}
+    return P, _modes_from_dict(n, ta), _modes_from_dict(n, tb)
+
+
+# --------------------------------------------------------------------------
+# Right-hand sides and vectors
+# --------------------------------------------------------------------------
+
+def random_vector(D: int, seed: int, dtype=np.complex128) -> np.ndarray:
+    """Complex standard-normal vector of length D."""
+    rng = np.random.default_rng(int(seed))
+    v = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    return v.astype(dtype)
+
+
+def sparse_vector(n: int, N: int, table: dict) -> np.ndarray:
+    """Dense length-N^n vector holding table[k] at k (signed index, stored k mod N)."""
+    D = N ** n
+    v = np.zeros(D, dtype=np.complex128)
+    for k, val in table.items():
+        i = 0
+        for t in range(n):
+            i = i * N + (int(k[t]) % N)
+        v[i] += val
+    return v
+
+
+def sine_source(n: int, N: int, axes) -> np.ndarray:
+    """F for f = sum_{t in axes} sin(y_t): Fhat_{+e_t} = -i/2, Fhat_{-e_t} = +i/2."""
+    table = {}
+    for t in axes:
+        table[_unit(n, t, 1)] = -0.5j
+        table[_unit(n, t, -1)] = 0.5j
+    return sparse_vector(n, N, table)
+
+
+def exponential_solution_modes(n_axes: int = 2, half: int = 32) -> dict:
+    """Coefficients uhat_k = exp(-(|k1|+|k2|)) for -half <= k1,k2 < half (Sec. 5.1.2)."""
+    out = {}
+    for a in range(-half, half):
+        for b in range(-half, half):
+            out[(a, b)] = complex(np.exp(-(abs(a) + abs(b))))
+    return out
