@@ -1,0 +1,218 @@
+/*
+ * qp.h - C ABI of the MI355X (gfx950) projection-method solver.
+ *
+ * The library solves the lifted Fourier-Galerkin system of the projection
+ * method (PM) for quasiperiodic elliptic problems
+ *
+ *     -div( a(x) grad u(x) ) = f(x),   x in R^d,   a(x) = A(P^T x),
+ *     A(y) = sum_{m in S} Ahat_m exp(i m.y),   y in T^n,
+ *
+ * (Jiang, Li, Zhang, Zhang, "Projection method for quasiperiodic elliptic
+ * equations and application to quasiperiodic homogenization", Sec. 2-4), and
+ * the corrector problems and homogenized coefficient of Sec. 5.2.
+ *
+ * Discrete system (Sec. 3.1, eq. n-discrete and eq. linear_system):
+ *     Q U = F,   Q_ij = Ahat_{k_V -_N k_U} (P k_V).(P k_U),
+ * over the frequency grid K_N^n = {k in Z^n : -N/2 <= k_t < N/2}, D = N^n.
+ *
+ * Conventions shared by every entry point
+ *   - Complex vectors have D entries stored as interleaved (re, im) pairs
+ *     (double: 16 bytes per entry, float: 8 bytes), in the tensor-to-vector
+ *     order C of Sec. 3.1.2: entry i holds k with
+ *         i = sum_t (k_t mod N) * N^(n-1-t),  k_1 slowest (FFT order per axis).
+ *   - The zero frequency is not an unknown (zero-mean trial and test space,
+ *     Sec. 3.1.1): solutions have U[C(0)] = 0 and rhs[C(0)] is ignored.
+ *   - "_d" entry points take device pointers (hipMalloc'ed or torch CUDA
+ *     tensors on the problem's device); the others take host pointers.
+ *     Every pointer is owned by the caller and must stay valid for the call.
+ *   - Calls are synchronous with respect to the host: on return, outputs are
+ *     written (the work is queued on the problem's stream and waited for).
+ *   - Errors: every function returns a qp_status; QP_OK is 0 and errors are
+ *     negative.  qp_last_error() returns a message for the calling thread.
+ *     A failed call leaves the problem usable unless it returned QP_EDEVICE.
+ *   - Calls on the same qp_problem must not overlap (one stream, one
+ *     workspace); distinct problems are independent.
+ */
+#ifndef QP_H
+#define QP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qp_problem qp_problem;
+
+typedef enum qp_status {
+    QP_OK = 0,
+    QP_EINVAL = -1,        /* invalid argument (see qp_create)                    */
+    QP_ENOTELLIPTIC = -2,  /* coefficient negative on the collocation grid        */
+    QP_ENOTSPD = -3,       /* PCG breakdown: (Q h, h) <= 0                         */
+    QP_ENOCONV = -4,       /* iteration limit reached; best iterate is returned    */
+    QP_ENOMEM = -5,        /* device allocation failed or workspace too small      */
+    QP_EDEVICE = -6,       /* HIP runtime error or no usable gfx950 device         */
+    QP_ENONFINITE = -7     /* NaN or Inf in an input or in the residual            */
+} qp_status;
+
+/* Limits of this build. */
+#define QP_MAX_DIM_N 8     /* parent dimension n  */
+#define QP_MAX_DIM_D 4     /* physical dimension d */
+#define QP_MAX_MODES 64    /* coefficient modes g  */
+
+enum { QP_PREC_FP64 = 0, QP_PREC_FP32_IR = 1 };
+enum { QP_PRECOND_PAPER = 0, QP_PRECOND_JACOBI = 1 };
+
+/* qp_solve_info.flags bits */
+enum {
+    QP_FLAG_DEGENERATE = 1,  /* min of A on the grid is 0 (within 1e-12 max|A|)  */
+    QP_FLAG_F0_IGNORED = 2   /* |rhs[C(0)]| > 1e-14 ||rhs||; it was ignored       */
+};
+
+typedef struct qp_options {
+    int precision;      /* QP_PREC_FP64 (default) or QP_PREC_FP32_IR: float
+                           vectors, stiffness product and preconditioner inside
+                           FP64 refinement (the float residual is replaced by
+                           the FP64 residual of the FP64 solution); scalars,
+                           dot products, residuals and A* stay FP64              */
+    int precond;        /* QP_PRECOND_PAPER (default): M of eq. precond;
+                           QP_PRECOND_JACOBI: 1 / q_kk                            */
+    int maxit;          /* PCG iteration limit; default 10000                     */
+    double inner_tol;   /* FP32-IR: replace the float residual once it has
+                           dropped by this factor since the last replacement;
+                           default 1e-4                                          */
+    int poll_every;     /* iterations queued between convergence polls, and the
+                           longest FP32-IR run between replacements; 0 = 8       */
+    int profile;        /* nonzero: bracket every stiffness-product launch with
+                           HIP events; totals reported in qp_solve_info           */
+    void *stream;       /* hipStream_t to run on; NULL = a stream the library
+                           creates and owns                                      */
+    void *workspace;    /* optional device buffer of qp_workspace_bytes() bytes;
+                           NULL = the library allocates its own                  */
+    size_t workspace_bytes;
+} qp_options;
+
+typedef struct qp_solve_info {
+    int status;           /* qp_status of the solve                              */
+    int iters;            /* PCG iterations (float iterations for FP32-IR)       */
+    int outer_iters;      /* FP32-IR: FP64 residual replacements (0 for FP64)    */
+    int flags;            /* QP_FLAG_* bits                                      */
+    double rel_resid;     /* final ||r||_2 / ||F'||_2: the PCG residual for FP64,
+                             the true FP64 residual F' - Q U for FP32-IR         */
+    double seconds;       /* time of the solve on the device stream              */
+    int matvec_launches;  /* profile only: FP64 stiffness products that ran      */
+    double matvec_ms;     /*   and their summed event-timed duration             */
+    int matvec32_launches;/* profile only: float stiffness products that ran     */
+    double matvec32_ms;
+} qp_solve_info;
+
+/* Fill *opt with the defaults listed above. */
+void qp_default_options(qp_options *opt);
+
+/* Device bytes a problem of this shape needs when the caller supplies the
+ * workspace (qp_options.workspace).  Host-only; no device call. */
+size_t qp_workspace_bytes(int d, int n, int N, int g);
+
+/*
+ * Create a problem (Sec. 3.1: P, the coefficient modes and N define Q).
+ *   d, n    physical and parent dimensions, 1 <= d <= n, d <= QP_MAX_DIM_D,
+ *           n <= QP_MAX_DIM_N
+ *   P       d x n projection matrix, row-major, host (Def. 2.1)
+ *   g       number of coefficient modes, 1 <= g <= QP_MAX_MODES
+ *   modes   g x n int32 modes m, host; every |m_t| < N/2 (no aliasing)
+ *   coef    g complex Ahat_m as (re, im) pairs, host
+ *   N       points per parent dimension (N >= 2, N^n < 2^31)
+ *   opt     options or NULL for the defaults
+ * Returns QP_EINVAL for: a size outside the limits, non-finite P or coef,
+ * a repeated mode, |m_t| >= N/2, a missing or non-positive Ahat_0, a field
+ * that is not real (Ahat_{-m} != conj(Ahat_m) beyond 1e-14 max|Ahat|), or P
+ * with P k = 0 for some nonzero k in K_N^n (|P k| < 1e-12 |P|).
+ * QP_ENOTELLIPTIC if min over the collocation grid of A is below
+ * -1e-12 max|A|.  On success *out owns device memory until qp_destroy.
+ * Argument checks run on the host before any device call.
+ */
+qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g,
+                    const int32_t *modes, const double *coef, int N,
+                    const qp_options *opt);
+
+/* Release the problem and everything it owns.  NULL is ignored. */
+void qp_destroy(qp_problem *p);
+
+/* D = N^n. */
+int64_t qp_dim(const qp_problem *p);
+
+/* Replace the solver options (precision, preconditioner, limits, profile).
+ * The stream and workspace of a created problem cannot change. */
+qp_status qp_set_options(qp_problem *p, const qp_options *opt);
+
+/*
+ * Solve Q U = F' by C-PCG (Alg. 2) with the diagonal preconditioner M of
+ * eq. precond applied as z = M r, from U_0 = 0, until
+ * ||F' - Q U||_2 <= tol ||F'||_2 (F' = rhs without its zero frequency).
+ * rhs, u: D complex each (host for qp_solve, device for qp_solve_d); they
+ * must not overlap.  info may be NULL.  On QP_ENOCONV u holds the last
+ * iterate.  QP_ENONFINITE if rhs holds NaN/Inf.
+ */
+qp_status qp_solve(qp_problem *p, const double *rhs, double *u, double tol,
+                   qp_solve_info *info);
+qp_status qp_solve_d(qp_problem *p, const double *rhs, double *u, double tol,
+                     qp_solve_info *info);
+
+/*
+ * Corrector chi_j, 0 <= j < d, of the corrector equation
+ * -div(a(e_j + grad chi_j)) = 0 (Sec. 5.2, eq. corrector), i.e. the solve
+ * with F_k = i (P k)_j Ahat_k (the coefficients of d a / d x_j, App. D).
+ * chi: D complex (host / device), or NULL.  The result is also kept in the
+ * problem's corrector slot j until the next qp_corrector* call with that j.
+ */
+qp_status qp_corrector(qp_problem *p, int j, double *chi, double tol,
+                       qp_solve_info *info);
+qp_status qp_corrector_d(qp_problem *p, int j, double *chi, double tol,
+                         qp_solve_info *info);
+
+/*
+ * Homogenized coefficient A* (Sec. 5.2, eq. homcoefficient; App. D):
+ *     A*_ij = mean{ e_i . a (e_j + grad chi_j) }
+ * solving the d correctors to `tol` first.  With the discrete mean over the
+ * collocation grid this is Ahat_0 delta_ij + sum_m Ahat_m i(P(-m))_i chi_j[-m].
+ * Astar: host d*d row-major (flux form above).  Astar_energy (host d*d, may be
+ * NULL): the symmetric energy form Ahat_0 delta_ij - chi_i^H Q chi_j.
+ * info: host array of d entries (one per corrector), may be NULL.
+ */
+qp_status qp_homogenized(qp_problem *p, double *Astar, double tol,
+                         qp_solve_info *info);
+qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy,
+                            double tol, qp_solve_info *info);
+
+/* ---- single steps of the path, device pointers (used by parity tests) ---- */
+
+/* y = Q u in FP64 (eq. linear_system; y[C(0)] = 0, u[C(0)] ignored). */
+qp_status qp_matvec_d(qp_problem *p, const double *u, double *y);
+/* y = Q u with float data and arithmetic (the FP32-IR inner product). */
+qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y);
+/* The diagonal preconditioner (eq. precond; kind per the options), D doubles. */
+qp_status qp_precond_d(qp_problem *p, double *M);
+/* Corrector right-hand side F_k = i (P k)_j Ahat_k, D complex doubles. */
+qp_status qp_corrector_rhs_d(qp_problem *p, int j, double *F);
+/* Signed multi-index k = C^{-1}(i) of every entry: D x n int32 (Sec. 3.1.2). */
+qp_status qp_multi_index_d(qp_problem *p, int32_t *k);
+/* A* flux form from d correctors stored back to back (d*D complex, device);
+ * Astar: host d*d row-major. */
+qp_status qp_astar_d(qp_problem *p, const double *chi, double *Astar);
+/* Minimum and maximum of A over the collocation grid T_N^n (host outputs). */
+qp_status qp_coef_extrema(qp_problem *p, double *amin, double *amax);
+
+/* Wait for all work queued on the problem's stream. */
+qp_status qp_synchronize(qp_problem *p);
+
+/* Static description of a status code. */
+const char *qp_strerror(qp_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char *qp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QP_H */

@@ -1,0 +1,816 @@
+// Host side of the C ABI declared in include/qp.h: argument validation, the
+// device workspace, and the drivers that queue C-PCG (Alg. 2) and its FP32
+// refinement variant on one HIP stream.  The host never computes a Krylov
+// scalar: it queues batches of iterations and polls the device's `done` flag.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qp.h"
+#include "qp_internal.h"
+
+using qp::State;
+using qp::Table;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qp_status fail(qp_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define QP_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(QP_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+#define QP_TRY(call)                    \
+    do {                                \
+        qp_status s_ = (call);          \
+        if (s_ != QP_OK) return s_;     \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kExecLog = 4096;  // profiled launches remembered per solve and kind
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Offsets of every device buffer inside the workspace.
+struct Layout {
+    size_t F, U, r, h, q, M64, M32, x32, r32, h32, q32, chi, parts, states, small, exec, tab;
+    size_t total;
+};
+
+Layout make_layout(int d, int64_t D)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const size_t c64 = 16 * (size_t)D, c32 = 8 * (size_t)D;
+    L.F = take(c64);
+    L.U = take(c64);
+    L.r = take(c64);
+    L.h = take(c64);
+    L.q = take(c64);
+    L.M64 = take(8 * (size_t)D);
+    L.M32 = take(4 * (size_t)D);
+    L.x32 = take(c32);
+    L.r32 = take(c32);
+    L.h32 = take(c32);
+    L.q32 = take(c32);
+    L.chi = take(c64 * (size_t)d);
+    L.parts = take(3 * sizeof(double) * qp::kPartValues * qp::kMaxBlocks);
+    L.states = take(2 * sizeof(State));
+    L.small = take(sizeof(double) * 128);
+    L.exec = take(sizeof(int) * 2 * kExecLog);
+    L.tab = take(sizeof(Table));
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct qp_problem {
+    Table host{};
+    Table *tab = nullptr;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *ws = nullptr;
+    bool own_ws = false;
+    Layout L{};
+    qp_options opt{};
+    double amin = 0, amax = 0, pkmin = 0;
+    int flags = 0;
+    State *hstate = nullptr;   // pinned: two polling slots + final
+    double *hsmall = nullptr;  // pinned
+    int *hexec = nullptr;      // pinned copy of the execution log
+    std::vector<hipEvent_t> ev_hot, ev_res;  // profiling events (begin, end pairs)
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+
+    template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    double *F() const { return at<double>(L.F); }
+    double *U() const { return at<double>(L.U); }
+    double *r() const { return at<double>(L.r); }
+    double *h() const { return at<double>(L.h); }
+    double *q() const { return at<double>(L.q); }
+    double *M64() const { return at<double>(L.M64); }
+    float *M32() const { return at<float>(L.M32); }
+    float *x32() const { return at<float>(L.x32); }
+    float *r32() const { return at<float>(L.r32); }
+    float *h32() const { return at<float>(L.h32); }
+    float *q32() const { return at<float>(L.q32); }
+    double *chi(int j) const { return at<double>(L.chi) + (size_t)2 * host.D * j; }
+    qp::Parts parts() const
+    {
+        double *p = at<double>(L.parts);
+        const size_t stride = (size_t)qp::kPartValues * qp::kMaxBlocks;
+        return qp::Parts{p, p + stride, p + 2 * stride};
+    }
+    State *st() const { return at<State>(L.states); }
+    double *small() const { return at<double>(L.small); }
+    int *exec_hot() const { return at<int>(L.exec); }
+    int *exec_res() const { return at<int>(L.exec) + kExecLog; }
+};
+
+namespace {
+
+qp_status check_args(int d, int n, const double *P, int g, const int32_t *modes,
+                     const double *coef, int N)
+{
+    if (!P || !modes || !coef) return fail(QP_EINVAL, "null P, modes or coef");
+    if (d < 1 || d > QP_MAX_DIM_D) return fail(QP_EINVAL, "d=%d outside [1, %d]", d, QP_MAX_DIM_D);
+    if (n < d || n > QP_MAX_DIM_N) return fail(QP_EINVAL, "n=%d outside [d, %d]", n, QP_MAX_DIM_N);
+    if (N < 2) return fail(QP_EINVAL, "N=%d < 2", N);
+    if (g < 1 || g > QP_MAX_MODES) return fail(QP_EINVAL, "g=%d outside [1, %d]", g, QP_MAX_MODES);
+    int64_t D = 1;
+    for (int t = 0; t < n; ++t) {
+        D *= N;
+        if (D >= ((int64_t)1 << 31)) return fail(QP_EINVAL, "N^n exceeds 2^31 - 1");
+    }
+    for (int i = 0; i < d * n; ++i)
+        if (!std::isfinite(P[i])) return fail(QP_EINVAL, "P has a non-finite entry");
+    double cmax = 0.0;
+    for (int r = 0; r < g; ++r) {
+        if (!std::isfinite(coef[2 * r]) || !std::isfinite(coef[2 * r + 1]))
+            return fail(QP_EINVAL, "coefficient %d is not finite", r);
+        cmax = std::max(cmax, std::hypot(coef[2 * r], coef[2 * r + 1]));
+        for (int t = 0; t < n; ++t) {
+            const int64_t m = modes[r * n + t];
+            if (2 * std::llabs(m) >= N)
+                return fail(QP_EINVAL, "mode %d has |m_%d| = %lld >= N/2 (would alias)", r, t,
+                            (long long)std::llabs(m));
+        }
+    }
+    int zero = -1;
+    for (int r = 0; r < g; ++r) {
+        bool z = true;
+        for (int t = 0; t < n; ++t) z = z && modes[r * n + t] == 0;
+        if (z) zero = r;
+        for (int s = r + 1; s < g; ++s) {
+            bool same = true;
+            for (int t = 0; t < n; ++t) same = same && modes[r * n + t] == modes[s * n + t];
+            if (same) return fail(QP_EINVAL, "modes %d and %d are equal", r, s);
+        }
+    }
+    if (zero < 0) return fail(QP_EINVAL, "the mean coefficient Ahat_0 is missing");
+    const double tolh = 1e-14 * cmax;
+    if (!(coef[2 * zero] > 0.0) || std::fabs(coef[2 * zero + 1]) > tolh)
+        return fail(QP_EINVAL, "Ahat_0 must be real and positive");
+    for (int r = 0; r < g; ++r) {
+        int partner = -1;
+        for (int s = 0; s < g && partner < 0; ++s) {
+            bool neg = true;
+            for (int t = 0; t < n; ++t) neg = neg && modes[s * n + t] == -modes[r * n + t];
+            if (neg) partner = s;
+        }
+        if (partner < 0) return fail(QP_EINVAL, "mode %d has no -m partner (field not real)", r);
+        const double dr = coef[2 * partner] - coef[2 * r];
+        const double di = coef[2 * partner + 1] + coef[2 * r + 1];
+        if (std::hypot(dr, di) > tolh)
+            return fail(QP_EINVAL, "Ahat_{-m} != conj(Ahat_m) for mode %d (field not real)", r);
+    }
+    return QP_OK;
+}
+
+void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *modes,
+                 const double *coef, int N)
+{
+    std::memset(&T, 0, sizeof(T));
+    T.d = d;
+    T.n = n;
+    T.N = N;
+    T.g = g;
+    int64_t D = 1;
+    for (int t = 0; t < n; ++t) D *= N;
+    T.D = (int)D;
+    int64_t s = 1;
+    for (int t = n - 1; t >= 0; --t) {
+        T.stride[t] = (int)s;
+        s *= N;
+    }
+    int c = 0;
+    while ((1LL << c) < N) ++c;
+    T.shift = 31 + c;
+    T.magic = (uint64_t)((((unsigned __int128)1 << T.shift) + (unsigned)N - 1) / (unsigned)N);
+    for (int l = 0; l < d; ++l)
+        for (int t = 0; t < n; ++t) T.P[l][t] = P[l * n + t];
+    for (int r = 0; r < g; ++r) {
+        bool z = true;
+        int64_t off = 0, mi = 0, ni = 0;
+        for (int t = 0; t < n; ++t) {
+            const int m = modes[r * n + t];
+            T.modes[r][t] = m;
+            z = z && m == 0;
+            off -= (int64_t)m * T.stride[t];
+            mi = mi * N + ((m % N) + N) % N;
+            ni = ni * N + (((-m) % N) + N) % N;
+        }
+        T.off[r] = (int)off;
+        T.midx[r] = (int)mi;
+        T.nidx[r] = (int)ni;
+        T.coef[r][0] = coef[2 * r];
+        T.coef[r][1] = coef[2 * r + 1];
+        for (int l = 0; l < d; ++l) {
+            double v = 0.0;
+            for (int t = 0; t < n; ++t) v += P[l * n + t] * (double)modes[r * n + t];
+            T.Pm[r][l] = v;
+        }
+        if (z) {
+            T.zero_mode = r;
+            T.a0 = coef[2 * r];
+        }
+    }
+    T.real_coef = 1;
+    for (int r = 0; r < g; ++r)
+        if (coef[2 * r + 1] != 0.0) T.real_coef = 0;
+    int nb = (int)std::min<int64_t>(qp::kMaxBlocks, (D + qp::kBlock - 1) / qp::kBlock);
+    if (nb >= 64) nb -= nb % 8;
+    int64_t chunk = (D + nb - 1) / nb;
+    chunk = (chunk + qp::kBlock - 1) / qp::kBlock * qp::kBlock;
+    T.chunk = (int)chunk;
+    T.nblocks = (int)((D + chunk - 1) / chunk);
+}
+
+
+void release(qp_problem *p)
+{
+    if (!p) return;
+    for (auto e : p->ev_hot) (void)hipEventDestroy(e);
+    for (auto e : p->ev_res) (void)hipEventDestroy(e);
+    for (auto e : p->ev_poll)
+        if (e) (void)hipEventDestroy(e);
+    if (p->ev_t0) (void)hipEventDestroy(p->ev_t0);
+    if (p->ev_t1) (void)hipEventDestroy(p->ev_t1);
+    if (p->hstate) (void)hipHostFree(p->hstate);
+    if (p->hsmall) (void)hipHostFree(p->hsmall);
+    if (p->hexec) (void)hipHostFree(p->hexec);
+    if (p->own_ws && p->ws) (void)hipFree(p->ws);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+// ------------------------------------------------------------- profiling
+
+struct Profile {
+    int hot = 0, res = 0;  // launches queued (index into the event pools)
+};
+
+qp_status events_ready(std::vector<hipEvent_t> &pool, size_t pairs)
+{
+    while (pool.size() < 2 * pairs) {
+        hipEvent_t e;
+        QP_HIP(hipEventCreate(&e));
+        pool.push_back(e);
+    }
+    return QP_OK;
+}
+
+// Queue one stiffness product; with profiling on, bracket it with events and
+// give it a slot of the execution log.
+qp_status queue_matvec(qp_problem *p, int prec, int epi, const void *x, void *y, const double *f,
+                       Profile &pf)
+{
+    const bool resid = epi == qp::EPI_RESID;
+    int &idx = resid ? pf.res : pf.hot;
+    std::vector<hipEvent_t> &pool = resid ? p->ev_res : p->ev_hot;
+    int *exec = nullptr;
+    const bool prof = p->opt.profile && idx < kExecLog;
+    if (prof) {
+        QP_TRY(events_ready(pool, idx + 1));
+        exec = (resid ? p->exec_res() : p->exec_hot()) + idx;
+        QP_HIP(hipEventRecord(pool[2 * idx], p->stream));
+    }
+    QP_HIP(qp::launch_matvec(prec, epi, p->tab, p->host, x, y, f, p->M32(), p->parts(), p->st(),
+                             exec, p->stream));
+    if (prof) QP_HIP(hipEventRecord(pool[2 * idx + 1], p->stream));
+    ++idx;
+    return QP_OK;
+}
+
+// Sum of the event-timed durations of the launches that ran.
+qp_status profile_totals(qp_problem *p, const Profile &pf, qp_solve_info *info, bool ir)
+{
+    const int nh = std::min(pf.hot, kExecLog), nr = std::min(pf.res, kExecLog);
+    QP_HIP(hipMemcpyAsync(p->hexec, p->exec_hot(), sizeof(int) * 2 * kExecLog,
+                          hipMemcpyDeviceToHost, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    auto total = [&](std::vector<hipEvent_t> &pool, const int *log, int n, int &count) {
+        double ms = 0.0;
+        count = 0;
+        for (int k = 0; k < n; ++k) {
+            if (!log[k]) continue;
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
+                ms += t;
+                ++count;
+            }
+        }
+        return ms;
+    };
+    int c = 0;
+    if (ir) {
+        info->matvec32_ms = total(p->ev_hot, p->hexec, nh, c);
+        info->matvec32_launches = c;
+        info->matvec_ms = total(p->ev_res, p->hexec + kExecLog, nr, c);
+        info->matvec_launches = c;
+    } else {
+        info->matvec_ms = total(p->ev_hot, p->hexec, nh, c);
+        info->matvec_launches = c;
+    }
+    return QP_OK;
+}
+
+qp_status clear_exec_log(qp_problem *p)
+{
+    if (p->opt.profile)
+        QP_HIP(hipMemsetAsync(p->exec_hot(), 0, sizeof(int) * 2 * kExecLog, p->stream));
+    return QP_OK;
+}
+
+// ------------------------------------------------------------- solvers
+
+// Double-buffered polling: after each batch the state is copied to pinned
+// memory; the batch before the newest is inspected, so the device always has
+// queued work.  Kernels of a finished solve return at once.
+struct Poller {
+    qp_problem *p;
+    int slot = 0;
+    bool pending[2] = {false, false};
+    // Record a poll point; returns true when an older poll saw `done`.
+    qp_status push(bool &finished)
+    {
+        finished = false;
+        QP_HIP(hipMemcpyAsync(&p->hstate[slot], p->st(), sizeof(State), hipMemcpyDeviceToHost,
+                              p->stream));
+        QP_HIP(hipEventRecord(p->ev_poll[slot], p->stream));
+        pending[slot] = true;
+        const int other = slot ^ 1;
+        if (pending[other]) {
+            QP_HIP(hipEventSynchronize(p->ev_poll[other]));
+            pending[other] = false;
+            finished = p->hstate[other].done != 0;
+        }
+        slot = other;
+        return QP_OK;
+    }
+    qp_status final_state(State &out)
+    {
+        QP_HIP(hipMemcpyAsync(&p->hstate[2], p->st(), sizeof(State), hipMemcpyDeviceToHost,
+                              p->stream));
+        QP_HIP(hipStreamSynchronize(p->stream));
+        out = p->hstate[2];
+        return QP_OK;
+    }
+};
+
+qp_status solve_fp64(qp_problem *p, const double *rhs, double *U, double tol, State &st,
+                     Profile &pf)
+{
+    const qp::Parts parts = p->parts();
+    QP_HIP(qp::launch_state_reset(p->st(), p->stream));
+    QP_HIP(qp::launch_pcg_init(qp::F64, p->tab, p->host, rhs, nullptr, U, p->r(), p->h(), p->M64(),
+                               parts, p->st(), p->stream));
+    QP_HIP(qp::launch_pcg_start(qp::F64, p->host, tol, 0.0, p->opt.maxit, parts, p->st(), p->stream));
+    const int batch = p->opt.poll_every > 0 ? p->opt.poll_every : 8;
+    Poller poll{p};
+    int j = 0;
+    while (j < p->opt.maxit) {
+        const int k = std::min(batch, p->opt.maxit - j);
+        for (int it = 0; it < k; ++it, ++j) {
+            QP_TRY(queue_matvec(p, qp::F64, qp::EPI_ALPHA, p->h(), p->q(), nullptr, pf));
+            QP_HIP(qp::launch_pcg_update(qp::F64, j, p->tab, p->host, U, p->r(), p->h(), p->q(),
+                                         p->M64(), parts, p->st(), p->stream));
+            QP_HIP(qp::launch_pcg_direction(qp::F64, j, p->tab, p->host, p->r(), p->h(), p->M64(),
+                                            parts, p->st(), p->stream));
+        }
+        bool fin = false;
+        QP_TRY(poll.push(fin));
+        if (fin) break;
+    }
+    return poll.final_state(st);
+}
+
+// FP32-IR: float C-PCG whose residual is replaced by the FP64 residual
+// F' - Q X of the FP64 solution X whenever the float residual has dropped by
+// `inner_tol` (or reached tol), and at least every `poll_every` iterations.
+qp_status solve_ir(qp_problem *p, const double *rhs, double *X, double tol, State &st, Profile &pf)
+{
+    const qp::Parts parts = p->parts();
+    QP_HIP(qp::launch_state_reset(p->st(), p->stream));
+    QP_HIP(qp::launch_ir_unit(p->tab, p->host, rhs, parts, p->st(), p->stream));
+    QP_HIP(qp::launch_pcg_init(qp::F32, p->tab, p->host, rhs, X, p->x32(), p->r32(), p->h32(),
+                               p->M32(), parts, p->st(), p->stream));
+    QP_HIP(qp::launch_pcg_start(qp::F32, p->host, tol, p->opt.inner_tol, p->opt.maxit, parts,
+                                p->st(), p->stream));
+    const int batch = std::max(2, p->opt.poll_every > 0 ? p->opt.poll_every : 8);
+    Poller poll{p};
+    int j = 0;
+    bool fin = false;
+    auto replacement = [&](int jj) -> qp_status {
+        QP_HIP(qp::launch_ir_fold(p->tab, p->host, X, p->x32(), p->st(), p->stream));
+        QP_TRY(queue_matvec(p, qp::F64, qp::EPI_RESID, X, p->r32(), rhs, pf));
+        QP_HIP(qp::launch_ir_direction(jj, p->tab, p->host, p->r32(), p->h32(), p->M32(), parts,
+                                       p->st(), p->stream));
+        return QP_OK;
+    };
+    while (j < p->opt.maxit) {
+        const int k = std::min(batch, p->opt.maxit - j);
+        for (int it = 0; it < k; ++it, ++j) {
+            QP_TRY(queue_matvec(p, qp::F32, qp::EPI_ALPHA, p->h32(), p->q32(), nullptr, pf));
+            QP_HIP(qp::launch_pcg_update(qp::F32, j, p->tab, p->host, p->x32(), p->r32(), p->h32(),
+                                         p->q32(), p->M32(), parts, p->st(), p->stream));
+            if (it + 1 < k)
+                QP_HIP(qp::launch_pcg_direction(qp::F32, j, p->tab, p->host, p->r32(), p->h32(),
+                                                p->M32(), parts, p->st(), p->stream));
+            else
+                QP_TRY(replacement(j));
+        }
+        QP_TRY(poll.push(fin));
+        if (fin) break;
+    }
+    QP_TRY(poll.final_state(st));
+    if (!st.done) {
+        // iteration limit: the last batch ended in a replacement, so X holds
+        // every increment; report the true residual of that replacement
+        st.status = QP_ENOCONV;
+    }
+    return QP_OK;
+}
+
+qp_status solve_dispatch(qp_problem *p, const double *rhs, double *U, double tol,
+                         qp_solve_info *info)
+{
+    qp_solve_info local;
+    if (!info) info = &local;
+    std::memset(info, 0, sizeof(*info));
+    info->flags = p->flags;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QP_EINVAL, "tol must be positive and finite");
+    const bool ir = p->opt.precision == QP_PREC_FP32_IR;
+    Profile pf;
+    State st{};
+    QP_TRY(clear_exec_log(p));
+    QP_HIP(hipEventRecord(p->ev_t0, p->stream));
+    QP_TRY(ir ? solve_ir(p, rhs, U, tol, st, pf) : solve_fp64(p, rhs, U, tol, st, pf));
+    QP_HIP(hipEventRecord(p->ev_t1, p->stream));
+    QP_HIP(hipEventSynchronize(p->ev_t1));
+    float ms = 0.f;
+    QP_HIP(hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1));
+    info->status = st.status;
+    info->iters = st.iters;
+    info->outer_iters = ir ? st.replacements : 0;
+    info->rel_resid = ir ? std::sqrt(st.rr) : (st.rr0 > 0 ? std::sqrt(st.rr / st.rr0) : 0.0);
+    info->seconds = ms * 1e-3;
+    if (p->opt.profile) QP_TRY(profile_totals(p, pf, info, ir));
+    const qp_status s = (qp_status)st.status;
+    if (s == QP_ENOTSPD) fail(s, "PCG breakdown: (Q h, h) <= 0");
+    else if (s == QP_ENOCONV) fail(s, "iteration limit reached before the tolerance");
+    else if (s == QP_ENONFINITE) fail(s, "non-finite value in the right-hand side or residual");
+    return s;
+}
+
+qp_status check_options(const qp_options *o)
+{
+    if (o->precision != QP_PREC_FP64 && o->precision != QP_PREC_FP32_IR)
+        return fail(QP_EINVAL, "unknown precision %d", o->precision);
+    if (o->precond != QP_PRECOND_PAPER && o->precond != QP_PRECOND_JACOBI)
+        return fail(QP_EINVAL, "unknown preconditioner %d", o->precond);
+    if (o->maxit < 1 || !(o->inner_tol > 0.0) || o->inner_tol >= 1.0 ||
+        o->poll_every < 0)
+        return fail(QP_EINVAL, "invalid iteration limits or inner tolerance");
+    return QP_OK;
+}
+
+qp_status compute_setup(qp_problem *p)
+{
+    const qp::Parts parts = p->parts();
+    QP_HIP(qp::launch_precond(p->tab, p->host, p->opt.precond, p->M64(), p->M32(), parts, p->small(),
+                              p->stream));
+    QP_HIP(qp::launch_extrema(p->tab, p->host, parts, p->small() + 1, p->stream));
+    QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    p->pkmin = p->hsmall[0];
+    p->amin = p->hsmall[1];
+    p->amax = p->hsmall[2];
+    return QP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void qp_default_options(qp_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = QP_PREC_FP64;
+    opt->precond = QP_PRECOND_PAPER;
+    opt->maxit = 10000;
+    opt->inner_tol = 1e-4;
+    opt->poll_every = 0;
+}
+
+size_t qp_workspace_bytes(int d, int n, int N, int g)
+{
+    (void)g;
+    if (d < 1 || n < 1 || N < 2 || n > QP_MAX_DIM_N || d > QP_MAX_DIM_D) return 0;
+    int64_t D = 1;
+    for (int t = 0; t < n; ++t) {
+        D *= N;
+        if (D >= ((int64_t)1 << 31)) return 0;
+    }
+    return make_layout(d, D).total;
+}
+
+qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, const int32_t *modes,
+                    const double *coef, int N, const qp_options *opt)
+{
+    g_last_error.clear();
+    if (!out) return fail(QP_EINVAL, "out is null");
+    *out = nullptr;
+    QP_TRY(check_args(d, n, P, g, modes, coef, N));
+    qp_options o;
+    qp_default_options(&o);
+    if (opt) o = *opt;
+    QP_TRY(check_options(&o));
+
+    qp_problem *p = new (std::nothrow) qp_problem();
+    if (!p) return fail(QP_ENOMEM, "host allocation failed");
+    p->opt = o;
+    build_table(p->host, d, n, P, g, modes, coef, N);
+    p->L = make_layout(d, p->host.D);
+
+    auto bail = [&](qp_status st) {
+        release(p);
+        return st;
+    };
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+        return bail(fail(QP_EDEVICE, "no HIP device available"));
+    if (hipGetDevice(&p->device) != hipSuccess) return bail(fail(QP_EDEVICE, "hipGetDevice failed"));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) != hipSuccess)
+        return bail(fail(QP_EDEVICE, "hipGetDeviceProperties failed"));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return bail(fail(QP_EDEVICE, "device %d is %s; this library is built for gfx950", p->device,
+                         prop.gcnArchName));
+    if (o.stream) {
+        p->stream = static_cast<hipStream_t>(o.stream);
+    } else {
+        if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(QP_EDEVICE, "hipStreamCreate failed"));
+        p->own_stream = true;
+    }
+    if (o.workspace) {
+        if (o.workspace_bytes < p->L.total)
+            return bail(fail(QP_ENOMEM, "workspace has %zu bytes, %zu needed", o.workspace_bytes,
+                             p->L.total));
+        if (reinterpret_cast<uintptr_t>(o.workspace) % kAlign != 0)
+            return bail(fail(QP_EINVAL, "workspace must be 256-byte aligned"));
+        p->ws = static_cast<char *>(o.workspace);
+    } else {
+        if (hipMalloc(&p->ws, p->L.total) != hipSuccess)
+            return bail(fail(QP_ENOMEM, "hipMalloc of %zu bytes failed", p->L.total));
+        p->own_ws = true;
+    }
+    p->opt.workspace = nullptr;
+    if (hipHostMalloc(&p->hstate, 3 * sizeof(State), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&p->hsmall, 128 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&p->hexec, 2 * kExecLog * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(QP_ENOMEM, "pinned host allocation failed"));
+    for (auto &e : p->ev_poll)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(QP_EDEVICE, "hipEventCreate failed"));
+    if (hipEventCreate(&p->ev_t0) != hipSuccess || hipEventCreate(&p->ev_t1) != hipSuccess)
+        return bail(fail(QP_EDEVICE, "hipEventCreate failed"));
+    p->tab = p->at<Table>(p->L.tab);
+    if (hipMemcpyAsync(p->tab, &p->host, sizeof(Table), hipMemcpyHostToDevice, p->stream) != hipSuccess)
+        return bail(fail(QP_EDEVICE, "table upload failed"));
+    qp_status s = compute_setup(p);
+    if (s != QP_OK) return bail(s);
+
+    double pn = 0.0;
+    for (int i = 0; i < d * n; ++i) pn += P[i] * P[i];
+    if (!(p->pkmin >= 1e-24 * pn))
+        return bail(fail(QP_EINVAL, "P k = 0 for a nonzero k in the grid (dependent columns of P)"));
+    const double scale = std::max(std::fabs(p->amin), std::fabs(p->amax));
+    if (p->amin < -1e-12 * scale)
+        return bail(fail(QP_ENOTELLIPTIC, "coefficient minimum on the grid is %.6g < 0", p->amin));
+    if (std::fabs(p->amin) <= 1e-12 * scale) p->flags |= QP_FLAG_DEGENERATE;
+    *out = p;
+    return QP_OK;
+}
+
+void qp_destroy(qp_problem *p)
+{
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    release(p);
+}
+
+int64_t qp_dim(const qp_problem *p) { return p ? (int64_t)p->host.D : 0; }
+
+qp_status qp_set_options(qp_problem *p, const qp_options *opt)
+{
+    if (!p || !opt) return fail(QP_EINVAL, "null argument");
+    QP_TRY(check_options(opt));
+    const int old_precond = p->opt.precond;
+    void *stream = p->opt.stream;
+    p->opt = *opt;
+    p->opt.stream = stream;
+    p->opt.workspace = nullptr;
+    if (opt->precond != old_precond) return compute_setup(p);
+    return QP_OK;
+}
+
+qp_status qp_solve_d(qp_problem *p, const double *rhs, double *u, double tol, qp_solve_info *info)
+{
+    if (!p || !rhs || !u) return fail(QP_EINVAL, "null argument");
+    if (rhs == u) return fail(QP_EINVAL, "rhs and u must not overlap");
+    return solve_dispatch(p, rhs, u, tol, info);
+}
+
+qp_status qp_solve(qp_problem *p, const double *rhs, double *u, double tol, qp_solve_info *info)
+{
+    if (!p || !rhs || !u) return fail(QP_EINVAL, "null argument");
+    const size_t bytes = 16 * (size_t)p->host.D;
+    QP_HIP(hipMemcpyAsync(p->F(), rhs, bytes, hipMemcpyHostToDevice, p->stream));
+    qp_status s = solve_dispatch(p, p->F(), p->U(), tol, info);
+    if (s == QP_EDEVICE || s == QP_EINVAL) return s;
+    QP_HIP(hipMemcpyAsync(u, p->U(), bytes, hipMemcpyDeviceToHost, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return s;
+}
+
+qp_status qp_corrector_d(qp_problem *p, int j, double *chi, double tol, qp_solve_info *info)
+{
+    if (!p) return fail(QP_EINVAL, "null problem");
+    if (j < 0 || j >= p->host.d) return fail(QP_EINVAL, "corrector index %d outside [0, d)", j);
+    QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, p->F(), p->stream));
+    qp_status s = solve_dispatch(p, p->F(), p->chi(j), tol, info);
+    if (s == QP_EDEVICE || s == QP_EINVAL) return s;
+    if (chi) {
+        QP_HIP(hipMemcpyAsync(chi, p->chi(j), 16 * (size_t)p->host.D, hipMemcpyDeviceToDevice, p->stream));
+        QP_HIP(hipStreamSynchronize(p->stream));
+    }
+    return s;
+}
+
+qp_status qp_corrector(qp_problem *p, int j, double *chi, double tol, qp_solve_info *info)
+{
+    qp_status s = qp_corrector_d(p, j, nullptr, tol, info);
+    if (s == QP_EDEVICE || s == QP_EINVAL) return s;
+    if (chi) {
+        QP_HIP(hipMemcpyAsync(chi, p->chi(j), 16 * (size_t)p->host.D, hipMemcpyDeviceToHost, p->stream));
+        QP_HIP(hipStreamSynchronize(p->stream));
+    }
+    return s;
+}
+
+qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy, double tol,
+                            qp_solve_info *info)
+{
+    if (!p || !Astar) return fail(QP_EINVAL, "null argument");
+    const int d = p->host.d;
+    qp_status worst = QP_OK;
+    for (int j = 0; j < d; ++j) {
+        qp_status s = qp_corrector_d(p, j, nullptr, tol, info ? &info[j] : nullptr);
+        if (s == QP_EDEVICE || s == QP_EINVAL) return s;
+        if (s != QP_OK && worst == QP_OK) worst = s;
+    }
+    QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), p->stream));
+    if (Astar_energy) {
+        const qp::Parts parts = p->parts();
+        for (int j = 0; j < d; ++j) {
+            QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->chi(j), p->q(),
+                                     nullptr, nullptr, parts, p->st(), nullptr, p->stream));
+            for (int i = 0; i < d; ++i)
+                QP_HIP(qp::launch_dot(p->tab, p->host, p->chi(i), p->q(), parts,
+                                      p->small() + 64 + i * d + j, p->stream));
+        }
+    }
+    QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    for (int e = 0; e < d * d; ++e) Astar[e] = p->hsmall[e];
+    if (Astar_energy)
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j)
+                Astar_energy[i * d + j] = (i == j ? p->host.a0 : 0.0) - p->hsmall[64 + i * d + j];
+    if (worst != QP_OK) fail(worst, "a corrector solve did not converge");
+    return worst;
+}
+
+qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info *info)
+{
+    return qp_homogenized_ex(p, Astar, nullptr, tol, info);
+}
+
+qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
+{
+    if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
+    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, u, y, nullptr, nullptr,
+                             p->parts(), p->st(), nullptr, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
+qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
+{
+    if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
+    QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, p->tab, p->host, u, y, nullptr, nullptr,
+                             p->parts(), p->st(), nullptr, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
+qp_status qp_precond_d(qp_problem *p, double *M)
+{
+    if (!p || !M) return fail(QP_EINVAL, "null argument");
+    QP_HIP(hipMemcpyAsync(M, p->M64(), 8 * (size_t)p->host.D, hipMemcpyDeviceToDevice, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
+qp_status qp_corrector_rhs_d(qp_problem *p, int j, double *F)
+{
+    if (!p || !F) return fail(QP_EINVAL, "null argument");
+    if (j < 0 || j >= p->host.d) return fail(QP_EINVAL, "corrector index %d outside [0, d)", j);
+    QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, F, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
+qp_status qp_multi_index_d(qp_problem *p, int32_t *k)
+{
+    if (!p || !k) return fail(QP_EINVAL, "null argument");
+    QP_HIP(qp::launch_multi_index(p->tab, p->host, k, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
+qp_status qp_astar_d(qp_problem *p, const double *chi, double *Astar)
+{
+    if (!p || !chi || !Astar) return fail(QP_EINVAL, "null argument");
+    QP_HIP(qp::launch_astar(p->tab, p->host, chi, p->small(), p->stream));
+    QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 32 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    const int d = p->host.d;
+    for (int e = 0; e < d * d; ++e) Astar[e] = p->hsmall[e];
+    return QP_OK;
+}
+
+qp_status qp_coef_extrema(qp_problem *p, double *amin, double *amax)
+{
+    if (!p) return fail(QP_EINVAL, "null problem");
+    if (amin) *amin = p->amin;
+    if (amax) *amax = p->amax;
+    return QP_OK;
+}
+
+qp_status qp_synchronize(qp_problem *p)
+{
+    if (!p) return fail(QP_EINVAL, "null problem");
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
+const char *qp_strerror(qp_status s)
+{
+    switch (s) {
+    case QP_OK: return "success";
+    case QP_EINVAL: return "invalid argument";
+    case QP_ENOTELLIPTIC: return "coefficient is negative on the collocation grid";
+    case QP_ENOTSPD: return "PCG breakdown: the operator is not positive definite";
+    case QP_ENOCONV: return "iteration limit reached";
+    case QP_ENOMEM: return "out of memory";
+    case QP_EDEVICE: return "HIP device error";
+    case QP_ENONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+const char *qp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Device-side helpers shared by the gfx950 kernels (not part of the ABI).
+//
+// Grid traversal: every streaming kernel runs ht.nblocks workgroups of kBlock
+// threads.  Workgroup b owns a contiguous chunk of the frequency grid in the
+// storage order of Sec. 3.1.2; chunks are dealt so that each of the 8 XCDs
+// (which receive workgroups round robin) sweeps one contiguous eighth of the
+// grid, keeping a stencil's neighbours in that XCD's L2.
+//
+// Reductions never use device-scope fences (on gfx950 each one writes back
+// and invalidates the XCD's L2).  A kernel stores one partial per workgroup
+// with a plain store; the next kernel on the stream (kernel boundaries make
+// the stores visible) reduces all partials in its prologue, in the same fixed
+// order in every workgroup, so every workgroup sees bit-identical totals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "qp_internal.h"
+
+namespace qp {
+
+constexpr int kWave = 64;
+constexpr int kWaves = kBlock / kWave;
+
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+template <typename T> using cplx_t = typename Cplx<T>::type;
+
+__device__ __forceinline__ void chunk_of_block(const Table *__restrict__ tab, int &begin, int &end)
+{
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int logical = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    begin = logical * tab->chunk;
+    end = min(begin + tab->chunk, tab->D);
+}
+
+// floor(x / N) for 0 <= x < 2^31 by multiply-shift (magic from the host).
+__device__ __forceinline__ int div_n(const Table *__restrict__ tab, int x)
+{
+    return (int)(((uint64_t)(uint32_t)x * tab->magic) >> tab->shift);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Workgroup sum (or min) of NV values; the result is returned in every thread.
+template <int NV, bool MIN = false>
+__device__ __forceinline__ void block_reduce(double (&v)[NV])
+{
+    __shared__ double red[NV][kWaves];
+    const int lane = threadIdx.x % kWave;
+    const int wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = MIN ? wave_min(v[k]) : wave_sum(v[k]);
+        if (lane == 0) red[k][wid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = red[k][0];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) t = MIN ? fmin(t, red[k][w]) : t + red[k][w];
+        v[k] = t;
+    }
+    __syncthreads();
+}
+
+// Store this workgroup's totals: part[k * kMaxBlocks + blockIdx.x].
+template <int NV, bool MIN = false>
+__device__ __forceinline__ void store_partials(double (&v)[NV], double *__restrict__ part)
+{
+    block_reduce<NV, MIN>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) part[k * kMaxBlocks + blockIdx.x] = v[k];
+    }
+}
+
+// Sum (or min) of the nb partials a previous kernel stored; same order in
+// every workgroup, result in every thread.
+template <int NV, bool MIN = false>
+__device__ __forceinline__ void load_totals(const double *__restrict__ part, int nb, double (&v)[NV])
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = MIN ? INFINITY : 0.0;
+        for (int b = threadIdx.x; b < nb; b += kBlock) {
+            const double p = part[k * kMaxBlocks + b];
+            s = MIN ? fmin(s, p) : s + p;
+        }
+        v[k] = s;
+    }
+    block_reduce<NV, MIN>(v);
+}
+
+__device__ __forceinline__ bool finite(double x) { return x == x && fabs(x) != INFINITY; }
+
+}  // namespace qp

@@ -1,0 +1,137 @@
+// Internal interface between the host driver (qp_api.cpp) and the gfx950
+// kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qp.h"
+
+namespace qp {
+
+constexpr int kMaxN = QP_MAX_DIM_N;
+constexpr int kMaxD = QP_MAX_DIM_D;
+constexpr int kMaxG = QP_MAX_MODES;
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kMaxBlocks = 1024;  // grid cap of the streaming kernels: 4 per CU
+
+// Problem constants, resident in device memory and read with uniform
+// (scalar) loads by every kernel.
+struct Table {
+    int d, n, N, g;
+    int D;                    // N^n
+    int nblocks;              // grid of the streaming kernels
+    int chunk;                // elements per workgroup (multiple of kBlock)
+    int zero_mode;            // index of the mode m = 0
+    uint64_t magic;           // floor division by N: (x * magic) >> shift, x < 2^31
+    int shift;
+    int real_coef;            // every Ahat_m has zero imaginary part
+    int stride[kMaxN];        // N^(n-1-t)
+    double P[kMaxD][kMaxN];   // projection matrix, row-major
+    int modes[kMaxG][kMaxN];  // coefficient modes m
+    double coef[kMaxG][2];    // Ahat_m (re, im)
+    double Pm[kMaxG][kMaxD];  // P m
+    int off[kMaxG];           // -sum_t m_t N^(n-1-t): unwrapped storage offset
+    int midx[kMaxG];          // C(m): storage index of mode m
+    int nidx[kMaxG];          // C(-m)
+    double a0;                // Ahat_0
+};
+
+// Krylov state of one solve, device resident.  All scalars are FP64.
+// Fields are written by workgroup 0 of one kernel and read by later kernels
+// only (no kernel reads what it writes), except rz[], which alternates
+// between the two slots by iteration parity.
+struct State {
+    double rz[2];     // (r, M r): slot j & 1 holds the value entering iteration j
+    double alpha, beta, hq;
+    double rr;        // last ||r||^2 (recursive residual, solve units)
+    double rr0;       // ||F'||^2
+    double thresh;    // convergence: rr <= thresh (solve units)
+    double delta2;    // FP32-IR: replace the residual once rr <= delta2 * rr_last
+    double rr_last;   // FP32-IR: rr after the last residual replacement
+    double unit;      // FP32-IR: ||F'||; float vectors hold (true value) / unit
+    double inv_unit;
+    int iters;        // update steps performed
+    int replacements; // FP32-IR: FP64 residual replacements
+    int done;         // nonzero: every later kernel of this solve returns at once
+    int pause;        // FP32-IR: float iterations wait for the next replacement
+    int status;       // qp_status of the solve
+    int maxit;
+};
+
+enum Epilogue { EPI_NONE = 0, EPI_ALPHA = 1, EPI_RESID = 2 };
+enum Precision { F64 = 0, F32 = 1 };
+
+// Partial-sum buffers: each holds kPartValues * kMaxBlocks doubles.
+constexpr int kPartValues = 2;
+struct Parts {
+    double *a;  // written by the stiffness product (h^H Q h)
+    double *b;  // written by the vector update / residual ((r, M r), ||r||^2)
+    double *c;  // auxiliary reductions (norms, dots, extrema)
+};
+
+// ---- launchers; all enqueue on `s` and return the launch status ----
+
+// Stiffness product, one launch:
+//   EPI_NONE : y = Q x
+//   EPI_ALPHA: y = Q x and parts.a <- Re(x^H y); returns at once if the solve
+//              is done or paused; *exec (nullable) <- 1 when it ran
+//   EPI_RESID: FP64 only. y (float2) = (f' - Q x) * st->inv_unit and
+//              parts.b <- (sum M32 |y|^2, sum |(f' - Q x) inv_unit|^2)
+hipError_t launch_matvec(int prec, int epi, const Table *tab, const Table &ht, const void *x,
+                         void *y, const double *f, const float *M32, const Parts &parts,
+                         State *st, int *exec, hipStream_t s);
+
+// Start of a solve.  r = f' * scale (scale = 1 for F64, st->inv_unit for F32),
+// U = 0, X64 = 0 (if given), h = M r; parts.b <- ((r, M r), ||r||^2).
+hipError_t launch_pcg_init(int prec, const Table *tab, const Table &ht, const double *f,
+                           double *X64, void *U, void *r, void *h, const void *M,
+                           const Parts &parts, State *st, hipStream_t s);
+// One workgroup: totals of parts.b -> rz[0], rr; F64: rr0, thresh = tol^2 rr0;
+// F32: thresh = tol^2, delta2, rr_last.  done when rr is 0; status on NaN.
+hipError_t launch_pcg_start(int prec, const Table &ht, double tol, double delta, int maxit,
+                            const Parts &parts, State *st, hipStream_t s);
+// Iteration j: alpha = rz[j&1] / (totals of parts.a); U += alpha h;
+// r -= alpha q; parts.b <- ((r, M r), ||r||^2).
+hipError_t launch_pcg_update(int prec, int j, const Table *tab, const Table &ht, void *U,
+                             void *r, const void *h, const void *q, const void *M,
+                             const Parts &parts, State *st, hipStream_t s);
+// Iteration j: beta from parts.b; h = M r + beta h.  F64 stops on
+// convergence or at maxit; F32 pauses when the residual has dropped enough.
+hipError_t launch_pcg_direction(int prec, int j, const Table *tab, const Table &ht,
+                                const void *r, void *h, const void *M, const Parts &parts,
+                                State *st, hipStream_t s);
+// FP32-IR start: st->rr0 = ||f'||^2, unit = sqrt(rr0) (two launches).
+hipError_t launch_ir_unit(const Table *tab, const Table &ht, const double *f, const Parts &parts,
+                          State *st, hipStream_t s);
+// FP32-IR residual replacement: X += unit * x; x = 0.
+hipError_t launch_ir_fold(const Table *tab, const Table &ht, double *X, float *x, State *st,
+                          hipStream_t s);
+// FP32-IR, after the FP64 residual (EPI_RESID): convergence on the true
+// residual, else beta, h = M r + beta h and pause cleared.
+hipError_t launch_ir_direction(int j, const Table *tab, const Table &ht, const float *r,
+                               float *h, const float *M, const Parts &parts, State *st,
+                               hipStream_t s);
+
+// ---- setup and single-step kernels ----
+// M (double and float copies); kind 0 paper, 1 Jacobi; out[0] = min_{k!=0} |P k|^2.
+hipError_t launch_precond(const Table *tab, const Table &ht, int kind, double *M64, float *M32,
+                          const Parts &parts, double *out, hipStream_t s);
+// out[0] = min, out[1] = max of A over the collocation grid.
+hipError_t launch_extrema(const Table *tab, const Table &ht, const Parts &parts, double *out,
+                          hipStream_t s);
+// F_k = i (P k)_j Ahat_k.
+hipError_t launch_corrector_rhs(const Table *tab, const Table &ht, int j, double *F,
+                                hipStream_t s);
+// A* flux form from d correctors (d*D complex): out[0..d*d) real, out[d*d..) imag.
+hipError_t launch_astar(const Table *tab, const Table &ht, const double *chi, double *out,
+                        hipStream_t s);
+// out[0] = Re(x^H y).
+hipError_t launch_dot(const Table *tab, const Table &ht, const double *x, const double *y,
+                      const Parts &parts, double *out, hipStream_t s);
+// Signed multi-index of every entry (D x n int32).
+hipError_t launch_multi_index(const Table *tab, const Table &ht, int32_t *k, hipStream_t s);
+// Reset a State (flags, counters) with a kernel (no memset node).
+hipError_t launch_state_reset(State *st, hipStream_t s);
+
+}  // namespace qp

@@ -1,0 +1,253 @@
+// Setup and single-step kernels: the diagonal preconditioner, the grid
+// extrema of the coefficient, corrector right-hand sides, the homogenized
+// coefficient and plain dot products.
+#include "qp_device.h"
+
+namespace qp {
+namespace {
+
+// Storage digits of entry i (last digit fastest) and its signed index.
+__device__ __forceinline__ void digits(const Table *__restrict__ tab, int i, int *ib)
+{
+    const int N = tab->N;
+    int rest = i;
+    for (int t = tab->n - 1; t >= 0; --t) {
+        const int q = div_n(tab, rest);
+        ib[t] = rest - q * N;
+        rest = q;
+    }
+}
+
+__device__ __forceinline__ int signed_of(int b, int N) { return (2 * b < N) ? b : b - N; }
+
+// Diagonal preconditioner (eq. precond and its Theorem):
+//   kind 0:  M_k = q_kk / ||Q e_k||^2,  q_kk = Ahat_0 |P k|^2,
+//            ||Q e_k||^2 = sum_m |Ahat_m|^2 ((P rep(k + m)).(P k))^2
+//            (column k has one entry per mode, in row rep(k + m))
+//   kind 1:  M_k = 1 / q_kk
+// M_0 = 0.  Partials of min_{k != 0} |P k|^2 (dependent columns of P).
+__global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ tab, int kind,
+                                                    double *__restrict__ M64,
+                                                    float *__restrict__ M32,
+                                                    double *__restrict__ part)
+{
+    const int N = tab->N, n = tab->n, d = tab->d, g = tab->g;
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    double pkmin[1] = {INFINITY};
+    for (int i = begin + threadIdx.x; i < end; i += kBlock) {
+        int ib[kMaxN];
+        digits(tab, i, ib);
+        double pk[kMaxD];
+        for (int l = 0; l < d; ++l) {
+            double s = 0.0;
+            for (int t = 0; t < n; ++t) s += tab->P[l][t] * (double)signed_of(ib[t], N);
+            pk[l] = s;
+        }
+        double pk2 = 0.0;
+        for (int l = 0; l < d; ++l) pk2 += pk[l] * pk[l];
+        double m = 0.0;
+        if (i != 0) {
+            pkmin[0] = fmin(pkmin[0], pk2);
+            const double qkk = tab->a0 * pk2;
+            if (kind == 1) {
+                m = (qkk != 0.0) ? 1.0 / qkk : 0.0;
+            } else {
+                double col = 0.0;
+                for (int r = 0; r < g; ++r) {
+                    double w = 0.0;
+                    for (int l = 0; l < d; ++l) {
+                        double pj = 0.0;
+                        for (int t = 0; t < n; ++t) {
+                            int jb = ib[t] + tab->modes[r][t];
+                            jb += (jb < 0) ? N : 0;
+                            jb -= (jb >= N) ? N : 0;
+                            pj += tab->P[l][t] * (double)signed_of(jb, N);
+                        }
+                        w += pj * pk[l];
+                    }
+                    const double a2 = tab->coef[r][0] * tab->coef[r][0] +
+                                      tab->coef[r][1] * tab->coef[r][1];
+                    col += a2 * w * w;
+                }
+                m = (col != 0.0) ? qkk / col : 0.0;
+            }
+        }
+        M64[i] = m;
+        M32[i] = (float)m;
+    }
+    store_partials<1, true>(pkmin, part);
+}
+
+// min and -max of A(y) = sum_m Ahat_m exp(i m.y) over y = 2 pi j / N.  The
+// phase m.j is reduced mod N exactly in integers before the sine/cosine.
+__global__ __launch_bounds__(kBlock) void k_extrema(const Table *__restrict__ tab,
+                                                    double *__restrict__ part)
+{
+    const int N = tab->N, n = tab->n, g = tab->g;
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    double v[2] = {INFINITY, INFINITY};
+    for (int i = begin + threadIdx.x; i < end; i += kBlock) {
+        int ib[kMaxN];
+        digits(tab, i, ib);
+        double a = 0.0;
+        for (int r = 0; r < g; ++r) {
+            long long ph = 0;
+            for (int t = 0; t < n; ++t) ph += (long long)tab->modes[r][t] * ib[t];
+            ph %= N;
+            if (ph < 0) ph += N;
+            double sn, cs;
+            sincospi(2.0 * (double)ph / (double)N, &sn, &cs);
+            a += tab->coef[r][0] * cs - tab->coef[r][1] * sn;
+        }
+        v[0] = fmin(v[0], a);
+        v[1] = fmin(v[1], -a);
+    }
+    store_partials<2, true>(v, part);
+}
+
+template <int NV, bool MIN>
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ part, int nb,
+                                                     double *__restrict__ out, int negate_second)
+{
+    double v[NV];
+    load_totals<NV, MIN>(part, nb, v);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k) out[k] = (k == 1 && negate_second) ? -v[k] : v[k];
+    }
+}
+
+// F_k = i (P k)_j Ahat_k on the modes, 0 elsewhere (each entry written once).
+__global__ __launch_bounds__(kBlock) void k_corrector_rhs(const Table *__restrict__ tab, int j,
+                                                          double2 *__restrict__ F)
+{
+    const int g = tab->g;
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    for (int i = begin + threadIdx.x; i < end; i += kBlock) {
+        double2 v = make_double2(0.0, 0.0);
+        for (int r = 0; r < g; ++r) {
+            if (tab->midx[r] == i) {
+                const double s = tab->Pm[r][j];
+                v.x += -s * tab->coef[r][1];
+                v.y += s * tab->coef[r][0];
+            }
+        }
+        F[i] = v;
+    }
+}
+
+// A*_ij = Ahat_0 delta_ij + mean_N{ a d_i chi_j }
+//       = Ahat_0 delta_ij + sum_m Ahat_m i (P(-m))_i chi_j[C(-m)]
+// (the discrete mean keeps the frequency pairs whose sum is 0 mod N).
+__global__ void k_astar(const Table *__restrict__ tab, const double2 *__restrict__ chi,
+                        double *__restrict__ out)
+{
+    const int d = tab->d, g = tab->g;
+    const int e = threadIdx.x;
+    if (e >= d * d) return;
+    const int i = e / d, j = e % d;
+    const double2 *cj = chi + (size_t)j * tab->D;
+    double re = (i == j) ? tab->a0 : 0.0;
+    double im = 0.0;
+    for (int r = 0; r < g; ++r) {
+        const double2 c = cj[tab->nidx[r]];
+        const double pr = tab->coef[r][0] * c.x - tab->coef[r][1] * c.y;  // Ahat_m chi
+        const double pi = tab->coef[r][0] * c.y + tab->coef[r][1] * c.x;
+        const double s = tab->Pm[r][i];  // i (P(-m))_i = -i s
+        re += s * pi;
+        im -= s * pr;
+    }
+    out[e] = re;
+    out[d * d + e] = im;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(const Table *__restrict__ tab,
+                                                const double2 *__restrict__ x,
+                                                const double2 *__restrict__ y,
+                                                double *__restrict__ part)
+{
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    double acc[1] = {0.0};
+    for (int i = begin + threadIdx.x; i < end; i += kBlock) {
+        const double2 a = x[i], b = y[i];
+        acc[0] += a.x * b.x + a.y * b.y;
+    }
+    store_partials<1>(acc, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_multi_index(const Table *__restrict__ tab,
+                                                        int32_t *__restrict__ k)
+{
+    const int N = tab->N, n = tab->n;
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    for (int i = begin + threadIdx.x; i < end; i += kBlock) {
+        int ib[kMaxN];
+        digits(tab, i, ib);
+        for (int t = 0; t < n; ++t) k[(size_t)i * n + t] = signed_of(ib[t], N);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_precond(const Table *tab, const Table &ht, int kind, double *M64, float *M32,
+                          const Parts &parts, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_precond, dim3(ht.nblocks), dim3(kBlock), 0, s, tab, kind, M64, M32, parts.c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_finalize<1, true>), dim3(1), dim3(kBlock), 0, s, (const double *)parts.c,
+                       ht.nblocks, out, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_extrema(const Table *tab, const Table &ht, const Parts &parts, double *out,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_extrema, dim3(ht.nblocks), dim3(kBlock), 0, s, tab, parts.c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_finalize<2, true>), dim3(1), dim3(kBlock), 0, s, (const double *)parts.c,
+                       ht.nblocks, out, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_corrector_rhs(const Table *tab, const Table &ht, int j, double *F, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_corrector_rhs, dim3(ht.nblocks), dim3(kBlock), 0, s, tab, j,
+                       reinterpret_cast<double2 *>(F));
+    return hipGetLastError();
+}
+
+hipError_t launch_astar(const Table *tab, const Table &ht, const double *chi, double *out,
+                        hipStream_t s)
+{
+    (void)ht;
+    hipLaunchKernelGGL(k_astar, dim3(1), dim3(64), 0, s, tab, reinterpret_cast<const double2 *>(chi),
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const Table *tab, const Table &ht, const double *x, const double *y,
+                      const Parts &parts, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot, dim3(ht.nblocks), dim3(kBlock), 0, s, tab,
+                       reinterpret_cast<const double2 *>(x), reinterpret_cast<const double2 *>(y),
+                       parts.c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_finalize<1, false>), dim3(1), dim3(kBlock), 0, s, (const double *)parts.c,
+                       ht.nblocks, out, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_index(const Table *tab, const Table &ht, int32_t *k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_multi_index, dim3(ht.nblocks), dim3(kBlock), 0, s, tab, k);
+    return hipGetLastError();
+}
+
+}  // namespace qp

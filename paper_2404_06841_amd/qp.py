@@ -1,0 +1,333 @@
+"""ctypes binding of libqp.so (the C ABI in include/qp.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+gfx950 kernels.  Functions keep the C names; device arguments are torch CUDA
+tensors (complex128 / complex64 / float64 / int32), host arguments are numpy
+arrays.  PyTorch supplies device memory and the stream, nothing else.
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from types import SimpleNamespace
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqp.so")
+
+QP_OK = 0
+QP_EINVAL = -1
+QP_ENOTELLIPTIC = -2
+QP_ENOTSPD = -3
+QP_ENOCONV = -4
+QP_ENOMEM = -5
+QP_EDEVICE = -6
+QP_ENONFINITE = -7
+
+QP_PREC_FP64 = 0
+QP_PREC_FP32_IR = 1
+QP_PRECOND_PAPER = 0
+QP_PRECOND_JACOBI = 1
+QP_FLAG_DEGENERATE = 1
+QP_FLAG_F0_IGNORED = 2
+
+MAX_N, MAX_D, MAX_MODES = 8, 4, 64
+
+#: every symbol include/qp.h declares
+EXPORTED = (
+    "qp_default_options", "qp_workspace_bytes", "qp_create", "qp_destroy", "qp_dim",
+    "qp_set_options", "qp_solve", "qp_solve_d", "qp_corrector", "qp_corrector_d",
+    "qp_homogenized", "qp_homogenized_ex", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
+    "qp_corrector_rhs_d", "qp_multi_index_d", "qp_astar_d", "qp_coef_extrema",
+    "qp_synchronize", "qp_strerror", "qp_last_error",
+)
+
+
+class qp_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("precond", C.c_int), ("maxit", C.c_int),
+                ("inner_tol", C.c_double), ("poll_every", C.c_int),
+                ("profile", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
+
+
+class qp_solve_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
+                ("flags", C.c_int), ("rel_resid", C.c_double), ("seconds", C.c_double),
+                ("matvec_launches", C.c_int), ("matvec_ms", C.c_double),
+                ("matvec32_launches", C.c_int), ("matvec32_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class QPError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libqp.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2404_06841_amd.build` (no fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    sig = {
+        "qp_default_options": (None, [C.POINTER(qp_options)]),
+        "qp_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int]),
+        "qp_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, dp, C.c_int, ip, dp, C.c_int,
+                                C.POINTER(qp_options)]),
+        "qp_destroy": (None, [vp]),
+        "qp_dim": (C.c_int64, [vp]),
+        "qp_set_options": (C.c_int, [vp, C.POINTER(qp_options)]),
+        "qp_solve": (C.c_int, [vp, dp, dp, C.c_double, C.POINTER(qp_solve_info)]),
+        "qp_solve_d": (C.c_int, [vp, vp, vp, C.c_double, C.POINTER(qp_solve_info)]),
+        "qp_corrector": (C.c_int, [vp, C.c_int, dp, C.c_double, C.POINTER(qp_solve_info)]),
+        "qp_corrector_d": (C.c_int, [vp, C.c_int, vp, C.c_double, C.POINTER(qp_solve_info)]),
+        "qp_homogenized": (C.c_int, [vp, dp, C.c_double, C.POINTER(qp_solve_info)]),
+        "qp_homogenized_ex": (C.c_int, [vp, dp, dp, C.c_double, C.POINTER(qp_solve_info)]),
+        "qp_matvec_d": (C.c_int, [vp, vp, vp]),
+        "qp_matvec32_d": (C.c_int, [vp, vp, vp]),
+        "qp_precond_d": (C.c_int, [vp, vp]),
+        "qp_corrector_rhs_d": (C.c_int, [vp, C.c_int, vp]),
+        "qp_multi_index_d": (C.c_int, [vp, vp]),
+        "qp_astar_d": (C.c_int, [vp, vp, dp]),
+        "qp_coef_extrema": (C.c_int, [vp, dp, dp]),
+        "qp_synchronize": (C.c_int, [vp]),
+        "qp_strerror": (C.c_char_p, [C.c_int]),
+        "qp_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str) -> int:
+    if status != QP_OK:
+        msg = lib().qp_last_error().decode() or lib().qp_strerror(status).decode()
+        raise QPError(status, where, msg)
+    return status
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _tensor_ptr(t, dtype=None, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------
+# Thin wrappers with the C names
+# --------------------------------------------------------------------------
+
+def qp_default_options() -> qp_options:
+    o = qp_options()
+    lib().qp_default_options(C.byref(o))
+    return o
+
+
+def qp_workspace_bytes(d: int, n: int, N: int, g: int) -> int:
+    return int(lib().qp_workspace_bytes(d, n, N, g))
+
+
+def qp_create(d, n, P, modes, coef, N, opt: qp_options | None = None):
+    """Returns (status, handle); handle is None on failure."""
+    P = np.ascontiguousarray(P, dtype=np.float64).reshape(-1)
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1)
+    coef = np.ascontiguousarray(np.asarray(coef, dtype=np.complex128).reshape(-1)).view(np.float64)
+    g = coef.shape[0] // 2
+    h = C.c_void_p()
+    st = lib().qp_create(C.byref(h), int(d), int(n), _dptr(P), int(g),
+                         modes.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(coef), int(N),
+                         C.byref(opt) if opt is not None else None)
+    return st, (h if st == QP_OK else None)
+
+
+def qp_last_error() -> str:
+    return lib().qp_last_error().decode()
+
+
+def qp_strerror(status: int) -> str:
+    return lib().qp_strerror(int(status)).decode()
+
+
+# --------------------------------------------------------------------------
+# Convenience object
+# --------------------------------------------------------------------------
+
+class Problem:
+    """One qp_problem with a torch-allocated workspace on the current stream.
+
+    `prob` is any object with d, n, N, P, modes, coef (e.g. a workload)."""
+
+    def __init__(self, prob, precision: str = "fp64", precond: str = "paper",
+                 maxit: int = 10000, inner_tol: float = 1e-4,
+                 profile: bool = False, stream=None, poll_every: int = 0):
+        import torch
+        self.d, self.n, self.N = int(prob.d), int(prob.n), int(prob.N)
+        self.D = self.N ** self.n
+        modes = np.asarray(prob.modes, dtype=np.int32).reshape(-1, self.n)
+        self.g = modes.shape[0]
+        opt = qp_default_options()
+        opt.precision = QP_PREC_FP32_IR if precision == "fp32ir" else QP_PREC_FP64
+        opt.precond = QP_PRECOND_JACOBI if precond == "jacobi" else QP_PRECOND_PAPER
+        opt.maxit = int(maxit)
+        opt.inner_tol = float(inner_tol)
+        opt.profile = 1 if profile else 0
+        opt.poll_every = int(poll_every)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        opt.stream = C.c_void_p(self.stream.cuda_stream)
+        nbytes = qp_workspace_bytes(self.d, self.n, self.N, self.g)
+        if nbytes <= 0:
+            raise QPError(QP_EINVAL, "qp_workspace_bytes", "unsupported shape")
+        # 256-byte aligned torch allocation
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        opt.workspace = C.c_void_p((base + 255) // 256 * 256)
+        opt.workspace_bytes = nbytes
+        self.opt = opt
+        st, h = qp_create(self.d, self.n, prob.P, modes, prob.coef, self.N, opt)
+        _check(st, "qp_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lib().qp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- options
+    def set_precision(self, precision: str):
+        self.opt.precision = QP_PREC_FP32_IR if precision == "fp32ir" else QP_PREC_FP64
+        _check(lib().qp_set_options(self.h, C.byref(self.opt)), "qp_set_options")
+
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opt, k, v)
+        _check(lib().qp_set_options(self.h, C.byref(self.opt)), "qp_set_options")
+
+    # -- solves (device tensors)
+    def solve_d(self, rhs, out=None, tol: float = 1e-12, check: bool = True):
+        import torch
+        if out is None:
+            out = torch.empty(self.D, dtype=torch.complex128, device="cuda")
+        info = qp_solve_info()
+        st = lib().qp_solve_d(self.h, _tensor_ptr(rhs, torch.complex128, self.D),
+                              _tensor_ptr(out, torch.complex128, self.D), float(tol), C.byref(info))
+        if check:
+            _check(st, "qp_solve_d")
+        return out, info
+
+    def solve(self, rhs: np.ndarray, tol: float = 1e-12, check: bool = True):
+        rhs = np.ascontiguousarray(rhs, dtype=np.complex128).reshape(-1)
+        out = np.empty(self.D, dtype=np.complex128)
+        info = qp_solve_info()
+        st = lib().qp_solve(self.h, _dptr(rhs.view(np.float64)), _dptr(out.view(np.float64)),
+                            float(tol), C.byref(info))
+        if check:
+            _check(st, "qp_solve")
+        return out, info
+
+    def corrector_d(self, j: int, out=None, tol: float = 1e-12, check: bool = True):
+        import torch
+        if out is None:
+            out = torch.empty(self.D, dtype=torch.complex128, device="cuda")
+        info = qp_solve_info()
+        st = lib().qp_corrector_d(self.h, int(j), _tensor_ptr(out, torch.complex128, self.D),
+                                  float(tol), C.byref(info))
+        if check:
+            _check(st, "qp_corrector_d")
+        return out, info
+
+    def homogenized(self, tol: float = 1e-12, energy: bool = True, check: bool = True):
+        A = np.zeros(self.d * self.d)
+        E = np.zeros(self.d * self.d)
+        infos = (qp_solve_info * self.d)()
+        st = lib().qp_homogenized_ex(self.h, _dptr(A), _dptr(E) if energy else None, float(tol),
+                                     infos)
+        if check:
+            _check(st, "qp_homogenized_ex")
+        return SimpleNamespace(A=A.reshape(self.d, self.d),
+                               A_energy=E.reshape(self.d, self.d) if energy else None,
+                               infos=[infos[j] for j in range(self.d)], status=st)
+
+    # -- single steps
+    def matvec_d(self, u, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.D, dtype=torch.complex128, device="cuda")
+        _check(lib().qp_matvec_d(self.h, _tensor_ptr(u, torch.complex128, self.D),
+                                 _tensor_ptr(out, torch.complex128, self.D)), "qp_matvec_d")
+        return out
+
+    def matvec32_d(self, u, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.D, dtype=torch.complex64, device="cuda")
+        _check(lib().qp_matvec32_d(self.h, _tensor_ptr(u, torch.complex64, self.D),
+                                   _tensor_ptr(out, torch.complex64, self.D)), "qp_matvec32_d")
+        return out
+
+    def precond_d(self):
+        import torch
+        out = torch.empty(self.D, dtype=torch.float64, device="cuda")
+        _check(lib().qp_precond_d(self.h, _tensor_ptr(out, torch.float64, self.D)), "qp_precond_d")
+        return out
+
+    def corrector_rhs_d(self, j: int):
+        import torch
+        out = torch.empty(self.D, dtype=torch.complex128, device="cuda")
+        _check(lib().qp_corrector_rhs_d(self.h, int(j), _tensor_ptr(out, torch.complex128, self.D)),
+               "qp_corrector_rhs_d")
+        return out
+
+    def multi_index_d(self):
+        import torch
+        out = torch.empty(self.D * self.n, dtype=torch.int32, device="cuda")
+        _check(lib().qp_multi_index_d(self.h, _tensor_ptr(out, torch.int32, self.D * self.n)),
+               "qp_multi_index_d")
+        return out.view(self.D, self.n)
+
+    def astar_d(self, chis):
+        import torch
+        A = np.zeros(self.d * self.d)
+        _check(lib().qp_astar_d(self.h, _tensor_ptr(chis, torch.complex128, self.d * self.D),
+                                _dptr(A)), "qp_astar_d")
+        return A.reshape(self.d, self.d)
+
+    def coef_extrema(self):
+        lo, hi = C.c_double(), C.c_double()
+        _check(lib().qp_coef_extrema(self.h, C.byref(lo), C.byref(hi)), "qp_coef_extrema")
+        return lo.value, hi.value
+
+    def synchronize(self):
+        _check(lib().qp_synchronize(self.h), "qp_synchronize")

@@ -1,0 +1,43 @@
+"""Write tests/golden/oracle_astar.json: homogenized coefficients computed by
+the CPU oracle (and nothing else) for the full-size workloads that are too slow
+to recompute inside a test.
+
+    python tests/golden/make_golden.py
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from paper_2404_06841_amd import workloads as W  # noqa: E402
+
+CASES = {
+    "c2_eightfold_N16": lambda: W.eightfold(16),
+    "c3_eightfold_random_N32": lambda: W.eightfold_random(32, 0),
+}
+
+
+def main():
+    out = {"_about": "A* (flux and energy forms) of the CPU oracle at tol 1e-12, "
+                     "written by tests/golden/make_golden.py"}
+    for name, make in CASES.items():
+        prob = make()
+        t = time.time()
+        r = oracle.homogenize(prob, tol=1e-12)
+        out[name] = {"N": prob.N, "D": prob.D, "tol": 1e-12,
+                     "A": r.A.tolist(), "A_energy": r.A_energy.tolist(),
+                     "iters": [i.iters for i in r.infos],
+                     "seconds": time.time() - t}
+        print(name, out[name], flush=True)
+    with open(os.path.join(HERE, "oracle_astar.json"), "w") as f:
+        json.dump(out, f, indent=2)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,276 @@
+"""Parity of the gfx950 path (through the C ABI) with the FP64 CPU oracle.
+
+Every case uses the same seeded inputs on both sides.  Tolerances:
+  * index map: bit-exact;
+  * FP64 stiffness product / preconditioner / right-hand sides: entrywise
+    |gpu - oracle| <= 1e-13 * max|oracle| (summation order differs only);
+  * FP32 stiffness product: <= 2e-5 * max|oracle| (float unit roundoff 6e-8
+    times the g-term sums and the size of W);
+  * solves at tolerance tol: ||U_gpu - U_oracle|| <= 1e3 * tol * ||U_oracle||
+    (both are within kappa*tol of the same unique discrete solution);
+  * A*: relative error <= 1e-10 against the oracle solved at tol 1e-12.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_06841_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2404_06841_amd import qp  # noqa: E402  (loads libqp.so; fails loudly if missing)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x: np.ndarray, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t) -> np.ndarray:
+    return t.detach().cpu().numpy()
+
+
+PROBLEMS = {
+    "c1_1d_n2_N32": lambda: W.one_d_two_mode(32, 2.0),
+    "ex1_N16": lambda: W.one_d_two_mode(16, 6.0, 2 * np.pi),
+    "three_mode_N9": lambda: W.one_d_three_mode(9),
+    "c2_eightfold_N16": lambda: W.eightfold(16),
+    "eightfold_N6": lambda: W.eightfold(6),
+    "random_N12": lambda: W.eightfold_random(12, 5),
+    "random_N5": lambda: W.eightfold_random(5, 7),
+    "paper2d_N6_complexcoef": lambda: W.paper_four_mode_2d(6),
+    "icosa_N6": lambda: W.icosahedral(6),
+    "icosa_N4": lambda: W.icosahedral(4),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(PROBLEMS))
+def case(request):
+    prob = PROBLEMS[request.param]()
+    say(f"[case] {request.param} d={prob.d} n={prob.n} N={prob.N} D={prob.D} g={prob.g}")
+    gp = qp.Problem(prob)
+    yield request.param, prob, gp
+    gp.close()
+
+
+def test_multi_index_bit_exact(case):
+    name, prob, gp = case
+    k = host(gp.multi_index_d())
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([np.arange(min(prob.D, 4096)), rng.integers(0, prob.D, 2000),
+                                    [prob.D - 1]]))
+    for i in idx:
+        assert tuple(k[i]) == oracle.multi_index(prob.n, prob.N, int(i)), (name, i)
+
+
+def test_precond_matches_oracle(case):
+    name, prob, gp = case
+    M = host(gp.precond_d())
+    ref = oracle.precond(prob, 0)
+    assert np.abs(M - ref).max() <= 1e-13 * np.abs(ref).max(), name
+
+
+def test_extrema_match_oracle(case):
+    name, prob, gp = case
+    lo, hi = gp.coef_extrema()
+    rlo, rhi = oracle.coef_extrema(prob)
+    assert lo == pytest.approx(rlo, abs=1e-12) and hi == pytest.approx(rhi, abs=1e-12)
+
+
+def test_matvec_fp64_matches_oracle(case):
+    name, prob, gp = case
+    u = W.random_vector(prob.D, seed=21)
+    y = host(gp.matvec_d(dev(u)))
+    ref = oracle.matvec(prob, u)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max(), name
+    assert y[0] == 0
+
+
+def test_matvec_fp32_matches_oracle(case):
+    name, prob, gp = case
+    u = W.random_vector(prob.D, seed=22).astype(np.complex64)
+    y = host(gp.matvec32_d(dev(u, torch.complex64)))
+    ref = oracle.matvec(prob, u.astype(np.complex128))
+    assert np.abs(y - ref).max() <= 2e-5 * np.abs(ref).max(), name
+
+
+def test_corrector_rhs_matches_oracle(case):
+    name, prob, gp = case
+    for j in range(prob.d):
+        F = host(gp.corrector_rhs_d(j))
+        ref = oracle.corrector_rhs(prob, j)
+        assert np.abs(F - ref).max() <= 1e-15 * max(1.0, np.abs(ref).max()), (name, j)
+
+
+def test_solve_fp64_matches_oracle(case):
+    name, prob, gp = case
+    if prob.name == "1d_n2" and prob.meta.get("mean") == 2.0:
+        pytest.skip("degenerate field: covered by the corrector test")
+    F = W.random_vector(prob.D, seed=23)
+    tol = 1e-12
+    U, info = gp.solve_d(dev(F), tol=tol)
+    ref, st, it, rr = oracle.pcg(prob, F, tol=tol)
+    U = host(U)
+    assert info.status == 0 and st == 0
+    assert abs(info.iters - it) <= 2, (name, info.iters, it)
+    assert info.rel_resid <= tol
+    assert U[0] == 0
+    assert np.linalg.norm(U - ref) <= 1e3 * tol * np.linalg.norm(ref), name
+
+
+def _astar_scale(prob, A):
+    # A* lies between the harmonic and arithmetic means of a, so Ahat_0 is its
+    # natural scale (the degenerate 1D field has A* = 0 exactly at even N).
+    a0 = float(np.real(prob.coef[[i for i, m in enumerate(prob.modes) if not np.any(m)][0]]))
+    return max(np.abs(A).max(), a0)
+
+
+def test_homogenized_matches_oracle(case):
+    name, prob, gp = case
+    r = gp.homogenized(tol=1e-12)
+    ref = oracle.homogenize(prob, tol=1e-12)
+    scale = _astar_scale(prob, ref.A)
+    assert np.abs(r.A - ref.A).max() <= 1e-10 * scale, (name, r.A, ref.A)
+    assert np.abs(r.A_energy - ref.A_energy).max() <= 1e-10 * scale, name
+
+
+def test_fp32_ir_homogenized_matches_oracle(case):
+    name, prob, gp = case
+    gp.set_precision("fp32ir")
+    try:
+        r = gp.homogenized(tol=1e-12)
+    finally:
+        gp.set_precision("fp64")
+    ref = oracle.homogenize(prob, tol=1e-12)
+    scale = _astar_scale(prob, ref.A)
+    assert all(i.status == 0 and i.rel_resid <= 1e-12 for i in r.infos), name
+    assert np.abs(r.A - ref.A).max() <= 1e-10 * scale, (name, r.A, ref.A)
+
+
+# ------------------------------------------------------------- full-size cases
+
+def test_c3_fullsize_fp64_and_fp32ir_astar():
+    gold = json.load(open(os.path.join(GOLDEN, "oracle_astar.json")))["c3_eightfold_random_N32"]
+    prob = W.eightfold_random(32, 0)
+    say(f"[case] c3 N=32 D={prob.D}")
+    gp = qp.Problem(prob)
+    A_ref = np.array(gold["A"])
+    for prec in ("fp64", "fp32ir"):
+        gp.set_precision(prec)
+        r = gp.homogenized(tol=1e-12)
+        err = np.abs(r.A - A_ref).max() / np.abs(A_ref).max()
+        say(f"  {prec}: iters {[i.iters for i in r.infos]} outer {[i.outer_iters for i in r.infos]} "
+            f"rel err {err:.2e}")
+        assert err <= 1e-10
+    gp.close()
+
+
+def test_c3_fullsize_matvec_sampled_rows():
+    prob = W.eightfold_random(32, 0)
+    gp = qp.Problem(prob)
+    u = W.random_vector(prob.D, seed=31)
+    y = host(gp.matvec_d(dev(u)))
+    ref = oracle.matvec(prob, u)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    y32 = host(gp.matvec32_d(dev(u.astype(np.complex64), torch.complex64)))
+    assert np.abs(y32 - ref).max() <= 2e-5 * np.abs(ref).max()
+    gp.close()
+
+
+# ------------------------------------------------------------- error paths
+
+def test_literal_indefinite_fields_rejected():
+    for prob in (W.eightfold(8, amplitude=1.0), W.icosahedral(4, amplitude=1.0)):
+        st, h = qp.qp_create(prob.d, prob.n, prob.P, prob.modes, prob.coef, prob.N)
+        assert st == qp.QP_ENOTELLIPTIC and h is None
+
+
+def test_dependent_projection_rejected():
+    prob = W.one_d_two_mode(8, 6.0)
+    P = np.array([[1.0, 2.0]])
+    st, h = qp.qp_create(1, 2, P, prob.modes, prob.coef, 8)
+    assert st == qp.QP_EINVAL and "dependent" in qp.qp_last_error()
+
+
+def test_degenerate_field_flag_and_solve():
+    prob = W.one_d_two_mode(8, 2.0)  # A = 0 at the grid point (pi, pi)
+    gp = qp.Problem(prob)
+    F = W.sine_source(2, 8, [0, 1])
+    U, info = gp.solve_d(dev(F), tol=1e-12)
+    assert info.flags & qp.QP_FLAG_DEGENERATE
+    ref, st, it, rr = oracle.pcg(prob, F, tol=1e-12)
+    assert np.linalg.norm(host(U) - ref) <= 1e-8 * np.linalg.norm(ref)
+    gp.close()
+
+
+def test_iteration_limit_and_nonfinite_rhs():
+    prob = W.eightfold(8)
+    gp = qp.Problem(prob, maxit=1)
+    F = W.random_vector(prob.D, seed=1)
+    U, info = gp.solve_d(dev(F), tol=1e-12, check=False)
+    assert info.status == qp.QP_ENOCONV and info.iters == 1
+    ref, st, it, rr = oracle.pcg(prob, F, tol=1e-12, maxit=1)
+    assert np.linalg.norm(host(U) - ref) <= 1e-12 * np.linalg.norm(ref)
+    F[5] = np.nan
+    gp2 = qp.Problem(prob)
+    U, info = gp2.solve_d(dev(F), tol=1e-12, check=False)
+    assert info.status == qp.QP_ENONFINITE
+    gp.close()
+    gp2.close()
+
+
+def test_zero_rhs_and_ignored_zero_frequency():
+    prob = W.eightfold(6)
+    gp = qp.Problem(prob)
+    F = np.zeros(prob.D, complex)
+    F[0] = 5.0  # the zero frequency is not an equation
+    U, info = gp.solve_d(dev(F), tol=1e-12)
+    assert info.iters == 0 and np.all(host(U) == 0)
+    gp.close()
+
+
+def test_repeat_is_bitwise_identical():
+    prob = W.eightfold_random(12, 2)
+    gp = qp.Problem(prob)
+    F = dev(W.random_vector(prob.D, seed=8))
+    a, _ = gp.solve_d(F, tol=1e-12)
+    a = a.clone()
+    b, _ = gp.solve_d(F, tol=1e-12)
+    assert torch.equal(a, b)
+    gp.set_precision("fp32ir")
+    c, _ = gp.solve_d(F, tol=1e-12)
+    c = c.clone()
+    d, _ = gp.solve_d(F, tol=1e-12)
+    assert torch.equal(c, d)
+    gp.close()
+
+
+def test_host_pointer_entry_points():
+    prob = W.eightfold(8)
+    gp = qp.Problem(prob)
+    F = W.random_vector(prob.D, seed=4)
+    U, info = gp.solve(F, tol=1e-12)
+    ref, *_ = oracle.pcg(prob, F, tol=1e-12)
+    assert np.linalg.norm(U - ref) <= 1e-9 * np.linalg.norm(ref)
+    chi = np.empty(prob.D, complex)
+    st = qp.lib().qp_corrector(gp.h, 1, chi.ctypes.data_as(qp.C.POINTER(qp.C.c_double)), 1e-12, None)
+    assert st == 0
+    rc, *_ = oracle.pcg(prob, oracle.corrector_rhs(prob, 1), tol=1e-12)
+    assert np.linalg.norm(chi - rc) <= 1e-9 * np.linalg.norm(rc)
+    gp.close()
