@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, const Table *__res
 {
     if (st->done || st->pause) return;
     double hq[1];
-    load_totals<1>(part_in, gridDim.x, hq);
+    load_totals<1>(part_in, tab->nb_mv, hq);  // partials of the stiffness product
     if (!(hq[0] > 0.0)) {
         // (Q h, h) <= 0: Q is not positive definite on this Krylov space
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_direction(int j, const Table *__r
     if (st->done) return;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     double v[2];
-    load_totals<2>(part_in, gridDim.x, v);
+    load_totals<2>(part_in, tab->nb_mv, v);  // partials of the FP64 residual product
     const double rz_new = v[0], rr = v[1];  // true residual, scaled by 1/unit
     if (!finite(rr) || !finite(rz_new)) {
         if (lead) {

@@ -146,6 +146,12 @@ def paper_four_mode_2d(N: int = 6) -> Problem:
     return Problem("paper_2d_n4", 2, 4, int(N), P, modes, coef)
 
 
+def periodic_1d(N: int = 100, mean: float = 2.0, amp: float = 1.0) -> Problem:
+    """d = n = 1 (periodic): P = [1], A = mean + amp cos y."""
+    modes, coef = cosine_field(1, mean, [amp])
+    return Problem("periodic_1d", 1, 1, int(N), np.ones((1, 1)), modes, coef)
+
+
 def eightfold(N: int = 16, amplitude: float = 0.5, mean: float = 3.0) -> Problem:
     """d=2, n=4 eightfold: A = mean + amplitude * sum_{j=1..4} cos(y_j).
 

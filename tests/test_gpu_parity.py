@@ -57,6 +57,13 @@ PROBLEMS = {
     "paper2d_N6_complexcoef": lambda: W.paper_four_mode_2d(6),
     "icosa_N6": lambda: W.icosahedral(6),
     "icosa_N4": lambda: W.icosahedral(4),
+    "icosa_N8": lambda: W.icosahedral(8),
+    "ex1_N128_lines_split": lambda: W.one_d_two_mode(128, 6.0, 2 * np.pi),
+    "periodic_1d_N100": lambda: W.periodic_1d(100),
+    "periodic_1d_N9": lambda: W.periodic_1d(9),
+    "three_mode_N33_odd": lambda: W.one_d_three_mode(33),
+    "random_N24": lambda: W.eightfold_random(24, 3),
+    "random_N8": lambda: W.eightfold_random(8, 1),
 }
 
 
