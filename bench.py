@@ -1,0 +1,195 @@
+"""Benchmark: corrector solves per second of the projection-method hot path on
+one MI355X.
+
+Workload: the eightfold d=2, n=4 problem at N=32 per axis (1,048,576 complex
+unknowns) with 8 seeded random +-mode pairs around mean 3 (17 modes).  One step
+is one homogenization: the two corrector solves to relative residual 1e-12
+and the 2x2 homogenized coefficient A*.  The headline precision is FP32-IR
+(float stiffness product and preconditioner inside FP64 refinement); the same
+steps in plain FP64 are timed beside it.  A* of both is checked against the
+CPU oracle's value (tests/golden/oracle_astar.json).
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "corrector solves/s + matvec HBM GB/s, FP32-IR vs FP64 @1e-10; p99 latency"
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_fp32_eightfold_n4_N32.txt")
+MATVEC_SRC = os.path.join(ROOT, "paper_2404_06841_amd", "csrc", "qp_matvec.hip")
+
+
+def parse_args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_probe():
+    """A plain 512 MiB device-to-device copy, five times: the reference that
+    scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 512 * 1024 * 1024 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_copy": 4 * n, "copies": 5}), flush=True)
+
+
+def kernel_hash() -> str:
+    with open(MATVEC_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(D: int):
+    """HBM bytes per float stiffness-product launch from the committed rocprofv3
+    counter summary, or None when it was taken on another kernel version."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_hash") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_steps(gp, steps: int, torch):
+    """Time `steps` homogenizations; returns (seconds, per-solve latencies,
+    infos of the last step, A*)."""
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = None
+    mv_ms, mv_n = 0.0, 0
+    for _ in range(steps):
+        r = gp.homogenized(tol=TOL, energy=False)
+        for info in r.infos:
+            lat.append(info.seconds * 1e3)
+            mv_ms += info.matvec32_ms
+            mv_n += info.matvec32_launches
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat, r, (mv_ms, mv_n)
+
+
+def cpu_baseline(prob):
+    """The oracle, unmodified, on this host's cores: one FP64 homogenization of
+    the same workload (two corrector solves at tol 1e-12)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    r = oracle.homogenize(prob, tol=TOL)
+    dt = time.perf_counter() - t0
+    return {"value": round(prob.d / dt, 4), "unit": "corrector solves/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one homogenization ({prob.d} FP64 corrector solves, tol 1e-12, "
+                      f"{[i.iters for i in r.infos]} PCG iterations) of the same workload, "
+                      f"{dt:.2f} s"}
+
+
+def main():
+    args = parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(how the path would shard is described in DESIGN.md)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2404_06841_amd import qp
+    from paper_2404_06841_amd import workloads as W
+
+    prob = W.eightfold_random(32, 0)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_astar.json")))
+    A_ref = np.array(gold["c3_eightfold_random_N32"]["A"])
+
+    gp = qp.Problem(prob, precision="fp32ir", profile=True)
+    for _ in range(args.warmup):
+        gp.homogenized(tol=TOL, energy=False)
+    dt, lat, r, (mv_ms, mv_n) = run_steps(gp, args.steps, torch)
+    err_ir = float(np.abs(r.A - A_ref).max() / np.abs(A_ref).max())
+    solves = prob.d * args.steps
+    value = solves / dt
+
+    # the same steps in plain FP64 (comparison, not the headline)
+    gp.set_options(precision=qp.QP_PREC_FP64, profile=0)
+    for _ in range(args.warmup):
+        gp.homogenized(tol=TOL, energy=False)
+    dt64, lat64, r64, _ = run_steps(gp, args.steps, torch)
+    err_64 = float(np.abs(r64.A - A_ref).max() / np.abs(A_ref).max())
+    gp.close()
+
+    D = prob.D
+    algo_bytes = 16.0 * D  # float complex: read x once, write y once
+    avg_s = (mv_ms / mv_n) * 1e-3 if mv_n else float("nan")
+    achieved = algo_bytes / avg_s / 1e9 if mv_n else None
+    traffic = measured_traffic(D)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "traffic": traffic,
+                "kernel": "k_matvec<float> (FP32 stiffness product inside FP32-IR)",
+                "launches": mv_n, "avg_launch_us": round(avg_s * 1e6, 2) if mv_n else None,
+                "algorithmic_bytes_per_launch": algo_bytes}
+    lat_sorted = np.sort(np.array(lat))
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "corrector solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "eightfold d=2 n=4 N=32 (1,048,576 unknowns), 8 seeded random "
+                               "mode pairs around mean 3; 2 correctors + A* per step",
+                   "N": 32, "n": 4, "d": 2, "unknowns": D, "modes": int(prob.g), "tol": TOL,
+                   "precision": "fp32-ir", "parallelism": "single GPU"},
+        "astar_rel_err": err_ir,
+        "latency_ms": {"p50": round(float(np.percentile(lat_sorted, 50)), 4),
+                       "p99": round(float(np.percentile(lat_sorted, 99)), 4)},
+        "fp64": {"value": round(solves / dt64, 2), "ms_per_step": round(dt64 / args.steps * 1e3, 4),
+                 "astar_rel_err": err_64,
+                 "p99_ms": round(float(np.percentile(np.array(lat64), 99)), 4),
+                 "iters": [i.iters for i in r64.infos]},
+        "fp32ir_iters": [i.iters for i in r.infos],
+        "fp32ir_replacements": [i.outer_iters for i in r.infos],
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
