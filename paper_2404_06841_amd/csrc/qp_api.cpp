@@ -54,8 +54,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Offsets of every device buffer inside the workspace.
 struct Layout {
-    size_t F, U, r, h, q, M64, M32, x32, r32, h32, q32, chi, parts, states, small, exec, tab, wmask,
-        recs;
+    size_t F, U, r, h, q, M64, M32, x32, r32, h32, q32, chi, parts, states, small, exec, tab, recs;
     size_t total;
 };
 
@@ -86,7 +85,6 @@ Layout make_layout(int d, int n, int N, int64_t D)
     L.small = take(sizeof(double) * 128);
     L.exec = take(sizeof(int) * 2 * kExecLog);
     L.tab = take(sizeof(Table));
-    L.wmask = take(sizeof(uint64_t) * (size_t)std::max(1, n - 1) * (size_t)N);
     L.recs = take(sizeof(qp::ModeRec) * qp::kMaxG);
     L.total = o;
     return L;
@@ -136,9 +134,7 @@ struct qp_problem {
     double *small() const { return at<double>(L.small); }
     int *exec_hot() const { return at<int>(L.exec); }
     int *exec_res() const { return at<int>(L.exec) + kExecLog; }
-    const uint64_t *wmask() const { return at<uint64_t>(L.wmask); }
     const qp::ModeRec *recs() const { return at<qp::ModeRec>(L.recs); }
-    std::vector<uint64_t> wmask_host;
     std::vector<qp::ModeRec> recs_host;
 };
 
@@ -255,43 +251,46 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
         if (coef[2 * r + 1] != 0.0) T.real_coef = 0;
 
     // Tiled stiffness product: modes sorted by their last component (stable),
-    // one group per distinct value.
+    // so that consecutive gathers of a tile read neighbouring columns.
     std::vector<int> ord(g);
     for (int r = 0; r < g; ++r) ord[r] = r;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
         return modes[a * n + n - 1] < modes[b * n + n - 1];
     });
-    T.ngroups = 0;
     for (int k = 0; k < g; ++k) {
-        const int r = ord[k];
-        T.order[k] = r;
-        const int last = modes[r * n + n - 1];
-        if (k == 0 || last != T.gdelta[T.ngroups - 1]) {
-            T.gstart[T.ngroups] = k;
-            T.gdelta[T.ngroups] = last;
-            ++T.ngroups;
-        }
+        T.order[k] = ord[k];
+        if (ord[k] == T.zero_mode) T.zero_sorted = k;
     }
-    T.gstart[T.ngroups] = g;
-    {
-        long long ls = 1;
-        for (int t = n - 2; t >= 0; --t) {
-            T.lstride[t] = ls;
-            ls *= N;
-        }
-    }
-    if (n >= 2 && N <= 64) {
+    if (n >= 2 && N <= 32) {
+        // tiles of S lines of a plane
         T.lanes_p = N;
         T.tile_s = std::min(64 / N, N);
         T.tiles_per_unit = (N + T.tile_s - 1) / T.tile_s;
         T.ntiles = (int)(D / ((int64_t)N * N)) * T.tiles_per_unit;
+        const int kmin = -(N / 2), kmax = kmin + N - 1;
+        for (int tl = 0; tl < T.tiles_per_unit; ++tl) {
+            uint64_t mask = 0;
+            const int b0 = tl * T.tile_s, b1 = std::min(b0 + T.tile_s, N);
+            for (int k = 0; k < g; ++k) {
+                const int m = modes[ord[k] * n + n - 2];
+                for (int b = b0; b < b1; ++b) {
+                    const int ks = (2 * b < N) ? b : b - N;
+                    if (b - m < 0 || b - m >= N || ks - m < kmin || ks - m > kmax)
+                        mask |= (uint64_t)1 << k;
+                }
+            }
+            T.slotmask[tl] = mask;
+        }
     } else {
+        // tiles of (up to 64 positions of) one line
         T.lanes_p = std::min(N, 64);
         T.tile_s = 1;
         T.tiles_per_unit = (N + 63) / 64;
         T.ntiles = (int)(D / N) * T.tiles_per_unit;
     }
-    int nbm = std::min<int>(qp::kMaxBlocks, std::max(1, (T.ntiles + 3) / 4));
+    // work items of the stiffness product: (unit, four tiles of the unit)
+    const int64_t items = (int64_t)(T.ntiles / T.tiles_per_unit) * ((T.tiles_per_unit + 3) / 4);
+    int nbm = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, items));
     if (nbm >= 8) nbm -= nbm % 8;
     T.nb_mv = nbm;
     int nb = (int)std::min<int64_t>(qp::kMaxBlocks, (D + qp::kBlock - 1) / qp::kBlock);
@@ -317,41 +316,8 @@ void build_mode_records(const Table &T, std::vector<qp::ModeRec> &out)
         }
         R.c[0] = T.coef[r][0];
         R.c[1] = T.coef[r][1];
-        long long lro = 0;
-        for (int t = 0; t < T.n; ++t) {
-            const int m = T.modes[r][t];
-            R.mt[t] = (short)m;
-            if (t < T.n - 1) {
-                lro = lro * T.N + m;
-                if (m != 0) R.nz |= 1 << t;
-            }
-        }
-        R.lroffN = lro * T.N;
-        int grp = 0;
-        while (grp + 1 < T.ngroups && T.gstart[grp + 1] <= k) ++grp;
-        R.group = grp;
+        for (int t = 0; t < T.n; ++t) R.mt[t] = (short)T.modes[r][t];
     }
-}
-
-// For every axis t < n-1 and digit b: bit k set when sorted mode k moves a
-// neighbour across the storage range [0, N) or across K_N's faces, i.e. when
-// rep(k - m) is not k - m in that axis.
-void build_wrap_masks(const Table &T, std::vector<uint64_t> &out)
-{
-    const int N = T.N, n = T.n;
-    out.assign((size_t)std::max(1, n - 1) * N, 0);
-    const int kmin = -(N / 2), kmax = kmin + N - 1;
-    for (int t = 0; t < n - 1; ++t)
-        for (int b = 0; b < N; ++b) {
-            uint64_t mask = 0;
-            const int k = (2 * b < N) ? b : b - N;
-            for (int r = 0; r < T.g; ++r) {
-                const int m = T.modes[T.order[r]][t];
-                const int jb = b - m, jk = k - m;
-                if (jb < 0 || jb >= N || jk < kmin || jk > kmax) mask |= (uint64_t)1 << r;
-            }
-            out[(size_t)t * N + b] = mask;
-        }
 }
 
 void release(qp_problem *p)
@@ -402,7 +368,7 @@ qp_status queue_matvec(qp_problem *p, int prec, int epi, const void *x, void *y,
         exec = (resid ? p->exec_res() : p->exec_hot()) + idx;
         QP_HIP(hipEventRecord(pool[2 * idx], p->stream));
     }
-    QP_HIP(qp::launch_matvec(prec, epi, p->tab, p->host, p->recs(), p->wmask(), x, y, f, p->M32(),
+    QP_HIP(qp::launch_matvec(prec, epi, p->tab, p->host, p->recs(), x, y, f, p->M32(),
                              p->parts(), p->st(), exec, p->stream));
     if (prof) QP_HIP(hipEventRecord(pool[2 * idx + 1], p->stream));
     ++idx;
@@ -707,11 +673,6 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, cons
     p->tab = p->at<Table>(p->L.tab);
     if (hipMemcpyAsync(p->tab, &p->host, sizeof(Table), hipMemcpyHostToDevice, p->stream) != hipSuccess)
         return bail(fail(QP_EDEVICE, "table upload failed"));
-    build_wrap_masks(p->host, p->wmask_host);
-    if (hipMemcpyAsync(const_cast<uint64_t *>(p->wmask()), p->wmask_host.data(),
-                       sizeof(uint64_t) * p->wmask_host.size(), hipMemcpyHostToDevice,
-                       p->stream) != hipSuccess)
-        return bail(fail(QP_EDEVICE, "wrap mask upload failed"));
     build_mode_records(p->host, p->recs_host);
     if (hipMemcpyAsync(const_cast<qp::ModeRec *>(p->recs()), p->recs_host.data(),
                        sizeof(qp::ModeRec) * p->recs_host.size(), hipMemcpyHostToDevice,
@@ -813,7 +774,7 @@ qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy, 
     if (Astar_energy) {
         const qp::Parts parts = p->parts();
         for (int j = 0; j < d; ++j) {
-            QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(), p->wmask(), p->chi(j),
+            QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(), p->chi(j),
                                      p->q(), nullptr, nullptr, parts, p->st(), nullptr, p->stream));
             for (int i = 0; i < d; ++i)
                 QP_HIP(qp::launch_dot(p->tab, p->host, p->chi(i), p->q(), parts,
@@ -839,7 +800,7 @@ qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info
 qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
-    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(), p->wmask(), u, y, nullptr,
+    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(), u, y, nullptr,
                              nullptr, p->parts(), p->st(), nullptr, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
     return QP_OK;
@@ -848,7 +809,7 @@ qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
-    QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, p->tab, p->host, p->recs(), p->wmask(), u, y, nullptr,
+    QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, p->tab, p->host, p->recs(), u, y, nullptr,
                              nullptr, p->parts(), p->st(), nullptr, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
     return QP_OK;

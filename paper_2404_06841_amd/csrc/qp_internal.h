@@ -36,28 +36,24 @@ struct Table {
     int nidx[kMaxG];          // C(-m)
     double a0;                // Ahat_0
     // ---- tiled stiffness product (modes sorted by their last component) ----
-    int ngroups;              // distinct values of m_{n-1}
-    int gstart[kMaxG + 1];    // group g = sorted modes [gstart[g], gstart[g+1])
-    int gdelta[kMaxG];        // m_{n-1} of group g
     int order[kMaxG];         // sorted position -> mode index
+    int zero_sorted;          // sorted position of the mode m = 0
     int lanes_p;              // positions of a line per tile row (min(N, 64))
-    int tile_s;               // lines per tile
-    int tiles_per_unit;       // tiles per plane (N <= 64, n >= 2) or per line
+    int tile_s;               // lines per tile (> 1: tiles of a plane, n >= 2 and N <= 32)
+    int tiles_per_unit;       // tiles per plane (tile_s > 1) or per line
     int ntiles;
     int nb_mv;                // grid of the stiffness product (multiple of 8 when >= 8)
-    long long lstride[kMaxN]; // line-index stride of axis t < n-1: N^(n-2-t)
+    uint64_t slotmask[64];    // tile_s > 1: per tile of a plane, bit r when sorted mode
+                              // r's neighbour leaves [0, N) or K_N in axis n-2 for some line
 };
 
-// Per-mode record of the tiled stiffness product, in sorted order (one
-// aligned block, fetched with a single scalar load).
+// Per-mode record of the tiled stiffness product, in sorted order.
 struct alignas(128) ModeRec {
     double pm[kMaxD];   // P m (zero padded)
     double cpm[kMaxD];  // Re(Ahat_m) P m
     double c[2];        // Ahat_m
-    long long lroffN;   // (sum_{t<n-1} m_t N^(n-2-t)) * N: element offset of the source line
     short mt[kMaxN];    // m (all axes); |m_t| < N/2 < 2^15
-    int nz;             // bit t set when m_t != 0 for an axis t < n-1
-    int group;          // group of the sorted mode
+    int pad[8];
 };
 static_assert(sizeof(ModeRec) == 128, "mode record is one 128-byte block");
 
@@ -102,11 +98,9 @@ struct Parts {
 //              is done or paused; *exec (nullable) <- 1 when it ran
 //   EPI_RESID: FP64 only. y (float2) = (f' - Q x) * st->inv_unit and
 //              parts.b <- (sum M32 |y|^2, sum |(f' - Q x) inv_unit|^2)
-// wmask: per (dimension t < n-1, digit) bit masks (sorted mode order) of the
-// modes whose neighbour wraps in that dimension; (n-1) * N entries.
 // recs: g mode records in sorted order.
 hipError_t launch_matvec(int prec, int epi, const Table *tab, const Table &ht,
-                         const ModeRec *recs, const uint64_t *wmask, const void *x, void *y,
+                         const ModeRec *recs, const void *x, void *y,
                          const double *f, const float *M32, const Parts &parts, State *st,
                          int *exec, hipStream_t s);
 

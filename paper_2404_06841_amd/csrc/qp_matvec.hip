@@ -14,58 +14,84 @@
 // lanes differ only in their last digit and their slot digit (axis n-2);
 // every other digit is uniform over the wave.
 //
-// Modes are sorted by their last component m_{n-1} into groups.  For a group,
-// a lane's wrapped column and the correction of W for crossing the +-N/2 face
-// of the last axis depend only on the lane's position, so they are computed
-// once per workgroup and kept in LDS.  When only the last axis wraps,
-//   W = |P k|^2 - (P k).(P m) + c N (P k).p_{n-1},   c in {-1, 0, 1}.
+// With s = rep(k - m) = k - m + N c (c_t in {-1, 0, 1} per axis),
+//   W = (P k).(P s) = |P k|^2 - (P k).(P m) + N sum_t c_t (P k).p_t.
+// Lanes of a tile share every digit but the last and (for multi-line tiles)
+// the slot digit.  Per unit (the tiles sharing those uniform digits: a plane,
+// or a line when N > 64) the workgroup folds the uniform axes' wraps into one
+// record per mode: P m' = P m - N sum_{t uniform} c_t p_t and the uniform part
+// of the neighbour's address.  Per mode and lane, a table built once per
+// workgroup holds the wrapped last-axis column and its face factor.  Modes
+// whose neighbour crosses a slot-axis boundary for some lane of the tile (a
+// host-prepared mask per tile row) are corrected per lane.  Neighbour loads
+// are issued in chunks of up to Inflight<T> before the first is consumed; the
+// mode count is padded to a multiple of 4 with zero-weight copies of m = 0.
 //
-// A per-tile bit mask (OR of per-digit masks prepared on the host) marks the
-// modes whose neighbour wraps in another axis for some lane.  Unmarked modes
-// read x at a wave-uniform base plus the lane's cached column (fast path);
-// marked modes also correct the address and W for the axes they move along.
-//
-// Tile order: each XCD owns a contiguous eighth of the tiles, and its
+// Unit order: each XCD owns a contiguous eighth of the units, and its
 // workgroups sweep that range together (adjacent workgroups take adjacent
-// tiles), so the neighbours of the current front are in the XCD's L2 or in
+// units), so the neighbours of the current front are in the XCD's L2 or in
 // the shared Infinity Cache.
+#include <type_traits>
+
 #include "qp_device.h"
 
 namespace qp {
 namespace {
 
-constexpr int kGC = 8;     // groups cached in LDS
-constexpr int kChunk = 4;  // loads of a group issued before the first is consumed
+template <typename T>
+struct Inflight;
+#ifndef QP_INFLIGHT_F32
+#define QP_INFLIGHT_F32 16
+#endif
+#ifndef QP_INFLIGHT_F64
+#define QP_INFLIGHT_F64 8
+#endif
+template <>
+struct Inflight<float> {
+    static constexpr int v = QP_INFLIGHT_F32;
+};
+template <>
+struct Inflight<double> {
+    static constexpr int v = QP_INFLIGHT_F64;
+};
 
-// Mode record as staged in LDS (read back with broadcast loads).
-struct LRec {
-    double w[kMaxD];  // Re(Ahat) P m for real coefficients, P m otherwise
-    double c[2];      // Ahat_m
-    int lro;          // element offset of the source line
-    int nz;           // axes t < n-1 with m_t != 0
+// Static mode data, staged once per workgroup.
+template <typename T, int DT>
+struct SRec {
+    T pm[DT];         // P m
+    T c[2];           // Ahat_m
     short mt[kMaxN];  // m
+};
+
+// Mode data of the current unit: uniform-axis wraps folded in.
+template <typename T, int DT>
+struct alignas(16) URec {
+    T apm[DT];  // a P m'
+    T a;        // Re(Ahat_m) for real coefficients, else 1 (0 for padding)
+    T cr, ci;   // Ahat_m for complex coefficients (0 for padding)
+    int lb;     // neighbour's element offset: uniform axes, minus m_slot N
+    int mslot;  // m_{n-2} (0 when the slot digit is uniform)
 };
 
 __device__ __forceinline__ int signed_digit(int b, int N) { return (2 * b < N) ? b : b - N; }
 
-// Lane geometry for the group with last-axis offset delta at absolute
-// position pos (0 <= pos < N): wrapped column and the face factor c with
-// rep(k - m)_{n-1} = k_{n-1} - delta + c N.
-__device__ __forceinline__ void group_geom(int N, int delta, int pos, int &colw, int &c)
+// Wrapped last-axis column of the neighbour and the face factor c with
+// rep(k - m)_{n-1} = k_{n-1} - delta + c N, at absolute position pos
+// (0 <= pos < N); K_N = [lo, hi] per axis.
+__device__ __forceinline__ void last_axis(int N, int lo, int hi, int delta, int pos, int &colw,
+                                          int &c)
 {
     int col = pos - delta;
     col += (col < 0) ? N : 0;
     col -= (col >= N) ? N : 0;
     colw = col;
-    const int j = signed_digit(col, N);
-    const int k = signed_digit(pos, N);
-    c = (j - (k - delta)) / N;
+    const int kd = signed_digit(pos, N) - delta;
+    c = (kd < lo) ? 1 : ((kd > hi) ? -1 : 0);
 }
 
 template <typename T, int DT, int EPI, bool REAL>
 __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab,
                                                    const ModeRec *__restrict__ recs,
-                                                   const uint64_t *__restrict__ wm,
                                                    const cplx_t<T> *__restrict__ x,
                                                    void *__restrict__ yv,
                                                    const double2 *__restrict__ f,
@@ -76,90 +102,87 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
 {
     if (EPI == EPI_ALPHA && (st->done || st->pause)) return;
     if (EPI == EPI_RESID && st->done) return;
-    __shared__ int2 s_geo[kGC][kBlock];
-    __shared__ LRec s_rec[kMaxG];
+    constexpr int KC = Inflight<T>::v;
+    // per padded mode and lane: (wrapped column, face factor as float); gp * kWave
+    // entries of dynamic LDS when N <= kWave
+    extern __shared__ int2 s_geo[];
+    __shared__ SRec<T, DT> s_mode[kMaxG];
+    __shared__ URec<T, DT> s_unit[kMaxG];
+    __shared__ T s_p[kMaxN][DT];   // P[l][t]
+    __shared__ T s_np[kMaxN][DT];  // N P[l][t]
 
     const int N = tab->N;
     const int n = tab->n;
-    const int ng = tab->ngroups;
+    const int g = tab->g;
+    const int gp = (g + 3) & ~3;  // padded mode count
+    const int zs = tab->zero_sorted;
     const int P = tab->lanes_p;
     const int S = tab->tile_s;
+    const int tpu = tab->tiles_per_unit;
     const int lane = threadIdx.x % kWave;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int s = lane / P;
     const int p = lane - s * P;
-    const bool planes = (n >= 2) && (N <= kWave);
+    const bool slot_lanes = S > 1;  // tiles of S lines of a plane: lanes differ in axis n-2
+    const int nu = (n == 1) ? 0 : (slot_lanes ? n - 2 : n - 1);  // wave-uniform axes
     const bool cached = (N <= kWave);  // tiles then start at position 0
+    const int lo = -(N / 2), hi = N - 1 - N / 2;  // K_N = [lo, hi] per axis
+
+    for (int r = threadIdx.x; r < g; r += kBlock) {
+        const ModeRec &R = recs[r];
+        SRec<T, DT> M;
+#pragma unroll
+        for (int l = 0; l < DT; ++l) M.pm[l] = (T)R.pm[l];
+        M.c[0] = (T)R.c[0];
+        M.c[1] = (T)R.c[1];
+#pragma unroll
+        for (int t = 0; t < kMaxN; ++t) M.mt[t] = R.mt[t];
+        s_mode[r] = M;
+    }
     if (cached) {
-        for (int g = 0; g < ng && g < kGC; ++g) {
+        for (int e = threadIdx.x; e < gp * kWave; e += kBlock) {
+            const int r = e / kWave, l = e - (e / kWave) * kWave;
+            const int pl = l - (l / P) * P;  // position of lane l
             int colw, c;
-            group_geom(N, tab->gdelta[g], p, colw, c);
-            s_geo[g][threadIdx.x] = make_int2(s * N + colw, c);
+            last_axis(N, lo, hi, r < g ? recs[r].mt[n - 1] : 0, pl, colw, c);
+            s_geo[e] = make_int2(colw, __float_as_int((float)c));
         }
     }
-    for (int r = threadIdx.x; r < tab->g; r += kBlock) {
-        const ModeRec &R = recs[r];
-        LRec L;
-#pragma unroll
-        for (int l = 0; l < kMaxD; ++l) L.w[l] = REAL ? R.cpm[l] : R.pm[l];
-        L.c[0] = R.c[0];
-        L.c[1] = R.c[1];
-        L.lro = (int)R.lroffN;
-        L.nz = R.nz;
-#pragma unroll
-        for (int t = 0; t < kMaxN; ++t) L.mt[t] = R.mt[t];
-        s_rec[r] = L;
+    if (threadIdx.x < kMaxN * DT) {
+        const int t = threadIdx.x / DT, l = threadIdx.x - (threadIdx.x / DT) * DT;
+        const T v = (t < n) ? (T)tab->P[l][t] : (T)0;
+        s_p[t][l] = v;
+        s_np[t][l] = (T)N * v;
     }
     __syncthreads();
     const double inv_unit = (EPI == EPI_RESID) ? st->inv_unit : 1.0;
-    const T NT = (T)N;
 
-    // XCD-front order over the tiles
+    // Work items: (unit, group of kWaves tiles of the unit), in XCD-front order.
+    const int qpu = (tpu + kWaves - 1) / kWaves;
+    const int nitems = (tab->ntiles / tpu) * qpu;
     const int nb = gridDim.x;
     const int b = blockIdx.x;
     const bool by_xcd = (nb % 8 == 0);
     const int xcd = by_xcd ? b % 8 : 0;
     const int nloc = by_xcd ? nb / 8 : nb;
     const int loc = by_xcd ? b / 8 : b;
-    const int per = by_xcd ? (tab->ntiles + 7) / 8 : tab->ntiles;
-    const int xbeg = xcd * per;
-    const int xend = min(xbeg + per, tab->ntiles);
+    const int per = by_xcd ? (nitems + 7) / 8 : nitems;
+    const int ibeg = xcd * per;
+    const int iend = min(ibeg + per, nitems);
     double dots[2] = {0.0, 0.0};
 
-    for (int kt = 0;; ++kt) {
-        const int tile = xbeg + (kt * nloc + loc) * kWaves + wave;
-        if (tile >= xend) break;
-        // ---- tile geometry (uniform) ----
-        int L0, St, p0, slot0, plane;
-        const int tpu = tab->tiles_per_unit;
-        if (planes) {
-            plane = tile / tpu;
-            slot0 = (tile - plane * tpu) * S;
-            St = min(S, N - slot0);
-            L0 = plane * N + slot0;
-            p0 = 0;
-        } else {
-            L0 = tile / tpu;
-            p0 = (tile - L0 * tpu) * kWave;
-            St = 1;
-            plane = (n >= 2) ? div_n(tab, L0) : 0;
-            slot0 = (n >= 2) ? L0 - plane * N : 0;
-        }
-        const bool active = (s < St) && (p0 + p < N);
-
-        // ---- digits: last (per lane), slot (per lane), the rest (uniform) ----
-        const int pos = p0 + p;
-        const int kpos = signed_digit(pos, N);
-        const int ibs = (n >= 2) ? slot0 + s : 0;
-        const int ks = signed_digit(ibs, N);
-        int ibu[kMaxN], ku[kMaxN];
+    for (int item = ibeg + loc; item < iend; item += nloc) {
+        const int unit = item / qpu;
+        const int tl = (item - unit * qpu) * kWaves + wave;
+        // ---- uniform digits of the unit (axes 0 .. nu-1) ----
+        int ibu[kMaxN - 1], ku[kMaxN - 1];
         {
-            int rest = plane;
+            int rest = unit;
 #pragma unroll
-            for (int t = kMaxN - 3; t >= 0; --t) {
+            for (int t = kMaxN - 2; t >= 0; --t) {
                 ibu[t] = 0;
                 ku[t] = 0;
-                if (t <= n - 3) {
+                if (t < nu) {
                     const int qt = div_n(tab, rest);
                     ibu[t] = rest - qt * N;
                     ku[t] = signed_digit(ibu[t], N);
@@ -167,147 +190,194 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                 }
             }
         }
-        // ---- P k, |P k|^2, q_t = (P k).p_t ----
-        T pk[DT];
-        T s2 = 0;
+        // ---- unit records (thread r prepares sorted mode r) ----
+        if (threadIdx.x < gp) {
+            const int r = threadIdx.x;
+            const int rs = (r < g) ? r : zs;  // padding: the zero mode with weight 0
+            const SRec<T, DT> &M = s_mode[rs];
+            T v[DT];
+#pragma unroll
+            for (int l = 0; l < DT; ++l) v[l] = M.pm[l];
+            int lb = 0;
+#pragma unroll
+            for (int t = 0; t < kMaxN - 1; ++t) {
+                if (t < nu) {
+                    const int m = M.mt[t];
+                    int jb = ibu[t] - m;
+                    jb += (jb < 0) ? N : 0;
+                    jb -= (jb >= N) ? N : 0;
+                    lb += jb * tab->stride[t];
+                    const int kd = ku[t] - m;
+                    const T c = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
+#pragma unroll
+                    for (int l = 0; l < DT; ++l) v[l] -= c * s_np[t][l];
+                }
+            }
+            URec<T, DT> U;
+            U.mslot = slot_lanes ? (int)M.mt[n - 2] : 0;
+            U.lb = lb - U.mslot * N;
+            T a = REAL ? M.c[0] : (T)1;
+            U.cr = M.c[0];
+            U.ci = M.c[1];
+            if (r >= g) {
+                a = 0;
+                U.cr = 0;
+                U.ci = 0;
+            }
+            U.a = a;
+#pragma unroll
+            for (int l = 0; l < DT; ++l) U.apm[l] = a * v[l];
+            s_unit[r] = U;
+        }
+        T pku[DT];  // P k over the uniform axes
 #pragma unroll
         for (int l = 0; l < DT; ++l) {
-            T v = (T)tab->P[l][n - 1] * (T)kpos;
-            if (n >= 2) v += (T)tab->P[l][n - 2] * (T)ks;
-#pragma unroll
-            for (int t = 0; t < kMaxN - 2; ++t)
-                if (t <= n - 3) v += (T)tab->P[l][t] * (T)ku[t];
-            pk[l] = v;
-            s2 += v * v;
-        }
-        T q_last = 0, q_slot = 0;
-        T qu[kMaxN];
-#pragma unroll
-        for (int l = 0; l < DT; ++l) {
-            q_last += pk[l] * (T)tab->P[l][n - 1];
-            if (n >= 2) q_slot += pk[l] * (T)tab->P[l][n - 2];
-        }
-#pragma unroll
-        for (int t = 0; t < kMaxN - 2; ++t) {
             T v = 0;
-            if (t <= n - 3) {
 #pragma unroll
-                for (int l = 0; l < DT; ++l) v += pk[l] * (T)tab->P[l][t];
-            }
-            qu[t] = v;
+            for (int t = 0; t < kMaxN - 1; ++t)
+                if (t < nu) v += s_p[t][l] * (T)ku[t];
+            pku[l] = v;
         }
-        const T cq = NT * q_last;
+        __syncthreads();
 
-        // ---- modes whose neighbour wraps in an axis other than the last ----
-        uint64_t wmask = 0;
-        if (n >= 2) {
-#pragma unroll
-            for (int t = 0; t < kMaxN - 2; ++t)
-                if (t <= n - 3) wmask |= wm[t * N + ibu[t]];
-            for (int ss = 0; ss < St; ++ss) wmask |= wm[(n - 2) * N + slot0 + ss];
-        }
-
-        const int tbase = L0 * N;  // element index of the tile's first line
-        T acc_re = 0, acc_im = 0;
-        if (active) {
-            for (int g = 0; g < ng; ++g) {
-                int voff, c;
-                if (cached && g < kGC) {
-                    const int2 geo = s_geo[g][threadIdx.x];
-                    voff = geo.x;
-                    c = geo.y;
-                } else {
-                    int colw;
-                    group_geom(N, tab->gdelta[g], pos, colw, c);
-                    voff = s * N + colw;
-                }
-                const T base = s2 + (T)c * cq;
-                const int lane_idx = tbase + voff;
-                const int r1 = tab->gstart[g + 1];
-                for (int rb = tab->gstart[g]; rb < r1; rb += kChunk) {
-                    cplx_t<T> u[kChunk];
-                    T w[kChunk];
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k) {
-                        const int rr = rb + k;
-                        if (rr >= r1) break;
-                        const LRec &R = s_rec[rr];
-                        // REAL: w = Re(Ahat) W; otherwise w = W
-                        T wv = REAL ? (T)R.c[0] * base : base;
-#pragma unroll
-                        for (int l = 0; l < DT; ++l) wv -= pk[l] * (T)R.w[l];
-                        int idx = lane_idx - R.lro;
-                        if ((wmask >> rr) & 1ull) {
-                            // correct address and W for the axes this mode moves along
-                            T corr = 0;
-                            const int nz = R.nz;
-#pragma unroll
-                            for (int t = 0; t < kMaxN - 1; ++t) {
-                                if (t > n - 2 || !((nz >> t) & 1)) continue;
-                                const int m = R.mt[t];
-                                const int ib = (t < n - 2) ? ibu[t] : ibs;
-                                const int kv = (t < n - 2) ? ku[t] : ks;
-                                const T qt = (t < n - 2) ? qu[t] : q_slot;
-                                int jb = ib - m;
-                                const int step = (int)tab->lstride[t] * N * N;
-                                if (jb < 0) {
-                                    jb += N;
-                                    idx += step;
-                                } else if (jb >= N) {
-                                    jb -= N;
-                                    idx -= step;
-                                }
-                                corr += (T)(signed_digit(jb, N) - (kv - m)) * qt;
-                            }
-                            wv += REAL ? (T)R.c[0] * corr : corr;
-                        }
-                        u[k] = x[idx];
-                        w[k] = wv;
-                    }
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k) {
-                        const int rr = rb + k;
-                        if (rr >= r1) break;
-                        if (REAL) {
-                            acc_re += w[k] * u[k].x;
-                            acc_im += w[k] * u[k].y;
-                        } else {
-                            const LRec &R = s_rec[rr];
-                            const T cr = (T)R.c[0] * w[k];
-                            const T ci = (T)R.c[1] * w[k];
-                            acc_re += cr * u[k].x - ci * u[k].y;
-                            acc_im += cr * u[k].y + ci * u[k].x;
-                        }
-                    }
-                }
-            }
-        }
-        if (active) {
-            const size_t i = (size_t)(L0 + s) * N + pos;
-            if (i == 0) {
-                acc_re = 0;
-                acc_im = 0;
-            }
-            if (EPI == EPI_RESID) {
-                // replaced residual of FP32-IR: (f' - Q x) / ||F'|| as float
-                const double2 fv = f[i];
-                const double rx = (i != 0) ? (fv.x - (double)acc_re) * inv_unit : 0.0;
-                const double ry = (i != 0) ? (fv.y - (double)acc_im) * inv_unit : 0.0;
-                const float2 o = make_float2((float)rx, (float)ry);
-                static_cast<float2 *>(yv)[i] = o;
-                dots[0] += (double)M32[i] * ((double)o.x * (double)o.x + (double)o.y * (double)o.y);
-                dots[1] += rx * rx + ry * ry;
+        if (tl < tpu) {
+            // ---- tile geometry ----
+            int L0, St, p0, slot0;
+            if (slot_lanes) {
+                slot0 = tl * S;
+                St = min(S, N - slot0);
+                L0 = unit * N + slot0;
+                p0 = 0;
             } else {
-                cplx_t<T> o;
-                o.x = acc_re;
-                o.y = acc_im;
-                static_cast<cplx_t<T> *>(yv)[i] = o;
-                if (EPI == EPI_ALPHA) {
-                    const cplx_t<T> xi = x[i];
-                    dots[0] += (double)xi.x * (double)acc_re + (double)xi.y * (double)acc_im;
+                L0 = unit;
+                p0 = tl * kWave;
+                St = 1;
+                slot0 = 0;
+            }
+            // Lanes outside the tile run the same loop on clamped coordinates
+            // (their loads stay in bounds) and store nothing.
+            const bool active = (s < St) && (p0 + p < N);
+            const int se = (s < St) ? s : 0;
+            const int pos = min(p0 + p, N - 1);
+            const int ibs = slot0 + se;
+            const int lane_line = (slot_lanes ? ibs : 0) * N;
+            const int kpos = signed_digit(pos, N);
+            const int ks = signed_digit(ibs, N);
+            // ---- P k, |P k|^2, N (P k).p_t for the per-lane axes ----
+            T pk[DT];
+            T s2 = 0;
+#pragma unroll
+            for (int l = 0; l < DT; ++l) {
+                T v = pku[l] + s_p[n - 1][l] * (T)kpos;
+                if (slot_lanes) v += s_p[n - 2][l] * (T)ks;
+                pk[l] = v;
+                s2 += v * v;
+            }
+            T cq = 0, cqs = 0;
+#pragma unroll
+            for (int l = 0; l < DT; ++l) {
+                cq += pk[l] * s_np[n - 1][l];
+                if (slot_lanes) cqs += pk[l] * s_np[n - 2][l];
+            }
+            const uint64_t slow = slot_lanes ? tab->slotmask[tl] : 0ull;
+
+            // One chunk of C modes from rb: all C neighbour loads are issued
+            // before the first is consumed.
+            T acc_re = 0, acc_im = 0;
+            auto chunk = [&](auto Cc, auto Gc, int rb) {
+                constexpr int C = decltype(Cc)::value;
+                constexpr bool GEO = decltype(Gc)::value;  // lane geometry from s_geo
+                cplx_t<T> u[C];
+                T w[C];
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const int r = rb + k;
+                    const URec<T, DT> &R = s_unit[r];
+                    int colw;
+                    T c;
+                    if (GEO) {
+                        const int2 ge = s_geo[r * kWave + lane];
+                        colw = ge.x;
+                        c = (T)__int_as_float(ge.y);
+                    } else {
+                        int ci;
+                        last_axis(N, lo, hi, r < g ? (int)s_mode[r].mt[n - 1] : 0, pos, colw, ci);
+                        c = (T)ci;
+                    }
+                    // a W = a (|P k|^2 + c N q_last) - (P k).(a P m')
+                    const T a = R.a;
+                    T wv = a * (s2 + c * cq);
+#pragma unroll
+                    for (int l = 0; l < DT; ++l) wv -= pk[l] * R.apm[l];
+                    int idx = R.lb + lane_line + colw;
+                    if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
+                        const int m = R.mslot;
+                        const int jb = ibs - m;
+                        idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
+                        const int kd = ks - m;
+                        const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
+                        wv += a * cs * cqs;
+                    }
+                    u[k] = x[(unsigned)idx];
+                    w[k] = wv;
+                }
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    if (REAL) {
+                        acc_re += w[k] * u[k].x;
+                        acc_im += w[k] * u[k].y;
+                    } else {
+                        const URec<T, DT> &R = s_unit[rb + k];
+                        const T cr = R.cr * w[k];
+                        const T ci = R.ci * w[k];
+                        acc_re += cr * u[k].x - ci * u[k].y;
+                        acc_im += cr * u[k].y + ci * u[k].x;
+                    }
+                }
+            };
+            auto all_modes = [&](auto Gc) {
+                using std::integral_constant;
+                int rb = 0;
+                for (; rb + KC <= gp; rb += KC) chunk(integral_constant<int, KC>(), Gc, rb);
+                if (KC / 2 >= 4 && rb + KC / 2 <= gp) {
+                    chunk(integral_constant<int, (KC / 2 >= 4 ? KC / 2 : 4)>(), Gc, rb);
+                    rb += KC / 2;
+                }
+                for (; rb < gp; rb += 4) chunk(integral_constant<int, 4>(), Gc, rb);
+            };
+            if (cached)
+                all_modes(std::true_type());
+            else
+                all_modes(std::false_type());
+
+            if (active) {
+                const size_t i = (size_t)(L0 + s) * N + p0 + p;
+                if (i == 0) {
+                    acc_re = 0;
+                    acc_im = 0;
+                }
+                if (EPI == EPI_RESID) {
+                    // replaced residual of FP32-IR: (f' - Q x) / ||F'|| as float
+                    const double2 fv = f[i];
+                    const double rx = (i != 0) ? (fv.x - (double)acc_re) * inv_unit : 0.0;
+                    const double ry = (i != 0) ? (fv.y - (double)acc_im) * inv_unit : 0.0;
+                    const float2 o = make_float2((float)rx, (float)ry);
+                    static_cast<float2 *>(yv)[i] = o;
+                    dots[0] += (double)M32[i] * ((double)o.x * (double)o.x + (double)o.y * (double)o.y);
+                    dots[1] += rx * rx + ry * ry;
+                } else {
+                    cplx_t<T> o;
+                    o.x = acc_re;
+                    o.y = acc_im;
+                    static_cast<cplx_t<T> *>(yv)[i] = o;
+                    if (EPI == EPI_ALPHA) {
+                        const cplx_t<T> xi = x[i];
+                        dots[0] += (double)xi.x * (double)acc_re + (double)xi.y * (double)acc_im;
+                    }
                 }
             }
         }
+        __syncthreads();  // the unit records are rewritten next
     }
     if (EPI == EPI_ALPHA) {
         double v[1] = {dots[0]};
@@ -320,17 +390,18 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
 }
 
 template <typename T, int EPI, bool REAL>
-hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, const uint64_t *wm,
+hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs,
                     const void *x, void *y, const double *f, const float *M32, double *part,
                     State *st, int *exec, hipStream_t s)
 {
     const dim3 grid(ht.nb_mv), block(kBlock);
+    const size_t lds = (ht.N <= kWave) ? sizeof(int2) * kWave * (size_t)((ht.g + 3) & ~3) : 0;
     auto X = static_cast<const cplx_t<T> *>(x);
     auto Fv = reinterpret_cast<const double2 *>(f);
     switch (ht.d) {
 #define QP_CASE(DD)                                                                             \
     case DD:                                                                                     \
-        hipLaunchKernelGGL((k_matvec<T, DD, EPI, REAL>), grid, block, 0, s, tab, recs, wm, X, y, \
+        hipLaunchKernelGGL((k_matvec<T, DD, EPI, REAL>), grid, block, lds, s, tab, recs, X, y, \
                            Fv, M32, part, st, exec);                                             \
         break;
         QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
@@ -342,32 +413,32 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, cons
 }
 
 template <typename T, int EPI>
-hipError_t dispatch_coef(const Table *tab, const Table &ht, const ModeRec *recs, const uint64_t *wm,
+hipError_t dispatch_coef(const Table *tab, const Table &ht, const ModeRec *recs,
                          const void *x, void *y, const double *f, const float *M32, double *part,
                          State *st, int *exec, hipStream_t s)
 {
     if (ht.real_coef)
-        return dispatch<T, EPI, true>(tab, ht, recs, wm, x, y, f, M32, part, st, exec, s);
-    return dispatch<T, EPI, false>(tab, ht, recs, wm, x, y, f, M32, part, st, exec, s);
+        return dispatch<T, EPI, true>(tab, ht, recs, x, y, f, M32, part, st, exec, s);
+    return dispatch<T, EPI, false>(tab, ht, recs, x, y, f, M32, part, st, exec, s);
 }
 
 }  // namespace
 
 hipError_t launch_matvec(int prec, int epi, const Table *tab, const Table &ht, const ModeRec *recs,
-                         const uint64_t *wm, const void *x, void *y, const double *f,
+                         const void *x, void *y, const double *f,
                          const float *M32, const Parts &parts, State *st, int *exec, hipStream_t s)
 {
     if (prec == F64) {
         if (epi == EPI_NONE)
-            return dispatch_coef<double, EPI_NONE>(tab, ht, recs, wm, x, y, f, M32, parts.a, st, exec, s);
+            return dispatch_coef<double, EPI_NONE>(tab, ht, recs, x, y, f, M32, parts.a, st, exec, s);
         if (epi == EPI_ALPHA)
-            return dispatch_coef<double, EPI_ALPHA>(tab, ht, recs, wm, x, y, f, M32, parts.a, st, exec, s);
-        return dispatch_coef<double, EPI_RESID>(tab, ht, recs, wm, x, y, f, M32, parts.b, st, exec, s);
+            return dispatch_coef<double, EPI_ALPHA>(tab, ht, recs, x, y, f, M32, parts.a, st, exec, s);
+        return dispatch_coef<double, EPI_RESID>(tab, ht, recs, x, y, f, M32, parts.b, st, exec, s);
     }
     if (epi == EPI_NONE)
-        return dispatch_coef<float, EPI_NONE>(tab, ht, recs, wm, x, y, f, M32, parts.a, st, exec, s);
+        return dispatch_coef<float, EPI_NONE>(tab, ht, recs, x, y, f, M32, parts.a, st, exec, s);
     if (epi == EPI_ALPHA)
-        return dispatch_coef<float, EPI_ALPHA>(tab, ht, recs, wm, x, y, f, M32, parts.a, st, exec, s);
+        return dispatch_coef<float, EPI_ALPHA>(tab, ht, recs, x, y, f, M32, parts.a, st, exec, s);
     return hipErrorInvalidValue;  // the replaced residual is always computed in FP64
 }
 
