@@ -83,14 +83,19 @@ typedef struct qp_options {
                            dropped by this factor since the last replacement;
                            default 1e-4                                          */
     int poll_every;     /* iterations queued between convergence polls, and the
-                           longest FP32-IR run between replacements; 0 = 8       */
+                           longest FP32-IR run between replacements; 0 = 8,
+                           rounded up to an even count, at most 64                */
     int profile;        /* nonzero: bracket every stiffness-product launch with
-                           HIP events; totals reported in qp_solve_info           */
+                           HIP events; totals reported in qp_solve_info.  Batches
+                           are then launched directly (no graph replay)          */
     void *stream;       /* hipStream_t to run on; NULL = a stream the library
                            creates and owns                                      */
     void *workspace;    /* optional device buffer of qp_workspace_bytes() bytes;
                            NULL = the library allocates its own                  */
     size_t workspace_bytes;
+    int graphs;         /* nonzero (default): each full batch of poll_every
+                           iterations is captured once as a HIP graph and
+                           replayed; 0 = launch every kernel directly            */
 } qp_options;
 
 typedef struct qp_solve_info {

@@ -48,17 +48,32 @@ qp_status fail(qp_status s, const char *fmt, ...)
     } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kExecLog = 4096;  // profiled launches remembered per solve and kind
+constexpr int kMaxBatch = 64;                // iterations per batch (poll_every cap)
+constexpr int kExecInts = 2 * kMaxBatch + 2;  // execution log: hot A/B sets, then residual A/B
+constexpr size_t kMaxGraphs = 16;           // instantiated batch graphs kept per problem
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// The stiffness product tiles planes (S lines per wave) when n >= 2 and
+// N <= 32; its units are then the N^(n-2) planes.
+bool plane_tiles(int n, int N) { return n >= 2 && N <= 32; }
+
+int64_t plane_units(int n, int N)
+{
+    if (!plane_tiles(n, N)) return 0;
+    int64_t u = 1;
+    for (int t = 0; t < n - 2; ++t) u *= N;
+    return u;
+}
 
 // Offsets of every device buffer inside the workspace.
 struct Layout {
     size_t F, U, r, h, q, M64, M32, x32, r32, h32, q32, chi, parts, states, small, exec, tab, recs;
+    size_t urec[2], upku[2];  // unit records and unit P k, by precision (plane tiles)
     size_t total;
 };
 
-Layout make_layout(int d, int n, int N, int64_t D)
+Layout make_layout(int d, int n, int N, int64_t D, int g)
 {
     Layout L{};
     size_t o = 0;
@@ -83,9 +98,14 @@ Layout make_layout(int d, int n, int N, int64_t D)
     L.parts = take(3 * sizeof(double) * qp::kPartValues * qp::kMaxBlocks);
     L.states = take(2 * sizeof(State));
     L.small = take(sizeof(double) * 128);
-    L.exec = take(sizeof(int) * 2 * kExecLog);
+    L.exec = take(sizeof(int) * kExecInts);
     L.tab = take(sizeof(Table));
     L.recs = take(sizeof(qp::ModeRec) * qp::kMaxG);
+    const size_t urecs = (size_t)plane_units(n, N) * (size_t)((g + 3) & ~3);
+    for (int prec = 0; prec < 2; ++prec) {
+        L.urec[prec] = take(qp::kUnitRecBytes[prec] * urecs);
+        L.upku[prec] = take((prec == qp::F64 ? 8 : 4) * (size_t)qp::kMaxD * plane_units(n, N));
+    }
     L.total = o;
     return L;
 }
@@ -108,6 +128,14 @@ struct qp_problem {
     double *hsmall = nullptr;  // pinned
     int *hexec = nullptr;      // pinned copy of the execution log
     std::vector<hipEvent_t> ev_hot, ev_res;  // profiling events (begin, end pairs)
+    struct Graph {
+        bool ir;
+        int k, ab;
+        bool prof;
+        const void *u, *f;  // solution and right-hand side the graph was captured on
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
     hipEvent_t ev_poll[2] = {nullptr, nullptr};
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
 
@@ -133,8 +161,10 @@ struct qp_problem {
     State *st() const { return at<State>(L.states); }
     double *small() const { return at<double>(L.small); }
     int *exec_hot() const { return at<int>(L.exec); }
-    int *exec_res() const { return at<int>(L.exec) + kExecLog; }
+    int *exec_res() const { return at<int>(L.exec) + 2 * kMaxBatch; }
     const qp::ModeRec *recs() const { return at<qp::ModeRec>(L.recs); }
+    void *urec(int prec) const { return at<char>(L.urec[prec]); }
+    void *upku(int prec) const { return at<char>(L.upku[prec]); }
     std::vector<qp::ModeRec> recs_host;
 };
 
@@ -261,7 +291,7 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
         T.order[k] = ord[k];
         if (ord[k] == T.zero_mode) T.zero_sorted = k;
     }
-    if (n >= 2 && N <= 32) {
+    if (plane_tiles(n, N)) {
         // tiles of S lines of a plane
         T.lanes_p = N;
         T.tile_s = std::min(64 / N, N);
@@ -288,9 +318,18 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
         T.tiles_per_unit = (N + 63) / 64;
         T.ntiles = (int)(D / N) * T.tiles_per_unit;
     }
-    // work items of the stiffness product: (unit, four tiles of the unit)
-    const int64_t items = (int64_t)(T.ntiles / T.tiles_per_unit) * ((T.tiles_per_unit + 3) / 4);
-    int nbm = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, items));
+    // work items of the stiffness product: (unit, consecutive tiles of the
+    // unit), one per wave for plane tiles (as long as that leaves about four
+    // waves per SIMD), four tiles per workgroup for line tiles
+    T.item_tiles = 1;
+    if (T.tile_s > 1)
+        while (T.item_tiles < 4 && T.ntiles / (2 * T.item_tiles) >= 4096) T.item_tiles *= 2;
+    const int64_t units = T.ntiles / T.tiles_per_unit;
+    const int64_t items = T.tile_s > 1
+                              ? units * ((T.tiles_per_unit + T.item_tiles - 1) / T.item_tiles)
+                              : units * ((T.tiles_per_unit + 3) / 4);
+    const int64_t want = T.tile_s > 1 ? (items + 3) / 4 : items;
+    int nbm = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, want));
     if (nbm >= 8) nbm -= nbm % 8;
     T.nb_mv = nbm;
     int nb = (int)std::min<int64_t>(qp::kMaxBlocks, (D + qp::kBlock - 1) / qp::kBlock);
@@ -323,6 +362,7 @@ void build_mode_records(const Table &T, std::vector<qp::ModeRec> &out)
 void release(qp_problem *p)
 {
     if (!p) return;
+    for (auto &G : p->graphs) (void)hipGraphExecDestroy(G.exec);
     for (auto e : p->ev_hot) (void)hipEventDestroy(e);
     for (auto e : p->ev_res) (void)hipEventDestroy(e);
     for (auto e : p->ev_poll)
@@ -337,108 +377,201 @@ void release(qp_problem *p)
     delete p;
 }
 
-// ------------------------------------------------------------- profiling
+// ------------------------------------------------------------- batches
 
+// A solve runs in batches of `batch` PCG iterations (even, so that iteration
+// it of a batch has the parity of its absolute index: the kernels only use
+// that parity).  A full batch is captured once as a HIP graph and replayed;
+// the host polls the device state once per batch.  With profiling, every
+// stiffness product of a batch is bracketed by events of the batch's slot set
+// (A/B alternate, so one set is read while the other runs) and the batch is
+// launched directly: events recorded by graph nodes cannot be timed by this
+// runtime (hipEventElapsedTime rejects them).
 struct Profile {
-    int hot = 0, res = 0;  // launches queued (index into the event pools)
+    double hot_ms = 0.0, res_ms = 0.0;
+    int hot_n = 0, res_n = 0;
 };
 
-qp_status events_ready(std::vector<hipEvent_t> &pool, size_t pairs)
+int batch_size(const qp_options &o)
 {
-    while (pool.size() < 2 * pairs) {
-        hipEvent_t e;
-        QP_HIP(hipEventCreate(&e));
-        pool.push_back(e);
-    }
+    int b = o.poll_every > 0 ? o.poll_every : 8;
+    b = std::min(kMaxBatch, std::max(2, b));
+    return (b + 1) & ~1;
+}
+
+qp_status events_ready(qp_problem *p)
+{
+    auto fill = [](std::vector<hipEvent_t> &pool, size_t n) -> qp_status {
+        while (pool.size() < n) {
+            hipEvent_t e;
+            QP_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return QP_OK;
+    };
+    QP_TRY(fill(p->ev_hot, 2 * 2 * kMaxBatch));
+    QP_TRY(fill(p->ev_res, 2 * 2));
     return QP_OK;
 }
 
-// Queue one stiffness product; with profiling on, bracket it with events and
-// give it a slot of the execution log.
+// Queue one stiffness product.  slot >= 0: profiled, with event pair and
+// execution-log entry `slot` of its kind.
 qp_status queue_matvec(qp_problem *p, int prec, int epi, const void *x, void *y, const double *f,
-                       Profile &pf)
+                       int slot)
 {
     const bool resid = epi == qp::EPI_RESID;
-    int &idx = resid ? pf.res : pf.hot;
     std::vector<hipEvent_t> &pool = resid ? p->ev_res : p->ev_hot;
     int *exec = nullptr;
-    const bool prof = p->opt.profile && idx < kExecLog;
-    if (prof) {
-        QP_TRY(events_ready(pool, idx + 1));
-        exec = (resid ? p->exec_res() : p->exec_hot()) + idx;
-        QP_HIP(hipEventRecord(pool[2 * idx], p->stream));
+    if (slot >= 0) {
+        exec = (resid ? p->exec_res() : p->exec_hot()) + slot;
+        QP_HIP(hipEventRecord(pool[2 * slot], p->stream));
     }
-    QP_HIP(qp::launch_matvec(prec, epi, p->tab, p->host, p->recs(), x, y, f, p->M32(),
-                             p->parts(), p->st(), exec, p->stream));
-    if (prof) QP_HIP(hipEventRecord(pool[2 * idx + 1], p->stream));
-    ++idx;
+    QP_HIP(qp::launch_matvec(prec, epi, p->tab, p->host, p->recs(), p->urec(prec), p->upku(prec),
+                             x, y, f, p->M32(), p->parts(), p->st(), exec, p->stream));
+    if (slot >= 0) QP_HIP(hipEventRecord(pool[2 * slot + 1], p->stream));
     return QP_OK;
 }
 
-// Sum of the event-timed durations of the launches that ran.
-qp_status profile_totals(qp_problem *p, const Profile &pf, qp_solve_info *info, bool ir)
+// k FP64 iterations (it = 0 .. k-1) on U.
+qp_status enqueue_fp64(qp_problem *p, double *U, int k, int ab, bool prof)
 {
-    const int nh = std::min(pf.hot, kExecLog), nr = std::min(pf.res, kExecLog);
-    QP_HIP(hipMemcpyAsync(p->hexec, p->exec_hot(), sizeof(int) * 2 * kExecLog,
-                          hipMemcpyDeviceToHost, p->stream));
-    QP_HIP(hipStreamSynchronize(p->stream));
-    auto total = [&](std::vector<hipEvent_t> &pool, const int *log, int n, int &count) {
-        double ms = 0.0;
-        count = 0;
-        for (int k = 0; k < n; ++k) {
-            if (!log[k]) continue;
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
-                ms += t;
-                ++count;
-            }
+    const qp::Parts parts = p->parts();
+    for (int it = 0; it < k; ++it) {
+        QP_TRY(queue_matvec(p, qp::F64, qp::EPI_ALPHA, p->h(), p->q(), nullptr,
+                            prof ? ab * kMaxBatch + it : -1));
+        QP_HIP(qp::launch_pcg_update(qp::F64, it, p->tab, p->host, U, p->r(), p->h(), p->q(),
+                                     p->M64(), parts, p->st(), p->stream));
+        QP_HIP(qp::launch_pcg_direction(qp::F64, it, p->tab, p->host, p->r(), p->h(), p->M64(),
+                                        parts, p->st(), p->stream));
+    }
+    return QP_OK;
+}
+
+// k FP32-IR iterations on the FP64 solution X for right-hand side rhs; the
+// last one ends in a residual replacement.
+qp_status enqueue_ir(qp_problem *p, double *X, const double *rhs, int k, int ab, bool prof)
+{
+    const qp::Parts parts = p->parts();
+    for (int it = 0; it < k; ++it) {
+        QP_TRY(queue_matvec(p, qp::F32, qp::EPI_ALPHA, p->h32(), p->q32(), nullptr,
+                            prof ? ab * kMaxBatch + it : -1));
+        QP_HIP(qp::launch_pcg_update(qp::F32, it, p->tab, p->host, p->x32(), p->r32(), p->h32(),
+                                     p->q32(), p->M32(), parts, p->st(), p->stream));
+        if (it + 1 < k) {
+            QP_HIP(qp::launch_pcg_direction(qp::F32, it, p->tab, p->host, p->r32(), p->h32(),
+                                            p->M32(), parts, p->st(), p->stream));
+        } else {
+            QP_HIP(qp::launch_ir_fold(p->tab, p->host, X, p->x32(), p->st(), p->stream));
+            QP_TRY(queue_matvec(p, qp::F64, qp::EPI_RESID, X, p->r32(), rhs, prof ? ab : -1));
+            QP_HIP(qp::launch_ir_direction(it, p->tab, p->host, p->r32(), p->h32(), p->M32(),
+                                           parts, p->st(), p->stream));
         }
-        return ms;
-    };
-    int c = 0;
-    if (ir) {
-        info->matvec32_ms = total(p->ev_hot, p->hexec, nh, c);
-        info->matvec32_launches = c;
-        info->matvec_ms = total(p->ev_res, p->hexec + kExecLog, nr, c);
-        info->matvec_launches = c;
-    } else {
-        info->matvec_ms = total(p->ev_hot, p->hexec, nh, c);
-        info->matvec_launches = c;
     }
     return QP_OK;
 }
 
-qp_status clear_exec_log(qp_problem *p)
+// Queue one batch: a graph replay when it is a full batch and graphs are on,
+// else direct launches.
+qp_status queue_batch(qp_problem *p, bool ir, double *U, const double *rhs, int k, int ab,
+                      bool prof)
 {
-    if (p->opt.profile)
-        QP_HIP(hipMemsetAsync(p->exec_hot(), 0, sizeof(int) * 2 * kExecLog, p->stream));
+    const int full = batch_size(p->opt);
+    if (!p->opt.graphs || prof || k != full)
+        return ir ? enqueue_ir(p, U, rhs, k, ab, prof) : enqueue_fp64(p, U, k, ab, prof);
+    for (auto &G : p->graphs)
+        if (G.ir == ir && G.k == k && G.ab == ab && G.prof == prof && G.u == U && G.f == rhs) {
+            QP_HIP(hipGraphLaunch(G.exec, p->stream));
+            return QP_OK;
+        }
+    if (p->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        p->graphs.erase(p->graphs.begin());
+    }
+    QP_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed));
+    const qp_status qs = ir ? enqueue_ir(p, U, rhs, k, ab, prof) : enqueue_fp64(p, U, k, ab, prof);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->stream, &graph);
+    if (qs != QP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return qs;
+    }
+    if (ec != hipSuccess || !graph)
+        return fail(QP_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(QP_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    p->graphs.push_back({ir, k, ab, prof, U, rhs, exec});
+    QP_HIP(hipGraphLaunch(exec, p->stream));
     return QP_OK;
 }
 
-// ------------------------------------------------------------- solvers
-
-// Double-buffered polling: after each batch the state is copied to pinned
-// memory; the batch before the newest is inspected, so the device always has
-// queued work.  Kernels of a finished solve return at once.
+// Double-buffered polling: after each batch the state (and, when profiling,
+// the batch's execution log) is copied to pinned memory; the batch before the
+// newest is inspected, so the device always has queued work.  Kernels of a
+// finished solve return at once.
 struct Poller {
     qp_problem *p;
-    int slot = 0;
-    bool pending[2] = {false, false};
-    // Record a poll point; returns true when an older poll saw `done`.
-    qp_status push(bool &finished)
+    bool prof;
+    Profile &pf;
+    struct Rec {
+        bool pending = false;
+        int k = 0, nres = 0;
+    } rec[2];
+    int slot = 0;  // slot set of the batch being pushed
+
+    qp_status account(int s)
+    {
+        const int *hot = p->hexec + s * kMaxBatch;
+        for (int it = 0; it < rec[s].k; ++it) {
+            if (!hot[it]) continue;
+            float t = 0.f;
+            const int e = s * kMaxBatch + it;
+            QP_HIP(hipEventElapsedTime(&t, p->ev_hot[2 * e], p->ev_hot[2 * e + 1]));
+            pf.hot_ms += t;
+            ++pf.hot_n;
+        }
+        if (rec[s].nres && p->hexec[2 * kMaxBatch + s]) {
+            float t = 0.f;
+            QP_HIP(hipEventElapsedTime(&t, p->ev_res[2 * s], p->ev_res[2 * s + 1]));
+            pf.res_ms += t;
+            ++pf.res_n;
+        }
+        return QP_OK;
+    }
+    // Record the poll point of the batch just queued (k stiffness products,
+    // nres residual replacements); finished = an older poll saw `done`.
+    qp_status push(int k, int nres, bool &finished)
     {
         finished = false;
         QP_HIP(hipMemcpyAsync(&p->hstate[slot], p->st(), sizeof(State), hipMemcpyDeviceToHost,
                               p->stream));
+        if (prof) {
+            QP_HIP(hipMemcpyAsync(p->hexec + slot * kMaxBatch, p->exec_hot() + slot * kMaxBatch,
+                                  sizeof(int) * k, hipMemcpyDeviceToHost, p->stream));
+            QP_HIP(hipMemcpyAsync(p->hexec + 2 * kMaxBatch + slot, p->exec_res() + slot, sizeof(int),
+                                  hipMemcpyDeviceToHost, p->stream));
+        }
         QP_HIP(hipEventRecord(p->ev_poll[slot], p->stream));
-        pending[slot] = true;
+        rec[slot] = Rec{true, k, nres};
         const int other = slot ^ 1;
-        if (pending[other]) {
+        if (rec[other].pending) {
             QP_HIP(hipEventSynchronize(p->ev_poll[other]));
-            pending[other] = false;
+            rec[other].pending = false;
             finished = p->hstate[other].done != 0;
+            if (prof) {
+                QP_TRY(account(other));
+                // the next batch of this slot set starts from a clear log
+                QP_TRY(clear_exec(other));
+            }
         }
         slot = other;
+        return QP_OK;
+    }
+    qp_status clear_exec(int s)
+    {
+        QP_HIP(hipMemsetAsync(p->exec_hot() + s * kMaxBatch, 0, sizeof(int) * kMaxBatch, p->stream));
+        QP_HIP(hipMemsetAsync(p->exec_res() + s, 0, sizeof(int), p->stream));
         return QP_OK;
     }
     qp_status final_state(State &out)
@@ -446,6 +579,11 @@ struct Poller {
         QP_HIP(hipMemcpyAsync(&p->hstate[2], p->st(), sizeof(State), hipMemcpyDeviceToHost,
                               p->stream));
         QP_HIP(hipStreamSynchronize(p->stream));
+        for (int s = 0; s < 2; ++s)
+            if (rec[s].pending) {
+                rec[s].pending = false;
+                if (prof) QP_TRY(account(s));
+            }
         out = p->hstate[2];
         return QP_OK;
     }
@@ -455,24 +593,19 @@ qp_status solve_fp64(qp_problem *p, const double *rhs, double *U, double tol, St
                      Profile &pf)
 {
     const qp::Parts parts = p->parts();
+    const bool prof = p->opt.profile != 0;
     QP_HIP(qp::launch_state_reset(p->st(), p->stream));
     QP_HIP(qp::launch_pcg_init(qp::F64, p->tab, p->host, rhs, nullptr, U, p->r(), p->h(), p->M64(),
                                parts, p->st(), p->stream));
     QP_HIP(qp::launch_pcg_start(qp::F64, p->host, tol, 0.0, p->opt.maxit, parts, p->st(), p->stream));
-    const int batch = p->opt.poll_every > 0 ? p->opt.poll_every : 8;
-    Poller poll{p};
-    int j = 0;
-    while (j < p->opt.maxit) {
+    const int batch = batch_size(p->opt);
+    Poller poll{p, prof, pf};
+    for (int j = 0; j < p->opt.maxit;) {
         const int k = std::min(batch, p->opt.maxit - j);
-        for (int it = 0; it < k; ++it, ++j) {
-            QP_TRY(queue_matvec(p, qp::F64, qp::EPI_ALPHA, p->h(), p->q(), nullptr, pf));
-            QP_HIP(qp::launch_pcg_update(qp::F64, j, p->tab, p->host, U, p->r(), p->h(), p->q(),
-                                         p->M64(), parts, p->st(), p->stream));
-            QP_HIP(qp::launch_pcg_direction(qp::F64, j, p->tab, p->host, p->r(), p->h(), p->M64(),
-                                            parts, p->st(), p->stream));
-        }
+        QP_TRY(queue_batch(p, false, U, nullptr, k, poll.slot, prof));
+        j += k;
         bool fin = false;
-        QP_TRY(poll.push(fin));
+        QP_TRY(poll.push(k, 0, fin));
         if (fin) break;
     }
     return poll.final_state(st);
@@ -480,40 +613,25 @@ qp_status solve_fp64(qp_problem *p, const double *rhs, double *U, double tol, St
 
 // FP32-IR: float C-PCG whose residual is replaced by the FP64 residual
 // F' - Q X of the FP64 solution X whenever the float residual has dropped by
-// `inner_tol` (or reached tol), and at least every `poll_every` iterations.
+// `inner_tol` (or reached tol), and at the end of every batch.
 qp_status solve_ir(qp_problem *p, const double *rhs, double *X, double tol, State &st, Profile &pf)
 {
     const qp::Parts parts = p->parts();
+    const bool prof = p->opt.profile != 0;
     QP_HIP(qp::launch_state_reset(p->st(), p->stream));
     QP_HIP(qp::launch_ir_unit(p->tab, p->host, rhs, parts, p->st(), p->stream));
     QP_HIP(qp::launch_pcg_init(qp::F32, p->tab, p->host, rhs, X, p->x32(), p->r32(), p->h32(),
                                p->M32(), parts, p->st(), p->stream));
     QP_HIP(qp::launch_pcg_start(qp::F32, p->host, tol, p->opt.inner_tol, p->opt.maxit, parts,
                                 p->st(), p->stream));
-    const int batch = std::max(2, p->opt.poll_every > 0 ? p->opt.poll_every : 8);
-    Poller poll{p};
-    int j = 0;
-    bool fin = false;
-    auto replacement = [&](int jj) -> qp_status {
-        QP_HIP(qp::launch_ir_fold(p->tab, p->host, X, p->x32(), p->st(), p->stream));
-        QP_TRY(queue_matvec(p, qp::F64, qp::EPI_RESID, X, p->r32(), rhs, pf));
-        QP_HIP(qp::launch_ir_direction(jj, p->tab, p->host, p->r32(), p->h32(), p->M32(), parts,
-                                       p->st(), p->stream));
-        return QP_OK;
-    };
-    while (j < p->opt.maxit) {
+    const int batch = batch_size(p->opt);
+    Poller poll{p, prof, pf};
+    for (int j = 0; j < p->opt.maxit;) {
         const int k = std::min(batch, p->opt.maxit - j);
-        for (int it = 0; it < k; ++it, ++j) {
-            QP_TRY(queue_matvec(p, qp::F32, qp::EPI_ALPHA, p->h32(), p->q32(), nullptr, pf));
-            QP_HIP(qp::launch_pcg_update(qp::F32, j, p->tab, p->host, p->x32(), p->r32(), p->h32(),
-                                         p->q32(), p->M32(), parts, p->st(), p->stream));
-            if (it + 1 < k)
-                QP_HIP(qp::launch_pcg_direction(qp::F32, j, p->tab, p->host, p->r32(), p->h32(),
-                                                p->M32(), parts, p->st(), p->stream));
-            else
-                QP_TRY(replacement(j));
-        }
-        QP_TRY(poll.push(fin));
+        QP_TRY(queue_batch(p, true, X, rhs, k, poll.slot, prof));
+        j += k;
+        bool fin = false;
+        QP_TRY(poll.push(k, 1, fin));
         if (fin) break;
     }
     QP_TRY(poll.final_state(st));
@@ -536,7 +654,10 @@ qp_status solve_dispatch(qp_problem *p, const double *rhs, double *U, double tol
     const bool ir = p->opt.precision == QP_PREC_FP32_IR;
     Profile pf;
     State st{};
-    QP_TRY(clear_exec_log(p));
+    if (p->opt.profile) {
+        QP_TRY(events_ready(p));
+        QP_HIP(hipMemsetAsync(p->exec_hot(), 0, sizeof(int) * kExecInts, p->stream));
+    }
     QP_HIP(hipEventRecord(p->ev_t0, p->stream));
     QP_TRY(ir ? solve_ir(p, rhs, U, tol, st, pf) : solve_fp64(p, rhs, U, tol, st, pf));
     QP_HIP(hipEventRecord(p->ev_t1, p->stream));
@@ -548,7 +669,17 @@ qp_status solve_dispatch(qp_problem *p, const double *rhs, double *U, double tol
     info->outer_iters = ir ? st.replacements : 0;
     info->rel_resid = ir ? std::sqrt(st.rr) : (st.rr0 > 0 ? std::sqrt(st.rr / st.rr0) : 0.0);
     info->seconds = ms * 1e-3;
-    if (p->opt.profile) QP_TRY(profile_totals(p, pf, info, ir));
+    if (p->opt.profile) {
+        if (ir) {
+            info->matvec32_ms = pf.hot_ms;
+            info->matvec32_launches = pf.hot_n;
+            info->matvec_ms = pf.res_ms;
+            info->matvec_launches = pf.res_n;
+        } else {
+            info->matvec_ms = pf.hot_ms;
+            info->matvec_launches = pf.hot_n;
+        }
+    }
     const qp_status s = (qp_status)st.status;
     if (s == QP_ENOTSPD) fail(s, "PCG breakdown: (Q h, h) <= 0");
     else if (s == QP_ENOCONV) fail(s, "iteration limit reached before the tolerance");
@@ -563,7 +694,7 @@ qp_status check_options(const qp_options *o)
     if (o->precond != QP_PRECOND_PAPER && o->precond != QP_PRECOND_JACOBI)
         return fail(QP_EINVAL, "unknown preconditioner %d", o->precond);
     if (o->maxit < 1 || !(o->inner_tol > 0.0) || o->inner_tol >= 1.0 ||
-        o->poll_every < 0)
+        o->poll_every < 0 || o->poll_every > kMaxBatch)
         return fail(QP_EINVAL, "invalid iteration limits or inner tolerance");
     return QP_OK;
 }
@@ -595,18 +726,19 @@ void qp_default_options(qp_options *opt)
     opt->maxit = 10000;
     opt->inner_tol = 1e-4;
     opt->poll_every = 0;
+    opt->graphs = 1;
 }
 
 size_t qp_workspace_bytes(int d, int n, int N, int g)
 {
-    (void)g;
     if (d < 1 || n < 1 || N < 2 || n > QP_MAX_DIM_N || d > QP_MAX_DIM_D) return 0;
     int64_t D = 1;
     for (int t = 0; t < n; ++t) {
         D *= N;
         if (D >= ((int64_t)1 << 31)) return 0;
     }
-    return make_layout(d, n, N, D).total;
+    if (g < 1 || g > QP_MAX_MODES) return 0;
+    return make_layout(d, n, N, D, g).total;
 }
 
 qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, const int32_t *modes,
@@ -625,7 +757,7 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, cons
     if (!p) return fail(QP_ENOMEM, "host allocation failed");
     p->opt = o;
     build_table(p->host, d, n, P, g, modes, coef, N);
-    p->L = make_layout(d, n, N, p->host.D);
+    p->L = make_layout(d, n, N, p->host.D, g);
 
     auto bail = [&](qp_status st) {
         release(p);
@@ -663,7 +795,7 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, cons
     p->opt.workspace = nullptr;
     if (hipHostMalloc(&p->hstate, 3 * sizeof(State), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&p->hsmall, 128 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&p->hexec, 2 * kExecLog * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc(&p->hexec, kExecInts * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(QP_ENOMEM, "pinned host allocation failed"));
     for (auto &e : p->ev_poll)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
@@ -678,6 +810,10 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, cons
                        sizeof(qp::ModeRec) * p->recs_host.size(), hipMemcpyHostToDevice,
                        p->stream) != hipSuccess)
         return bail(fail(QP_EDEVICE, "mode record upload failed"));
+    for (int prec = 0; prec < 2; ++prec)
+        if (qp::launch_unit_records(prec, p->tab, p->host, p->recs(), p->urec(prec), p->upku(prec),
+                                    p->stream) != hipSuccess)
+            return bail(fail(QP_EDEVICE, "unit record set-up failed"));
     qp_status s = compute_setup(p);
     if (s != QP_OK) return bail(s);
 
@@ -774,7 +910,8 @@ qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy, 
     if (Astar_energy) {
         const qp::Parts parts = p->parts();
         for (int j = 0; j < d; ++j) {
-            QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(), p->chi(j),
+            QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(),
+                                     p->urec(qp::F64), p->upku(qp::F64), p->chi(j),
                                      p->q(), nullptr, nullptr, parts, p->st(), nullptr, p->stream));
             for (int i = 0; i < d; ++i)
                 QP_HIP(qp::launch_dot(p->tab, p->host, p->chi(i), p->q(), parts,
@@ -800,7 +937,8 @@ qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info
 qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
-    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(), u, y, nullptr,
+    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(), p->urec(qp::F64),
+                             p->upku(qp::F64), u, y, nullptr,
                              nullptr, p->parts(), p->st(), nullptr, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
     return QP_OK;
@@ -809,7 +947,8 @@ qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
-    QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, p->tab, p->host, p->recs(), u, y, nullptr,
+    QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, p->tab, p->host, p->recs(), p->urec(qp::F32),
+                             p->upku(qp::F32), u, y, nullptr,
                              nullptr, p->parts(), p->st(), nullptr, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
     return QP_OK;

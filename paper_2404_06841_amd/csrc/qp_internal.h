@@ -43,6 +43,7 @@ struct Table {
     int tiles_per_unit;       // tiles per plane (tile_s > 1) or per line
     int ntiles;
     int nb_mv;                // grid of the stiffness product (multiple of 8 when >= 8)
+    int item_tiles;           // plane tiles: consecutive tiles of a unit per wave item
     uint64_t slotmask[64];    // tile_s > 1: per tile of a plane, bit r when sorted mode
                               // r's neighbour leaves [0, N) or K_N in axis n-2 for some line
 };
@@ -56,6 +57,20 @@ struct alignas(128) ModeRec {
     int pad[8];
 };
 static_assert(sizeof(ModeRec) == 128, "mode record is one 128-byte block");
+
+// Mode record of one unit of the plane-tiled stiffness product (the tiles
+// sharing every digit but the last two), precomputed once per problem:
+// units * padded modes records per precision.
+template <typename T, int DT>
+struct alignas(16) UnitRec {
+    T apm[DT];  // a (P m - N sum_{t < n-2} c_t p_t), c_t the wrap of axis t
+    T a;        // Re(Ahat_m) for real coefficients, else 1; 0 for padding
+    T cr, ci;   // Ahat_m (complex multiply-add); 0 for padding
+    int lb;     // element offset of the neighbour's row over axes < n-2, minus m_{n-2} N
+    int mslot;  // m_{n-2}
+};
+// bytes reserved per record (at least sizeof(UnitRec<T, kMaxD>)), by Precision
+constexpr size_t kUnitRecBytes[2] = {64, 48};
 
 // Krylov state of one solve, device resident.  All scalars are FP64.
 // Fields are written by workgroup 0 of one kernel and read by later kernels
@@ -98,9 +113,11 @@ struct Parts {
 //              is done or paused; *exec (nullable) <- 1 when it ran
 //   EPI_RESID: FP64 only. y (float2) = (f' - Q x) * st->inv_unit and
 //              parts.b <- (sum M32 |y|^2, sum |(f' - Q x) inv_unit|^2)
-// recs: g mode records in sorted order.
+// recs: g mode records in sorted order; urec / upku: the unit records and
+// the units' P k over axes < n-2 of precision prec (plane tiles only).
 hipError_t launch_matvec(int prec, int epi, const Table *tab, const Table &ht,
-                         const ModeRec *recs, const void *x, void *y,
+                         const ModeRec *recs, const void *urec, const void *upku,
+                         const void *x, void *y,
                          const double *f, const float *M32, const Parts &parts, State *st,
                          int *exec, hipStream_t s);
 
@@ -136,6 +153,9 @@ hipError_t launch_ir_direction(int j, const Table *tab, const Table &ht, const f
                                hipStream_t s);
 
 // ---- setup and single-step kernels ----
+// Unit records and unit P k of precision prec (plane tiles, tile_s > 1).
+hipError_t launch_unit_records(int prec, const Table *tab, const Table &ht, const ModeRec *recs,
+                               void *urec, void *upku, hipStream_t s);
 // M (double and float copies); kind 0 paper, 1 Jacobi; out[0] = min_{k!=0} |P k|^2.
 hipError_t launch_precond(const Table *tab, const Table &ht, int kind, double *M64, float *M32,
                           const Parts &parts, double *out, hipStream_t s);

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir,
         }
     } else {
         const bool conv = rr <= st->thresh;
-        const bool limit = (j + 1) >= st->maxit;
+        const bool limit = st->iters >= st->maxit;  // iters counts this update
         if (conv || limit) {
             if (lead) {
                 st->rr = rr;

@@ -31,6 +31,7 @@
 // workgroups sweep that range together (adjacent workgroups take adjacent
 // units), so the neighbours of the current front are in the XCD's L2 or in
 // the shared Infinity Cache.
+#include <algorithm>
 #include <type_traits>
 
 #include "qp_device.h"
@@ -389,15 +390,330 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
     }
 }
 
+// ---------------------------------------------------------------- plane tiles
+//
+// n >= 2 and N <= 32: a tile is S = min(64 / N, N) lines of one plane (axes
+// n-2, n-1), so lanes differ in the slot digit (axis n-2) and the position.
+// The unit records (uniform-axis wraps folded in) are precomputed, so a wave
+// reads them with uniform scalar loads and tiles need no set-up beyond their
+// lanes' P k; waves take tiles independently.
+
+static_assert(sizeof(UnitRec<double, kMaxD>) <= kUnitRecBytes[F64], "unit record size");
+static_assert(sizeof(UnitRec<float, kMaxD>) <= kUnitRecBytes[F32], "unit record size");
+
+// One thread per (unit, padded mode): the record of sorted mode r (padding:
+// the zero mode with weight 0), computed in FP64 and rounded once.
+template <typename T, int DT, bool REAL>
+__global__ __launch_bounds__(kBlock) void k_unit_records(const Table *__restrict__ tab,
+                                                         const ModeRec *__restrict__ recs,
+                                                         UnitRec<T, DT> *__restrict__ out,
+                                                         T *__restrict__ upku)
+{
+    const int N = tab->N, n = tab->n, g = tab->g;
+    const int gp = (g + 3) & ~3;
+    const int nu = n - 2;
+    const int lo = -(N / 2), hi = N - 1 - N / 2;
+    const int units = tab->ntiles / tab->tiles_per_unit;
+    const long long total = (long long)units * gp;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total;
+         e += (long long)gridDim.x * kBlock) {
+        const int unit = (int)(e / gp);
+        const int r = (int)(e - (long long)unit * gp);
+        int ibu[kMaxN], ku[kMaxN];
+        int rest = unit;
+        for (int t = nu - 1; t >= 0; --t) {
+            const int q = rest / N;
+            ibu[t] = rest - q * N;
+            ku[t] = (2 * ibu[t] < N) ? ibu[t] : ibu[t] - N;
+            rest = q;
+        }
+        const ModeRec &M = recs[r < g ? r : tab->zero_sorted];
+        double v[DT];
+        for (int l = 0; l < DT; ++l) v[l] = M.pm[l];
+        int lb = 0;
+        for (int t = 0; t < nu; ++t) {
+            const int m = M.mt[t];
+            int jb = ibu[t] - m;
+            jb += (jb < 0) ? N : 0;
+            jb -= (jb >= N) ? N : 0;
+            lb += jb * tab->stride[t];
+            const int kd = ku[t] - m;
+            const int c = (kd < lo) ? 1 : ((kd > hi) ? -1 : 0);
+            for (int l = 0; l < DT; ++l) v[l] -= (double)c * N * tab->P[l][t];
+        }
+        UnitRec<T, DT> R;
+        const double a = (r >= g) ? 0.0 : (REAL ? M.c[0] : 1.0);
+        for (int l = 0; l < DT; ++l) R.apm[l] = (T)(a * v[l]);
+        R.a = (T)a;
+        R.cr = (r >= g) ? (T)0 : (T)M.c[0];
+        R.ci = (r >= g) ? (T)0 : (T)M.c[1];
+        R.mslot = M.mt[n - 2];
+        R.lb = lb - R.mslot * N;
+        out[e] = R;
+        if (r == 0) {
+            for (int l = 0; l < DT; ++l) {
+                double pu = 0.0;
+                for (int t = 0; t < nu; ++t) pu += tab->P[l][t] * (double)ku[t];
+                upku[(size_t)unit * DT + l] = (T)pu;
+            }
+        }
+    }
+}
+
+// Epilogue of one output entry i of the stiffness product.
+template <typename T, int EPI>
+__device__ __forceinline__ void put_output(size_t i, T acc_re, T acc_im,
+                                           const cplx_t<T> *__restrict__ x, void *__restrict__ yv,
+                                           const double2 *__restrict__ f,
+                                           const float *__restrict__ M32, double inv_unit,
+                                           double (&dots)[2])
+{
+    if (i == 0) {
+        acc_re = 0;
+        acc_im = 0;
+    }
+    if (EPI == EPI_RESID) {
+        // replaced residual of FP32-IR: (f' - Q x) / ||F'|| as float
+        const double2 fv = f[i];
+        const double rx = (i != 0) ? (fv.x - (double)acc_re) * inv_unit : 0.0;
+        const double ry = (i != 0) ? (fv.y - (double)acc_im) * inv_unit : 0.0;
+        const float2 o = make_float2((float)rx, (float)ry);
+        static_cast<float2 *>(yv)[i] = o;
+        dots[0] += (double)M32[i] * ((double)o.x * (double)o.x + (double)o.y * (double)o.y);
+        dots[1] += rx * rx + ry * ry;
+    } else {
+        cplx_t<T> o;
+        o.x = acc_re;
+        o.y = acc_im;
+        static_cast<cplx_t<T> *>(yv)[i] = o;
+        if (EPI == EPI_ALPHA) {
+            const cplx_t<T> xi = x[i];
+            dots[0] += (double)xi.x * (double)acc_re + (double)xi.y * (double)acc_im;
+        }
+    }
+}
+
+template <int EPI>
+__device__ __forceinline__ void put_partials(double (&dots)[2], double *__restrict__ part,
+                                             State *__restrict__ st, int *__restrict__ exec)
+{
+    if (EPI == EPI_ALPHA) {
+        double v[1] = {dots[0]};
+        store_partials<1>(v, part);
+        if (exec && blockIdx.x == 0 && threadIdx.x == 0) *exec = 1;
+    } else if (EPI == EPI_RESID) {
+        store_partials<2>(dots, part);
+        if (exec && blockIdx.x == 0 && threadIdx.x == 0) *exec = 1;
+    }
+}
+
+// Orders this wave's LDS accesses before and after (lanes exchange records).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Work items of the plane kernel: (unit, up to tab->item_tiles consecutive
+// tiles); a wave copies the unit's records to its LDS once per item.
+
+template <typename T, int DT, int EPI, bool REAL>
+__global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict__ tab,
+                                                         const ModeRec *__restrict__ recs,
+                                                         const UnitRec<T, DT> *__restrict__ urec,
+                                                         const T *__restrict__ upku,
+                                                         const cplx_t<T> *__restrict__ x,
+                                                         void *__restrict__ yv,
+                                                         const double2 *__restrict__ f,
+                                                         const float *__restrict__ M32,
+                                                         double *__restrict__ part,
+                                                         State *__restrict__ st,
+                                                         int *__restrict__ exec)
+{
+    if (EPI == EPI_ALPHA && (st->done || st->pause)) return;
+    if (EPI == EPI_RESID && st->done) return;
+    constexpr int KC = Inflight<T>::v;
+    using Rec = UnitRec<T, DT>;
+    // dynamic LDS: gp * kWave lane-geometry entries (column, face factor),
+    // then kWaves * gp unit records
+    extern __shared__ int2 s_geo[];
+
+    const int N = tab->N;
+    const int n = tab->n;
+    const int g = tab->g;
+    const int gp = (g + 3) & ~3;
+    const int S = tab->tile_s;
+    const int tpu = tab->tiles_per_unit;
+    const int lane = threadIdx.x % kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int s = lane / N;
+    const int p = lane - s * N;
+    const int lo = -(N / 2), hi = N - 1 - N / 2;
+    Rec *s_rec = reinterpret_cast<Rec *>(s_geo + gp * kWave) + wave * gp;
+    for (int e = threadIdx.x; e < gp * kWave; e += kBlock) {
+        const int r = e / kWave, l = e - (e / kWave) * kWave;
+        const int pl = l - (l / N) * N;  // position of lane l
+        int colw, c;
+        last_axis(N, lo, hi, r < g ? recs[r].mt[n - 1] : 0, pl, colw, c);
+        s_geo[e] = make_int2(colw, __float_as_int((float)c));
+    }
+    T pl_[DT], ps_[DT];  // p_{n-1}, p_{n-2}
+#pragma unroll
+    for (int l = 0; l < DT; ++l) {
+        pl_[l] = (T)tab->P[l][n - 1];
+        ps_[l] = (T)tab->P[l][n - 2];
+    }
+    __syncthreads();
+    const double inv_unit = (EPI == EPI_RESID) ? st->inv_unit : 1.0;
+    const T NT = (T)N;
+
+    // items in XCD-front order: each XCD owns a contiguous eighth, its waves
+    // sweep it together
+    const int it = tab->item_tiles;
+    const int ipu = (tpu + it - 1) / it;  // items per unit
+    const int nitems = (tab->ntiles / tpu) * ipu;
+    const int nw = gridDim.x * kWaves;
+    const int b = blockIdx.x;
+    const bool by_xcd = (gridDim.x % 8 == 0);
+    const int xcd = by_xcd ? b % 8 : 0;
+    const int nloc = by_xcd ? nw / 8 : nw;
+    const int loc = (by_xcd ? b / 8 : b) * kWaves + wave;
+    const int per = by_xcd ? (nitems + 7) / 8 : nitems;
+    const int ibeg = xcd * per;
+    const int iend = min(ibeg + per, nitems);
+    const int nvec = gp * (int)sizeof(Rec) / 16;  // 16-byte pieces of a unit's records
+    double dots[2] = {0.0, 0.0};
+
+    for (int item = ibeg + loc; item < iend; item += nloc) {
+        const int unit = item / ipu;
+        const int tl0 = (item - unit * ipu) * it;
+        // ---- the unit's records to this wave's LDS ----
+        {
+            const uint4 *src = reinterpret_cast<const uint4 *>(urec + (size_t)unit * gp);
+            uint4 *dst = reinterpret_cast<uint4 *>(s_rec);
+            wave_sync();  // the previous item's records have been read
+            for (int v = lane; v < nvec; v += kWave) dst[v] = src[v];
+            wave_sync();
+        }
+        T pku[DT];
+#pragma unroll
+        for (int l = 0; l < DT; ++l) pku[l] = upku[(size_t)unit * DT + l];
+
+        for (int tl = tl0; tl < min(tl0 + it, tpu); ++tl) {
+            const int slot0 = tl * S;
+            const int St = min(S, N - slot0);
+            const int L0 = unit * N + slot0;
+            // Lanes outside the tile run the same loop on clamped coordinates
+            // (their loads stay in bounds) and store nothing.
+            const bool active = s < St;
+            const int se = active ? s : 0;
+            const int ibs = slot0 + se;
+            const int lane_line = ibs * N;
+            const int kpos = signed_digit(p, N);
+            const int ks = signed_digit(ibs, N);
+            // ---- P k, |P k|^2, N (P k).p_t for the two per-lane axes ----
+            T pk[DT];
+            T s2 = 0, cq = 0, cqs = 0;
+#pragma unroll
+            for (int l = 0; l < DT; ++l) {
+                const T v = pku[l] + ps_[l] * (T)ks + pl_[l] * (T)kpos;
+                pk[l] = v;
+                s2 += v * v;
+                cq += v * pl_[l];
+                cqs += v * ps_[l];
+            }
+            cq *= NT;
+            cqs *= NT;
+            const uint64_t slow = tab->slotmask[tl];
+
+            T acc_re = 0, acc_im = 0;
+            auto chunk = [&](auto Cc, int rb) {
+                constexpr int C = decltype(Cc)::value;
+                cplx_t<T> u[C];
+                T w[C];
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const int r = rb + k;
+                    const Rec &Q = s_rec[r];  // LDS broadcast
+                    const int2 ge = s_geo[r * kWave + lane];
+                    const T c = (T)__int_as_float(ge.y);
+                    // a W = a (|P k|^2 + c N q_last) - (P k).(a P m')
+                    T wv = Q.a * (s2 + c * cq);
+#pragma unroll
+                    for (int l = 0; l < DT; ++l) wv -= pk[l] * Q.apm[l];
+                    int idx = Q.lb + lane_line + ge.x;
+                    if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
+                        const int m = Q.mslot;
+                        const int jb = ibs - m;
+                        idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
+                        const int kd = ks - m;
+                        const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
+                        wv += Q.a * cs * cqs;
+                    }
+                    u[k] = x[(unsigned)idx];
+                    w[k] = wv;
+                }
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    if (REAL) {
+                        acc_re += w[k] * u[k].x;
+                        acc_im += w[k] * u[k].y;
+                    } else {
+                        const Rec &Q = s_rec[rb + k];
+                        const T cr = Q.cr * w[k];
+                        const T ci = Q.ci * w[k];
+                        acc_re += cr * u[k].x - ci * u[k].y;
+                        acc_im += cr * u[k].y + ci * u[k].x;
+                    }
+                }
+            };
+            {
+                using std::integral_constant;
+                int rb = 0;
+                for (; rb + KC <= gp; rb += KC) chunk(integral_constant<int, KC>(), rb);
+                if (KC / 2 >= 4 && rb + KC / 2 <= gp) {
+                    chunk(integral_constant<int, (KC / 2 >= 4 ? KC / 2 : 4)>(), rb);
+                    rb += KC / 2;
+                }
+                for (; rb < gp; rb += 4) chunk(integral_constant<int, 4>(), rb);
+            }
+            if (active)
+                put_output<T, EPI>((size_t)(L0 + s) * N + p, acc_re, acc_im, x, yv, f, M32,
+                                   inv_unit, dots);
+        }
+    }
+    put_partials<EPI>(dots, part, st, exec);
+}
+
 template <typename T, int EPI, bool REAL>
-hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs,
-                    const void *x, void *y, const double *f, const float *M32, double *part,
-                    State *st, int *exec, hipStream_t s)
+hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, const void *urec,
+                    const void *upku, const void *x, void *y, const double *f, const float *M32,
+                    double *part, State *st, int *exec, hipStream_t s)
 {
     const dim3 grid(ht.nb_mv), block(kBlock);
     const size_t lds = (ht.N <= kWave) ? sizeof(int2) * kWave * (size_t)((ht.g + 3) & ~3) : 0;
     auto X = static_cast<const cplx_t<T> *>(x);
     auto Fv = reinterpret_cast<const double2 *>(f);
+    auto Pu = static_cast<const T *>(upku);
+    if (ht.tile_s > 1) {
+        if (!urec || !upku) return hipErrorInvalidValue;
+        const size_t gp = (size_t)((ht.g + 3) & ~3);
+        switch (ht.d) {
+#define QP_CASE(DD)                                                                              \
+    case DD:                                                                                      \
+        hipLaunchKernelGGL((k_matvec_plane<T, DD, EPI, REAL>), grid, block,                      \
+                           lds + kWaves * gp * sizeof(UnitRec<T, DD>), s, tab, recs,             \
+                           static_cast<const UnitRec<T, DD> *>(urec), Pu, X, y, Fv, M32, part, st, \
+                           exec);                                                                 \
+        break;
+            QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
+#undef QP_CASE
+        default:
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (ht.d) {
 #define QP_CASE(DD)                                                                             \
     case DD:                                                                                     \
@@ -413,33 +729,71 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs,
 }
 
 template <typename T, int EPI>
-hipError_t dispatch_coef(const Table *tab, const Table &ht, const ModeRec *recs,
-                         const void *x, void *y, const double *f, const float *M32, double *part,
-                         State *st, int *exec, hipStream_t s)
+hipError_t dispatch_coef(const Table *tab, const Table &ht, const ModeRec *recs, const void *urec,
+                         const void *upku, const void *x, void *y, const double *f,
+                         const float *M32, double *part, State *st, int *exec, hipStream_t s)
 {
     if (ht.real_coef)
-        return dispatch<T, EPI, true>(tab, ht, recs, x, y, f, M32, part, st, exec, s);
-    return dispatch<T, EPI, false>(tab, ht, recs, x, y, f, M32, part, st, exec, s);
+        return dispatch<T, EPI, true>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+    return dispatch<T, EPI, false>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+}
+
+template <typename T, bool REAL>
+hipError_t unit_records(const Table *tab, const Table &ht, const ModeRec *recs, void *urec,
+                        void *upku, hipStream_t s)
+{
+    const long long total = (long long)(ht.ntiles / ht.tiles_per_unit) * ((ht.g + 3) & ~3);
+    const int grid = (int)std::min<long long>(4096, (total + kBlock - 1) / kBlock);
+    auto Pu = static_cast<T *>(upku);
+    switch (ht.d) {
+#define QP_CASE(DD)                                                                           \
+    case DD:                                                                                   \
+        hipLaunchKernelGGL((k_unit_records<T, DD, REAL>), dim3(grid), dim3(kBlock), 0, s, tab, \
+                           recs, static_cast<UnitRec<T, DD> *>(urec), Pu);                     \
+        break;
+        QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
+#undef QP_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_matvec(int prec, int epi, const Table *tab, const Table &ht, const ModeRec *recs,
-                         const void *x, void *y, const double *f,
-                         const float *M32, const Parts &parts, State *st, int *exec, hipStream_t s)
+                         const void *urec, const void *upku, const void *x, void *y,
+                         const double *f, const float *M32, const Parts &parts, State *st,
+                         int *exec, hipStream_t s)
 {
     if (prec == F64) {
         if (epi == EPI_NONE)
-            return dispatch_coef<double, EPI_NONE>(tab, ht, recs, x, y, f, M32, parts.a, st, exec, s);
+            return dispatch_coef<double, EPI_NONE>(tab, ht, recs, urec, upku, x, y, f, M32, parts.a,
+                                                   st, exec, s);
         if (epi == EPI_ALPHA)
-            return dispatch_coef<double, EPI_ALPHA>(tab, ht, recs, x, y, f, M32, parts.a, st, exec, s);
-        return dispatch_coef<double, EPI_RESID>(tab, ht, recs, x, y, f, M32, parts.b, st, exec, s);
+            return dispatch_coef<double, EPI_ALPHA>(tab, ht, recs, urec, upku, x, y, f, M32,
+                                                    parts.a, st, exec, s);
+        return dispatch_coef<double, EPI_RESID>(tab, ht, recs, urec, upku, x, y, f, M32, parts.b,
+                                                st, exec, s);
     }
     if (epi == EPI_NONE)
-        return dispatch_coef<float, EPI_NONE>(tab, ht, recs, x, y, f, M32, parts.a, st, exec, s);
+        return dispatch_coef<float, EPI_NONE>(tab, ht, recs, urec, upku, x, y, f, M32, parts.a, st,
+                                              exec, s);
     if (epi == EPI_ALPHA)
-        return dispatch_coef<float, EPI_ALPHA>(tab, ht, recs, x, y, f, M32, parts.a, st, exec, s);
+        return dispatch_coef<float, EPI_ALPHA>(tab, ht, recs, urec, upku, x, y, f, M32, parts.a, st,
+                                               exec, s);
     return hipErrorInvalidValue;  // the replaced residual is always computed in FP64
+}
+
+hipError_t launch_unit_records(int prec, const Table *tab, const Table &ht, const ModeRec *recs,
+                               void *urec, void *upku, hipStream_t s)
+{
+    if (ht.tile_s <= 1) return hipSuccess;  // line tiles build their records in the kernel
+    if (prec == F64)
+        return ht.real_coef ? unit_records<double, true>(tab, ht, recs, urec, upku, s)
+                            : unit_records<double, false>(tab, ht, recs, urec, upku, s);
+    return ht.real_coef ? unit_records<float, true>(tab, ht, recs, urec, upku, s)
+                        : unit_records<float, false>(tab, ht, recs, urec, upku, s);
 }
 
 }  // namespace qp

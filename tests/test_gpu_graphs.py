@@ -1,0 +1,121 @@
+"""Batches of PCG iterations replayed as HIP graphs (through the C ABI).
+
+Graph replays must give exactly what direct launches give: the kernels, their
+arguments and the fixed-order reductions are the same, so FP64 and FP32-IR
+solves are compared bitwise.  Every cached graph is replayed several times
+with unrelated eager work and synchronisations between the replays.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_06841_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2404_06841_amd import qp  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=torch.complex128)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_graph_replays_equal_direct_launches(prec):
+    prob = W.eightfold_random(12, 2)
+    say("graphs vs direct", prec, prob.N)
+    F = dev(W.random_vector(prob.D, seed=8))
+    direct = qp.Problem(prob, precision=prec, graphs=False)
+    ref, iref = direct.solve_d(F, tol=1e-12)
+    ref = ref.clone()
+    gp = qp.Problem(prob, precision=prec)
+    out = torch.empty_like(ref)
+    for rep in range(4):
+        out.fill_(7.0)
+        u, info = gp.solve_d(F, out=out, tol=1e-12)
+        assert info.iters == iref.iters and info.outer_iters == iref.outer_iters
+        assert torch.equal(u, ref), f"replay {rep} differs"
+        # unrelated eager work and a synchronisation between replays
+        x = torch.randn(1 << 16, device="cuda")
+        assert float((x * x).sum()) > 0
+        torch.cuda.synchronize()
+    Fh = F.cpu().numpy()
+    uo, *_ = oracle.pcg(prob, Fh, tol=1e-12)
+    assert np.linalg.norm(ref.cpu().numpy() - uo) <= 1e-9 * np.linalg.norm(uo)
+    direct.close()
+    gp.close()
+
+
+def test_graph_cache_follows_the_output_buffer():
+    prob = W.eightfold(8)
+    F = dev(W.random_vector(prob.D, seed=3))
+    gp = qp.Problem(prob)
+    outs = [torch.empty(prob.D, dtype=torch.complex128, device="cuda") for _ in range(3)]
+    res = []
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+            u, _ = gp.solve_d(F, out=o, tol=1e-12)
+            res.append(u.clone())
+    for r in res[1:]:
+        assert torch.equal(r, res[0])
+    gp.close()
+
+
+def test_partial_last_batch_stops_at_the_limit():
+    prob = W.eightfold(8)
+    F = W.random_vector(prob.D, seed=1)
+    ref, st, it, rr = oracle.pcg(prob, F, tol=1e-14, maxit=11)
+    for graphs in (True, False):
+        gp = qp.Problem(prob, maxit=11, graphs=graphs)
+        u, info = gp.solve_d(dev(F), tol=1e-14, check=False)
+        assert info.status == qp.QP_ENOCONV and info.iters == 11
+        assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+        gp.close()
+
+
+def test_batch_length_does_not_change_fp64_iterates():
+    prob = W.eightfold_random(8, 1)
+    F = dev(W.random_vector(prob.D, seed=2))
+    a = qp.Problem(prob)
+    b = qp.Problem(prob, poll_every=5)  # rounded up to 6
+    ua, ia = a.solve_d(F, tol=1e-12)
+    ub, ib = b.solve_d(F, tol=1e-12)
+    assert ia.iters == ib.iters and torch.equal(ua, ub)
+    a.close()
+    b.close()
+
+
+def test_profiled_solves_time_every_product():
+    # profiling launches batches directly whatever `graphs` says, so both
+    # settings must time the same launches
+    prob = W.eightfold_random(16, 4)
+    counts = {}
+    for graphs in (True, False):
+        gp = qp.Problem(prob, precision="fp32ir", profile=True, graphs=graphs)
+        r = gp.homogenized(tol=1e-12)
+        n32 = sum(i.matvec32_launches for i in r.infos)
+        n64 = sum(i.matvec_launches for i in r.infos)
+        ms = sum(i.matvec32_ms for i in r.infos)
+        iters = sum(i.iters for i in r.infos)
+        say("profiled", graphs, n32, n64, ms, iters)
+        assert n32 == iters
+        for i in r.infos:  # one residual product per replacement, plus the final one
+            assert i.matvec_launches in (i.outer_iters, i.outer_iters + 1)
+        assert ms > 0
+        counts[graphs] = (n32, n64)
+        gp.close()
+    assert counts[True] == counts[False]
