@@ -42,16 +42,20 @@ def parse_args():
 
 
 def copy_probe():
-    """A plain 512 MiB device-to-device copy, five times: the reference that
-    scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    """Plain copies of known size, five times each, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters to bytes: the runtime's device-to-device copy and an
+    elementwise torch kernel (y = x * 1) over 512 MiB."""
     import torch
     n = 512 * 1024 * 1024 // 4
     x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for _ in range(5):
         y.copy_(x)
+    for _ in range(5):
+        torch.mul(x, 1.0, out=y)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_per_copy": 4 * n, "copies": 5}), flush=True)
+    print(json.dumps({"copy_probe_bytes_per_copy": 4 * n, "copies": 5,
+                      "kernels": ["runtime copy", "elementwise mul"]}), flush=True)
 
 
 def kernel_hash() -> str:

@@ -321,9 +321,17 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
     // work items of the stiffness product: (unit, consecutive tiles of the
     // unit), one per wave for plane tiles (as long as that leaves about four
     // waves per SIMD), four tiles per workgroup for line tiles
+#ifndef QP_ITEM_TARGET
+#define QP_ITEM_TARGET 4096
+#endif
+#ifndef QP_XCD_FRONT
+#define QP_XCD_FRONT 1
+#endif
     T.item_tiles = 1;
     if (T.tile_s > 1)
-        while (T.item_tiles < 4 && T.ntiles / (2 * T.item_tiles) >= 4096) T.item_tiles *= 2;
+        while (T.item_tiles < 4 && T.ntiles / (2 * T.item_tiles) >= QP_ITEM_TARGET)
+            T.item_tiles *= 2;
+    T.xcd_front = QP_XCD_FRONT;
     const int64_t units = T.ntiles / T.tiles_per_unit;
     const int64_t items = T.tile_s > 1
                               ? units * ((T.tiles_per_unit + T.item_tiles - 1) / T.item_tiles)
@@ -332,7 +340,7 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
     int nbm = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, want));
     if (nbm >= 8) nbm -= nbm % 8;
     T.nb_mv = nbm;
-    int nb = (int)std::min<int64_t>(qp::kMaxBlocks, (D + qp::kBlock - 1) / qp::kBlock);
+    int nb = (int)std::min<int64_t>(qp::kStreamBlocks, (D + qp::kBlock - 1) / qp::kBlock);
     if (nb >= 64) nb -= nb % 8;
     int64_t chunk = (D + nb - 1) / nb;
     chunk = (chunk + qp::kBlock - 1) / qp::kBlock * qp::kBlock;
@@ -540,10 +548,12 @@ struct Poller {
         return QP_OK;
     }
     // Record the poll point of the batch just queued (k stiffness products,
-    // nres residual replacements); finished = an older poll saw `done`.
-    qp_status push(int k, int nres, bool &finished)
+    // nres residual replacements); finished = an older poll saw `done`;
+    // seen = the state that poll saw (null when there was none yet).
+    qp_status push(int k, int nres, bool &finished, const State **seen)
     {
         finished = false;
+        *seen = nullptr;
         QP_HIP(hipMemcpyAsync(&p->hstate[slot], p->st(), sizeof(State), hipMemcpyDeviceToHost,
                               p->stream));
         if (prof) {
@@ -559,6 +569,7 @@ struct Poller {
             QP_HIP(hipEventSynchronize(p->ev_poll[other]));
             rec[other].pending = false;
             finished = p->hstate[other].done != 0;
+            *seen = &p->hstate[other];
             if (prof) {
                 QP_TRY(account(other));
                 // the next batch of this slot set starts from a clear log
@@ -589,6 +600,40 @@ struct Poller {
     }
 };
 
+// Residual trend between polls: log-decay per iteration of the squared
+// residual estimate the device reports.
+struct Trend {
+    int it = -1;
+    double rr = 0.0;
+    double rate = 0.0;  // < 0 once known
+    void observe(int iters, double rr_now)
+    {
+        if (it >= 0 && iters > it && rr > 0.0 && rr_now > 0.0 && rr_now < rr)
+            rate = std::log(rr_now / rr) / (iters - it);
+        it = iters;
+        rr = rr_now;
+    }
+    // iterations from the last observation until the estimate reaches target
+    double iters_to(double target) const
+    {
+        if (!(rate < 0.0) || !(rr > 0.0)) return -1.0;
+        if (rr <= target) return 0.0;
+        return std::log(target / rr) / rate;
+    }
+};
+
+// Length of the next batch when `need` more iterations are expected after
+// the last observation and `queued` of them are already queued: just past the
+// expected event (plus one), even, between 2 and the full batch.
+int next_batch(double need, int queued, int full)
+{
+    if (need < 0.0) return full;
+    const double rem = need - queued;
+    int L = (int)std::ceil(std::max(rem, 0.0)) + 1;
+    L = std::min(full, std::max(2, L));
+    return (L + 1) & ~1;
+}
+
 qp_status solve_fp64(qp_problem *p, const double *rhs, double *U, double tol, State &st,
                      Profile &pf)
 {
@@ -600,20 +645,32 @@ qp_status solve_fp64(qp_problem *p, const double *rhs, double *U, double tol, St
     QP_HIP(qp::launch_pcg_start(qp::F64, p->host, tol, 0.0, p->opt.maxit, parts, p->st(), p->stream));
     const int batch = batch_size(p->opt);
     Poller poll{p, prof, pf};
+    Trend trend;
+    int k = batch;
     for (int j = 0; j < p->opt.maxit;) {
-        const int k = std::min(batch, p->opt.maxit - j);
+        k = std::min(k, p->opt.maxit - j);
         QP_TRY(queue_batch(p, false, U, nullptr, k, poll.slot, prof));
         j += k;
         bool fin = false;
-        QP_TRY(poll.push(k, 0, fin));
+        const State *seen = nullptr;
+        QP_TRY(poll.push(k, 0, fin, &seen));
         if (fin) break;
+        // Convergence expected within the queued batch: queue a short one.
+        int next = batch;
+        if (seen) {
+            if (trend.it < 0) trend.observe(0, seen->rr0);
+            trend.observe(seen->iters, seen->rr);
+            next = next_batch(trend.iters_to(seen->thresh), j - seen->iters, batch);
+        }
+        k = next;
     }
     return poll.final_state(st);
 }
 
 // FP32-IR: float C-PCG whose residual is replaced by the FP64 residual
 // F' - Q X of the FP64 solution X whenever the float residual has dropped by
-// `inner_tol` (or reached tol), and at the end of every batch.
+// `inner_tol` (or reached tol), and at the end of every batch.  Batches are
+// sized to end just after the expected replacement point.
 qp_status solve_ir(qp_problem *p, const double *rhs, double *X, double tol, State &st, Profile &pf)
 {
     const qp::Parts parts = p->parts();
@@ -626,13 +683,38 @@ qp_status solve_ir(qp_problem *p, const double *rhs, double *X, double tol, Stat
                                 p->st(), p->stream));
     const int batch = batch_size(p->opt);
     Poller poll{p, prof, pf};
+    Trend trend;
+    int k = batch;
     for (int j = 0; j < p->opt.maxit;) {
-        const int k = std::min(batch, p->opt.maxit - j);
+        k = std::min(k, p->opt.maxit - j);
         QP_TRY(queue_batch(p, true, X, rhs, k, poll.slot, prof));
         j += k;
         bool fin = false;
-        QP_TRY(poll.push(k, 1, fin));
+        const State *seen = nullptr;
+        QP_TRY(poll.push(k, 1, fin, &seen));
         if (fin) break;
+        int next = batch;
+        if (seen) {
+            // seen: after a replacement (scaled true residual rr = rr_last)
+            if (trend.it < 0) trend.observe(0, 1.0);
+            trend.observe(seen->iters, seen->rr);
+            const double target = std::max(seen->thresh, seen->delta2 * seen->rr_last);
+            const double need = trend.iters_to(target);
+            const int ahead = k;  // float iterations queued after the batch `seen` ended
+            if (need >= 0.0 && need <= ahead) {
+                // the queued batch reaches the next replacement point
+                if (target <= seen->thresh) {
+                    next = 2;  // and that one should converge
+                } else {
+                    const double t2 = std::max(seen->thresh, seen->delta2 * target);
+                    const double need2 = std::log(t2 / target) / trend.rate;
+                    next = next_batch(need2, 0, batch);
+                }
+            } else {
+                next = next_batch(need, ahead, batch);
+            }
+        }
+        k = next;
     }
     QP_TRY(poll.final_state(st));
     if (!st.done) {

@@ -13,7 +13,11 @@ constexpr int kMaxN = QP_MAX_DIM_N;
 constexpr int kMaxD = QP_MAX_DIM_D;
 constexpr int kMaxG = QP_MAX_MODES;
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
-constexpr int kMaxBlocks = 1024;  // grid cap of the streaming kernels: 4 per CU
+#ifndef QP_MAX_BLOCKS
+#define QP_MAX_BLOCKS 1024
+#endif
+constexpr int kMaxBlocks = QP_MAX_BLOCKS;  // grid cap (partial sums per reduction)
+constexpr int kStreamBlocks = 1024;        // grid cap of the streaming kernels: 4 per CU
 
 // Problem constants, resident in device memory and read with uniform
 // (scalar) loads by every kernel.
@@ -44,6 +48,7 @@ struct Table {
     int ntiles;
     int nb_mv;                // grid of the stiffness product (multiple of 8 when >= 8)
     int item_tiles;           // plane tiles: consecutive tiles of a unit per wave item
+    int xcd_front;            // plane tiles: each XCD sweeps its own contiguous eighth
     uint64_t slotmask[64];    // tile_s > 1: per tile of a plane, bit r when sorted mode
                               // r's neighbour leaves [0, N) or K_N in axis n-2 for some line
 };

@@ -575,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
     const int nitems = (tab->ntiles / tpu) * ipu;
     const int nw = gridDim.x * kWaves;
     const int b = blockIdx.x;
-    const bool by_xcd = (gridDim.x % 8 == 0);
+    const bool by_xcd = tab->xcd_front && (gridDim.x % 8 == 0);
     const int xcd = by_xcd ? b % 8 : 0;
     const int nloc = by_xcd ? nw / 8 : nw;
     const int loc = (by_xcd ? b / 8 : b) * kWaves + wave;
