@@ -110,6 +110,9 @@ typedef struct qp_solve_info {
     double matvec_ms;     /*   and their summed event-timed duration             */
     int matvec32_launches;/* profile only: float stiffness products that ran     */
     double matvec32_ms;
+    int matvec_rhs;       /* profile only: right-hand sides those FP64 launches
+                             served (a launch serves every unfinished one)       */
+    int matvec32_rhs;     /* the same for the float launches                     */
 } qp_solve_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -165,6 +168,18 @@ qp_status qp_solve_d(qp_problem *p, const double *rhs, double *u, double tol,
                      qp_solve_info *info);
 
 /*
+ * K independent solves with the same operator (1 <= K <= d), run together:
+ * one stiffness-product launch serves every right-hand side that has not
+ * converged, so each (entry, mode) weight is computed once for all of them.
+ * rhs, u: device, K consecutive vectors of D complex (vector r at element
+ * r * D); they must not overlap.  infos: host array of K entries, or NULL.
+ * Each right-hand side stops at its own tolerance; the iterates are the same
+ * as those of K separate qp_solve_d calls.  Returns the first non-QP_OK status.
+ */
+qp_status qp_solve_multi_d(qp_problem *p, int K, const double *rhs, double *u, double tol,
+                           qp_solve_info *infos);
+
+/*
  * Corrector chi_j, 0 <= j < d, of the corrector equation
  * -div(a(e_j + grad chi_j)) = 0 (Sec. 5.2, eq. corrector), i.e. the solve
  * with F_k = i (P k)_j Ahat_k (the coefficients of d a / d x_j, App. D).
@@ -183,7 +198,8 @@ qp_status qp_corrector_d(qp_problem *p, int j, double *chi, double tol,
  * collocation grid this is Ahat_0 delta_ij + sum_m Ahat_m i(P(-m))_i chi_j[-m].
  * Astar: host d*d row-major (flux form above).  Astar_energy (host d*d, may be
  * NULL): the symmetric energy form Ahat_0 delta_ij - chi_i^H Q chi_j.
- * info: host array of d entries (one per corrector), may be NULL.
+ * info: host array of d entries (one per corrector), may be NULL.  The d
+ * correctors are solved together (as by qp_solve_multi_d).
  */
 qp_status qp_homogenized(qp_problem *p, double *Astar, double tol,
                          qp_solve_info *info);

@@ -83,20 +83,21 @@ Layout make_layout(int d, int n, int N, int64_t D, int g)
         return at;
     };
     const size_t c64 = 16 * (size_t)D, c32 = 8 * (size_t)D;
-    L.F = take(c64);
-    L.U = take(c64);
-    L.r = take(c64);
-    L.h = take(c64);
-    L.q = take(c64);
+    const size_t K = (size_t)d;  // right-hand sides solved together (the d correctors)
+    L.F = take(c64 * K);
+    L.U = take(c64 * K);
+    L.r = take(c64 * K);
+    L.h = take(c64 * K);
+    L.q = take(c64 * K);
     L.M64 = take(8 * (size_t)D);
     L.M32 = take(4 * (size_t)D);
-    L.x32 = take(c32);
-    L.r32 = take(c32);
-    L.h32 = take(c32);
-    L.q32 = take(c32);
+    L.x32 = take(c32 * K);
+    L.r32 = take(c32 * K);
+    L.h32 = take(c32 * K);
+    L.q32 = take(c32 * K);
     L.chi = take(c64 * (size_t)d);
-    L.parts = take(3 * sizeof(double) * qp::kPartValues * qp::kMaxBlocks);
-    L.states = take(2 * sizeof(State));
+    L.parts = take(3 * sizeof(double) * qp::kMaxRhs * qp::kPartStride);
+    L.states = take(qp::kMaxRhs * sizeof(State));
     L.small = take(sizeof(double) * 128);
     L.exec = take(sizeof(int) * kExecInts);
     L.tab = take(sizeof(Table));
@@ -124,13 +125,13 @@ struct qp_problem {
     qp_options opt{};
     double amin = 0, amax = 0, pkmin = 0;
     int flags = 0;
-    State *hstate = nullptr;   // pinned: two polling slots + final
+    State *hstate = nullptr;   // pinned: two polling slots + final, kMaxRhs states each
     double *hsmall = nullptr;  // pinned
     int *hexec = nullptr;      // pinned copy of the execution log
     std::vector<hipEvent_t> ev_hot, ev_res;  // profiling events (begin, end pairs)
     struct Graph {
         bool ir;
-        int k, ab;
+        int K, k, ab;
         bool prof;
         const void *u, *f;  // solution and right-hand side the graph was captured on
         hipGraphExec_t exec;
@@ -155,7 +156,7 @@ struct qp_problem {
     qp::Parts parts() const
     {
         double *p = at<double>(L.parts);
-        const size_t stride = (size_t)qp::kPartValues * qp::kMaxBlocks;
+        const size_t stride = qp::kMaxRhs * qp::kPartStride;
         return qp::Parts{p, p + stride, p + 2 * stride};
     }
     State *st() const { return at<State>(L.states); }
@@ -397,7 +398,8 @@ void release(qp_problem *p)
 // runtime (hipEventElapsedTime rejects them).
 struct Profile {
     double hot_ms = 0.0, res_ms = 0.0;
-    int hot_n = 0, res_n = 0;
+    int hot_n = 0, res_n = 0;      // launches that did work
+    int hot_rhs = 0, res_rhs = 0;  // right-hand sides they served
 };
 
 int batch_size(const qp_options &o)
@@ -424,8 +426,8 @@ qp_status events_ready(qp_problem *p)
 
 // Queue one stiffness product.  slot >= 0: profiled, with event pair and
 // execution-log entry `slot` of its kind.
-qp_status queue_matvec(qp_problem *p, int prec, int epi, const void *x, void *y, const double *f,
-                       int slot)
+qp_status queue_matvec(qp_problem *p, int prec, int epi, int K, const void *x, void *y,
+                       const double *f, int slot)
 {
     const bool resid = epi == qp::EPI_RESID;
     std::vector<hipEvent_t> &pool = resid ? p->ev_res : p->ev_hot;
@@ -434,60 +436,69 @@ qp_status queue_matvec(qp_problem *p, int prec, int epi, const void *x, void *y,
         exec = (resid ? p->exec_res() : p->exec_hot()) + slot;
         QP_HIP(hipEventRecord(pool[2 * slot], p->stream));
     }
-    QP_HIP(qp::launch_matvec(prec, epi, p->tab, p->host, p->recs(), p->urec(prec), p->upku(prec),
-                             x, y, f, p->M32(), p->parts(), p->st(), exec, p->stream));
+    QP_HIP(qp::launch_matvec(prec, epi, K, p->tab, p->host, p->recs(), p->urec(prec),
+                             p->upku(prec), x, y, f, p->M32(), p->parts(), p->st(), exec,
+                             p->stream));
     if (slot >= 0) QP_HIP(hipEventRecord(pool[2 * slot + 1], p->stream));
     return QP_OK;
 }
 
-// k FP64 iterations (it = 0 .. k-1) on U.
-qp_status enqueue_fp64(qp_problem *p, double *U, int k, int ab, bool prof)
+// k FP64 iterations (it = 0 .. k-1) of K right-hand sides on U.
+qp_status enqueue_fp64(qp_problem *p, int K, double *U, int k, int ab, bool prof)
 {
     const qp::Parts parts = p->parts();
     for (int it = 0; it < k; ++it) {
-        QP_TRY(queue_matvec(p, qp::F64, qp::EPI_ALPHA, p->h(), p->q(), nullptr,
+        QP_TRY(queue_matvec(p, qp::F64, qp::EPI_ALPHA, K, p->h(), p->q(), nullptr,
                             prof ? ab * kMaxBatch + it : -1));
-        QP_HIP(qp::launch_pcg_update(qp::F64, it, p->tab, p->host, U, p->r(), p->h(), p->q(),
+        QP_HIP(qp::launch_pcg_update(qp::F64, it, K, p->tab, p->host, U, p->r(), p->h(), p->q(),
                                      p->M64(), parts, p->st(), p->stream));
-        QP_HIP(qp::launch_pcg_direction(qp::F64, it, p->tab, p->host, p->r(), p->h(), p->M64(),
+        QP_HIP(qp::launch_pcg_direction(qp::F64, it, K, p->tab, p->host, p->r(), p->h(), p->M64(),
                                         parts, p->st(), p->stream));
     }
     return QP_OK;
 }
 
-// k FP32-IR iterations on the FP64 solution X for right-hand side rhs; the
-// last one ends in a residual replacement.
-qp_status enqueue_ir(qp_problem *p, double *X, const double *rhs, int k, int ab, bool prof)
+// FP32-IR residual replacement for the paused right-hand sides, after float
+// iteration it: fold, FP64 residual, convergence test and direction.
+qp_status enqueue_replacement(qp_problem *p, int K, double *X, const double *rhs, int it, int ab,
+                              bool prof)
+{
+    const qp::Parts parts = p->parts();
+    QP_HIP(qp::launch_ir_fold(K, p->tab, p->host, X, p->x32(), p->st(), p->stream));
+    QP_TRY(queue_matvec(p, qp::F64, qp::EPI_RESID, K, X, p->r32(), rhs, prof ? ab : -1));
+    QP_HIP(qp::launch_ir_direction(it, K, p->tab, p->host, p->r32(), p->h32(), p->M32(), parts,
+                                   p->st(), p->stream));
+    return QP_OK;
+}
+
+// k FP32-IR iterations of K right-hand sides on the FP64 solutions X for the
+// right-hand sides rhs; the batch ends with the replacement of the paused ones.
+qp_status enqueue_ir(qp_problem *p, int K, double *X, const double *rhs, int k, int ab, bool prof)
 {
     const qp::Parts parts = p->parts();
     for (int it = 0; it < k; ++it) {
-        QP_TRY(queue_matvec(p, qp::F32, qp::EPI_ALPHA, p->h32(), p->q32(), nullptr,
+        QP_TRY(queue_matvec(p, qp::F32, qp::EPI_ALPHA, K, p->h32(), p->q32(), nullptr,
                             prof ? ab * kMaxBatch + it : -1));
-        QP_HIP(qp::launch_pcg_update(qp::F32, it, p->tab, p->host, p->x32(), p->r32(), p->h32(),
+        QP_HIP(qp::launch_pcg_update(qp::F32, it, K, p->tab, p->host, p->x32(), p->r32(), p->h32(),
                                      p->q32(), p->M32(), parts, p->st(), p->stream));
-        if (it + 1 < k) {
-            QP_HIP(qp::launch_pcg_direction(qp::F32, it, p->tab, p->host, p->r32(), p->h32(),
-                                            p->M32(), parts, p->st(), p->stream));
-        } else {
-            QP_HIP(qp::launch_ir_fold(p->tab, p->host, X, p->x32(), p->st(), p->stream));
-            QP_TRY(queue_matvec(p, qp::F64, qp::EPI_RESID, X, p->r32(), rhs, prof ? ab : -1));
-            QP_HIP(qp::launch_ir_direction(it, p->tab, p->host, p->r32(), p->h32(), p->M32(),
-                                           parts, p->st(), p->stream));
-        }
+        QP_HIP(qp::launch_pcg_direction(qp::F32, it, K, p->tab, p->host, p->r32(), p->h32(),
+                                        p->M32(), parts, p->st(), p->stream));
+        if (it + 1 == k) QP_TRY(enqueue_replacement(p, K, X, rhs, it, ab, prof));
     }
     return QP_OK;
 }
 
 // Queue one batch: a graph replay when it is a full batch and graphs are on,
 // else direct launches.
-qp_status queue_batch(qp_problem *p, bool ir, double *U, const double *rhs, int k, int ab,
+qp_status queue_batch(qp_problem *p, bool ir, int K, double *U, const double *rhs, int k, int ab,
                       bool prof)
 {
     const int full = batch_size(p->opt);
     if (!p->opt.graphs || prof || k != full)
-        return ir ? enqueue_ir(p, U, rhs, k, ab, prof) : enqueue_fp64(p, U, k, ab, prof);
+        return ir ? enqueue_ir(p, K, U, rhs, k, ab, prof) : enqueue_fp64(p, K, U, k, ab, prof);
     for (auto &G : p->graphs)
-        if (G.ir == ir && G.k == k && G.ab == ab && G.prof == prof && G.u == U && G.f == rhs) {
+        if (G.ir == ir && G.K == K && G.k == k && G.ab == ab && G.prof == prof && G.u == U &&
+            G.f == rhs) {
             QP_HIP(hipGraphLaunch(G.exec, p->stream));
             return QP_OK;
         }
@@ -496,7 +507,8 @@ qp_status queue_batch(qp_problem *p, bool ir, double *U, const double *rhs, int 
         p->graphs.erase(p->graphs.begin());
     }
     QP_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed));
-    const qp_status qs = ir ? enqueue_ir(p, U, rhs, k, ab, prof) : enqueue_fp64(p, U, k, ab, prof);
+    const qp_status qs =
+        ir ? enqueue_ir(p, K, U, rhs, k, ab, prof) : enqueue_fp64(p, K, U, k, ab, prof);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(p->stream, &graph);
     if (qs != QP_OK) {
@@ -509,17 +521,18 @@ qp_status queue_batch(qp_problem *p, bool ir, double *U, const double *rhs, int 
     const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return fail(QP_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
-    p->graphs.push_back({ir, k, ab, prof, U, rhs, exec});
+    p->graphs.push_back({ir, K, k, ab, prof, U, rhs, exec});
     QP_HIP(hipGraphLaunch(exec, p->stream));
     return QP_OK;
 }
 
-// Double-buffered polling: after each batch the state (and, when profiling,
-// the batch's execution log) is copied to pinned memory; the batch before the
-// newest is inspected, so the device always has queued work.  Kernels of a
-// finished solve return at once.
+// Double-buffered polling: after each batch the K states (and, when
+// profiling, the batch's execution log) are copied to pinned memory; the
+// batch before the newest is inspected, so the device always has queued work.
+// Kernels of a finished right-hand side skip it.
 struct Poller {
     qp_problem *p;
+    int K;
     bool prof;
     Profile &pf;
     struct Rec {
@@ -527,6 +540,8 @@ struct Poller {
         int k = 0, nres = 0;
     } rec[2];
     int slot = 0;  // slot set of the batch being pushed
+
+    State *host_states(int s) const { return p->hstate + s * qp::kMaxRhs; }
 
     qp_status account(int s)
     {
@@ -538,23 +553,26 @@ struct Poller {
             QP_HIP(hipEventElapsedTime(&t, p->ev_hot[2 * e], p->ev_hot[2 * e + 1]));
             pf.hot_ms += t;
             ++pf.hot_n;
+            pf.hot_rhs += hot[it];
         }
-        if (rec[s].nres && p->hexec[2 * kMaxBatch + s]) {
+        const int res = p->hexec[2 * kMaxBatch + s];
+        if (rec[s].nres && res) {
             float t = 0.f;
             QP_HIP(hipEventElapsedTime(&t, p->ev_res[2 * s], p->ev_res[2 * s + 1]));
             pf.res_ms += t;
             ++pf.res_n;
+            pf.res_rhs += res;
         }
         return QP_OK;
     }
     // Record the poll point of the batch just queued (k stiffness products,
-    // nres residual replacements); finished = an older poll saw `done`;
-    // seen = the state that poll saw (null when there was none yet).
+    // nres residual replacements); finished = an older poll saw every state
+    // done; seen = the states that poll saw (null when there was none yet).
     qp_status push(int k, int nres, bool &finished, const State **seen)
     {
         finished = false;
         *seen = nullptr;
-        QP_HIP(hipMemcpyAsync(&p->hstate[slot], p->st(), sizeof(State), hipMemcpyDeviceToHost,
+        QP_HIP(hipMemcpyAsync(host_states(slot), p->st(), sizeof(State) * K, hipMemcpyDeviceToHost,
                               p->stream));
         if (prof) {
             QP_HIP(hipMemcpyAsync(p->hexec + slot * kMaxBatch, p->exec_hot() + slot * kMaxBatch,
@@ -568,8 +586,10 @@ struct Poller {
         if (rec[other].pending) {
             QP_HIP(hipEventSynchronize(p->ev_poll[other]));
             rec[other].pending = false;
-            finished = p->hstate[other].done != 0;
-            *seen = &p->hstate[other];
+            const State *hs = host_states(other);
+            finished = true;
+            for (int r = 0; r < K; ++r) finished = finished && hs[r].done != 0;
+            *seen = hs;
             if (prof) {
                 QP_TRY(account(other));
                 // the next batch of this slot set starts from a clear log
@@ -585,17 +605,17 @@ struct Poller {
         QP_HIP(hipMemsetAsync(p->exec_res() + s, 0, sizeof(int), p->stream));
         return QP_OK;
     }
-    qp_status final_state(State &out)
+    qp_status final_states(State *out)
     {
-        QP_HIP(hipMemcpyAsync(&p->hstate[2], p->st(), sizeof(State), hipMemcpyDeviceToHost,
-                              p->stream));
+        State *fin = host_states(2);
+        QP_HIP(hipMemcpyAsync(fin, p->st(), sizeof(State) * K, hipMemcpyDeviceToHost, p->stream));
         QP_HIP(hipStreamSynchronize(p->stream));
         for (int s = 0; s < 2; ++s)
             if (rec[s].pending) {
                 rec[s].pending = false;
                 if (prof) QP_TRY(account(s));
             }
-        out = p->hstate[2];
+        for (int r = 0; r < K; ++r) out[r] = fin[r];
         return QP_OK;
     }
 };
@@ -634,22 +654,23 @@ int next_batch(double need, int queued, int full)
     return (L + 1) & ~1;
 }
 
-qp_status solve_fp64(qp_problem *p, const double *rhs, double *U, double tol, State &st,
+qp_status solve_fp64(qp_problem *p, int K, const double *rhs, double *U, double tol, State *st,
                      Profile &pf)
 {
     const qp::Parts parts = p->parts();
     const bool prof = p->opt.profile != 0;
-    QP_HIP(qp::launch_state_reset(p->st(), p->stream));
-    QP_HIP(qp::launch_pcg_init(qp::F64, p->tab, p->host, rhs, nullptr, U, p->r(), p->h(), p->M64(),
-                               parts, p->st(), p->stream));
-    QP_HIP(qp::launch_pcg_start(qp::F64, p->host, tol, 0.0, p->opt.maxit, parts, p->st(), p->stream));
+    QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
+    QP_HIP(qp::launch_pcg_init(qp::F64, K, p->tab, p->host, rhs, nullptr, U, p->r(), p->h(),
+                               p->M64(), parts, p->st(), p->stream));
+    QP_HIP(qp::launch_pcg_start(qp::F64, K, p->host, tol, 0.0, p->opt.maxit, parts, p->st(),
+                                p->stream));
     const int batch = batch_size(p->opt);
-    Poller poll{p, prof, pf};
-    Trend trend;
+    Poller poll{p, K, prof, pf};
+    Trend trend[qp::kMaxRhs];
     int k = batch;
     for (int j = 0; j < p->opt.maxit;) {
         k = std::min(k, p->opt.maxit - j);
-        QP_TRY(queue_batch(p, false, U, nullptr, k, poll.slot, prof));
+        QP_TRY(queue_batch(p, false, K, U, nullptr, k, poll.slot, prof));
         j += k;
         bool fin = false;
         const State *seen = nullptr;
@@ -658,36 +679,44 @@ qp_status solve_fp64(qp_problem *p, const double *rhs, double *U, double tol, St
         // Convergence expected within the queued batch: queue a short one.
         int next = batch;
         if (seen) {
-            if (trend.it < 0) trend.observe(0, seen->rr0);
-            trend.observe(seen->iters, seen->rr);
-            next = next_batch(trend.iters_to(seen->thresh), j - seen->iters, batch);
+            double need = 0.0;
+            for (int r = 0; r < K; ++r) {
+                if (seen[r].done) continue;
+                if (trend[r].it < 0) trend[r].observe(0, seen[r].rr0);
+                trend[r].observe(seen[r].iters, seen[r].rr);
+                const double nr = trend[r].iters_to(seen[r].thresh);
+                need = (nr < 0.0 || need < 0.0) ? -1.0 : std::max(need, nr);
+            }
+            next = next_batch(need, k, batch);
         }
         k = next;
     }
-    return poll.final_state(st);
+    return poll.final_states(st);
 }
 
 // FP32-IR: float C-PCG whose residual is replaced by the FP64 residual
 // F' - Q X of the FP64 solution X whenever the float residual has dropped by
-// `inner_tol` (or reached tol), and at the end of every batch.  Batches are
-// sized to end just after the expected replacement point.
-qp_status solve_ir(qp_problem *p, const double *rhs, double *X, double tol, State &st, Profile &pf)
+// `inner_tol` (or reached tol).  The replacement steps sit at the end of every
+// batch and act on the paused right-hand sides; batches are sized to end just
+// after the expected pause.
+qp_status solve_ir(qp_problem *p, int K, const double *rhs, double *X, double tol, State *st,
+                   Profile &pf)
 {
     const qp::Parts parts = p->parts();
     const bool prof = p->opt.profile != 0;
-    QP_HIP(qp::launch_state_reset(p->st(), p->stream));
-    QP_HIP(qp::launch_ir_unit(p->tab, p->host, rhs, parts, p->st(), p->stream));
-    QP_HIP(qp::launch_pcg_init(qp::F32, p->tab, p->host, rhs, X, p->x32(), p->r32(), p->h32(),
+    QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
+    QP_HIP(qp::launch_ir_unit(K, p->tab, p->host, rhs, parts, p->st(), p->stream));
+    QP_HIP(qp::launch_pcg_init(qp::F32, K, p->tab, p->host, rhs, X, p->x32(), p->r32(), p->h32(),
                                p->M32(), parts, p->st(), p->stream));
-    QP_HIP(qp::launch_pcg_start(qp::F32, p->host, tol, p->opt.inner_tol, p->opt.maxit, parts,
+    QP_HIP(qp::launch_pcg_start(qp::F32, K, p->host, tol, p->opt.inner_tol, p->opt.maxit, parts,
                                 p->st(), p->stream));
     const int batch = batch_size(p->opt);
-    Poller poll{p, prof, pf};
-    Trend trend;
+    Poller poll{p, K, prof, pf};
+    Trend trend[qp::kMaxRhs];
     int k = batch;
     for (int j = 0; j < p->opt.maxit;) {
         k = std::min(k, p->opt.maxit - j);
-        QP_TRY(queue_batch(p, true, X, rhs, k, poll.slot, prof));
+        QP_TRY(queue_batch(p, true, K, X, rhs, k, poll.slot, prof));
         j += k;
         bool fin = false;
         const State *seen = nullptr;
@@ -695,78 +724,122 @@ qp_status solve_ir(qp_problem *p, const double *rhs, double *X, double tol, Stat
         if (fin) break;
         int next = batch;
         if (seen) {
-            // seen: after a replacement (scaled true residual rr = rr_last)
-            if (trend.it < 0) trend.observe(0, 1.0);
-            trend.observe(seen->iters, seen->rr);
-            const double target = std::max(seen->thresh, seen->delta2 * seen->rr_last);
-            const double need = trend.iters_to(target);
-            const int ahead = k;  // float iterations queued after the batch `seen` ended
-            if (need >= 0.0 && need <= ahead) {
-                // the queued batch reaches the next replacement point
-                if (target <= seen->thresh) {
-                    next = 2;  // and that one should converge
+            // seen: after a replacement (scaled true residual rr = rr_last);
+            // the batch to size comes after the one queued (k iterations)
+            int want = 2;
+            bool known = true;
+            for (int r = 0; r < K && known; ++r) {
+                if (seen[r].done) continue;
+                if (trend[r].it < 0) trend[r].observe(0, 1.0);
+                trend[r].observe(seen[r].iters, seen[r].rr);
+                const double target =
+                    std::max(seen[r].thresh, seen[r].delta2 * seen[r].rr_last);
+                const double need = trend[r].iters_to(target);
+                int L;
+                if (need < 0.0) {
+                    known = false;
+                    break;
+                } else if (need <= k) {
+                    // the queued batch reaches the next replacement point
+                    if (target <= seen[r].thresh) {
+                        L = 2;  // and that one should converge
+                    } else {
+                        const double t2 = std::max(seen[r].thresh, seen[r].delta2 * target);
+                        L = next_batch(std::log(t2 / target) / trend[r].rate, 0, batch);
+                    }
                 } else {
-                    const double t2 = std::max(seen->thresh, seen->delta2 * target);
-                    const double need2 = std::log(t2 / target) / trend.rate;
-                    next = next_batch(need2, 0, batch);
+                    L = next_batch(need, k, batch);
                 }
-            } else {
-                next = next_batch(need, ahead, batch);
+                want = std::max(want, L);
             }
+            next = known ? want : batch;
         }
         k = next;
     }
-    QP_TRY(poll.final_state(st));
-    if (!st.done) {
-        // iteration limit: the last batch ended in a replacement, so X holds
-        // every increment; report the true residual of that replacement
-        st.status = QP_ENOCONV;
+    QP_TRY(poll.final_states(st));
+    bool all_done = true;
+    for (int r = 0; r < K; ++r) all_done = all_done && st[r].done;
+    if (!all_done) {
+        // iteration limit: fold every unfinished increment into X with one
+        // forced replacement, whose true residual decides the status
+        QP_HIP(qp::launch_ir_force(K, p->st(), p->stream));
+        QP_TRY(enqueue_replacement(p, K, X, rhs, p->opt.maxit, 0, false));
+        QP_HIP(hipMemcpyAsync(p->hstate + 2 * qp::kMaxRhs, p->st(), sizeof(State) * K,
+                              hipMemcpyDeviceToHost, p->stream));
+        QP_HIP(hipStreamSynchronize(p->stream));
+        for (int r = 0; r < K; ++r) {
+            st[r] = p->hstate[2 * qp::kMaxRhs + r];
+            if (!st[r].done) st[r].status = QP_ENOCONV;
+        }
     }
     return QP_OK;
 }
 
-qp_status solve_dispatch(qp_problem *p, const double *rhs, double *U, double tol,
-                         qp_solve_info *info)
+// K right-hand sides (rhs + r D, solutions U + r D); infos: K entries or null.
+qp_status solve_dispatch(qp_problem *p, int K, const double *rhs, double *U, double tol,
+                         qp_solve_info *infos)
 {
-    qp_solve_info local;
-    if (!info) info = &local;
-    std::memset(info, 0, sizeof(*info));
-    info->flags = p->flags;
+    const int D2 = 2 * p->host.D;
+    if (K > 1 && p->host.tile_s <= 1) {
+        // line tiles serve one right-hand side per launch: solve them in turn
+        qp_status worst = QP_OK;
+        for (int r = 0; r < K; ++r) {
+            const qp_status s =
+                solve_dispatch(p, 1, rhs + (size_t)r * D2, U + (size_t)r * D2, tol,
+                               infos ? infos + r : nullptr);
+            if (s == QP_EDEVICE || s == QP_EINVAL) return s;
+            if (s != QP_OK && worst == QP_OK) worst = s;
+        }
+        return worst;
+    }
+    qp_solve_info local[qp::kMaxRhs];
+    if (!infos) infos = local;
+    std::memset(infos, 0, sizeof(qp_solve_info) * K);
+    for (int r = 0; r < K; ++r) infos[r].flags = p->flags;
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QP_EINVAL, "tol must be positive and finite");
     const bool ir = p->opt.precision == QP_PREC_FP32_IR;
     Profile pf;
-    State st{};
+    State st[qp::kMaxRhs];
     if (p->opt.profile) {
         QP_TRY(events_ready(p));
         QP_HIP(hipMemsetAsync(p->exec_hot(), 0, sizeof(int) * kExecInts, p->stream));
     }
     QP_HIP(hipEventRecord(p->ev_t0, p->stream));
-    QP_TRY(ir ? solve_ir(p, rhs, U, tol, st, pf) : solve_fp64(p, rhs, U, tol, st, pf));
+    QP_TRY(ir ? solve_ir(p, K, rhs, U, tol, st, pf) : solve_fp64(p, K, rhs, U, tol, st, pf));
     QP_HIP(hipEventRecord(p->ev_t1, p->stream));
     QP_HIP(hipEventSynchronize(p->ev_t1));
     float ms = 0.f;
     QP_HIP(hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1));
-    info->status = st.status;
-    info->iters = st.iters;
-    info->outer_iters = ir ? st.replacements : 0;
-    info->rel_resid = ir ? std::sqrt(st.rr) : (st.rr0 > 0 ? std::sqrt(st.rr / st.rr0) : 0.0);
-    info->seconds = ms * 1e-3;
-    if (p->opt.profile) {
-        if (ir) {
-            info->matvec32_ms = pf.hot_ms;
-            info->matvec32_launches = pf.hot_n;
-            info->matvec_ms = pf.res_ms;
-            info->matvec_launches = pf.res_n;
-        } else {
-            info->matvec_ms = pf.hot_ms;
-            info->matvec_launches = pf.hot_n;
+    qp_status worst = QP_OK;
+    for (int r = 0; r < K; ++r) {
+        qp_solve_info *info = infos + r;
+        info->status = st[r].status;
+        info->iters = st[r].iters;
+        info->outer_iters = ir ? st[r].replacements : 0;
+        info->rel_resid =
+            ir ? std::sqrt(st[r].rr) : (st[r].rr0 > 0 ? std::sqrt(st[r].rr / st[r].rr0) : 0.0);
+        info->seconds = ms * 1e-3;
+        if (p->opt.profile) {
+            if (ir) {
+                info->matvec32_ms = pf.hot_ms;
+                info->matvec32_launches = pf.hot_n;
+                info->matvec32_rhs = pf.hot_rhs;
+                info->matvec_ms = pf.res_ms;
+                info->matvec_launches = pf.res_n;
+                info->matvec_rhs = pf.res_rhs;
+            } else {
+                info->matvec_ms = pf.hot_ms;
+                info->matvec_launches = pf.hot_n;
+                info->matvec_rhs = pf.hot_rhs;
+            }
         }
+        const qp_status s = (qp_status)st[r].status;
+        if (s != QP_OK && worst == QP_OK) worst = s;
     }
-    const qp_status s = (qp_status)st.status;
-    if (s == QP_ENOTSPD) fail(s, "PCG breakdown: (Q h, h) <= 0");
-    else if (s == QP_ENOCONV) fail(s, "iteration limit reached before the tolerance");
-    else if (s == QP_ENONFINITE) fail(s, "non-finite value in the right-hand side or residual");
-    return s;
+    if (worst == QP_ENOTSPD) fail(worst, "PCG breakdown: (Q h, h) <= 0");
+    else if (worst == QP_ENOCONV) fail(worst, "iteration limit reached before the tolerance");
+    else if (worst == QP_ENONFINITE) fail(worst, "non-finite value in the right-hand side or residual");
+    return worst;
 }
 
 qp_status check_options(const qp_options *o)
@@ -875,7 +948,8 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, cons
         p->own_ws = true;
     }
     p->opt.workspace = nullptr;
-    if (hipHostMalloc(&p->hstate, 3 * sizeof(State), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc(&p->hstate, 3 * qp::kMaxRhs * sizeof(State), hipHostMallocDefault) !=
+            hipSuccess ||
         hipHostMalloc(&p->hsmall, 128 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&p->hexec, kExecInts * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(QP_ENOMEM, "pinned host allocation failed"));
@@ -937,7 +1011,19 @@ qp_status qp_solve_d(qp_problem *p, const double *rhs, double *u, double tol, qp
 {
     if (!p || !rhs || !u) return fail(QP_EINVAL, "null argument");
     if (rhs == u) return fail(QP_EINVAL, "rhs and u must not overlap");
-    return solve_dispatch(p, rhs, u, tol, info);
+    return solve_dispatch(p, 1, rhs, u, tol, info);
+}
+
+qp_status qp_solve_multi_d(qp_problem *p, int K, const double *rhs, double *u, double tol,
+                           qp_solve_info *infos)
+{
+    if (!p || !rhs || !u) return fail(QP_EINVAL, "null argument");
+    if (K < 1 || K > p->host.d)
+        return fail(QP_EINVAL, "K = %d right-hand sides outside [1, d = %d]", K, p->host.d);
+    const size_t bytes = 16 * (size_t)p->host.D * K;
+    const char *a = reinterpret_cast<const char *>(rhs), *b = reinterpret_cast<const char *>(u);
+    if (a < b + bytes && b < a + bytes) return fail(QP_EINVAL, "rhs and u must not overlap");
+    return solve_dispatch(p, K, rhs, u, tol, infos);
 }
 
 qp_status qp_solve(qp_problem *p, const double *rhs, double *u, double tol, qp_solve_info *info)
@@ -945,7 +1031,7 @@ qp_status qp_solve(qp_problem *p, const double *rhs, double *u, double tol, qp_s
     if (!p || !rhs || !u) return fail(QP_EINVAL, "null argument");
     const size_t bytes = 16 * (size_t)p->host.D;
     QP_HIP(hipMemcpyAsync(p->F(), rhs, bytes, hipMemcpyHostToDevice, p->stream));
-    qp_status s = solve_dispatch(p, p->F(), p->U(), tol, info);
+    qp_status s = solve_dispatch(p, 1, p->F(), p->U(), tol, info);
     if (s == QP_EDEVICE || s == QP_EINVAL) return s;
     QP_HIP(hipMemcpyAsync(u, p->U(), bytes, hipMemcpyDeviceToHost, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
@@ -957,7 +1043,7 @@ qp_status qp_corrector_d(qp_problem *p, int j, double *chi, double tol, qp_solve
     if (!p) return fail(QP_EINVAL, "null problem");
     if (j < 0 || j >= p->host.d) return fail(QP_EINVAL, "corrector index %d outside [0, d)", j);
     QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, p->F(), p->stream));
-    qp_status s = solve_dispatch(p, p->F(), p->chi(j), tol, info);
+    qp_status s = solve_dispatch(p, 1, p->F(), p->chi(j), tol, info);
     if (s == QP_EDEVICE || s == QP_EINVAL) return s;
     if (chi) {
         QP_HIP(hipMemcpyAsync(chi, p->chi(j), 16 * (size_t)p->host.D, hipMemcpyDeviceToDevice, p->stream));
@@ -982,19 +1068,19 @@ qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy, 
 {
     if (!p || !Astar) return fail(QP_EINVAL, "null argument");
     const int d = p->host.d;
-    qp_status worst = QP_OK;
-    for (int j = 0; j < d; ++j) {
-        qp_status s = qp_corrector_d(p, j, nullptr, tol, info ? &info[j] : nullptr);
-        if (s == QP_EDEVICE || s == QP_EINVAL) return s;
-        if (s != QP_OK && worst == QP_OK) worst = s;
-    }
+    // the d corrector right-hand sides, solved together
+    for (int j = 0; j < d; ++j)
+        QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, p->F() + (size_t)2 * p->host.D * j,
+                                        p->stream));
+    const qp_status worst = solve_dispatch(p, d, p->F(), p->chi(0), tol, info);
+    if (worst == QP_EDEVICE || worst == QP_EINVAL) return worst;
     QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), p->stream));
     if (Astar_energy) {
         const qp::Parts parts = p->parts();
         for (int j = 0; j < d; ++j) {
-            QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(),
-                                     p->urec(qp::F64), p->upku(qp::F64), p->chi(j),
-                                     p->q(), nullptr, nullptr, parts, p->st(), nullptr, p->stream));
+            QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, 1, p->tab, p->host, p->recs(),
+                                     p->urec(qp::F64), p->upku(qp::F64), p->chi(j), p->q(), nullptr,
+                                     nullptr, parts, p->st(), nullptr, p->stream));
             for (int i = 0; i < d; ++i)
                 QP_HIP(qp::launch_dot(p->tab, p->host, p->chi(i), p->q(), parts,
                                       p->small() + 64 + i * d + j, p->stream));
@@ -1019,7 +1105,7 @@ qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info
 qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
-    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, p->tab, p->host, p->recs(), p->urec(qp::F64),
+    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, 1, p->tab, p->host, p->recs(), p->urec(qp::F64),
                              p->upku(qp::F64), u, y, nullptr,
                              nullptr, p->parts(), p->st(), nullptr, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
@@ -1029,7 +1115,7 @@ qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
-    QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, p->tab, p->host, p->recs(), p->urec(qp::F32),
+    QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, 1, p->tab, p->host, p->recs(), p->urec(qp::F32),
                              p->upku(qp::F32), u, y, nullptr,
                              nullptr, p->parts(), p->st(), nullptr, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));

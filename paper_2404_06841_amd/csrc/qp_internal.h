@@ -102,8 +102,11 @@ struct State {
 enum Epilogue { EPI_NONE = 0, EPI_ALPHA = 1, EPI_RESID = 2 };
 enum Precision { F64 = 0, F32 = 1 };
 
-// Partial-sum buffers: each holds kPartValues * kMaxBlocks doubles.
+// Partial-sum buffers: each holds kMaxRhs slices of kPartStride doubles
+// (kPartValues values per workgroup); right-hand side k uses slice k.
 constexpr int kPartValues = 2;
+constexpr int kMaxRhs = kMaxD;  // right-hand sides solved together (the d correctors)
+constexpr size_t kPartStride = (size_t)kPartValues * kMaxBlocks;
 struct Parts {
     double *a;  // written by the stiffness product (h^H Q h)
     double *b;  // written by the vector update / residual ((r, M r), ||r||^2)
@@ -111,16 +114,22 @@ struct Parts {
 };
 
 // ---- launchers; all enqueue on `s` and return the launch status ----
+//
+// K right-hand sides (1 <= K <= kMaxRhs) are served by one launch: vector k
+// of a family starts at element k * D, its state is st[k], its partials are
+// slice k of the partial buffers.
 
-// Stiffness product, one launch:
-//   EPI_NONE : y = Q x
-//   EPI_ALPHA: y = Q x and parts.a <- Re(x^H y); returns at once if the solve
-//              is done or paused; *exec (nullable) <- 1 when it ran
-//   EPI_RESID: FP64 only. y (float2) = (f' - Q x) * st->inv_unit and
-//              parts.b <- (sum M32 |y|^2, sum |(f' - Q x) inv_unit|^2)
+// Stiffness product, one launch over K vectors (K > 1 for plane tiles only):
+//   EPI_NONE : y_k = Q x_k
+//   EPI_ALPHA: y_k = Q x_k and parts.a[k] <- Re(x_k^H y_k), for the right-hand
+//              sides neither done nor paused (returns at once if none);
+//              *exec (nullable) <- the number of right-hand sides served
+//   EPI_RESID: FP64 only. y_k (float2) = (f'_k - Q x_k) * st[k].inv_unit and
+//              parts.b[k] <- (sum M32 |y_k|^2, sum |(f'_k - Q x_k) inv_unit|^2),
+//              for the right-hand sides paused and not done
 // recs: g mode records in sorted order; urec / upku: the unit records and
 // the units' P k over axes < n-2 of precision prec (plane tiles only).
-hipError_t launch_matvec(int prec, int epi, const Table *tab, const Table &ht,
+hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table &ht,
                          const ModeRec *recs, const void *urec, const void *upku,
                          const void *x, void *y,
                          const double *f, const float *M32, const Parts &parts, State *st,
@@ -128,34 +137,37 @@ hipError_t launch_matvec(int prec, int epi, const Table *tab, const Table &ht,
 
 // Start of a solve.  r = f' * scale (scale = 1 for F64, st->inv_unit for F32),
 // U = 0, X64 = 0 (if given), h = M r; parts.b <- ((r, M r), ||r||^2).
-hipError_t launch_pcg_init(int prec, const Table *tab, const Table &ht, const double *f,
+hipError_t launch_pcg_init(int prec, int K, const Table *tab, const Table &ht, const double *f,
                            double *X64, void *U, void *r, void *h, const void *M,
                            const Parts &parts, State *st, hipStream_t s);
 // One workgroup: totals of parts.b -> rz[0], rr; F64: rr0, thresh = tol^2 rr0;
 // F32: thresh = tol^2, delta2, rr_last.  done when rr is 0; status on NaN.
-hipError_t launch_pcg_start(int prec, const Table &ht, double tol, double delta, int maxit,
-                            const Parts &parts, State *st, hipStream_t s);
+hipError_t launch_pcg_start(int prec, int K, const Table &ht, double tol, double delta,
+                            int maxit, const Parts &parts, State *st, hipStream_t s);
 // Iteration j: alpha = rz[j&1] / (totals of parts.a); U += alpha h;
 // r -= alpha q; parts.b <- ((r, M r), ||r||^2).
-hipError_t launch_pcg_update(int prec, int j, const Table *tab, const Table &ht, void *U,
+hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Table &ht, void *U,
                              void *r, const void *h, const void *q, const void *M,
                              const Parts &parts, State *st, hipStream_t s);
 // Iteration j: beta from parts.b; h = M r + beta h.  F64 stops on
 // convergence or at maxit; F32 pauses when the residual has dropped enough.
-hipError_t launch_pcg_direction(int prec, int j, const Table *tab, const Table &ht,
+hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const Table &ht,
                                 const void *r, void *h, const void *M, const Parts &parts,
                                 State *st, hipStream_t s);
 // FP32-IR start: st->rr0 = ||f'||^2, unit = sqrt(rr0) (two launches).
-hipError_t launch_ir_unit(const Table *tab, const Table &ht, const double *f, const Parts &parts,
+hipError_t launch_ir_unit(int K, const Table *tab, const Table &ht, const double *f,
+                          const Parts &parts, State *st, hipStream_t s);
+// FP32-IR residual replacement (paused right-hand sides): X += unit * x; x = 0.
+hipError_t launch_ir_fold(int K, const Table *tab, const Table &ht, double *X, float *x,
                           State *st, hipStream_t s);
-// FP32-IR residual replacement: X += unit * x; x = 0.
-hipError_t launch_ir_fold(const Table *tab, const Table &ht, double *X, float *x, State *st,
-                          hipStream_t s);
-// FP32-IR, after the FP64 residual (EPI_RESID): convergence on the true
-// residual, else beta, h = M r + beta h and pause cleared.
-hipError_t launch_ir_direction(int j, const Table *tab, const Table &ht, const float *r,
+// FP32-IR, after the FP64 residual (EPI_RESID), paused right-hand sides:
+// convergence on the true residual, else beta, h = M r + beta h, pause cleared.
+hipError_t launch_ir_direction(int j, int K, const Table *tab, const Table &ht, const float *r,
                                float *h, const float *M, const Parts &parts, State *st,
                                hipStream_t s);
+
+// FP32-IR: pause every unfinished right-hand side (final forced replacement).
+hipError_t launch_ir_force(int K, State *st, hipStream_t s);
 
 // ---- setup and single-step kernels ----
 // Unit records and unit P k of precision prec (plane tiles, tile_s > 1).
@@ -178,7 +190,7 @@ hipError_t launch_dot(const Table *tab, const Table &ht, const double *x, const 
                       const Parts &parts, double *out, hipStream_t s);
 // Signed multi-index of every entry (D x n int32).
 hipError_t launch_multi_index(const Table *tab, const Table &ht, int32_t *k, hipStream_t s);
-// Reset a State (flags, counters) with a kernel (no memset node).
-hipError_t launch_state_reset(State *st, hipStream_t s);
+// Reset K States (flags, counters) with a kernel (no memset node).
+hipError_t launch_state_reset(int K, State *st, hipStream_t s);
 
 }  // namespace qp

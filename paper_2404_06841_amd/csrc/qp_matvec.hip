@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                                                    int *__restrict__ exec)
 {
     if (EPI == EPI_ALPHA && (st->done || st->pause)) return;
-    if (EPI == EPI_RESID && st->done) return;
+    if (EPI == EPI_RESID && (st->done || !st->pause)) return;  // replaced only once paused
     constexpr int KC = Inflight<T>::v;
     // per padded mode and lane: (wrapped column, face factor as float); gp * kWave
     // entries of dynamic LDS when N <= kWave
@@ -518,7 +518,7 @@ __device__ __forceinline__ void wave_sync()
 // Work items of the plane kernel: (unit, up to tab->item_tiles consecutive
 // tiles); a wave copies the unit's records to its LDS once per item.
 
-template <typename T, int DT, int EPI, bool REAL>
+template <typename T, int DT, int EPI, bool REAL, int KR>
 __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict__ tab,
                                                          const ModeRec *__restrict__ recs,
                                                          const UnitRec<T, DT> *__restrict__ urec,
@@ -531,9 +531,18 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
                                                          State *__restrict__ st,
                                                          int *__restrict__ exec)
 {
-    if (EPI == EPI_ALPHA && (st->done || st->pause)) return;
-    if (EPI == EPI_RESID && st->done) return;
-    constexpr int KC = Inflight<T>::v;
+    // right-hand sides served by this launch (uniform)
+    bool act[KR];
+    int nact = 0;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        act[k] = (EPI == EPI_ALPHA) ? !(st[k].done || st[k].pause)
+                                    : ((EPI == EPI_RESID) ? (!st[k].done && st[k].pause) : true);
+        nact += act[k] ? 1 : 0;
+    }
+    if (nact == 0) return;
+    // neighbour loads in flight per chunk: about Inflight<T> over all right-hand sides
+    constexpr int KC = (Inflight<T>::v / KR >= 8) ? (Inflight<T>::v / KR) / 4 * 4 : 4;
     using Rec = UnitRec<T, DT>;
     // dynamic LDS: gp * kWave lane-geometry entries (column, face factor),
     // then kWaves * gp unit records
@@ -545,6 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
     const int gp = (g + 3) & ~3;
     const int S = tab->tile_s;
     const int tpu = tab->tiles_per_unit;
+    const size_t D = tab->D;
     const int lane = threadIdx.x % kWave;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int s = lane / N;
@@ -565,7 +575,9 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
         ps_[l] = (T)tab->P[l][n - 2];
     }
     __syncthreads();
-    const double inv_unit = (EPI == EPI_RESID) ? st->inv_unit : 1.0;
+    double inv_unit[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) inv_unit[k] = (EPI == EPI_RESID) ? st[k].inv_unit : 1.0;
     const T NT = (T)N;
 
     // items in XCD-front order: each XCD owns a contiguous eighth, its waves
@@ -583,7 +595,9 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
     const int ibeg = xcd * per;
     const int iend = min(ibeg + per, nitems);
     const int nvec = gp * (int)sizeof(Rec) / 16;  // 16-byte pieces of a unit's records
-    double dots[2] = {0.0, 0.0};
+    double dots[KR][2];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) dots[k][0] = dots[k][1] = 0.0;
 
     for (int item = ibeg + loc; item < iend; item += nloc) {
         const int unit = item / ipu;
@@ -627,14 +641,16 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
             cqs *= NT;
             const uint64_t slow = tab->slotmask[tl];
 
-            T acc_re = 0, acc_im = 0;
+            T acc_re[KR], acc_im[KR];
+#pragma unroll
+            for (int k = 0; k < KR; ++k) acc_re[k] = acc_im[k] = 0;
             auto chunk = [&](auto Cc, int rb) {
                 constexpr int C = decltype(Cc)::value;
-                cplx_t<T> u[C];
+                cplx_t<T> u[C][KR];
                 T w[C];
 #pragma unroll
-                for (int k = 0; k < C; ++k) {
-                    const int r = rb + k;
+                for (int m = 0; m < C; ++m) {
+                    const int r = rb + m;
                     const Rec &Q = s_rec[r];  // LDS broadcast
                     const int2 ge = s_geo[r * kWave + lane];
                     const T c = (T)__int_as_float(ge.y);
@@ -644,27 +660,38 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
                     for (int l = 0; l < DT; ++l) wv -= pk[l] * Q.apm[l];
                     int idx = Q.lb + lane_line + ge.x;
                     if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
-                        const int m = Q.mslot;
-                        const int jb = ibs - m;
+                        const int mm = Q.mslot;
+                        const int jb = ibs - mm;
                         idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
-                        const int kd = ks - m;
+                        const int kd = ks - mm;
                         const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
                         wv += Q.a * cs * cqs;
                     }
-                    u[k] = x[(unsigned)idx];
-                    w[k] = wv;
+#pragma unroll
+                    for (int k = 0; k < KR; ++k) {
+                        if (act[k]) {
+                            u[m][k] = x[k * D + (unsigned)idx];
+                        } else {
+                            u[m][k].x = 0;
+                            u[m][k].y = 0;
+                        }
+                    }
+                    w[m] = wv;
                 }
 #pragma unroll
-                for (int k = 0; k < C; ++k) {
-                    if (REAL) {
-                        acc_re += w[k] * u[k].x;
-                        acc_im += w[k] * u[k].y;
-                    } else {
-                        const Rec &Q = s_rec[rb + k];
-                        const T cr = Q.cr * w[k];
-                        const T ci = Q.ci * w[k];
-                        acc_re += cr * u[k].x - ci * u[k].y;
-                        acc_im += cr * u[k].y + ci * u[k].x;
+                for (int m = 0; m < C; ++m) {
+#pragma unroll
+                    for (int k = 0; k < KR; ++k) {
+                        if (REAL) {
+                            acc_re[k] += w[m] * u[m][k].x;
+                            acc_im[k] += w[m] * u[m][k].y;
+                        } else {
+                            const Rec &Q = s_rec[rb + m];
+                            const T cr = Q.cr * w[m];
+                            const T ci = Q.ci * w[m];
+                            acc_re[k] += cr * u[m][k].x - ci * u[m][k].y;
+                            acc_im[k] += cr * u[m][k].y + ci * u[m][k].x;
+                        }
                     }
                 }
             };
@@ -678,15 +705,28 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
                 }
                 for (; rb < gp; rb += 4) chunk(integral_constant<int, 4>(), rb);
             }
-            if (active)
-                put_output<T, EPI>((size_t)(L0 + s) * N + p, acc_re, acc_im, x, yv, f, M32,
-                                   inv_unit, dots);
+            if (active) {
+                const size_t i = (size_t)(L0 + s) * N + p;
+#pragma unroll
+                for (int k = 0; k < KR; ++k) {
+                    if (!act[k]) continue;
+                    void *yk = (EPI == EPI_RESID)
+                                   ? (void *)(static_cast<float2 *>(yv) + k * D)
+                                   : (void *)(static_cast<cplx_t<T> *>(yv) + k * D);
+                    put_output<T, EPI>(i, acc_re[k], acc_im[k], x + k * D, yk,
+                                       f ? f + k * D : f, M32, inv_unit[k], dots[k]);
+                }
+            }
         }
     }
-    put_partials<EPI>(dots, part, st, exec);
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+        if (act[k]) put_partials<EPI>(dots[k], part + k * kPartStride, st, nullptr);
+    if ((EPI == EPI_ALPHA || EPI == EPI_RESID) && exec && blockIdx.x == 0 && threadIdx.x == 0)
+        *exec = nact;
 }
 
-template <typename T, int EPI, bool REAL>
+template <typename T, int EPI, bool REAL, int KR>
 hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, const void *urec,
                     const void *upku, const void *x, void *y, const double *f, const float *M32,
                     double *part, State *st, int *exec, hipStream_t s)
@@ -702,7 +742,7 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, cons
         switch (ht.d) {
 #define QP_CASE(DD)                                                                              \
     case DD:                                                                                      \
-        hipLaunchKernelGGL((k_matvec_plane<T, DD, EPI, REAL>), grid, block,                      \
+        hipLaunchKernelGGL((k_matvec_plane<T, DD, EPI, REAL, KR>), grid, block,                  \
                            lds + kWaves * gp * sizeof(UnitRec<T, DD>), s, tab, recs,             \
                            static_cast<const UnitRec<T, DD> *>(urec), Pu, X, y, Fv, M32, part, st, \
                            exec);                                                                 \
@@ -714,6 +754,7 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, cons
         }
         return hipGetLastError();
     }
+    if (KR != 1) return hipErrorInvalidValue;  // line tiles serve one right-hand side
     switch (ht.d) {
 #define QP_CASE(DD)                                                                             \
     case DD:                                                                                     \
@@ -728,14 +769,29 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, cons
     return hipGetLastError();
 }
 
+template <typename T, int EPI, bool REAL>
+hipError_t dispatch_k(int K, const Table *tab, const Table &ht, const ModeRec *recs,
+                      const void *urec, const void *upku, const void *x, void *y, const double *f,
+                      const float *M32, double *part, State *st, int *exec, hipStream_t s)
+{
+    switch (K) {
+    case 1: return dispatch<T, EPI, REAL, 1>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+    case 2: return dispatch<T, EPI, REAL, 2>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+    case 3: return dispatch<T, EPI, REAL, 3>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+    case 4: return dispatch<T, EPI, REAL, 4>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, int EPI>
-hipError_t dispatch_coef(const Table *tab, const Table &ht, const ModeRec *recs, const void *urec,
-                         const void *upku, const void *x, void *y, const double *f,
-                         const float *M32, double *part, State *st, int *exec, hipStream_t s)
+hipError_t dispatch_coef(int K, const Table *tab, const Table &ht, const ModeRec *recs,
+                         const void *urec, const void *upku, const void *x, void *y,
+                         const double *f, const float *M32, double *part, State *st, int *exec,
+                         hipStream_t s)
 {
     if (ht.real_coef)
-        return dispatch<T, EPI, true>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
-    return dispatch<T, EPI, false>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+        return dispatch_k<T, EPI, true>(K, tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+    return dispatch_k<T, EPI, false>(K, tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
 }
 
 template <typename T, bool REAL>
@@ -761,27 +817,27 @@ hipError_t unit_records(const Table *tab, const Table &ht, const ModeRec *recs, 
 
 }  // namespace
 
-hipError_t launch_matvec(int prec, int epi, const Table *tab, const Table &ht, const ModeRec *recs,
-                         const void *urec, const void *upku, const void *x, void *y,
-                         const double *f, const float *M32, const Parts &parts, State *st,
+hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table &ht,
+                         const ModeRec *recs, const void *urec, const void *upku, const void *x,
+                         void *y, const double *f, const float *M32, const Parts &parts, State *st,
                          int *exec, hipStream_t s)
 {
     if (prec == F64) {
         if (epi == EPI_NONE)
-            return dispatch_coef<double, EPI_NONE>(tab, ht, recs, urec, upku, x, y, f, M32, parts.a,
-                                                   st, exec, s);
+            return dispatch_coef<double, EPI_NONE>(K, tab, ht, recs, urec, upku, x, y, f, M32,
+                                                   parts.a, st, exec, s);
         if (epi == EPI_ALPHA)
-            return dispatch_coef<double, EPI_ALPHA>(tab, ht, recs, urec, upku, x, y, f, M32,
+            return dispatch_coef<double, EPI_ALPHA>(K, tab, ht, recs, urec, upku, x, y, f, M32,
                                                     parts.a, st, exec, s);
-        return dispatch_coef<double, EPI_RESID>(tab, ht, recs, urec, upku, x, y, f, M32, parts.b,
+        return dispatch_coef<double, EPI_RESID>(K, tab, ht, recs, urec, upku, x, y, f, M32, parts.b,
                                                 st, exec, s);
     }
     if (epi == EPI_NONE)
-        return dispatch_coef<float, EPI_NONE>(tab, ht, recs, urec, upku, x, y, f, M32, parts.a, st,
-                                              exec, s);
+        return dispatch_coef<float, EPI_NONE>(K, tab, ht, recs, urec, upku, x, y, f, M32, parts.a,
+                                              st, exec, s);
     if (epi == EPI_ALPHA)
-        return dispatch_coef<float, EPI_ALPHA>(tab, ht, recs, urec, upku, x, y, f, M32, parts.a, st,
-                                               exec, s);
+        return dispatch_coef<float, EPI_ALPHA>(K, tab, ht, recs, urec, upku, x, y, f, M32, parts.a,
+                                               st, exec, s);
     return hipErrorInvalidValue;  // the replaced residual is always computed in FP64
 }
 

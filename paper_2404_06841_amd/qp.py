@@ -40,7 +40,8 @@ MAX_N, MAX_D, MAX_MODES = 8, 4, 64
 #: every symbol include/qp.h declares
 EXPORTED = (
     "qp_default_options", "qp_workspace_bytes", "qp_create", "qp_destroy", "qp_dim",
-    "qp_set_options", "qp_solve", "qp_solve_d", "qp_corrector", "qp_corrector_d",
+    "qp_set_options", "qp_solve", "qp_solve_d", "qp_solve_multi_d", "qp_corrector",
+    "qp_corrector_d",
     "qp_homogenized", "qp_homogenized_ex", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
     "qp_corrector_rhs_d", "qp_multi_index_d", "qp_astar_d", "qp_coef_extrema",
     "qp_synchronize", "qp_strerror", "qp_last_error",
@@ -58,7 +59,8 @@ class qp_solve_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
                 ("flags", C.c_int), ("rel_resid", C.c_double), ("seconds", C.c_double),
                 ("matvec_launches", C.c_int), ("matvec_ms", C.c_double),
-                ("matvec32_launches", C.c_int), ("matvec32_ms", C.c_double)]
+                ("matvec32_launches", C.c_int), ("matvec32_ms", C.c_double),
+                ("matvec_rhs", C.c_int), ("matvec32_rhs", C.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,6 +95,7 @@ def lib():
         "qp_set_options": (C.c_int, [vp, C.POINTER(qp_options)]),
         "qp_solve": (C.c_int, [vp, dp, dp, C.c_double, C.POINTER(qp_solve_info)]),
         "qp_solve_d": (C.c_int, [vp, vp, vp, C.c_double, C.POINTER(qp_solve_info)]),
+        "qp_solve_multi_d": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, C.POINTER(qp_solve_info)]),
         "qp_corrector": (C.c_int, [vp, C.c_int, dp, C.c_double, C.POINTER(qp_solve_info)]),
         "qp_corrector_d": (C.c_int, [vp, C.c_int, vp, C.c_double, C.POINTER(qp_solve_info)]),
         "qp_homogenized": (C.c_int, [vp, dp, C.c_double, C.POINTER(qp_solve_info)]),
@@ -248,6 +251,20 @@ class Problem:
         if check:
             _check(st, "qp_solve_d")
         return out, info
+
+    def solve_multi_d(self, rhs, out=None, tol: float = 1e-12, check: bool = True):
+        """K solves at once: rhs is a (K, D) complex128 device tensor."""
+        import torch
+        K = int(rhs.shape[0])
+        if out is None:
+            out = torch.empty((K, self.D), dtype=torch.complex128, device="cuda")
+        infos = (qp_solve_info * K)()
+        st = lib().qp_solve_multi_d(self.h, K, _tensor_ptr(rhs, torch.complex128, K * self.D),
+                                    _tensor_ptr(out, torch.complex128, K * self.D), float(tol),
+                                    infos)
+        if check:
+            _check(st, "qp_solve_multi_d")
+        return out, list(infos)
 
     def solve(self, rhs: np.ndarray, tol: float = 1e-12, check: bool = True):
         rhs = np.ascontiguousarray(rhs, dtype=np.complex128).reshape(-1)
