@@ -79,8 +79,8 @@ constexpr size_t kUnitRecBytes[2] = {64, 48};
 
 // Krylov state of one solve, device resident.  All scalars are FP64.
 // Fields are written by workgroup 0 of one kernel and read by later kernels
-// only (no kernel reads what it writes), except rz[], which alternates
-// between the two slots by iteration parity.
+// only: no kernel takes a decision from a field it writes itself (rz[]
+// alternates between two slots by iteration parity).
 struct State {
     double rz[2];     // (r, M r): slot j & 1 holds the value entering iteration j
     double alpha, beta, hq;
@@ -97,6 +97,8 @@ struct State {
     int pause;        // FP32-IR: float iterations wait for the next replacement
     int status;       // qp_status of the solve
     int maxit;
+    int did_update;   // the update of the current iteration ran (written by the update)
+    int replace;      // FP32-IR: this replacement acts (written by the fold)
 };
 
 enum Epilogue { EPI_NONE = 0, EPI_ALPHA = 1, EPI_RESID = 2 };
@@ -149,8 +151,9 @@ hipError_t launch_pcg_start(int prec, int K, const Table &ht, double tol, double
 hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Table &ht, void *U,
                              void *r, const void *h, const void *q, const void *M,
                              const Parts &parts, State *st, hipStream_t s);
-// Iteration j: beta from parts.b; h = M r + beta h.  F64 stops on
-// convergence or at maxit; F32 pauses when the residual has dropped enough.
+// Iteration j (right-hand sides whose update ran): beta from parts.b;
+// h = M r + beta h.  F64 stops on convergence or at maxit; F32 pauses when
+// the residual has dropped enough.
 hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const Table &ht,
                                 const void *r, void *h, const void *M, const Parts &parts,
                                 State *st, hipStream_t s);

@@ -92,6 +92,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_start(int K, int is_ir, double t
         st->replacements = 0;
         st->maxit = maxit;
         st->pause = 0;
+        st->did_update = 0;
+        st->replace = 0;
         st->alpha = st->beta = st->hq = 0.0;
         if (is_ir) {
             st->thresh = tol * tol;  // float residual is scaled to ||r_0|| = 1
@@ -128,19 +130,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
                                                        State *__restrict__ sts)
 {
     const size_t D = tab->D;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block(tab, begin, end);
     for (int k = 0; k < K; ++k) {
         State *st = sts + k;
-        if (st->done || st->pause) continue;
+        if (st->done || st->pause) {
+            if (lead) st->did_update = 0;
+            continue;
+        }
         double hq[1];
         load_totals<1>(part_in + k * kPartStride, tab->nb_mv, hq);  // the product's partials
         if (!(hq[0] > 0.0)) {
             // (Q h, h) <= 0: Q is not positive definite on this Krylov space
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (lead) {
                 st->hq = hq[0];
                 st->status = finite(hq[0]) ? QP_ENOTSPD : QP_ENONFINITE;
                 st->done = 1;
+                st->did_update = 0;
             }
             continue;
         }
@@ -164,10 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
             acc[1] += n2;
         }
         store_partials<2>(acc, part_out + k * kPartStride);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (lead) {
             st->alpha = alpha;
             st->hq = hq[0];
             st->iters = st->iters + 1;
+            st->did_update = 1;
         }
     }
 }
@@ -187,11 +195,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int 
     chunk_of_block(tab, begin, end);
     for (int k = 0; k < K; ++k) {
         State *st = sts + k;
-        if (st->done) continue;
         const double rz_old = st->rz[j & 1];
-        if (st->pause) {
-            // carry the last rz forward so iteration j+1 finds it in its slot
-            if (lead) st->rz[(j + 1) & 1] = rz_old;
+        if (!st->did_update) {
+            // no update this iteration; a paused solve carries rz forward so
+            // iteration j+1 finds it in its slot
+            if (lead && !st->done && st->pause) st->rz[(j + 1) & 1] = rz_old;
             continue;
         }
         double v[2];
@@ -280,13 +288,18 @@ __global__ __launch_bounds__(kBlock) void k_ir_unit(int K, const double *__restr
 __global__ __launch_bounds__(kBlock) void k_ir_fold(int K, const Table *__restrict__ tab,
                                                     double2 *__restrict__ X,
                                                     float2 *__restrict__ x,
-                                                    const State *__restrict__ sts)
+                                                    State *__restrict__ sts)
 {
     const size_t D = tab->D;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block(tab, begin, end);
     for (int k = 0; k < K; ++k) {
-        if (sts[k].done || !sts[k].pause) continue;  // replaced only once paused
+        // replaced only once paused; the decision is kept for the later
+        // replacement steps, which must not read the flags they change
+        const bool rep = !sts[k].done && sts[k].pause;
+        if (lead) sts[k].replace = rep ? 1 : 0;
+        if (!rep) continue;
         const double unit = sts[k].unit;
         QP_STREAM(i) {
             const size_t e = k * D + i;
@@ -313,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_direction(int j, int K, const Tab
     chunk_of_block(tab, begin, end);
     for (int k = 0; k < K; ++k) {
         State *st = sts + k;
-        if (st->done || !st->pause) continue;  // replaced only once paused
+        if (!st->replace) continue;  // decided by the fold
         double v[2];
         load_totals<2>(part_in + k * kPartStride, tab->nb_mv, v);  // FP64 residual product
         const double rz_new = v[0], rr = v[1];  // true residual, scaled by 1/unit
@@ -382,6 +395,8 @@ __global__ void k_state_reset(int K, State *sts)
     st->pause = 0;
     st->status = 0;
     st->maxit = 0;
+    st->did_update = 0;
+    st->replace = 0;
 }
 
 }  // namespace
@@ -458,8 +473,7 @@ hipError_t launch_ir_fold(int K, const Table *tab, const Table &ht, double *X, f
                           hipStream_t s)
 {
     hipLaunchKernelGGL(k_ir_fold, dim3(ht.nblocks), dim3(kBlock), 0, s, K, tab,
-                       reinterpret_cast<double2 *>(X), reinterpret_cast<float2 *>(x),
-                       (const State *)st);
+                       reinterpret_cast<double2 *>(X), reinterpret_cast<float2 *>(x), st);
     return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                                                    int *__restrict__ exec)
 {
     if (EPI == EPI_ALPHA && (st->done || st->pause)) return;
-    if (EPI == EPI_RESID && (st->done || !st->pause)) return;  // replaced only once paused
+    if (EPI == EPI_RESID && !st->replace) return;  // replaced only once paused (fold decides)
     constexpr int KC = Inflight<T>::v;
     // per padded mode and lane: (wrapped column, face factor as float); gp * kWave
     // entries of dynamic LDS when N <= kWave
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
         act[k] = (EPI == EPI_ALPHA) ? !(st[k].done || st[k].pause)
-                                    : ((EPI == EPI_RESID) ? (!st[k].done && st[k].pause) : true);
+                                    : ((EPI == EPI_RESID) ? (st[k].replace != 0) : true);
         nact += act[k] ? 1 : 0;
     }
     if (nact == 0) return;
