@@ -102,18 +102,24 @@ def run_steps(gp, steps: int, torch):
 
 
 def cpu_baseline(prob):
-    """The oracle, unmodified, on this host's cores: one FP64 homogenization of
-    the same workload (two corrector solves at tol 1e-12)."""
+    """The oracle, unmodified, on this host's cores: FP64 homogenizations of the
+    same workload (two corrector solves at tol 1e-12 each), repeated until at
+    least 10 s of CPU work have run."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    reps, iters = 0, None
     t0 = time.perf_counter()
-    r = oracle.homogenize(prob, tol=TOL)
-    dt = time.perf_counter() - t0
-    return {"value": round(prob.d / dt, 4), "unit": "corrector solves/s", "cores": threads,
+    while True:
+        r = oracle.homogenize(prob, tol=TOL)
+        reps += 1
+        iters = [i.iters for i in r.infos]
+        dt = time.perf_counter() - t0
+        if dt >= 10.0 or reps >= 20:
+            break
+    return {"value": round(prob.d * reps / dt, 4), "unit": "corrector solves/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"one homogenization ({prob.d} FP64 corrector solves, tol 1e-12, "
-                      f"{[i.iters for i in r.infos]} PCG iterations) of the same workload, "
-                      f"{dt:.2f} s"}
+            "sample": f"{reps} homogenizations ({prob.d * reps} FP64 corrector solves, tol 1e-12, "
+                      f"{iters} PCG iterations each) of the same workload, {dt:.2f} s"}
 
 
 def main():
