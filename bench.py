@@ -27,7 +27,9 @@ METRIC = "corrector solves/s + matvec HBM GB/s, FP32-IR vs FP64 @1e-10; p99 late
 HBM_PEAK_GBS = 8000.0
 TOL = 1e-12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_fp32_eightfold_n4_N32.txt")
-MATVEC_SRC = os.path.join(ROOT, "paper_2404_06841_amd", "csrc", "qp_matvec.hip")
+# sources of the stiffness-product kernels (the product and its device helpers)
+MATVEC_SRC = [os.path.join(ROOT, "paper_2404_06841_amd", "csrc", f)
+              for f in ("qp_matvec.hip", "qp_device.h")]
 
 
 def parse_args():
@@ -59,8 +61,11 @@ def copy_probe():
 
 
 def kernel_hash() -> str:
-    with open(MATVEC_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in MATVEC_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(D: int):

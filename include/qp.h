@@ -96,6 +96,11 @@ typedef struct qp_options {
     int graphs;         /* nonzero (default): each full batch of poll_every
                            iterations is captured once as a HIP graph and
                            replayed; 0 = launch every kernel directly            */
+    int gather64;       /* nonzero: the stiffness product forms 64-bit neighbour
+                           addresses and serves one right-hand side per launch.
+                           Always on when N^n >= 2^28 (vectors of 4 GiB or more,
+                           beyond the 32-bit record indices of the default
+                           gathers); default 0                                   */
 } qp_options;
 
 typedef struct qp_solve_info {

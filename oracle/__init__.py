@@ -50,6 +50,8 @@ def _load():
     lib.qo_multi_index.argtypes = [C.c_int, C.c_int, C.c_long, C.POINTER(C.c_int)]
     lib.qo_matvec.restype = None
     lib.qo_matvec.argtypes = [pp, dp, dp]
+    lib.qo_matvec_rows.restype = None
+    lib.qo_matvec_rows.argtypes = [pp, dp, C.c_long, C.POINTER(C.c_long), dp]
     lib.qo_precond.restype = None
     lib.qo_precond.argtypes = [pp, C.c_int, dp]
     lib.qo_pcg.restype = C.c_int
@@ -122,6 +124,20 @@ def matvec(prob, u) -> np.ndarray:
     u = _cvec(u, b.D)
     y = np.empty(b.D, dtype=np.complex128)
     _load().qo_matvec(b.ref, _dptr(u.view(np.float64)), _dptr(y.view(np.float64)))
+    return y
+
+
+def matvec_rows(prob, u, rows) -> np.ndarray:
+    """(Q u) at the given storage indices only (for vectors too large for a
+    full CPU product)."""
+    b = _Bound(prob)
+    u = _cvec(u, b.D)
+    rows = np.ascontiguousarray(rows, dtype=np.int64).reshape(-1)
+    if rows.size and (rows.min() < 0 or rows.max() >= b.D):
+        raise ValueError("row index out of range")
+    y = np.empty(rows.size, dtype=np.complex128)
+    _load().qo_matvec_rows(b.ref, _dptr(u.view(np.float64)), int(rows.size),
+                           rows.ctypes.data_as(C.POINTER(C.c_long)), _dptr(y.view(np.float64)))
     return y
 
 

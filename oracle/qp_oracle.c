@@ -127,28 +127,40 @@ static int is_zero(int n, const int *k)
  * (eq. n-discrete).  Only the g nonzero Ahat contribute: for a mode m the
  * column is the k_U in K_N^n congruent to k_V - m.  Row k_V = 0 is not part of
  * the test space and is returned as 0. */
+static double complex matvec_row(const qo_problem *p, const double complex *u, long i)
+{
+    int kv[8], ku[8];
+    double pkv[8], pku[8];
+    qo_multi_index(p->n, p->N, i, kv);
+    if (is_zero(p->n, kv)) return 0.0;
+    proj(p, kv, pkv);
+    double complex acc = 0.0;
+    for (int r = 0; r < p->g; ++r) {
+        for (int t = 0; t < p->n; ++t)
+            ku[t] = qo_rep(p->N, (long)kv[t] - p->modes[r * p->n + t]);
+        proj(p, ku, pku);
+        const double w = dotd(p->d, pkv, pku);
+        acc += coef_at(p, r) * w * u[qo_index(p->n, p->N, ku)];
+    }
+    return acc;
+}
+
 void qo_matvec(const qo_problem *p, const double *u_, double *y_)
 {
     const double complex *u = (const double complex *)u_;
     double complex *y = (double complex *)y_;
     const long D = qo_size(p->n, p->N);
 #pragma omp parallel for schedule(static)
-    for (long i = 0; i < D; ++i) {
-        int kv[8], ku[8];
-        double pkv[8], pku[8];
-        qo_multi_index(p->n, p->N, i, kv);
-        if (is_zero(p->n, kv)) { y[i] = 0.0; continue; }
-        proj(p, kv, pkv);
-        double complex acc = 0.0;
-        for (int r = 0; r < p->g; ++r) {
-            for (int t = 0; t < p->n; ++t)
-                ku[t] = qo_rep(p->N, (long)kv[t] - p->modes[r * p->n + t]);
-            proj(p, ku, pku);
-            const double w = dotd(p->d, pkv, pku);
-            acc += coef_at(p, r) * w * u[qo_index(p->n, p->N, ku)];
-        }
-        y[i] = acc;
-    }
+    for (long i = 0; i < D; ++i) y[i] = matvec_row(p, u, i);
+}
+
+/* The same product at the listed rows only: y[j] = (Q u)_{rows[j]}. */
+void qo_matvec_rows(const qo_problem *p, const double *u_, long nrows, const long *rows,
+                    double *y_)
+{
+    const double complex *u = (const double complex *)u_;
+    double complex *y = (double complex *)y_;
+    for (long j = 0; j < nrows; ++j) y[j] = matvec_row(p, u, rows[j]);
 }
 
 /* Diagonal preconditioner.

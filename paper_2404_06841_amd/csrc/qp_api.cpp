@@ -780,8 +780,9 @@ qp_status solve_dispatch(qp_problem *p, int K, const double *rhs, double *U, dou
                          qp_solve_info *infos)
 {
     const int D2 = 2 * p->host.D;
-    if (K > 1 && p->host.tile_s <= 1) {
-        // line tiles serve one right-hand side per launch: solve them in turn
+    if (K > 1 && (p->host.tile_s <= 1 || p->host.wide)) {
+        // line tiles and 64-bit gathers serve one right-hand side per launch:
+        // solve them in turn
         qp_status worst = QP_OK;
         for (int r = 0; r < K; ++r) {
             const qp_status s =
@@ -912,6 +913,9 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, cons
     if (!p) return fail(QP_ENOMEM, "host allocation failed");
     p->opt = o;
     build_table(p->host, d, n, P, g, modes, coef, N);
+    // record indices of the default gathers are scaled by the entry size in 32
+    // bits: vectors of 2^28 entries or more take 64-bit addresses
+    if (p->host.tile_s > 1 && (o.gather64 || p->host.D >= ((int64_t)1 << 28))) p->host.wide = 1;
     p->L = make_layout(d, n, N, p->host.D, g);
 
     auto bail = [&](qp_status st) {

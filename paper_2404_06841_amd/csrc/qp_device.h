@@ -28,6 +28,47 @@ template <> struct Cplx<double> { using type = double2; };
 template <> struct Cplx<float> { using type = float2; };
 template <typename T> using cplx_t = typename Cplx<T>::type;
 
+// ---- structured-buffer gathers ----
+// A buffer resource (four scalar registers) names `count` records of `stride`
+// bytes at `base`.  A load at record index j reads base + j * stride, with the
+// product formed by the address unit (so one 32-bit index register serves
+// every resource, whatever the record size), and an index at or beyond
+// `count` returns zero without a memory access.
+typedef int rsrc_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+__device__ f32x2_t struct_load_f32x2(rsrc_t r, int index, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.buffer.load.v2f32");
+__device__ f64x2_t struct_load_f64x2(rsrc_t r, int index, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.buffer.load.v2f64");
+
+// gfx9 resource word 3: 32-bit data format, no swizzle, no thread-id offset.
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, int stride, unsigned count)
+{
+    const unsigned long long a = (unsigned long long)base;
+    rsrc_t r;
+    r.x = __builtin_amdgcn_readfirstlane((int)(unsigned)a);
+    r.y = __builtin_amdgcn_readfirstlane(
+        (int)(((unsigned)(a >> 32) & 0xffffu) | ((unsigned)stride << 16)));
+    r.z = __builtin_amdgcn_readfirstlane((int)count);
+    r.w = kRsrcWord3;
+    return r;
+}
+
+template <typename T> __device__ __forceinline__ cplx_t<T> gather(rsrc_t r, int index);
+template <> __device__ __forceinline__ float2 gather<float>(rsrc_t r, int index)
+{
+    const f32x2_t v = struct_load_f32x2(r, index, 0, 0, 0);
+    return make_float2(v.x, v.y);
+}
+template <> __device__ __forceinline__ double2 gather<double>(rsrc_t r, int index)
+{
+    const f64x2_t v = struct_load_f64x2(r, index, 0, 0, 0);
+    return make_double2(v.x, v.y);
+}
+
 __device__ __forceinline__ void chunk_of_block(const Table *__restrict__ tab, int &begin, int &end)
 {
     const int nb = gridDim.x;

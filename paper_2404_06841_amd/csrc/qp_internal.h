@@ -49,6 +49,8 @@ struct Table {
     int nb_mv;                // grid of the stiffness product (multiple of 8 when >= 8)
     int item_tiles;           // plane tiles: consecutive tiles of a unit per wave item
     int xcd_front;            // plane tiles: each XCD sweeps its own contiguous eighth
+    int wide;                 // plane tiles: 64-bit neighbour addresses, one right-hand
+                              // side per launch (else 32-bit record indices)
     uint64_t slotmask[64];    // tile_s > 1: per tile of a plane, bit r when sorted mode
                               // r's neighbour leaves [0, N) or K_N in axis n-2 for some line
 };
@@ -71,9 +73,13 @@ struct alignas(16) UnitRec {
     T apm[DT];  // a (P m - N sum_{t < n-2} c_t p_t), c_t the wrap of axis t
     T a;        // Re(Ahat_m) for real coefficients, else 1; 0 for padding
     T cr, ci;   // Ahat_m (complex multiply-add); 0 for padding
-    int lb;     // element offset of the neighbour's row over axes < n-2, minus m_{n-2} N
+    int lb;     // element offset of the neighbour's row over axes < n-2, minus m_{n-2} N;
+                // kNoNeighbour for padding
     int mslot;  // m_{n-2}
 };
+// Row offset of a padding record: adding any in-plane offset (< 2^30) leaves
+// an index whose unsigned value exceeds every vector length (< 2^31).
+constexpr int kNoNeighbour = -(1 << 30);
 // bytes reserved per record (at least sizeof(UnitRec<T, kMaxD>)), by Precision
 constexpr size_t kUnitRecBytes[2] = {64, 48};
 

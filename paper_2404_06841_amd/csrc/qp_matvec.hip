@@ -448,7 +448,10 @@ __global__ __launch_bounds__(kBlock) void k_unit_records(const Table *__restrict
         R.cr = (r >= g) ? (T)0 : (T)M.c[0];
         R.ci = (r >= g) ? (T)0 : (T)M.c[1];
         R.mslot = M.mt[n - 2];
-        R.lb = lb - R.mslot * N;
+        // padding records gather from an index beyond every vector (as an
+        // unsigned record index), which the buffer loads return as zero; the
+        // 64-bit gathers load the zero mode's neighbour with weight 0 instead
+        R.lb = (r >= g && !tab->wide) ? kNoNeighbour : lb - R.mslot * N;
         out[e] = R;
         if (r == 0) {
             for (int l = 0; l < DT; ++l) {
@@ -518,7 +521,7 @@ __device__ __forceinline__ void wave_sync()
 // Work items of the plane kernel: (unit, up to tab->item_tiles consecutive
 // tiles); a wave copies the unit's records to its LDS once per item.
 
-template <typename T, int DT, int EPI, bool REAL, int KR>
+template <typename T, int DT, int EPI, bool REAL, int KR, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict__ tab,
                                                          const ModeRec *__restrict__ recs,
                                                          const UnitRec<T, DT> *__restrict__ urec,
@@ -541,6 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
         nact += act[k] ? 1 : 0;
     }
     if (nact == 0) return;
+    static_assert(!WIDE || KR == 1, "64-bit gathers serve one right-hand side");
     // neighbour loads in flight per chunk: about Inflight<T> over all right-hand sides
     constexpr int KC = (Inflight<T>::v / KR >= 8) ? (Inflight<T>::v / KR) / 4 * 4 : 4;
     using Rec = UnitRec<T, DT>;
@@ -579,6 +583,12 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
 #pragma unroll
     for (int k = 0; k < KR; ++k) inv_unit[k] = (EPI == EPI_RESID) ? st[k].inv_unit : 1.0;
     const T NT = (T)N;
+    // one gather resource per right-hand side; a right-hand side not served
+    // by this launch has no records, so its gathers read zero without traffic
+    rsrc_t xr[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+        xr[k] = make_rsrc(x + k * D, (int)sizeof(cplx_t<T>), act[k] ? (unsigned)D : 0u);
 
     // items in XCD-front order: each XCD owns a contiguous eighth, its waves
     // sweep it together
@@ -668,14 +678,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
                         wv += Q.a * cs * cqs;
                     }
 #pragma unroll
-                    for (int k = 0; k < KR; ++k) {
-                        if (act[k]) {
-                            u[m][k] = x[k * D + (unsigned)idx];
-                        } else {
-                            u[m][k].x = 0;
-                            u[m][k].y = 0;
-                        }
-                    }
+                    for (int k = 0; k < KR; ++k)
+                        u[m][k] = WIDE ? x[(unsigned)idx] : gather<T>(xr[k], idx);
                     w[m] = wv;
                 }
 #pragma unroll
@@ -726,6 +730,30 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
         *exec = nact;
 }
 
+template <typename T, int EPI, bool REAL, int KR, bool WIDE>
+hipError_t launch_plane(const Table &ht, size_t lds, const Table *tab, const ModeRec *recs,
+                        const void *urec, const T *Pu, const cplx_t<T> *X, void *y,
+                        const double2 *Fv, const float *M32, double *part, State *st, int *exec,
+                        hipStream_t s)
+{
+    const dim3 grid(ht.nb_mv), block(kBlock);
+    const size_t gp = (size_t)((ht.g + 3) & ~3);
+    switch (ht.d) {
+#define QP_CASE(DD)                                                                              \
+    case DD:                                                                                      \
+        hipLaunchKernelGGL((k_matvec_plane<T, DD, EPI, REAL, KR, WIDE>), grid, block,            \
+                           lds + kWaves * gp * sizeof(UnitRec<T, DD>), s, tab, recs,             \
+                           static_cast<const UnitRec<T, DD> *>(urec), Pu, X, y, Fv, M32, part, st, \
+                           exec);                                                                 \
+        break;
+        QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
+#undef QP_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int EPI, bool REAL, int KR>
 hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, const void *urec,
                     const void *upku, const void *x, void *y, const double *f, const float *M32,
@@ -738,21 +766,13 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, cons
     auto Pu = static_cast<const T *>(upku);
     if (ht.tile_s > 1) {
         if (!urec || !upku) return hipErrorInvalidValue;
-        const size_t gp = (size_t)((ht.g + 3) & ~3);
-        switch (ht.d) {
-#define QP_CASE(DD)                                                                              \
-    case DD:                                                                                      \
-        hipLaunchKernelGGL((k_matvec_plane<T, DD, EPI, REAL, KR>), grid, block,                  \
-                           lds + kWaves * gp * sizeof(UnitRec<T, DD>), s, tab, recs,             \
-                           static_cast<const UnitRec<T, DD> *>(urec), Pu, X, y, Fv, M32, part, st, \
-                           exec);                                                                 \
-        break;
-            QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
-#undef QP_CASE
-        default:
-            return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
+        if (!ht.wide)
+            return launch_plane<T, EPI, REAL, KR, false>(ht, lds, tab, recs, urec, Pu, X, y, Fv,
+                                                        M32, part, st, exec, s);
+        if constexpr (KR == 1)
+            return launch_plane<T, EPI, REAL, 1, true>(ht, lds, tab, recs, urec, Pu, X, y, Fv, M32,
+                                                      part, st, exec, s);
+        return hipErrorInvalidValue;  // 64-bit gathers serve one right-hand side per launch
     }
     if (KR != 1) return hipErrorInvalidValue;  // line tiles serve one right-hand side
     switch (ht.d) {

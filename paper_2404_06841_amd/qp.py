@@ -52,7 +52,8 @@ class qp_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("precond", C.c_int), ("maxit", C.c_int),
                 ("inner_tol", C.c_double), ("poll_every", C.c_int),
                 ("profile", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t), ("graphs", C.c_int)]
+                ("workspace_bytes", C.c_size_t), ("graphs", C.c_int),
+                ("gather64", C.c_int)]
 
 
 class qp_solve_info(C.Structure):
@@ -190,7 +191,7 @@ class Problem:
     def __init__(self, prob, precision: str = "fp64", precond: str = "paper",
                  maxit: int = 10000, inner_tol: float = 1e-4,
                  profile: bool = False, stream=None, poll_every: int = 0,
-                 graphs: bool = True):
+                 graphs: bool = True, gather64: bool = False):
         import torch
         self.d, self.n, self.N = int(prob.d), int(prob.n), int(prob.N)
         self.D = self.N ** self.n
@@ -204,6 +205,7 @@ class Problem:
         opt.profile = 1 if profile else 0
         opt.poll_every = int(poll_every)
         opt.graphs = 1 if graphs else 0
+        opt.gather64 = 1 if gather64 else 0
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         nbytes = qp_workspace_bytes(self.d, self.n, self.N, self.g)

@@ -35,6 +35,7 @@ def test_default_options_and_strings():
     assert o.precision == qp.QP_PREC_FP64 and o.precond == qp.QP_PRECOND_PAPER
     assert o.maxit == 10000 and o.inner_tol == pytest.approx(1e-4) and o.poll_every == 0
     assert o.graphs == 1
+    assert o.gather64 == 0
     assert o.stream is None and o.workspace is None
     for s in range(0, -8, -1):
         assert qp.qp_strerror(s)

@@ -67,6 +67,17 @@ def test_matvec_equals_dense_alg1(prob):
     np.testing.assert_allclose(y, Q @ u, rtol=0, atol=1e-12 * np.abs(Q @ u).max())
 
 
+@pytest.mark.parametrize("prob", SMALL, ids=lambda p: f"{p.name}_N{p.N}")
+def test_matvec_rows_equal_dense_rows(prob):
+    # the row-sampled product used for vectors too large for a CPU product
+    Q = ind.dense_Q(prob)
+    u = W.random_vector(prob.D, seed=13)
+    rows = np.random.default_rng(0).choice(prob.D, size=min(prob.D, 17), replace=False)
+    y = oracle.matvec_rows(prob, u, rows)
+    ref = Q @ u
+    np.testing.assert_allclose(y, ref[rows], rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("prob", SMALL + [W.eightfold_random(12, 1), W.eightfold(10), W.icosahedral(4)],
                          ids=lambda p: f"{p.name}_N{p.N}")
 def test_matvec_equals_pseudospectral(prob):
