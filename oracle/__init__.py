@@ -7,7 +7,10 @@ library.  The arithmetic lives in ``qp_oracle.c`` (compiled by ``build.py``);
 this module only marshals numpy arrays.
 
 A problem is any object with attributes d, n, N, P (d x n), modes (g x n int)
-and coef (g complex), e.g. the inputs made by the workload generator.
+and coef (g complex), e.g. the inputs made by the workload generator; an
+optional attribute coefs (d x g complex, not None) makes the coefficient the
+diagonal matrix diag(a_1..a_d) of App. D, row l holding a_l's Fourier
+coefficients on the shared mode list.
 """
 from __future__ import annotations
 
@@ -27,7 +30,7 @@ PCG_OK, PCG_NOCONV, PCG_NOTSPD = 0, 1, 2
 class _Problem(C.Structure):
     _fields_ = [("d", C.c_int), ("n", C.c_int), ("N", C.c_int), ("g", C.c_int),
                 ("P", C.POINTER(C.c_double)), ("modes", C.POINTER(C.c_int)),
-                ("coef", C.POINTER(C.c_double))]
+                ("coef", C.POINTER(C.c_double)), ("coefs", C.POINTER(C.c_double))]
 
 
 def _load():
@@ -77,12 +80,23 @@ class _Bound:
             raise ValueError("oracle supports n <= 8")
         self.P = np.ascontiguousarray(prob.P, dtype=np.float64).reshape(prob.d, prob.n)
         self.modes = np.ascontiguousarray(prob.modes, dtype=np.int32).reshape(-1, prob.n)
-        coef = np.ascontiguousarray(prob.coef, dtype=np.complex128).reshape(-1)
+        g = int(self.modes.shape[0])
+        coefs = getattr(prob, "coefs", None)
+        if coefs is not None:
+            # diagonal coefficient diag(a_1..a_d): row l holds a_l's Ahat per mode
+            cs = np.ascontiguousarray(coefs, dtype=np.complex128).reshape(int(prob.d), g)
+            self.coefs = cs.reshape(-1).view(np.float64).copy()
+            coef = cs[0]
+        else:
+            self.coefs = None
+            coef = np.ascontiguousarray(prob.coef, dtype=np.complex128).reshape(-1)
         self.coef = coef.view(np.float64).copy()
-        self.struct = _Problem(int(prob.d), int(prob.n), int(prob.N), int(self.modes.shape[0]),
+        self.struct = _Problem(int(prob.d), int(prob.n), int(prob.N), g,
                                self.P.ctypes.data_as(C.POINTER(C.c_double)),
                                self.modes.ctypes.data_as(C.POINTER(C.c_int)),
-                               self.coef.ctypes.data_as(C.POINTER(C.c_double)))
+                               self.coef.ctypes.data_as(C.POINTER(C.c_double)),
+                               None if self.coefs is None
+                               else self.coefs.ctypes.data_as(C.POINTER(C.c_double)))
         self.D = int(prob.N) ** int(prob.n)
 
     @property

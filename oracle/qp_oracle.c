@@ -39,6 +39,9 @@ typedef struct {
     const double *P;      /* d x n projection matrix, row-major          */
     const int *modes;     /* g x n integer modes m                       */
     const double *coef;   /* g complex coefficients Ahat_m (re, im)      */
+    const double *coefs;  /* NULL (scalar coefficient a), or a diagonal
+                             coefficient diag(a_1..a_d) (App. D): d x g
+                             complex, Ahat of a_l at mode r at (l g + r)   */
 } qo_problem;
 
 /* D = N^n */
@@ -104,16 +107,39 @@ static double complex coef_at(const qo_problem *p, int r)
     return p->coef[2 * r] + I * p->coef[2 * r + 1];
 }
 
-/* Ahat for the mode congruent to `k` mod N, or 0 when no mode is. */
-static double complex coef_of_class(const qo_problem *p, const int *k)
+/* Ahat of the l-th diagonal entry a_l at mode r (the scalar a when there is
+ * no diagonal coefficient). */
+static double complex coef_l(const qo_problem *p, int r, int l)
+{
+    if (!p->coefs) return coef_at(p, r);
+    const double *c = p->coefs + 2 * ((long)l * p->g + r);
+    return c[0] + I * c[1];
+}
+
+/* Index of the mode congruent to `k` mod N, or -1 when no mode is. */
+static int mode_of_class(const qo_problem *p, const int *k)
 {
     for (int r = 0; r < p->g; ++r) {
         int same = 1;
         for (int t = 0; t < p->n; ++t)
             if (qo_rep(p->N, (long)k[t] - p->modes[r * p->n + t]) != 0) { same = 0; break; }
-        if (same) return coef_at(p, r);
+        if (same) return r;
     }
-    return 0.0;
+    return -1;
+}
+
+/* Ahat for the mode congruent to `k` mod N, or 0 when no mode is. */
+static double complex coef_of_class(const qo_problem *p, const int *k)
+{
+    const int r = mode_of_class(p, k);
+    return (r < 0) ? 0.0 : coef_at(p, r);
+}
+
+/* The same for the diagonal entry a_l. */
+static double complex coef_of_class_l(const qo_problem *p, const int *k, int l)
+{
+    const int r = mode_of_class(p, k);
+    return (r < 0) ? 0.0 : coef_l(p, r, l);
 }
 
 static int is_zero(int n, const int *k)
@@ -139,8 +165,15 @@ static double complex matvec_row(const qo_problem *p, const double complex *u, l
         for (int t = 0; t < p->n; ++t)
             ku[t] = qo_rep(p->N, (long)kv[t] - p->modes[r * p->n + t]);
         proj(p, ku, pku);
-        const double w = dotd(p->d, pkv, pku);
-        acc += coef_at(p, r) * w * u[qo_index(p->n, p->N, ku)];
+        const double complex uj = u[qo_index(p->n, p->N, ku)];
+        if (!p->coefs) {
+            const double w = dotd(p->d, pkv, pku);
+            acc += coef_at(p, r) * w * uj;
+        } else {
+            /* diagonal coefficient (App. D): Q = sum_l A^l o W^l with
+             * W^l = (P k_V)_l (P k_U)_l */
+            for (int l = 0; l < p->d; ++l) acc += coef_l(p, r, l) * (pkv[l] * pku[l]) * uj;
+        }
     }
     return acc;
 }
@@ -176,6 +209,8 @@ void qo_precond(const qo_problem *p, int kind, double *M)
     const long D = qo_size(p->n, p->N);
     int zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const double a0 = creal(coef_of_class(p, zero));
+    double a0l[8];  /* diagonal coefficient: q_jj = sum_l Ahat^l_0 (P k_j)_l^2 */
+    for (int l = 0; l < p->d; ++l) a0l[l] = creal(coef_of_class_l(p, zero, l));
 #pragma omp parallel for schedule(static)
     for (long j = 0; j < D; ++j) {
         int kj[8], ki[8];
@@ -183,15 +218,22 @@ void qo_precond(const qo_problem *p, int kind, double *M)
         qo_multi_index(p->n, p->N, j, kj);
         if (is_zero(p->n, kj)) { M[j] = 0.0; continue; }
         proj(p, kj, pkj);
-        const double qjj = a0 * dotd(p->d, pkj, pkj);
+        double qjj = a0 * dotd(p->d, pkj, pkj);
+        if (p->coefs) {
+            qjj = 0.0;
+            for (int l = 0; l < p->d; ++l) qjj += a0l[l] * pkj[l] * pkj[l];
+        }
         if (kind == 1) { M[j] = (qjj != 0.0) ? 1.0 / qjj : 0.0; continue; }
         double colnorm2 = 0.0;
         for (int r = 0; r < p->g; ++r) {
             for (int t = 0; t < p->n; ++t)
                 ki[t] = qo_rep(p->N, (long)kj[t] + p->modes[r * p->n + t]);
             proj(p, ki, pki);
-            const double w = dotd(p->d, pki, pkj);
-            const double complex q = coef_at(p, r) * w;
+            double complex q = coef_at(p, r) * dotd(p->d, pki, pkj);
+            if (p->coefs) {
+                q = 0.0;
+                for (int l = 0; l < p->d; ++l) q += coef_l(p, r, l) * (pki[l] * pkj[l]);
+            }
             colnorm2 += creal(q) * creal(q) + cimag(q) * cimag(q);
         }
         M[j] = (colnorm2 != 0.0) ? qjj / colnorm2 : 0.0;
@@ -266,7 +308,9 @@ done:
 /* Right-hand side of the corrector equation -div(a(e_j + grad chi)) = 0, i.e.
  * -div(a grad chi) = d a / d x_j (Sec. 5.2, eq. corrector; App. D, f_1 = d_x1 alpha).
  * The x_j-derivative of exp(i (P k).x) is i (P k)_j exp(i (P k).x), so
- * F_k = i (P k)_j Ahat_k on the coefficient's modes and 0 elsewhere. */
+ * F_k = i (P k)_j Ahat_k on the coefficient's modes and 0 elsewhere.  For a
+ * diagonal coefficient the source is d a_j / d x_j (App. D: f_1 = d_x1 alpha,
+ * f_2 = d_x2 beta), so Ahat is that of a_j. */
 void qo_corrector_rhs(const qo_problem *p, int j, double *F_)
 {
     double complex *F = (double complex *)F_;
@@ -276,7 +320,7 @@ void qo_corrector_rhs(const qo_problem *p, int j, double *F_)
     for (int r = 0; r < p->g; ++r) {
         const int *m = p->modes + r * p->n;
         proj(p, m, pk);
-        F[qo_index(p->n, p->N, m)] += I * pk[j] * coef_at(p, r);
+        F[qo_index(p->n, p->N, m)] += I * pk[j] * coef_l(p, r, j);
     }
 }
 
@@ -287,13 +331,15 @@ void qo_corrector_rhs(const qo_problem *p, int j, double *F_)
  * (Sec. 2.3), the product of the two trigonometric polynomials keeps the
  * frequency pairs whose sum is 0 mod N:
  *   mean_N{a d_i chi} = sum_{k in K_N^n} Ahat_{class(-k)} * i (P k)_i * chi_k.
+ * For a diagonal coefficient e_i . A (e_j + grad chi_j) = a_i (delta_ij +
+ * d_{x_i} chi_j) (App. D, eqs. homcoefficient11-22), so Ahat is that of a_i.
  * Returns the real part; *imag receives the imaginary part (0 for real a). */
 double qo_astar_flux(const qo_problem *p, int i_, int j_, const double *chi_, double *imag)
 {
     const double complex *chi = (const double complex *)chi_;
     const long D = qo_size(p->n, p->N);
     int zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double complex acc = (i_ == j_) ? coef_of_class(p, zero) : 0.0;
+    double complex acc = (i_ == j_) ? coef_of_class_l(p, zero, i_) : 0.0;
     double re = 0.0, im = 0.0;
 #pragma omp parallel for schedule(static) reduction(+ : re, im)
     for (long idx = 0; idx < D; ++idx) {
@@ -301,7 +347,7 @@ double qo_astar_flux(const qo_problem *p, int i_, int j_, const double *chi_, do
         double pk[8];
         qo_multi_index(p->n, p->N, idx, k);
         for (int t = 0; t < p->n; ++t) mk[t] = -k[t];
-        const double complex am = coef_of_class(p, mk);
+        const double complex am = coef_of_class_l(p, mk, i_);
         if (am == 0.0) continue;
         proj(p, k, pk);
         const double complex v = am * I * pk[i_] * chi[idx];
@@ -315,7 +361,8 @@ double qo_astar_flux(const qo_problem *p, int i_, int j_, const double *chi_, do
 
 /* Homogenized coefficient, energy form: A*_ij = Ahat_0 delta_ij - chi_i^H Q chi_j
  * (equal to the flux form at the exact discrete corrector since Q chi_j = F_j
- * and Q is Hermitian; symmetric by construction). */
+ * and Q is Hermitian; symmetric by construction).  For a diagonal coefficient
+ * the first term is the mean of A, Ahat^i_0 delta_ij. */
 double qo_astar_energy(const qo_problem *p, int i_, int j_, const double *chi_i_,
                        const double *chi_j_, double *imag)
 {
@@ -325,13 +372,14 @@ double qo_astar_energy(const qo_problem *p, int i_, int j_, const double *chi_i_
     qo_matvec(p, chi_j_, (double *)q);
     const double complex e = inner(D, q, (const double complex *)chi_i_); /* chi_i^H Q chi_j */
     free(q);
-    const double complex a = ((i_ == j_) ? coef_of_class(p, zero) : 0.0) - e;
+    const double complex a = ((i_ == j_) ? coef_of_class_l(p, zero, i_) : 0.0) - e;
     if (imag) *imag = cimag(a);
     return creal(a);
 }
 
 /* Minimum and maximum of A(y) = sum_m Ahat_m exp(i m.y) over the collocation
- * grid y_j = 2 pi j / N (Sec. 2.3); used for the ellipticity check. */
+ * grid y_j = 2 pi j / N (Sec. 2.3); used for the ellipticity check.  For a
+ * diagonal coefficient: the extrema over every entry a_l. */
 void qo_coef_extrema(const qo_problem *p, double *amin, double *amax)
 {
     const long D = qo_size(p->n, p->N);
@@ -344,15 +392,18 @@ void qo_coef_extrema(const qo_problem *p, double *amin, double *amax)
             y[t] = 2.0 * M_PI * (double)(rest % p->N) / (double)p->N;
             rest /= p->N;
         }
-        double complex a = 0.0;
-        for (int r = 0; r < p->g; ++r) {
-            double ph = 0.0;
-            for (int t = 0; t < p->n; ++t) ph += p->modes[r * p->n + t] * y[t];
-            a += coef_at(p, r) * cexp(I * ph);
+        const int nl = p->coefs ? p->d : 1;
+        for (int l = 0; l < nl; ++l) {
+            double complex a = 0.0;
+            for (int r = 0; r < p->g; ++r) {
+                double ph = 0.0;
+                for (int t = 0; t < p->n; ++t) ph += p->modes[r * p->n + t] * y[t];
+                a += coef_l(p, r, l) * cexp(I * ph);
+            }
+            const double v = creal(a);
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
         }
-        const double v = creal(a);
-        if (v < lo) lo = v;
-        if (v > hi) hi = v;
     }
     *amin = lo;
     *amax = hi;

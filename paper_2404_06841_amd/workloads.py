@@ -12,6 +12,9 @@ Conventions (Sec. 2.1 and Sec. 3.1 of the paper):
   the n-torus, A(y) = sum_m Ahat_m exp(i m.y).  A problem is given by P (d x n,
   row-major), the integer mode list m (g x n) and the complex coefficients
   Ahat_m (g,).  A real coefficient needs Ahat_{-m} = conj(Ahat_m).
+* A diagonal coefficient diag(a_1, ..., a_d) (App. D) shares one mode list;
+  ``coefs`` (d x g) then holds a_l's Ahat per mode (0 where a_l has no such
+  mode), and ``coef`` repeats row 0.
 * Vectors of unknowns have D = N^n complex entries in the tensor-to-vector
   order of Sec. 3.1.2: row-major, k_1 slowest, each index stored as k mod N
   (FFT order).
@@ -46,6 +49,7 @@ class Problem:
     modes: np.ndarray  # (g, n) int32
     coef: np.ndarray  # (g,) complex128
     meta: dict = field(default_factory=dict)
+    coefs: np.ndarray | None = None  # (d, g) complex128: diagonal coefficient
 
     @property
     def D(self) -> int:
@@ -57,7 +61,8 @@ class Problem:
 
     def with_N(self, N: int) -> "Problem":
         return Problem(self.name, self.d, self.n, int(N), self.P.copy(),
-                       self.modes.copy(), self.coef.copy(), dict(self.meta))
+                       self.modes.copy(), self.coef.copy(), dict(self.meta),
+                       None if self.coefs is None else self.coefs.copy())
 
 
 def _modes_from_dict(n: int, table: dict) -> tuple[np.ndarray, np.ndarray]:
@@ -239,6 +244,78 @@ def anisotropic_paper_example():
           _unit(n, 2, 2): -0.25 + 0j, _unit(n, 2, -2): -0.25 + 0j,
           _unit(n, 3, 2): -0.25 + 0j, _unit(n, 3, -2): -0.25 + 0j}
     return P, _modes_from_dict(n, ta), _modes_from_dict(n, tb)
+
+
+def diagonal(name: str, d: int, n: int, N: int, P: np.ndarray, fields, meta=None) -> Problem:
+    """Diagonal coefficient diag(a_1..a_d) from d (modes, coef) fields with a
+    common P: the union of the modes, coefs[l] = a_l's Ahat on it."""
+    if len(fields) != d:
+        raise ValueError("one field per physical axis")
+    tables = []
+    for modes, coef in fields:
+        tables.append({tuple(int(x) for x in m): complex(c) for m, c in zip(modes, coef)})
+    keys = sorted(set().union(*[t.keys() for t in tables]))
+    modes = np.array(keys, dtype=np.int32).reshape(len(keys), n)
+    coefs = np.array([[t.get(k, 0j) for k in keys] for t in tables], dtype=np.complex128)
+    return Problem(name, int(d), int(n), int(N), np.asarray(P, dtype=np.float64).reshape(d, n),
+                   modes, coefs[0].copy(), dict(meta or {}), coefs)
+
+
+def paper_homogenization(N: int = 8) -> Problem:
+    """The homogenization example of Sec. 5.2 / App. D: A = diag(alpha, beta)."""
+    P, fa, fb = anisotropic_paper_example()
+    return diagonal("paper_homogenization", 2, 4, N, P, [fa, fb])
+
+
+def laminate(N: int = 8) -> Problem:
+    """A = diag(a_1(x_1), a_2(x_1)) on the P of the homogenization example:
+    a_1 = 6 + cos(2 pi x_1) + cos(2 pi sqrt2 x_1) / 2 -> parent 6 + cos y3 + cos(y4)/2,
+    a_2 = 5 + sin(2 pi x_1) - cos(2 pi sqrt2 x_1) / 2 -> parent 5 + sin y3 - cos(y4)/2
+    (a_2 has imaginary Fourier coefficients)."""
+    P, _, _ = anisotropic_paper_example()
+    n = 4
+    t1 = {tuple([0] * n): 6.0 + 0j,
+          _unit(n, 2, 1): 0.5 + 0j, _unit(n, 2, -1): 0.5 + 0j,
+          _unit(n, 3, 1): 0.25 + 0j, _unit(n, 3, -1): 0.25 + 0j}
+    t2 = {tuple([0] * n): 5.0 + 0j,
+          _unit(n, 2, 1): -0.5j, _unit(n, 2, -1): 0.5j,
+          _unit(n, 3, 1): -0.25 + 0j, _unit(n, 3, -1): -0.25 + 0j}
+    return diagonal("laminate", 2, 4, N, P, [_modes_from_dict(n, t1), _modes_from_dict(n, t2)])
+
+
+def eightfold_diagonal(N: int = 16, instance: int = 0, pairs: int = 6,
+                       complex_phase: bool = False) -> Problem:
+    """Eightfold P with an independent seeded random field per diagonal entry
+    (as eightfold_random, means 3 and 4).  complex_phase: each +-pair's
+    coefficients get a seeded phase, Ahat_{+-m} = (c/2) exp(+-i phi)."""
+    rng = np.random.default_rng(BASE_SEED + 1000 + int(instance))
+    fields = []
+    for mean in (3.0, 4.0):
+        modes, coef, _ = random_modes(4, pairs, 2, rng, 0.4, 2.5, mean)
+        if complex_phase:
+            coef = coef.copy()
+            table = {tuple(int(x) for x in m): i for i, m in enumerate(modes)}
+            for i, m in enumerate(modes):
+                key = tuple(int(x) for x in m)
+                neg = tuple(-x for x in key)
+                if any(key) and key > neg:
+                    phi = rng.uniform(0.0, 2.0 * np.pi)
+                    coef[i] *= np.exp(1j * phi)
+                    coef[table[neg]] *= np.exp(-1j * phi)
+        fields.append((modes, coef))
+    return diagonal("eightfold_diagonal", 2, 4, N, eightfold_P(), fields,
+                    {"instance": int(instance), "complex_phase": bool(complex_phase)})
+
+
+def periodic_2d_diagonal(N: int = 40) -> Problem:
+    """d = n = 2 (periodic), A = diag(4 + cos y1 + cos y2 / 2, 3 + sin y2 / 2)."""
+    n = 2
+    P = np.array([[1.0, 0.0], [0.0, 1.0]], dtype=np.float64)
+    t1 = {(0, 0): 4.0 + 0j, (1, 0): 0.5 + 0j, (-1, 0): 0.5 + 0j,
+          (0, 1): 0.25 + 0j, (0, -1): 0.25 + 0j}
+    t2 = {(0, 0): 3.0 + 0j, (0, 1): -0.25j, (0, -1): 0.25j}
+    return diagonal("periodic_2d_diagonal", 2, n, N, P,
+                    [_modes_from_dict(n, t1), _modes_from_dict(n, t2)])
 
 
 # --------------------------------------------------------------------------

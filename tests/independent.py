@@ -71,6 +71,59 @@ def fft_apply_Q(prob, u) -> np.ndarray:
     return y
 
 
+# ---- diagonal coefficient A = diag(a_1..a_d) (App. D) ----
+
+def coef_table_l(prob, l: int) -> dict:
+    """a_l's Fourier coefficients as {mode: Ahat} (the scalar a when the
+    problem has no diagonal coefficient)."""
+    coefs = getattr(prob, "coefs", None)
+    row = prob.coef if coefs is None else np.asarray(coefs)[l]
+    return {tuple(int(x) for x in m): complex(c) for m, c in zip(prob.modes, row) if c != 0}
+
+
+def dense_Q_diagonal(prob) -> np.ndarray:
+    """Q = sum_l A^l o W^l assembled entry by entry (App. D): for the pair
+    (k_V, k_U), A^l_ij = Ahat of a_l at (k_V - k_U) mod N and
+    W^l_ij = (P k_V)_l (P k_U)_l."""
+    n, N, d = prob.n, prob.N, prob.d
+    K = signed_indices(n, N)
+    PK = K @ np.asarray(prob.P, dtype=np.float64).T
+    D = K.shape[0]
+    weights = N ** np.arange(n - 1, -1, -1)
+    Q = np.zeros((D, D), dtype=np.complex128)
+    for l in range(d):
+        ahat = np.zeros(D, dtype=np.complex128)
+        for m, c in coef_table_l(prob, l).items():
+            ahat[int(np.mod(np.array(m), N) @ weights)] += c
+        for i in range(D):
+            kA = np.mod(K[i][None, :] - K, N)
+            Q[i, :] += ahat[kA @ weights] * (PK[:, l] * PK[i, l])
+    return Q
+
+
+def coefficient_on_grid_l(prob, l: int) -> np.ndarray:
+    """a_l(y_j) on the collocation grid T_N^n, shape (N,)*n."""
+    n, N = prob.n, prob.N
+    spec = np.zeros((N,) * n, dtype=np.complex128)
+    for m, c in coef_table_l(prob, l).items():
+        spec[tuple(int(x) % N for x in m)] += c
+    return np.fft.ifftn(spec) * N ** n
+
+
+def fft_apply_Q_diagonal(prob, u) -> np.ndarray:
+    """Q u = sum_l (P k)_l DFT[a_l(y) IDFT[(P k)_l u]] (discrete orthogonality,
+    one coefficient per component of the lifted gradient)."""
+    n, N, d = prob.n, prob.N, prob.d
+    K = signed_indices(n, N).astype(np.float64)
+    PK = K @ np.asarray(prob.P, dtype=np.float64).T
+    y = np.zeros(N ** n, dtype=np.complex128)
+    for l in range(d):
+        a = coefficient_on_grid_l(prob, l)
+        g = np.fft.ifftn((PK[:, l] * u).reshape((N,) * n)) * N ** n
+        y += PK[:, l] * (np.fft.fftn(a * g) / N ** n).reshape(-1)
+    return y
+
+
 def rayleigh_quotient(prob, u) -> float:
     """(1/D) sum_y a(y) |sum_j (P j) u_j e^{i j.y}|^2."""
     n, N, d = prob.n, prob.N, prob.d
