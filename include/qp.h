@@ -149,6 +149,28 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g,
                     const int32_t *modes, const double *coef, int N,
                     const qp_options *opt);
 
+/*
+ * Create a problem with a diagonal coefficient A = diag(a_1, ..., a_d)
+ * (App. D): every a_l is a real quasiperiodic function with the same P, and
+ *   Q = sum_l A^l o W^l,  A^l_{k_V k_U} = Ahat of a_l at k_V -_N k_U,
+ *   W^l_{k_V k_U} = (P k_V)_l (P k_U)_l.
+ * The d entries share one mode list:
+ *   modes   g x n int32, host, as for qp_create (the union of the entries'
+ *           modes; a mode absent from a_l has coefficient 0 there)
+ *   coefs   d x g complex (re, im) pairs, host: a_l's Ahat at mode r is
+ *           element l * g + r
+ * Every other argument, and every later call, is as for a problem from
+ * qp_create; the corrector source of axis j is d a_j / d x_j
+ * (F_k = i (P k)_j Ahat of a_j at k) and A*_ij = mean{a_i (delta_ij +
+ * d_{x_i} chi_j)} (App. D, eqs. homcoefficient11-22).  Each a_l must pass
+ * qp_create's checks (real field, positive Ahat_0); QP_ENOTELLIPTIC if the
+ * minimum over the collocation grid of any a_l is below -1e-12 max|a|.
+ * QP_EINVAL for a null coefs.
+ */
+qp_status qp_create_diag(qp_problem **out, int d, int n, const double *P, int g,
+                         const int32_t *modes, const double *coefs, int N,
+                         const qp_options *opt);
+
 /* Release the problem and everything it owns.  NULL is ignored. */
 void qp_destroy(qp_problem *p);
 

@@ -229,8 +229,9 @@ qp_status check_args(int d, int n, const double *P, int g, const int32_t *modes,
     return QP_OK;
 }
 
+// coefs: null for a scalar coefficient, else d x g complex (a_l's Ahat per mode)
 void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *modes,
-                 const double *coef, int N)
+                 const double *coef, const double *coefs, int N)
 {
     std::memset(&T, 0, sizeof(T));
     T.d = d;
@@ -268,6 +269,11 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
         T.coef[r][0] = coef[2 * r];
         T.coef[r][1] = coef[2 * r + 1];
         for (int l = 0; l < d; ++l) {
+            const double *c = coefs ? coefs + 2 * ((size_t)l * g + r) : coef + 2 * r;
+            T.coefl[r][l][0] = c[0];
+            T.coefl[r][l][1] = c[1];
+        }
+        for (int l = 0; l < d; ++l) {
             double v = 0.0;
             for (int t = 0; t < n; ++t) v += P[l * n + t] * (double)modes[r * n + t];
             T.Pm[r][l] = v;
@@ -275,11 +281,14 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
         if (z) {
             T.zero_mode = r;
             T.a0 = coef[2 * r];
+            for (int l = 0; l < d; ++l) T.a0l[l] = T.coefl[r][l][0];
         }
     }
+    T.aniso = coefs ? 1 : 0;
     T.real_coef = 1;
     for (int r = 0; r < g; ++r)
-        if (coef[2 * r + 1] != 0.0) T.real_coef = 0;
+        for (int l = 0; l < d; ++l)
+            if (T.coefl[r][l][1] != 0.0) T.real_coef = 0;
 
     // Tiled stiffness product: modes sorted by their last component (stable),
     // so that consecutive gathers of a tile read neighbouring columns.
@@ -364,6 +373,10 @@ void build_mode_records(const Table &T, std::vector<qp::ModeRec> &out)
         }
         R.c[0] = T.coef[r][0];
         R.c[1] = T.coef[r][1];
+        for (int l = 0; l < T.d; ++l) {
+            R.cl[l][0] = T.coefl[r][l][0];
+            R.cl[l][1] = T.coefl[r][l][1];
+        }
         for (int t = 0; t < T.n; ++t) R.mt[t] = (short)T.modes[r][t];
     }
 }
@@ -897,13 +910,24 @@ size_t qp_workspace_bytes(int d, int n, int N, int g)
     return make_layout(d, n, N, D, g).total;
 }
 
-qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, const int32_t *modes,
-                    const double *coef, int N, const qp_options *opt)
+// coefs: null (scalar coefficient `coef`) or d x g complex (diagonal coefficient)
+static qp_status create_problem(qp_problem **out, int d, int n, const double *P, int g,
+                                const int32_t *modes, const double *coef, const double *coefs,
+                                int N, const qp_options *opt)
 {
     g_last_error.clear();
     if (!out) return fail(QP_EINVAL, "out is null");
     *out = nullptr;
-    QP_TRY(check_args(d, n, P, g, modes, coef, N));
+    if (coefs) {
+        if (d < 1 || d > QP_MAX_DIM_D) return fail(QP_EINVAL, "d=%d outside [1, %d]", d, QP_MAX_DIM_D);
+        for (int l = 0; l < d; ++l) {
+            const qp_status s = check_args(d, n, P, g, modes, coefs + 2 * (size_t)l * g, N);
+            if (s != QP_OK) return s;  // the message names the failing check
+        }
+        coef = coefs;
+    } else {
+        QP_TRY(check_args(d, n, P, g, modes, coef, N));
+    }
     qp_options o;
     qp_default_options(&o);
     if (opt) o = *opt;
@@ -912,7 +936,7 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, cons
     qp_problem *p = new (std::nothrow) qp_problem();
     if (!p) return fail(QP_ENOMEM, "host allocation failed");
     p->opt = o;
-    build_table(p->host, d, n, P, g, modes, coef, N);
+    build_table(p->host, d, n, P, g, modes, coef, coefs, N);
     // record indices of the default gathers are scaled by the entry size in 32
     // bits: vectors of 2^28 entries or more take 64-bit addresses
     if (p->host.tile_s > 1 && (o.gather64 || p->host.D >= ((int64_t)1 << 28))) p->host.wide = 1;
@@ -987,6 +1011,19 @@ qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, cons
     if (std::fabs(p->amin) <= 1e-12 * scale) p->flags |= QP_FLAG_DEGENERATE;
     *out = p;
     return QP_OK;
+}
+
+qp_status qp_create(qp_problem **out, int d, int n, const double *P, int g, const int32_t *modes,
+                    const double *coef, int N, const qp_options *opt)
+{
+    return create_problem(out, d, n, P, g, modes, coef, nullptr, N, opt);
+}
+
+qp_status qp_create_diag(qp_problem **out, int d, int n, const double *P, int g,
+                         const int32_t *modes, const double *coefs, int N, const qp_options *opt)
+{
+    if (!coefs) return fail(QP_EINVAL, "null coefs");
+    return create_problem(out, d, n, P, g, modes, nullptr, coefs, N, opt);
 }
 
 void qp_destroy(qp_problem *p)
@@ -1096,7 +1133,7 @@ qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy, 
     if (Astar_energy)
         for (int i = 0; i < d; ++i)
             for (int j = 0; j < d; ++j)
-                Astar_energy[i * d + j] = (i == j ? p->host.a0 : 0.0) - p->hsmall[64 + i * d + j];
+                Astar_energy[i * d + j] = (i == j ? p->host.a0l[i] : 0.0) - p->hsmall[64 + i * d + j];
     if (worst != QP_OK) fail(worst, "a corrector solve did not converge");
     return worst;
 }

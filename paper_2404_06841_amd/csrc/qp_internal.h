@@ -39,6 +39,11 @@ struct Table {
     int midx[kMaxG];          // C(m): storage index of mode m
     int nidx[kMaxG];          // C(-m)
     double a0;                // Ahat_0
+    // ---- diagonal coefficient diag(a_1..a_d) (App. D); for a scalar
+    // coefficient every entry repeats coef ----
+    int aniso;                // coefl differs between entries (diagonal coefficient)
+    double coefl[kMaxG][kMaxD][2];  // Ahat of a_l at mode r (re, im)
+    double a0l[kMaxD];        // Ahat^l_0
     // ---- tiled stiffness product (modes sorted by their last component) ----
     int order[kMaxG];         // sorted position -> mode index
     int zero_sorted;          // sorted position of the mode m = 0
@@ -57,13 +62,14 @@ struct Table {
 
 // Per-mode record of the tiled stiffness product, in sorted order.
 struct alignas(128) ModeRec {
-    double pm[kMaxD];   // P m (zero padded)
-    double cpm[kMaxD];  // Re(Ahat_m) P m
-    double c[2];        // Ahat_m
-    short mt[kMaxN];    // m (all axes); |m_t| < N/2 < 2^15
+    double pm[kMaxD];      // P m (zero padded)
+    double cpm[kMaxD];     // Re(Ahat_m) P m
+    double c[2];           // Ahat_m
+    short mt[kMaxN];       // m (all axes); |m_t| < N/2 < 2^15
+    double cl[kMaxD][2];   // Ahat of a_l at m (diagonal coefficient; else Ahat_m)
     int pad[8];
 };
-static_assert(sizeof(ModeRec) == 128, "mode record is one 128-byte block");
+static_assert(sizeof(ModeRec) == 256, "mode record is two 128-byte blocks");
 
 // Mode record of one unit of the plane-tiled stiffness product (the tiles
 // sharing every digit but the last two), precomputed once per problem:
@@ -80,8 +86,19 @@ struct alignas(16) UnitRec {
 // Row offset of a padding record: adding any in-plane offset (< 2^30) leaves
 // an index whose unsigned value exceeds every vector length (< 2^31).
 constexpr int kNoNeighbour = -(1 << 30);
-// bytes reserved per record (at least sizeof(UnitRec<T, kMaxD>)), by Precision
-constexpr size_t kUnitRecBytes[2] = {64, 48};
+// The same for a diagonal coefficient diag(a_1..a_d) (App. D): per physical
+// axis l, (P m')_l and a_l's Ahat_m.
+template <typename T, int DT>
+struct alignas(16) UnitRecA {
+    T pmw[DT];  // (P m - N sum_{t < n-2} c_t p_t)_l
+    T ar[DT];   // Re(Ahat of a_l at m); 0 for padding
+    T ai[DT];   // Im(Ahat of a_l at m); 0 for padding
+    int lb;     // as UnitRec
+    int mslot;
+};
+// bytes reserved per record (at least the size of either record for d =
+// kMaxD), by Precision
+constexpr size_t kUnitRecBytes[2] = {112, 64};
 
 // Krylov state of one solve, device resident.  All scalars are FP64.
 // Fields are written by workgroup 0 of one kernel and read by later kernels
@@ -142,6 +159,11 @@ hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table
                          const void *x, void *y,
                          const double *f, const float *M32, const Parts &parts, State *st,
                          int *exec, hipStream_t s);
+// The same for a diagonal coefficient (tab.aniso; called by launch_matvec).
+hipError_t launch_matvec_diag(int prec, int epi, int K, const Table *tab, const Table &ht,
+                              const ModeRec *recs, const void *urec, const void *upku,
+                              const void *x, void *y, const double *f, const float *M32,
+                              const Parts &parts, State *st, int *exec, hipStream_t s);
 
 // Start of a solve.  r = f' * scale (scale = 1 for F64, st->inv_unit for F32),
 // U = 0, X64 = 0 (if given), h = M r; parts.b <- ((r, M r), ||r||^2).
@@ -182,6 +204,8 @@ hipError_t launch_ir_force(int K, State *st, hipStream_t s);
 // Unit records and unit P k of precision prec (plane tiles, tile_s > 1).
 hipError_t launch_unit_records(int prec, const Table *tab, const Table &ht, const ModeRec *recs,
                                void *urec, void *upku, hipStream_t s);
+hipError_t launch_unit_records_diag(int prec, const Table *tab, const Table &ht,
+                                    const ModeRec *recs, void *urec, void *upku, hipStream_t s);
 // M (double and float copies); kind 0 paper, 1 Jacobi; out[0] = min_{k!=0} |P k|^2.
 hipError_t launch_precond(const Table *tab, const Table &ht, int kind, double *M64, float *M32,
                           const Parts &parts, double *out, hipStream_t s);

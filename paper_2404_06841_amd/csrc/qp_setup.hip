@@ -26,6 +26,8 @@ __device__ __forceinline__ int signed_of(int b, int N) { return (2 * b < N) ? b 
 //            (column k has one entry per mode, in row rep(k + m))
 //   kind 1:  M_k = 1 / q_kk
 // M_0 = 0.  Partials of min_{k != 0} |P k|^2 (dependent columns of P).
+// Diagonal coefficient (App. D): q_kk = sum_l Ahat^l_0 (P k)_l^2 and the
+// column entry of mode m is sum_l Ahat^l_m (P rep(k + m))_l (P k)_l.
 __global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ tab, int kind,
                                                     double *__restrict__ M64,
                                                     float *__restrict__ M32,
@@ -49,13 +51,17 @@ __global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ ta
         double m = 0.0;
         if (i != 0) {
             pkmin[0] = fmin(pkmin[0], pk2);
-            const double qkk = tab->a0 * pk2;
+            double qkk = tab->a0 * pk2;
+            if (tab->aniso) {
+                qkk = 0.0;
+                for (int l = 0; l < d; ++l) qkk += tab->a0l[l] * pk[l] * pk[l];
+            }
             if (kind == 1) {
                 m = (qkk != 0.0) ? 1.0 / qkk : 0.0;
             } else {
                 double col = 0.0;
                 for (int r = 0; r < g; ++r) {
-                    double w = 0.0;
+                    double w = 0.0, qr = 0.0, qi = 0.0;
                     for (int l = 0; l < d; ++l) {
                         double pj = 0.0;
                         for (int t = 0; t < n; ++t) {
@@ -65,10 +71,16 @@ __global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ ta
                             pj += tab->P[l][t] * (double)signed_of(jb, N);
                         }
                         w += pj * pk[l];
+                        qr += tab->coefl[r][l][0] * (pj * pk[l]);
+                        qi += tab->coefl[r][l][1] * (pj * pk[l]);
                     }
-                    const double a2 = tab->coef[r][0] * tab->coef[r][0] +
-                                      tab->coef[r][1] * tab->coef[r][1];
-                    col += a2 * w * w;
+                    if (tab->aniso) {
+                        col += qr * qr + qi * qi;
+                    } else {
+                        const double a2 = tab->coef[r][0] * tab->coef[r][0] +
+                                          tab->coef[r][1] * tab->coef[r][1];
+                        col += a2 * w * w;
+                    }
                 }
                 m = (col != 0.0) ? qkk / col : 0.0;
             }
@@ -79,19 +91,21 @@ __global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ ta
     store_partials<1, true>(pkmin, part);
 }
 
-// min and -max of A(y) = sum_m Ahat_m exp(i m.y) over y = 2 pi j / N.  The
-// phase m.j is reduced mod N exactly in integers before the sine/cosine.
+// min and -max of A(y) = sum_m Ahat_m exp(i m.y) over y = 2 pi j / N (for a
+// diagonal coefficient: over every entry a_l).  The phase m.j is reduced mod N
+// exactly in integers before the sine/cosine.
 __global__ __launch_bounds__(kBlock) void k_extrema(const Table *__restrict__ tab,
                                                     double *__restrict__ part)
 {
     const int N = tab->N, n = tab->n, g = tab->g;
+    const int entries = tab->aniso ? tab->d : 1;
     int begin, end;
     chunk_of_block(tab, begin, end);
     double v[2] = {INFINITY, INFINITY};
     for (int i = begin + threadIdx.x; i < end; i += kBlock) {
         int ib[kMaxN];
         digits(tab, i, ib);
-        double a = 0.0;
+        double a[kMaxD] = {0.0, 0.0, 0.0, 0.0};
         for (int r = 0; r < g; ++r) {
             long long ph = 0;
             for (int t = 0; t < n; ++t) ph += (long long)tab->modes[r][t] * ib[t];
@@ -99,10 +113,13 @@ __global__ __launch_bounds__(kBlock) void k_extrema(const Table *__restrict__ ta
             if (ph < 0) ph += N;
             double sn, cs;
             sincospi(2.0 * (double)ph / (double)N, &sn, &cs);
-            a += tab->coef[r][0] * cs - tab->coef[r][1] * sn;
+            for (int l = 0; l < entries; ++l)
+                a[l] += tab->coefl[r][l][0] * cs - tab->coefl[r][l][1] * sn;
         }
-        v[0] = fmin(v[0], a);
-        v[1] = fmin(v[1], -a);
+        for (int l = 0; l < entries; ++l) {
+            v[0] = fmin(v[0], a[l]);
+            v[1] = fmin(v[1], -a[l]);
+        }
     }
     store_partials<2, true>(v, part);
 }
@@ -118,7 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
     }
 }
 
-// F_k = i (P k)_j Ahat_k on the modes, 0 elsewhere (each entry written once).
+// F_k = i (P k)_j Ahat_k on the modes, 0 elsewhere (each entry written once);
+// for a diagonal coefficient Ahat is a_j's (the source d a_j / d x_j, App. D).
 __global__ __launch_bounds__(kBlock) void k_corrector_rhs(const Table *__restrict__ tab, int j,
                                                           double2 *__restrict__ F)
 {
@@ -130,8 +148,8 @@ __global__ __launch_bounds__(kBlock) void k_corrector_rhs(const Table *__restric
         for (int r = 0; r < g; ++r) {
             if (tab->midx[r] == i) {
                 const double s = tab->Pm[r][j];
-                v.x += -s * tab->coef[r][1];
-                v.y += s * tab->coef[r][0];
+                v.x += -s * tab->coefl[r][j][1];
+                v.y += s * tab->coefl[r][j][0];
             }
         }
         F[i] = v;
@@ -140,7 +158,9 @@ __global__ __launch_bounds__(kBlock) void k_corrector_rhs(const Table *__restric
 
 // A*_ij = Ahat_0 delta_ij + mean_N{ a d_i chi_j }
 //       = Ahat_0 delta_ij + sum_m Ahat_m i (P(-m))_i chi_j[C(-m)]
-// (the discrete mean keeps the frequency pairs whose sum is 0 mod N).
+// (the discrete mean keeps the frequency pairs whose sum is 0 mod N).  For a
+// diagonal coefficient the integrand is a_i (delta_ij + d_i chi_j), so Ahat is
+// a_i's (App. D, eqs. homcoefficient11-22).
 __global__ void k_astar(const Table *__restrict__ tab, const double2 *__restrict__ chi,
                         double *__restrict__ out)
 {
@@ -149,12 +169,13 @@ __global__ void k_astar(const Table *__restrict__ tab, const double2 *__restrict
     if (e >= d * d) return;
     const int i = e / d, j = e % d;
     const double2 *cj = chi + (size_t)j * tab->D;
-    double re = (i == j) ? tab->a0 : 0.0;
+    double re = (i == j) ? tab->a0l[i] : 0.0;
     double im = 0.0;
     for (int r = 0; r < g; ++r) {
         const double2 c = cj[tab->nidx[r]];
-        const double pr = tab->coef[r][0] * c.x - tab->coef[r][1] * c.y;  // Ahat_m chi
-        const double pi = tab->coef[r][0] * c.y + tab->coef[r][1] * c.x;
+        const double ar = tab->coefl[r][i][0], ai = tab->coefl[r][i][1];
+        const double pr = ar * c.x - ai * c.y;  // Ahat_m chi
+        const double pi = ar * c.y + ai * c.x;
         const double s = tab->Pm[r][i];  // i (P(-m))_i = -i s
         re += s * pi;
         im -= s * pr;

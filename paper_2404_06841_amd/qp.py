@@ -39,7 +39,8 @@ MAX_N, MAX_D, MAX_MODES = 8, 4, 64
 
 #: every symbol include/qp.h declares
 EXPORTED = (
-    "qp_default_options", "qp_workspace_bytes", "qp_create", "qp_destroy", "qp_dim",
+    "qp_default_options", "qp_workspace_bytes", "qp_create", "qp_create_diag", "qp_destroy",
+    "qp_dim",
     "qp_set_options", "qp_solve", "qp_solve_d", "qp_solve_multi_d", "qp_corrector",
     "qp_corrector_d",
     "qp_homogenized", "qp_homogenized_ex", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
@@ -91,6 +92,8 @@ def lib():
         "qp_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int]),
         "qp_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, dp, C.c_int, ip, dp, C.c_int,
                                 C.POINTER(qp_options)]),
+        "qp_create_diag": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, dp, C.c_int, ip, dp,
+                                     C.c_int, C.POINTER(qp_options)]),
         "qp_destroy": (None, [vp]),
         "qp_dim": (C.c_int64, [vp]),
         "qp_set_options": (C.c_int, [vp, C.POINTER(qp_options)]),
@@ -171,6 +174,20 @@ def qp_create(d, n, P, modes, coef, N, opt: qp_options | None = None):
     return st, (h if st == QP_OK else None)
 
 
+def qp_create_diag(d, n, P, modes, coefs, N, opt: qp_options | None = None):
+    """Diagonal coefficient diag(a_1..a_d): coefs is d x g complex (row l = a_l's
+    Ahat per mode).  Returns (status, handle); handle is None on failure."""
+    P = np.ascontiguousarray(P, dtype=np.float64).reshape(-1)
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1)
+    g = modes.size // int(n) if int(n) > 0 else 0
+    flat = np.ascontiguousarray(np.asarray(coefs, dtype=np.complex128).reshape(-1)).view(np.float64)
+    h = C.c_void_p()
+    st = lib().qp_create_diag(C.byref(h), int(d), int(n), _dptr(P), int(g),
+                              modes.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(flat), int(N),
+                              C.byref(opt) if opt is not None else None)
+    return st, (h if st == QP_OK else None)
+
+
 def qp_last_error() -> str:
     return lib().qp_last_error().decode()
 
@@ -186,7 +203,8 @@ def qp_strerror(status: int) -> str:
 class Problem:
     """One qp_problem with a torch-allocated workspace on the current stream.
 
-    `prob` is any object with d, n, N, P, modes, coef (e.g. a workload)."""
+    `prob` is any object with d, n, N, P, modes, coef (e.g. a workload); a
+    non-None attribute `coefs` (d x g) makes it a diagonal coefficient."""
 
     def __init__(self, prob, precision: str = "fp64", precond: str = "paper",
                  maxit: int = 10000, inner_tol: float = 1e-4,
@@ -217,8 +235,13 @@ class Problem:
         opt.workspace = C.c_void_p((base + 255) // 256 * 256)
         opt.workspace_bytes = nbytes
         self.opt = opt
-        st, h = qp_create(self.d, self.n, prob.P, modes, prob.coef, self.N, opt)
-        _check(st, "qp_create")
+        coefs = getattr(prob, "coefs", None)
+        if coefs is not None:
+            st, h = qp_create_diag(self.d, self.n, prob.P, modes, coefs, self.N, opt)
+            _check(st, "qp_create_diag")
+        else:
+            st, h = qp_create(self.d, self.n, prob.P, modes, prob.coef, self.N, opt)
+            _check(st, "qp_create")
         self.h = h
 
     def close(self):

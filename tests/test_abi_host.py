@@ -118,3 +118,45 @@ def test_valid_problem_without_device_reports_device_error():
         pytest.skip("a GPU is present")
     st, h = _create(BASE)
     assert st == qp.QP_EDEVICE and h is None
+
+
+DIAG = W.paper_homogenization(6)
+
+
+@pytest.mark.parametrize("case", ["null_coefs", "row1_not_hermitian", "row1_neg_mean",
+                                  "row0_zero_mean", "alias", "d_zero"])
+def test_invalid_diagonal_problems_rejected_on_host(case):
+    p = DIAG
+    coefs = p.coefs.copy()
+    N, d = p.N, p.d
+    zero = [i for i, m in enumerate(p.modes) if not any(m)][0]
+    other = [i for i, m in enumerate(p.modes) if any(m) and coefs[1, i] != 0][0]
+    if case == "null_coefs":
+        h = qp.C.c_void_p()
+        P = np.ascontiguousarray(p.P, dtype=np.float64).reshape(-1)
+        modes = np.ascontiguousarray(p.modes, dtype=np.int32).reshape(-1)
+        st = qp.lib().qp_create_diag(qp.C.byref(h), d, p.n, qp._dptr(P), p.g,
+                                     modes.ctypes.data_as(qp.C.POINTER(qp.C.c_int32)), None, N, None)
+        assert st == qp.QP_EINVAL and qp.qp_last_error()
+        return
+    if case == "row1_not_hermitian":
+        coefs[1, other] += 0.1j
+    elif case == "row1_neg_mean":
+        coefs[1, zero] = -1.0
+    elif case == "row0_zero_mean":
+        coefs[0, zero] = 0.0
+    elif case == "alias":
+        N = 4  # beta has |m_t| = 2 = N/2
+    elif case == "d_zero":
+        d = 0
+    st, h = qp.qp_create_diag(d, p.n, p.P, p.modes, coefs if d else coefs[:1], N)
+    assert st == qp.QP_EINVAL and h is None, (case, st, qp.qp_last_error())
+    assert qp.qp_last_error()
+
+
+def test_valid_diagonal_problem_without_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h = qp.qp_create_diag(DIAG.d, DIAG.n, DIAG.P, DIAG.modes, DIAG.coefs, DIAG.N)
+    assert st == qp.QP_EDEVICE and h is None
