@@ -29,7 +29,7 @@ TOL = 1e-12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_fp32_eightfold_n4_N32.txt")
 # sources of the stiffness-product kernels (the product and its device helpers)
 MATVEC_SRC = [os.path.join(ROOT, "paper_2404_06841_amd", "csrc", f)
-              for f in ("qp_matvec.hip", "qp_device.h")]
+              for f in ("qp_matvec.hip", "qp_matvec_kernels.h", "qp_device.h")]
 
 
 def parse_args():
@@ -104,6 +104,65 @@ def run_steps(gp, steps: int, torch):
         mv_rhs += i0.matvec32_rhs
     torch.cuda.synchronize()
     return time.perf_counter() - t0, lat, r, (mv_ms, mv_n, mv_rhs)
+
+
+def hbm_products(torch, qp, W):
+    """Stiffness products on a vector far larger than the caches: icosahedral
+    d=3, n=6 at N=16 (16,777,216 unknowns; 268 MB per FP64 vector), one
+    right-hand side per launch, timed with HIP events on the library's stream
+    (torch's current stream).  Algorithmic bytes: read x once, write y once."""
+    prob = W.icosahedral(16)
+    gp = qp.Problem(prob)
+    D = prob.D
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(16)
+    out = {"workload": "icosahedral d=3 n=6 N=16 (16,777,216 unknowns, 13 modes)"}
+    for name, dtype, fn, per in (("fp64", torch.complex128, gp.matvec_d, 32.0),
+                                 ("fp32", torch.complex64, gp.matvec32_d, 16.0)):
+        u = torch.randn(D, dtype=dtype, device="cuda", generator=gen)
+        y = torch.empty_like(u)
+        for _ in range(3):
+            fn(u, y)
+        # the entry point returns after its launch has completed, so each launch
+        # is bracketed on its own (the host turnaround between calls is excluded)
+        reps = 20
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record()
+            fn(u, y)
+            e1.record()
+        torch.cuda.synchronize()
+        us = sum(e0.elapsed_time(e1) for e0, e1 in ev) * 1e3 / reps
+        gbs = per * D / (us * 1e-6) / 1e9
+        out[name] = {"avg_launch_us": round(us, 2), "algorithmic_bytes": int(per * D),
+                     "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        del u, y
+    gp.close()
+    return out
+
+
+def diagonal_workload(torch, np, qp, W, gold, steps: int, warmup: int):
+    """The diagonal coefficient diag(a_1, a_2) of App. D on the eightfold P at
+    N=32 (an independent seeded random field per entry): homogenizations in
+    FP32-IR and FP64, A* checked against the oracle's stored value."""
+    prob = W.eightfold_diagonal(32, 0)
+    A_ref = np.array(gold["diag_eightfold_N32"]["A"])
+    res = {"workload": "eightfold d=2 n=4 N=32, A = diag(a_1, a_2), 6 seeded random mode "
+                       f"pairs per entry ({prob.g} modes)"}
+    gp = qp.Problem(prob, precision="fp32ir")
+    for prec in ("fp32ir", "fp64"):
+        gp.set_options(precision=qp.QP_PREC_FP32_IR if prec == "fp32ir" else qp.QP_PREC_FP64)
+        for _ in range(warmup):
+            gp.homogenized(tol=TOL, energy=False)
+        dt, lat, r, _ = run_steps(gp, steps, torch)
+        res[prec] = {"value": round(prob.d * steps / dt, 2), "unit": "corrector solves/s",
+                     "ms_per_step": round(dt / steps * 1e3, 4),
+                     "p99_ms": round(float(np.percentile(np.array(lat), 99)), 4),
+                     "astar_rel_err": float(np.abs(r.A - A_ref).max() / np.abs(A_ref).max()),
+                     "iters": [i.iters for i in r.infos]}
+    gp.close()
+    return res
 
 
 def cpu_baseline(prob):
@@ -218,6 +277,9 @@ def main():
         "fp32ir_iters": [i.iters for i in r.infos],
         "fp32ir_replacements": [i.outer_iters for i in r.infos],
         "roofline": roofline,
+        "diagonal_coefficient": diagonal_workload(torch, np, qp, W, gold,
+                                                  max(5, args.steps // 2), args.warmup),
+        "hbm_products": hbm_products(torch, qp, W),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)

@@ -297,11 +297,14 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
             const int ns = slot_lanes ? n - 2 : 0;  // slot axis (only read for slot lanes)
 #pragma unroll
             for (int l = 0; l < DT; ++l) {
-                cq += pk[l] * s_np[n - 1][l];
-                if (slot_lanes) cqs += pk[l] * s_np[ns][l];
-                sq[l] = pk[l] * pk[l];
-                ql[l] = pk[l] * s_np[n - 1][l];
-                qs[l] = slot_lanes ? pk[l] * s_np[ns][l] : (T)0;
+                if constexpr (AN) {
+                    sq[l] = pk[l] * pk[l];
+                    ql[l] = pk[l] * s_np[n - 1][l];
+                    qs[l] = slot_lanes ? pk[l] * s_np[ns][l] : (T)0;
+                } else {
+                    cq += pk[l] * s_np[n - 1][l];
+                    if (slot_lanes) cqs += pk[l] * s_np[ns][l];
+                }
             }
             const uint64_t slow = slot_lanes ? tab->slotmask[tl] : 0ull;
 
@@ -329,24 +332,25 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                         c = (T)ci;
                     }
                     int idx = R.lb + lane_line + colw;
-                    const bool cross = (slow >> r) & 1ull;  // slot-axis crossing for some lane
-                    T cs = 0;
-                    if (cross) {
-                        const int m = R.mslot;
-                        const int jb = ibs - m;
-                        idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
-                        const int kd = ks - m;
-                        cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
-                    }
                     if constexpr (AN) {
                         // sum_l Ahat^l (P k)_l (P j)_l
+                        T t[DT];
+#pragma unroll
+                        for (int l = 0; l < DT; ++l) t[l] = (sq[l] + c * ql[l]) - pk[l] * R.pmw[l];
+                        if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
+                            const int m = R.mslot;
+                            const int jb = ibs - m;
+                            idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
+                            const int kd = ks - m;
+                            const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
+#pragma unroll
+                            for (int l = 0; l < DT; ++l) t[l] += cs * qs[l];
+                        }
                         T a = 0, b = 0;
 #pragma unroll
                         for (int l = 0; l < DT; ++l) {
-                            T t = (sq[l] + c * ql[l]) - pk[l] * R.pmw[l];
-                            if (cross) t += cs * qs[l];
-                            a += R.ar[l] * t;
-                            if (!REAL) b += R.ai[l] * t;
+                            a += R.ar[l] * t[l];
+                            if (!REAL) b += R.ai[l] * t[l];
                         }
                         wr[k] = a;
                         wi[k] = b;
@@ -356,7 +360,14 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                         T wv = a * (s2 + c * cq);
 #pragma unroll
                         for (int l = 0; l < DT; ++l) wv -= pk[l] * R.apm[l];
-                        if (cross) wv += a * cs * cqs;
+                        if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
+                            const int m = R.mslot;
+                            const int jb = ibs - m;
+                            idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
+                            const int kd = ks - m;
+                            const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
+                            wv += a * cs * cqs;
+                        }
                         wr[k] = REAL ? wv : R.cr * wv;
                         wi[k] = REAL ? (T)0 : R.ci * wv;
                     }
@@ -696,12 +707,15 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
             for (int l = 0; l < DT; ++l) {
                 const T v = pku[l] + ps_[l] * (T)ks + pl_[l] * (T)kpos;
                 pk[l] = v;
-                s2 += v * v;
-                cq += v * pl_[l];
-                cqs += v * ps_[l];
-                sq[l] = v * v;
-                ql[l] = NT * (v * pl_[l]);
-                qs[l] = NT * (v * ps_[l]);
+                if constexpr (AN) {
+                    sq[l] = v * v;
+                    ql[l] = NT * (v * pl_[l]);
+                    qs[l] = NT * (v * ps_[l]);
+                } else {
+                    s2 += v * v;
+                    cq += v * pl_[l];
+                    cqs += v * ps_[l];
+                }
             }
             cq *= NT;
             cqs *= NT;
@@ -721,22 +735,18 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
                     const int2 ge = s_geo[r * kWave + lane];
                     const T c = (T)__int_as_float(ge.y);
                     int idx = Q.lb + lane_line + ge.x;
-                    const bool cross = (slow >> r) & 1ull;  // slot-axis crossing for some lane
-                    T cs = 0;
-                    if (cross) {
-                        const int mm = Q.mslot;
-                        const int jb = ibs - mm;
-                        idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
-                        const int kd = ks - mm;
-                        cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
-                    }
                     if constexpr (AN) {
                         // sum_l Ahat^l (P k)_l (P j)_l, (P j)_l = (P k - P m')_l
                         // + N c p_{n-1,l} + N cs p_{n-2,l}
                         T t[DT];
 #pragma unroll
                         for (int l = 0; l < DT; ++l) t[l] = (sq[l] + c * ql[l]) - pk[l] * Q.pmw[l];
-                        if (cross) {
+                        if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
+                            const int mm = Q.mslot;
+                            const int jb = ibs - mm;
+                            idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
+                            const int kd = ks - mm;
+                            const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
 #pragma unroll
                             for (int l = 0; l < DT; ++l) t[l] += cs * qs[l];
                         }
@@ -753,7 +763,14 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
                         T wv = Q.a * (s2 + c * cq);
 #pragma unroll
                         for (int l = 0; l < DT; ++l) wv -= pk[l] * Q.apm[l];
-                        if (cross) wv += Q.a * cs * cqs;
+                        if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
+                            const int mm = Q.mslot;
+                            const int jb = ibs - mm;
+                            idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
+                            const int kd = ks - mm;
+                            const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
+                            wv += Q.a * cs * cqs;
+                        }
                         wr[m] = REAL ? wv : Q.cr * wv;
                         wi[m] = REAL ? (T)0 : Q.ci * wv;
                     }

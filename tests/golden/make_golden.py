@@ -20,6 +20,9 @@ from paper_2404_06841_amd import workloads as W  # noqa: E402
 CASES = {
     "c2_eightfold_N16": lambda: W.eightfold(16),
     "c3_eightfold_random_N32": lambda: W.eightfold_random(32, 0),
+    # diagonal coefficient diag(a_1, a_2) (App. D): the benchmark's second workload
+    "diag_eightfold_N32": lambda: W.eightfold_diagonal(32, 0),
+    "paper_homogenization_N18": lambda: W.paper_homogenization(18),
 }
 
 
