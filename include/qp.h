@@ -233,6 +233,81 @@ qp_status qp_homogenized(qp_problem *p, double *Astar, double tol,
 qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy,
                             double tol, qp_solve_info *info);
 
+/*
+ * Homogenize several problems together (a batch of coefficient instances):
+ * each problem's result is the one qp_homogenized computes (same launches,
+ * same values), and the host keeps every problem's batches of iterations
+ * queued on that problem's stream, advancing whichever has a poll ready, so
+ * the device runs the problems' kernels concurrently.
+ *   problems  count distinct problems (count >= 1).  Their solves overlap
+ *             only if they run on different streams (qp_options.stream NULL
+ *             at creation gives each its own).
+ *   Astar     host, sum over i of d_i^2 doubles: problem i's d_i x d_i
+ *             coefficient (flux form, row-major) follows those of problems
+ *             0 .. i-1
+ *   infos     host, sum of d_i entries in the same order, or NULL
+ * Blocks until every problem has finished.  Returns QP_EINVAL for a null or
+ * repeated problem; otherwise the first non-QP_OK status in problem order
+ * (every problem is still run to its end).
+ */
+qp_status qp_homogenized_batch(qp_problem *const *problems, int count, double *Astar, double tol,
+                               qp_solve_info *infos);
+
+/* ---- serving: a request queue over a cache of problems ---- */
+
+/*
+ * A server runs homogenization requests as they arrive.  It creates the
+ * problems the requests describe and keeps them (workspace, tables,
+ * preconditioner) in a cache whose device bytes (qp_workspace_bytes of each)
+ * stay within hbm_budget.  Requests are admitted in arrival order: when
+ * their problem is cached and idle, or when it can be created within the
+ * budget after evicting idle problems (least recently used first); a
+ * request whose problem does not fit yet stops the creation of problems for
+ * the requests behind it.  Every admitted request runs on its problem's own
+ * stream; requests join and leave while the others keep iterating, and each
+ * result equals that of qp_homogenized on the same problem alone.
+ * opt: the problems' options (precision, preconditioner, limits; stream and
+ * workspace are ignored: every problem gets its own), NULL for the defaults.
+ * A server is used from one host thread at a time.
+ */
+typedef struct qp_server qp_server;
+qp_status qp_server_create(qp_server **out, size_t hbm_budget, const qp_options *opt);
+
+/*
+ * Queue a homogenization (as qp_homogenized) of the problem (d, n, P, g,
+ * modes, coefficient, N): coef as for qp_create, or coefs as for
+ * qp_create_diag (exactly one of the two is used: coefs when not NULL).
+ * The arrays are copied.  Astar (host, d*d) and infos (host, d entries, or
+ * NULL) receive the result and must stay valid until the request's ticket
+ * is returned by qp_server_progress.  *ticket: a positive request id.
+ * Returns QP_EINVAL for invalid arguments (the checks of qp_create that need
+ * no device) and QP_ENOMEM when the problem alone exceeds the budget;
+ * device-side checks (ellipticity, dependent P) surface as the request's
+ * status.
+ */
+qp_status qp_server_submit(qp_server *s, int d, int n, const double *P, int g,
+                           const int32_t *modes, const double *coef, const double *coefs, int N,
+                           double tol, double *Astar, qp_solve_info *infos, int64_t *ticket);
+
+/*
+ * Admit what fits and advance every running request, for at most wait_us
+ * microseconds or until some request has finished (or nothing is left).
+ * The finished tickets (up to max_done) go to done[] with their statuses in
+ * done_status[] (may be NULL); *ndone is their count.  Tickets not returned
+ * yet are returned by a later call.
+ */
+qp_status qp_server_progress(qp_server *s, int wait_us, int64_t *done, qp_status *done_status,
+                             int max_done, int *ndone);
+
+/* Requests queued, running, or finished but not yet returned. */
+int qp_server_pending(const qp_server *s);
+
+/* Device bytes held by the cached problems. */
+size_t qp_server_bytes(const qp_server *s);
+
+/* Finish the running requests, release every cached problem and the server. */
+void qp_server_destroy(qp_server *s);
+
 /* ---- single steps of the path, device pointers (used by parity tests) ---- */
 
 /* y = Q u in FP64 (eq. linear_system; y[C(0)] = 0, u[C(0)] ignored). */

@@ -5,12 +5,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "qp.h"
@@ -138,6 +141,7 @@ struct qp_problem {
     };
     std::vector<Graph> graphs;
     hipEvent_t ev_poll[2] = {nullptr, nullptr};
+    hipEvent_t ev_fin = nullptr;  // the last copy of a solve or homogenization arrived
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
 
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -389,6 +393,7 @@ void release(qp_problem *p)
     for (auto e : p->ev_res) (void)hipEventDestroy(e);
     for (auto e : p->ev_poll)
         if (e) (void)hipEventDestroy(e);
+    if (p->ev_fin) (void)hipEventDestroy(p->ev_fin);
     if (p->ev_t0) (void)hipEventDestroy(p->ev_t0);
     if (p->ev_t1) (void)hipEventDestroy(p->ev_t1);
     if (p->hstate) (void)hipHostFree(p->hstate);
@@ -544,10 +549,10 @@ qp_status queue_batch(qp_problem *p, bool ir, int K, double *U, const double *rh
 // batch before the newest is inspected, so the device always has queued work.
 // Kernels of a finished right-hand side skip it.
 struct Poller {
-    qp_problem *p;
-    int K;
-    bool prof;
-    Profile &pf;
+    qp_problem *p = nullptr;
+    int K = 0;
+    bool prof = false;
+    Profile *pf = nullptr;
     struct Rec {
         bool pending = false;
         int k = 0, nres = 0;
@@ -564,27 +569,24 @@ struct Poller {
             float t = 0.f;
             const int e = s * kMaxBatch + it;
             QP_HIP(hipEventElapsedTime(&t, p->ev_hot[2 * e], p->ev_hot[2 * e + 1]));
-            pf.hot_ms += t;
-            ++pf.hot_n;
-            pf.hot_rhs += hot[it];
+            pf->hot_ms += t;
+            ++pf->hot_n;
+            pf->hot_rhs += hot[it];
         }
         const int res = p->hexec[2 * kMaxBatch + s];
         if (rec[s].nres && res) {
             float t = 0.f;
             QP_HIP(hipEventElapsedTime(&t, p->ev_res[2 * s], p->ev_res[2 * s + 1]));
-            pf.res_ms += t;
-            ++pf.res_n;
-            pf.res_rhs += res;
+            pf->res_ms += t;
+            ++pf->res_n;
+            pf->res_rhs += res;
         }
         return QP_OK;
     }
-    // Record the poll point of the batch just queued (k stiffness products,
-    // nres residual replacements); finished = an older poll saw every state
-    // done; seen = the states that poll saw (null when there was none yet).
-    qp_status push(int k, int nres, bool &finished, const State **seen)
+    // Record the poll point of the batch just queued in the current slot (k
+    // stiffness products, nres residual replacements).
+    qp_status record(int k, int nres)
     {
-        finished = false;
-        *seen = nullptr;
         QP_HIP(hipMemcpyAsync(host_states(slot), p->st(), sizeof(State) * K, hipMemcpyDeviceToHost,
                               p->stream));
         if (prof) {
@@ -595,39 +597,67 @@ struct Poller {
         }
         QP_HIP(hipEventRecord(p->ev_poll[slot], p->stream));
         rec[slot] = Rec{true, k, nres};
-        const int other = slot ^ 1;
-        if (rec[other].pending) {
-            QP_HIP(hipEventSynchronize(p->ev_poll[other]));
-            rec[other].pending = false;
-            const State *hs = host_states(other);
-            finished = true;
-            for (int r = 0; r < K; ++r) finished = finished && hs[r].done != 0;
-            *seen = hs;
-            if (prof) {
-                QP_TRY(account(other));
-                // the next batch of this slot set starts from a clear log
-                QP_TRY(clear_exec(other));
-            }
-        }
-        slot = other;
         return QP_OK;
     }
+    bool other_pending() const { return rec[slot ^ 1].pending; }
+    // Whether the older poll has arrived (blocking: wait for it).
+    qp_status other_ready(bool blocking, bool &ready)
+    {
+        const int other = slot ^ 1;
+        if (blocking) {
+            QP_HIP(hipEventSynchronize(p->ev_poll[other]));
+            ready = true;
+            return QP_OK;
+        }
+        const hipError_t e = hipEventQuery(p->ev_poll[other]);
+        if (e == hipErrorNotReady) {
+            ready = false;
+            return QP_OK;
+        }
+        QP_HIP(e);
+        ready = true;
+        return QP_OK;
+    }
+    // Consume the older poll (it has arrived): finished = every state done;
+    // seen = the states it saw.
+    qp_status take_other(bool &finished, const State **seen)
+    {
+        const int other = slot ^ 1;
+        rec[other].pending = false;
+        const State *hs = host_states(other);
+        finished = true;
+        for (int r = 0; r < K; ++r) finished = finished && hs[r].done != 0;
+        *seen = hs;
+        if (prof) {
+            QP_TRY(account(other));
+            // the next batch of this slot set starts from a clear log
+            QP_TRY(clear_exec(other));
+        }
+        return QP_OK;
+    }
+    void flip() { slot ^= 1; }
     qp_status clear_exec(int s)
     {
         QP_HIP(hipMemsetAsync(p->exec_hot() + s * kMaxBatch, 0, sizeof(int) * kMaxBatch, p->stream));
         QP_HIP(hipMemsetAsync(p->exec_res() + s, 0, sizeof(int), p->stream));
         return QP_OK;
     }
-    qp_status final_states(State *out)
+    // Queue the copy of the final states (slot 2) behind everything queued.
+    qp_status queue_final()
     {
-        State *fin = host_states(2);
-        QP_HIP(hipMemcpyAsync(fin, p->st(), sizeof(State) * K, hipMemcpyDeviceToHost, p->stream));
-        QP_HIP(hipStreamSynchronize(p->stream));
+        QP_HIP(hipMemcpyAsync(host_states(2), p->st(), sizeof(State) * K, hipMemcpyDeviceToHost,
+                              p->stream));
+        return QP_OK;
+    }
+    // After the final copy has arrived: account the polls never inspected.
+    qp_status drain(State *out)
+    {
         for (int s = 0; s < 2; ++s)
             if (rec[s].pending) {
                 rec[s].pending = false;
                 if (prof) QP_TRY(account(s));
             }
+        const State *fin = host_states(2);
         for (int r = 0; r < K; ++r) out[r] = fin[r];
         return QP_OK;
     }
@@ -667,31 +697,84 @@ int next_batch(double need, int queued, int full)
     return (L + 1) & ~1;
 }
 
-qp_status solve_fp64(qp_problem *p, int K, const double *rhs, double *U, double tol, State *st,
-                     Profile &pf)
-{
-    const qp::Parts parts = p->parts();
-    const bool prof = p->opt.profile != 0;
-    QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
-    QP_HIP(qp::launch_pcg_init(qp::F64, K, p->tab, p->host, rhs, nullptr, U, p->r(), p->h(),
-                               p->M64(), parts, p->st(), p->stream));
-    QP_HIP(qp::launch_pcg_start(qp::F64, K, p->host, tol, 0.0, p->opt.maxit, parts, p->st(),
-                                p->stream));
-    const int batch = batch_size(p->opt);
-    Poller poll{p, K, prof, pf};
+// ---------------------------------------------------------------- solve jobs
+//
+// A solve of K right-hand sides as a state machine.  begin() queues the
+// set-up and advance() queues batches of iterations and consumes the polls.
+// A blocking advance waits for each poll (the single-problem entry points);
+// a non-blocking one returns as soon as the poll it needs has not arrived,
+// so one host thread keeps the solves of many problems, each on its own
+// stream, in flight at once.  Both queue the same launches in the same order.
+//
+// FP64: C-PCG in batches sized from the residual trend.  FP32-IR: float C-PCG
+// whose residual is replaced by the FP64 residual F' - Q X of the FP64
+// solution X whenever the float residual has dropped by `inner_tol` (or
+// reached tol); the replacement steps sit at the end of every batch and act
+// on the paused right-hand sides; batches are sized to end just after the
+// expected pause; an iteration limit ends with one forced replacement.
+struct SolveJob {
+    qp_problem *p = nullptr;
+    int K = 0;
+    const double *rhs = nullptr;
+    double *U = nullptr;
+    double tol = 0.0;
+    bool ir = false, prof = false;
+    enum Phase { kQueue, kWait, kFinal, kForce, kDone } phase = kDone;
+    Profile pf;
+    Poller poll;
     Trend trend[qp::kMaxRhs];
-    int k = batch;
-    for (int j = 0; j < p->opt.maxit;) {
-        k = std::min(k, p->opt.maxit - j);
-        QP_TRY(queue_batch(p, false, K, U, nullptr, k, poll.slot, prof));
-        j += k;
-        bool fin = false;
-        const State *seen = nullptr;
-        QP_TRY(poll.push(k, 0, fin, &seen));
-        if (fin) break;
-        // Convergence expected within the queued batch: queue a short one.
-        int next = batch;
-        if (seen) {
+    int batch = 0, j = 0, k = 0;
+    State st[qp::kMaxRhs];
+
+    bool done() const { return phase == kDone; }
+
+    qp_status begin(qp_problem *p_, int K_, const double *rhs_, double *U_, double tol_)
+    {
+        p = p_;
+        K = K_;
+        rhs = rhs_;
+        U = U_;
+        tol = tol_;
+        ir = p->opt.precision == QP_PREC_FP32_IR;
+        prof = p->opt.profile != 0;
+        pf = Profile{};
+        poll = Poller{};
+        poll.p = p;
+        poll.K = K;
+        poll.prof = prof;
+        poll.pf = &pf;
+        for (auto &t : trend) t = Trend{};
+        batch = batch_size(p->opt);
+        j = 0;
+        k = batch;
+        if (prof) {
+            QP_TRY(events_ready(p));
+            QP_HIP(hipMemsetAsync(p->exec_hot(), 0, sizeof(int) * kExecInts, p->stream));
+        }
+        QP_HIP(hipEventRecord(p->ev_t0, p->stream));
+        const qp::Parts parts = p->parts();
+        QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
+        if (ir) {
+            QP_HIP(qp::launch_ir_unit(K, p->tab, p->host, rhs, parts, p->st(), p->stream));
+            QP_HIP(qp::launch_pcg_init(qp::F32, K, p->tab, p->host, rhs, U, p->x32(), p->r32(),
+                                       p->h32(), p->M32(), parts, p->st(), p->stream));
+            QP_HIP(qp::launch_pcg_start(qp::F32, K, p->host, tol, p->opt.inner_tol, p->opt.maxit,
+                                        parts, p->st(), p->stream));
+        } else {
+            QP_HIP(qp::launch_pcg_init(qp::F64, K, p->tab, p->host, rhs, nullptr, U, p->r(), p->h(),
+                                       p->M64(), parts, p->st(), p->stream));
+            QP_HIP(qp::launch_pcg_start(qp::F64, K, p->host, tol, 0.0, p->opt.maxit, parts,
+                                        p->st(), p->stream));
+        }
+        phase = kQueue;
+        return QP_OK;
+    }
+
+    // Length of the batch after the queued one (k iterations) from the states
+    // an older poll saw.
+    int next_length(const State *seen)
+    {
+        if (!ir) {
             double need = 0.0;
             for (int r = 0; r < K; ++r) {
                 if (seen[r].done) continue;
@@ -700,161 +783,368 @@ qp_status solve_fp64(qp_problem *p, int K, const double *rhs, double *U, double 
                 const double nr = trend[r].iters_to(seen[r].thresh);
                 need = (nr < 0.0 || need < 0.0) ? -1.0 : std::max(need, nr);
             }
-            next = next_batch(need, k, batch);
+            return next_batch(need, k, batch);
         }
-        k = next;
+        // seen: after a replacement (scaled true residual rr = rr_last)
+        int want = 2;
+        for (int r = 0; r < K; ++r) {
+            if (seen[r].done) continue;
+            if (trend[r].it < 0) trend[r].observe(0, 1.0);
+            trend[r].observe(seen[r].iters, seen[r].rr);
+            const double target = std::max(seen[r].thresh, seen[r].delta2 * seen[r].rr_last);
+            const double need = trend[r].iters_to(target);
+            int L;
+            if (need < 0.0) {
+                return batch;
+            } else if (need <= k) {
+                // the queued batch reaches the next replacement point
+                if (target <= seen[r].thresh) {
+                    L = 2;  // and that one should converge
+                } else {
+                    const double t2 = std::max(seen[r].thresh, seen[r].delta2 * target);
+                    L = next_batch(std::log(t2 / target) / trend[r].rate, 0, batch);
+                }
+            } else {
+                L = next_batch(need, k, batch);
+            }
+            want = std::max(want, L);
+        }
+        return want;
     }
-    return poll.final_states(st);
-}
 
-// FP32-IR: float C-PCG whose residual is replaced by the FP64 residual
-// F' - Q X of the FP64 solution X whenever the float residual has dropped by
-// `inner_tol` (or reached tol).  The replacement steps sit at the end of every
-// batch and act on the paused right-hand sides; batches are sized to end just
-// after the expected pause.
-qp_status solve_ir(qp_problem *p, int K, const double *rhs, double *X, double tol, State *st,
-                   Profile &pf)
-{
-    const qp::Parts parts = p->parts();
-    const bool prof = p->opt.profile != 0;
-    QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
-    QP_HIP(qp::launch_ir_unit(K, p->tab, p->host, rhs, parts, p->st(), p->stream));
-    QP_HIP(qp::launch_pcg_init(qp::F32, K, p->tab, p->host, rhs, X, p->x32(), p->r32(), p->h32(),
-                               p->M32(), parts, p->st(), p->stream));
-    QP_HIP(qp::launch_pcg_start(qp::F32, K, p->host, tol, p->opt.inner_tol, p->opt.maxit, parts,
-                                p->st(), p->stream));
-    const int batch = batch_size(p->opt);
-    Poller poll{p, K, prof, pf};
-    Trend trend[qp::kMaxRhs];
-    int k = batch;
-    for (int j = 0; j < p->opt.maxit;) {
-        k = std::min(k, p->opt.maxit - j);
-        QP_TRY(queue_batch(p, true, K, X, rhs, k, poll.slot, prof));
-        j += k;
-        bool fin = false;
-        const State *seen = nullptr;
-        QP_TRY(poll.push(k, 1, fin, &seen));
-        if (fin) break;
-        int next = batch;
-        if (seen) {
-            // seen: after a replacement (scaled true residual rr = rr_last);
-            // the batch to size comes after the one queued (k iterations)
-            int want = 2;
-            bool known = true;
-            for (int r = 0; r < K && known; ++r) {
-                if (seen[r].done) continue;
-                if (trend[r].it < 0) trend[r].observe(0, 1.0);
-                trend[r].observe(seen[r].iters, seen[r].rr);
-                const double target =
-                    std::max(seen[r].thresh, seen[r].delta2 * seen[r].rr_last);
-                const double need = trend[r].iters_to(target);
-                int L;
-                if (need < 0.0) {
-                    known = false;
-                    break;
-                } else if (need <= k) {
-                    // the queued batch reaches the next replacement point
-                    if (target <= seen[r].thresh) {
-                        L = 2;  // and that one should converge
-                    } else {
-                        const double t2 = std::max(seen[r].thresh, seen[r].delta2 * target);
-                        L = next_batch(std::log(t2 / target) / trend[r].rate, 0, batch);
+    qp_status event_ready(hipEvent_t e, bool blocking, bool &ready)
+    {
+        if (blocking) {
+            QP_HIP(hipEventSynchronize(e));
+            ready = true;
+            return QP_OK;
+        }
+        const hipError_t q = hipEventQuery(e);
+        ready = q != hipErrorNotReady;
+        if (ready) QP_HIP(q);
+        return QP_OK;
+    }
+
+    // Advance as far as possible; progressed = something was queued or consumed.
+    qp_status advance(bool blocking, bool &progressed)
+    {
+        progressed = false;
+        for (;;) {
+            switch (phase) {
+            case kQueue: {
+                if (j >= p->opt.maxit) {
+                    QP_TRY(begin_final());
+                    progressed = true;
+                    continue;
+                }
+                k = std::min(k, p->opt.maxit - j);
+                QP_TRY(queue_batch(p, ir, K, U, rhs, k, poll.slot, prof));
+                j += k;
+                QP_TRY(poll.record(k, ir ? 1 : 0));
+                progressed = true;
+                if (poll.other_pending()) {
+                    phase = kWait;
+                } else {
+                    poll.flip();
+                    k = batch;
+                }
+                continue;
+            }
+            case kWait: {
+                bool ready = false;
+                QP_TRY(poll.other_ready(blocking, ready));
+                if (!ready) return QP_OK;
+                bool fin = false;
+                const State *seen = nullptr;
+                QP_TRY(poll.take_other(fin, &seen));
+                poll.flip();
+                progressed = true;
+                if (fin) {
+                    QP_TRY(begin_final());
+                } else {
+                    k = next_length(seen);
+                    phase = kQueue;
+                }
+                continue;
+            }
+            case kFinal:
+            case kForce: {
+                bool ready = false;
+                QP_TRY(event_ready(p->ev_fin, blocking, ready));
+                if (!ready) return QP_OK;
+                progressed = true;
+                if (phase == kFinal) {
+                    QP_TRY(poll.drain(st));
+                    bool all_done = true;
+                    for (int r = 0; r < K; ++r) all_done = all_done && st[r].done;
+                    if (ir && !all_done) {
+                        // iteration limit: fold every unfinished increment into X
+                        // with one forced replacement, whose true residual
+                        // decides the status
+                        QP_HIP(qp::launch_ir_force(K, p->st(), p->stream));
+                        QP_TRY(enqueue_replacement(p, K, U, rhs, p->opt.maxit, 0, false));
+                        QP_HIP(hipEventRecord(p->ev_t1, p->stream));
+                        QP_TRY(poll.queue_final());
+                        QP_HIP(hipEventRecord(p->ev_fin, p->stream));
+                        phase = kForce;
+                        continue;
                     }
                 } else {
-                    L = next_batch(need, k, batch);
+                    const State *fin = poll.host_states(2);
+                    for (int r = 0; r < K; ++r) {
+                        st[r] = fin[r];
+                        if (!st[r].done) st[r].status = QP_ENOCONV;
+                    }
                 }
-                want = std::max(want, L);
+                phase = kDone;
+                return QP_OK;
             }
-            next = known ? want : batch;
-        }
-        k = next;
-    }
-    QP_TRY(poll.final_states(st));
-    bool all_done = true;
-    for (int r = 0; r < K; ++r) all_done = all_done && st[r].done;
-    if (!all_done) {
-        // iteration limit: fold every unfinished increment into X with one
-        // forced replacement, whose true residual decides the status
-        QP_HIP(qp::launch_ir_force(K, p->st(), p->stream));
-        QP_TRY(enqueue_replacement(p, K, X, rhs, p->opt.maxit, 0, false));
-        QP_HIP(hipMemcpyAsync(p->hstate + 2 * qp::kMaxRhs, p->st(), sizeof(State) * K,
-                              hipMemcpyDeviceToHost, p->stream));
-        QP_HIP(hipStreamSynchronize(p->stream));
-        for (int r = 0; r < K; ++r) {
-            st[r] = p->hstate[2 * qp::kMaxRhs + r];
-            if (!st[r].done) st[r].status = QP_ENOCONV;
+            case kDone:
+                return QP_OK;
+            }
         }
     }
-    return QP_OK;
-}
 
-// K right-hand sides (rhs + r D, solutions U + r D); infos: K entries or null.
-qp_status solve_dispatch(qp_problem *p, int K, const double *rhs, double *U, double tol,
-                         qp_solve_info *infos)
-{
-    const int D2 = 2 * p->host.D;
-    if (K > 1 && (p->host.tile_s <= 1 || p->host.wide)) {
-        // line tiles and 64-bit gathers serve one right-hand side per launch:
-        // solve them in turn
+    qp_status begin_final()
+    {
+        QP_HIP(hipEventRecord(p->ev_t1, p->stream));
+        QP_TRY(poll.queue_final());
+        QP_HIP(hipEventRecord(p->ev_fin, p->stream));
+        phase = kFinal;
+        return QP_OK;
+    }
+
+    // Fill K infos (done() must hold); returns the first non-QP_OK status.
+    qp_status finish(qp_solve_info *infos)
+    {
+        float ms = 0.f;
+        QP_HIP(hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1));
         qp_status worst = QP_OK;
         for (int r = 0; r < K; ++r) {
-            const qp_status s =
-                solve_dispatch(p, 1, rhs + (size_t)r * D2, U + (size_t)r * D2, tol,
-                               infos ? infos + r : nullptr);
-            if (s == QP_EDEVICE || s == QP_EINVAL) return s;
+            qp_solve_info *info = infos + r;
+            std::memset(info, 0, sizeof(*info));
+            info->flags = p->flags;
+            info->status = st[r].status;
+            info->iters = st[r].iters;
+            info->outer_iters = ir ? st[r].replacements : 0;
+            info->rel_resid =
+                ir ? std::sqrt(st[r].rr) : (st[r].rr0 > 0 ? std::sqrt(st[r].rr / st[r].rr0) : 0.0);
+            info->seconds = ms * 1e-3;
+            if (prof) {
+                if (ir) {
+                    info->matvec32_ms = pf.hot_ms;
+                    info->matvec32_launches = pf.hot_n;
+                    info->matvec32_rhs = pf.hot_rhs;
+                    info->matvec_ms = pf.res_ms;
+                    info->matvec_launches = pf.res_n;
+                    info->matvec_rhs = pf.res_rhs;
+                } else {
+                    info->matvec_ms = pf.hot_ms;
+                    info->matvec_launches = pf.hot_n;
+                    info->matvec_rhs = pf.hot_rhs;
+                }
+            }
+            const qp_status s = (qp_status)st[r].status;
             if (s != QP_OK && worst == QP_OK) worst = s;
         }
         return worst;
     }
-    qp_solve_info local[qp::kMaxRhs];
-    if (!infos) infos = local;
-    std::memset(infos, 0, sizeof(qp_solve_info) * K);
-    for (int r = 0; r < K; ++r) infos[r].flags = p->flags;
-    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QP_EINVAL, "tol must be positive and finite");
-    const bool ir = p->opt.precision == QP_PREC_FP32_IR;
-    Profile pf;
-    State st[qp::kMaxRhs];
-    if (p->opt.profile) {
-        QP_TRY(events_ready(p));
-        QP_HIP(hipMemsetAsync(p->exec_hot(), 0, sizeof(int) * kExecInts, p->stream));
-    }
-    QP_HIP(hipEventRecord(p->ev_t0, p->stream));
-    QP_TRY(ir ? solve_ir(p, K, rhs, U, tol, st, pf) : solve_fp64(p, K, rhs, U, tol, st, pf));
-    QP_HIP(hipEventRecord(p->ev_t1, p->stream));
-    QP_HIP(hipEventSynchronize(p->ev_t1));
-    float ms = 0.f;
-    QP_HIP(hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1));
-    qp_status worst = QP_OK;
-    for (int r = 0; r < K; ++r) {
-        qp_solve_info *info = infos + r;
-        info->status = st[r].status;
-        info->iters = st[r].iters;
-        info->outer_iters = ir ? st[r].replacements : 0;
-        info->rel_resid =
-            ir ? std::sqrt(st[r].rr) : (st[r].rr0 > 0 ? std::sqrt(st[r].rr / st[r].rr0) : 0.0);
-        info->seconds = ms * 1e-3;
-        if (p->opt.profile) {
-            if (ir) {
-                info->matvec32_ms = pf.hot_ms;
-                info->matvec32_launches = pf.hot_n;
-                info->matvec32_rhs = pf.hot_rhs;
-                info->matvec_ms = pf.res_ms;
-                info->matvec_launches = pf.res_n;
-                info->matvec_rhs = pf.res_rhs;
-            } else {
-                info->matvec_ms = pf.hot_ms;
-                info->matvec_launches = pf.hot_n;
-                info->matvec_rhs = pf.hot_rhs;
-            }
-        }
-        const qp_status s = (qp_status)st[r].status;
-        if (s != QP_OK && worst == QP_OK) worst = s;
-    }
+};
+
+// Right-hand sides that one launch of this problem can serve together: the
+// plane tiles with 32-bit gathers serve up to d; line tiles and 64-bit
+// gathers one.
+int rhs_per_launch(const qp_problem *p)
+{
+    return (p->host.tile_s <= 1 || p->host.wide) ? 1 : p->host.d;
+}
+
+qp_status report(qp_status worst)
+{
     if (worst == QP_ENOTSPD) fail(worst, "PCG breakdown: (Q h, h) <= 0");
     else if (worst == QP_ENOCONV) fail(worst, "iteration limit reached before the tolerance");
     else if (worst == QP_ENONFINITE) fail(worst, "non-finite value in the right-hand side or residual");
     return worst;
 }
+
+// K right-hand sides (rhs + r D, solutions U + r D), solved in groups the
+// launches can serve together; blocking.  infos: K entries or null.
+qp_status solve_dispatch(qp_problem *p, int K, const double *rhs, double *U, double tol,
+                         qp_solve_info *infos)
+{
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QP_EINVAL, "tol must be positive and finite");
+    qp_solve_info local[qp::kMaxRhs];
+    if (!infos) infos = local;
+    const int G = rhs_per_launch(p);
+    const size_t D2 = 2 * (size_t)p->host.D;
+    qp_status worst = QP_OK;
+    for (int r0 = 0; r0 < K; r0 += G) {
+        const int Kg = std::min(G, K - r0);
+        SolveJob job;
+        QP_TRY(job.begin(p, Kg, rhs + r0 * D2, U + r0 * D2, tol));
+        bool progressed = false;
+        while (!job.done()) QP_TRY(job.advance(true, progressed));
+        const qp_status s = job.finish(infos + r0);
+        if (s != QP_OK && worst == QP_OK) worst = s;
+    }
+    return report(worst);
+}
+
+// A homogenization as a job: the d corrector right-hand sides, their solves
+// (together where the launches allow), and A* (flux form, plus the energy
+// form on request), with the same launches as qp_homogenized_ex.
+struct HomJob {
+    qp_problem *p = nullptr;
+    double tol = 0.0;
+    double *Astar = nullptr, *Aenergy = nullptr;
+    qp_solve_info *infos = nullptr;
+    qp_solve_info local[qp::kMaxRhs];
+    SolveJob sj;
+    int r0 = 0, G = 1;
+    qp_status worst = QP_OK;
+    enum Phase { kSolve, kAstar, kDone } phase = kDone;
+
+    bool done() const { return phase == kDone; }
+
+    qp_status begin(qp_problem *p_, double *Astar_, double *Aenergy_, double tol_,
+                    qp_solve_info *infos_)
+    {
+        p = p_;
+        Astar = Astar_;
+        Aenergy = Aenergy_;
+        tol = tol_;
+        infos = infos_ ? infos_ : local;
+        if (!(tol > 0.0) || !std::isfinite(tol))
+            return fail(QP_EINVAL, "tol must be positive and finite");
+        const int d = p->host.d;
+        for (int j = 0; j < d; ++j)
+            QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, p->F() + (size_t)2 * p->host.D * j,
+                                            p->stream));
+        G = rhs_per_launch(p);
+        r0 = 0;
+        worst = QP_OK;
+        QP_TRY(start_group());
+        phase = kSolve;
+        return QP_OK;
+    }
+
+    qp_status start_group()
+    {
+        const size_t D2 = 2 * (size_t)p->host.D;
+        const int Kg = std::min(G, p->host.d - r0);
+        return sj.begin(p, Kg, p->F() + r0 * D2, p->chi(0) + r0 * D2, tol);
+    }
+
+    qp_status advance(bool blocking, bool &progressed)
+    {
+        progressed = false;
+        const int d = p->host.d;
+        while (phase == kSolve) {
+            bool pr = false;
+            QP_TRY(sj.advance(blocking, pr));
+            progressed = progressed || pr;
+            if (!sj.done()) return QP_OK;
+            const qp_status s = sj.finish(infos + r0);
+            if (s != QP_OK && worst == QP_OK) worst = s;
+            r0 += G;
+            if (r0 < d) {
+                QP_TRY(start_group());
+                progressed = true;
+                continue;
+            }
+            if (worst == QP_EDEVICE || worst == QP_EINVAL) return worst;
+            QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), p->stream));
+            if (Aenergy) {
+                const qp::Parts parts = p->parts();
+                for (int j = 0; j < d; ++j) {
+                    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, 1, p->tab, p->host, p->recs(),
+                                             p->urec(qp::F64), p->upku(qp::F64), p->chi(j), p->q(),
+                                             nullptr, nullptr, parts, p->st(), nullptr, p->stream));
+                    for (int i = 0; i < d; ++i)
+                        QP_HIP(qp::launch_dot(p->tab, p->host, p->chi(i), p->q(), parts,
+                                              p->small() + 64 + i * d + j, p->stream));
+                }
+            }
+            QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double),
+                                  hipMemcpyDeviceToHost, p->stream));
+            QP_HIP(hipEventRecord(p->ev_fin, p->stream));
+            phase = kAstar;
+            progressed = true;
+        }
+        if (phase == kAstar) {
+            bool ready = false;
+            QP_TRY(sj.event_ready(p->ev_fin, blocking, ready));
+            if (!ready) return QP_OK;
+            for (int e = 0; e < d * d; ++e) Astar[e] = p->hsmall[e];
+            if (Aenergy)
+                for (int i = 0; i < d; ++i)
+                    for (int j = 0; j < d; ++j)
+                        Aenergy[i * d + j] =
+                            (i == j ? p->host.a0l[i] : 0.0) - p->hsmall[64 + i * d + j];
+            phase = kDone;
+            progressed = true;
+            if (worst != QP_OK) {
+                report(worst);
+                if (worst == QP_ENOCONV || worst == QP_ENOTSPD || worst == QP_ENONFINITE)
+                    fail(worst, "a corrector solve did not converge");
+            }
+        }
+        return QP_OK;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- serving
+//
+// A request is a homogenization of a problem given by its description.  The
+// server keeps created problems (workspace, tables, preconditioner) in a
+// cache bounded by an HBM budget; a request is admitted, in arrival order,
+// when its problem is cached and idle, or when the problem can be created
+// within the budget after evicting idle problems (least recently used
+// first).  Every admitted request runs as a HomJob on its problem's stream,
+// so requests join and leave the running set one by one while the others
+// keep iterating.
+struct qp_server {
+    size_t budget = 0, used = 0;
+    qp_options opt{};
+    struct Entry {
+        std::string key;
+        qp_problem *p = nullptr;
+        size_t bytes = 0;
+        bool busy = false;
+        uint64_t last_use = 0;
+    };
+    std::vector<Entry> cache;
+    struct Request {
+        int64_t ticket = 0;
+        std::string key;
+        int d = 0, n = 0, N = 0, g = 0;
+        bool diag = false;
+        std::vector<double> P, coef;
+        std::vector<int32_t> modes;
+        double tol = 0.0;
+        double *Astar = nullptr;
+        qp_solve_info *infos = nullptr;
+        size_t bytes = 0;
+    };
+    std::vector<Request> queue;
+    struct Running {
+        int64_t ticket = 0;
+        size_t entry = 0;
+        HomJob job;
+    };
+    std::vector<std::unique_ptr<Running>> running;
+    struct Finished {
+        int64_t ticket;
+        qp_status status;
+    };
+    std::vector<Finished> finished;
+    int64_t next_ticket = 1;
+    uint64_t clock = 0;
+};
+
+namespace {
 
 qp_status check_options(const qp_options *o)
 {
@@ -984,6 +1274,8 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     for (auto &e : p->ev_poll)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return bail(fail(QP_EDEVICE, "hipEventCreate failed"));
+    if (hipEventCreateWithFlags(&p->ev_fin, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(QP_EDEVICE, "hipEventCreate failed"));
     if (hipEventCreate(&p->ev_t0) != hipSuccess || hipEventCreate(&p->ev_t1) != hipSuccess)
         return bail(fail(QP_EDEVICE, "hipEventCreate failed"));
     p->tab = p->at<Table>(p->L.tab);
@@ -1108,33 +1400,52 @@ qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy, 
                             qp_solve_info *info)
 {
     if (!p || !Astar) return fail(QP_EINVAL, "null argument");
-    const int d = p->host.d;
-    // the d corrector right-hand sides, solved together
-    for (int j = 0; j < d; ++j)
-        QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, p->F() + (size_t)2 * p->host.D * j,
-                                        p->stream));
-    const qp_status worst = solve_dispatch(p, d, p->F(), p->chi(0), tol, info);
-    if (worst == QP_EDEVICE || worst == QP_EINVAL) return worst;
-    QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), p->stream));
-    if (Astar_energy) {
-        const qp::Parts parts = p->parts();
-        for (int j = 0; j < d; ++j) {
-            QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, 1, p->tab, p->host, p->recs(),
-                                     p->urec(qp::F64), p->upku(qp::F64), p->chi(j), p->q(), nullptr,
-                                     nullptr, parts, p->st(), nullptr, p->stream));
-            for (int i = 0; i < d; ++i)
-                QP_HIP(qp::launch_dot(p->tab, p->host, p->chi(i), p->q(), parts,
-                                      p->small() + 64 + i * d + j, p->stream));
-        }
+    HomJob job;
+    QP_TRY(job.begin(p, Astar, Astar_energy, tol, info));
+    bool progressed = false;
+    while (!job.done()) QP_TRY(job.advance(true, progressed));
+    return job.worst;
+}
+
+qp_status qp_homogenized_batch(qp_problem *const *problems, int count, double *Astar, double tol,
+                               qp_solve_info *infos)
+{
+    if (!problems || !Astar || count < 1) return fail(QP_EINVAL, "null argument or empty batch");
+    for (int i = 0; i < count; ++i) {
+        if (!problems[i]) return fail(QP_EINVAL, "problem %d is null", i);
+        for (int k = 0; k < i; ++k)
+            if (problems[k] == problems[i]) return fail(QP_EINVAL, "problem %d repeats problem %d", i, k);
     }
-    QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-    QP_HIP(hipStreamSynchronize(p->stream));
-    for (int e = 0; e < d * d; ++e) Astar[e] = p->hsmall[e];
-    if (Astar_energy)
-        for (int i = 0; i < d; ++i)
-            for (int j = 0; j < d; ++j)
-                Astar_energy[i * d + j] = (i == j ? p->host.a0l[i] : 0.0) - p->hsmall[64 + i * d + j];
-    if (worst != QP_OK) fail(worst, "a corrector solve did not converge");
+    std::vector<HomJob> jobs(count);
+    size_t ao = 0, io = 0;
+    for (int i = 0; i < count; ++i) {
+        const int d = problems[i]->host.d;
+        QP_TRY(jobs[i].begin(problems[i], Astar + ao, nullptr, tol, infos ? infos + io : nullptr));
+        ao += (size_t)d * d;
+        io += d;
+    }
+    // Round robin: every job queues what it can and returns when the poll it
+    // needs has not arrived; the streams run concurrently on the device.
+    for (;;) {
+        bool all = true, any = false;
+        for (auto &J : jobs) {
+            if (J.done()) continue;
+            bool pr = false;
+            const qp_status s = J.advance(false, pr);
+            if (s != QP_OK) {
+                for (auto &K : jobs) (void)hipStreamSynchronize(K.p->stream);
+                return s;
+            }
+            any = any || pr;
+            all = all && J.done();
+        }
+        if (all) break;
+        if (!any) std::this_thread::yield();
+    }
+    qp_status worst = QP_OK;
+    for (auto &J : jobs)
+        if (J.worst != QP_OK && worst == QP_OK) worst = J.worst;
+    if (worst != QP_OK) fail(worst, "a corrector solve of the batch did not converge");
     return worst;
 }
 
@@ -1230,5 +1541,216 @@ const char *qp_strerror(qp_status s)
 }
 
 const char *qp_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------- serving
+
+qp_status qp_server_create(qp_server **out, size_t hbm_budget, const qp_options *opt)
+{
+    g_last_error.clear();
+    if (!out) return fail(QP_EINVAL, "out is null");
+    *out = nullptr;
+    if (hbm_budget == 0) return fail(QP_EINVAL, "hbm_budget is 0");
+    qp_options o;
+    qp_default_options(&o);
+    if (opt) o = *opt;
+    QP_TRY(check_options(&o));
+    o.stream = nullptr;     // every cached problem gets a stream of its own
+    o.workspace = nullptr;  // and a workspace of its own
+    o.workspace_bytes = 0;
+    qp_server *s = new (std::nothrow) qp_server();
+    if (!s) return fail(QP_ENOMEM, "host allocation failed");
+    s->budget = hbm_budget;
+    s->opt = o;
+    *out = s;
+    return QP_OK;
+}
+
+qp_status qp_server_submit(qp_server *s, int d, int n, const double *P, int g,
+                           const int32_t *modes, const double *coef, const double *coefs, int N,
+                           double tol, double *Astar, qp_solve_info *infos, int64_t *ticket)
+{
+    if (!s || !Astar || !ticket) return fail(QP_EINVAL, "null argument");
+    *ticket = 0;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QP_EINVAL, "tol must be positive and finite");
+    if (coefs) {
+        if (d < 1 || d > QP_MAX_DIM_D) return fail(QP_EINVAL, "d=%d outside [1, %d]", d, QP_MAX_DIM_D);
+        for (int l = 0; l < d; ++l) QP_TRY(check_args(d, n, P, g, modes, coefs + 2 * (size_t)l * g, N));
+    } else {
+        QP_TRY(check_args(d, n, P, g, modes, coef, N));
+    }
+    const size_t bytes = qp_workspace_bytes(d, n, N, g);
+    if (bytes == 0) return fail(QP_EINVAL, "unsupported shape");
+    if (bytes > s->budget)
+        return fail(QP_ENOMEM, "the problem needs %zu bytes, more than the budget of %zu", bytes,
+                    s->budget);
+    qp_server::Request R;
+    R.d = d;
+    R.n = n;
+    R.N = N;
+    R.g = g;
+    R.diag = coefs != nullptr;
+    R.P.assign(P, P + (size_t)d * n);
+    R.modes.assign(modes, modes + (size_t)g * n);
+    const double *c = coefs ? coefs : coef;
+    R.coef.assign(c, c + 2 * (size_t)g * (coefs ? d : 1));
+    R.tol = tol;
+    R.Astar = Astar;
+    R.infos = infos;
+    R.bytes = bytes;
+    // cache key: the full description (the options are the server's)
+    std::string key;
+    auto put = [&key](const void *v, size_t nb) { key.append(static_cast<const char *>(v), nb); };
+    const int head[5] = {d, n, N, g, R.diag ? 1 : 0};
+    put(head, sizeof(head));
+    put(R.P.data(), R.P.size() * sizeof(double));
+    put(R.modes.data(), R.modes.size() * sizeof(int32_t));
+    put(R.coef.data(), R.coef.size() * sizeof(double));
+    R.key = std::move(key);
+    R.ticket = s->next_ticket++;
+    *ticket = R.ticket;
+    s->queue.push_back(std::move(R));
+    return QP_OK;
+}
+
+namespace {
+
+// Admit queued requests in arrival order.  A request whose problem would
+// have to be created but does not fit stops the creation of problems for
+// the requests behind it (they may still run on cached idle problems).
+qp_status server_admit(qp_server *s)
+{
+    bool create_ok = true;
+    for (size_t qi = 0; qi < s->queue.size();) {
+        qp_server::Request &R = s->queue[qi];
+        size_t e = s->cache.size();
+        for (size_t c = 0; c < s->cache.size(); ++c)
+            if (s->cache[c].key == R.key) e = c;
+        if (e < s->cache.size() && s->cache[e].busy) {
+            ++qi;
+            continue;
+        }
+        if (e == s->cache.size()) {
+            if (!create_ok) {
+                ++qi;
+                continue;
+            }
+            // evict idle problems, least recently used first, until it fits
+            while (s->used + R.bytes > s->budget) {
+                size_t victim = s->cache.size();
+                for (size_t c = 0; c < s->cache.size(); ++c)
+                    if (!s->cache[c].busy &&
+                        (victim == s->cache.size() || s->cache[c].last_use < s->cache[victim].last_use))
+                        victim = c;
+                if (victim == s->cache.size()) break;
+                qp_destroy(s->cache[victim].p);
+                s->used -= s->cache[victim].bytes;
+                s->cache.erase(s->cache.begin() + victim);
+                // running jobs refer to cache slots by index
+                for (auto &run : s->running)
+                    if (run->entry > victim) --run->entry;
+            }
+            if (s->used + R.bytes > s->budget) {
+                create_ok = false;
+                ++qi;
+                continue;
+            }
+            qp_problem *p = nullptr;
+            const qp_status cs =
+                create_problem(&p, R.d, R.n, R.P.data(), R.g, R.modes.data(),
+                               R.diag ? nullptr : R.coef.data(), R.diag ? R.coef.data() : nullptr,
+                               R.N, &s->opt);
+            if (cs != QP_OK) {
+                s->finished.push_back({R.ticket, cs});
+                s->queue.erase(s->queue.begin() + qi);
+                continue;
+            }
+            qp_server::Entry E;
+            E.key = R.key;
+            E.p = p;
+            E.bytes = R.bytes;
+            s->cache.push_back(std::move(E));
+            s->used += R.bytes;
+            e = s->cache.size() - 1;
+        }
+        qp_server::Entry &E = s->cache[e];
+        auto run = std::make_unique<qp_server::Running>();
+        run->ticket = R.ticket;
+        run->entry = e;
+        const qp_status bs = run->job.begin(E.p, R.Astar, nullptr, R.tol, R.infos);
+        if (bs != QP_OK) {
+            s->finished.push_back({R.ticket, bs});
+        } else {
+            E.busy = true;
+            E.last_use = ++s->clock;
+            s->running.push_back(std::move(run));
+        }
+        s->queue.erase(s->queue.begin() + qi);
+    }
+    return QP_OK;
+}
+
+}  // namespace
+
+qp_status qp_server_progress(qp_server *s, int wait_us, int64_t *done, qp_status *done_status,
+                             int max_done, int *ndone)
+{
+    if (!s || !ndone || (max_done > 0 && !done)) return fail(QP_EINVAL, "null argument");
+    *ndone = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        QP_TRY(server_admit(s));
+        bool any = false;
+        for (size_t i = 0; i < s->running.size();) {
+            qp_server::Running &run = *s->running[i];
+            bool pr = false;
+            const qp_status st = run.job.advance(false, pr);
+            any = any || pr;
+            if (st != QP_OK || run.job.done()) {
+                s->finished.push_back({run.ticket, st != QP_OK ? st : run.job.worst});
+                qp_server::Entry &E = s->cache[run.entry];
+                E.busy = false;
+                E.last_use = ++s->clock;
+                s->running.erase(s->running.begin() + i);
+                any = true;
+                continue;
+            }
+            ++i;
+        }
+        if (!s->finished.empty() || (s->running.empty() && s->queue.empty())) break;
+        const auto us = std::chrono::duration_cast<std::chrono::microseconds>(
+                            std::chrono::steady_clock::now() - t0).count();
+        if (us >= wait_us) break;
+        if (!any) std::this_thread::yield();
+    }
+    int k = 0;
+    while (k < max_done && !s->finished.empty()) {
+        done[k] = s->finished.front().ticket;
+        if (done_status) done_status[k] = s->finished.front().status;
+        s->finished.erase(s->finished.begin());
+        ++k;
+    }
+    *ndone = k;
+    return QP_OK;
+}
+
+int qp_server_pending(const qp_server *s)
+{
+    if (!s) return 0;
+    return (int)(s->queue.size() + s->running.size() + s->finished.size());
+}
+
+size_t qp_server_bytes(const qp_server *s) { return s ? s->used : 0; }
+
+void qp_server_destroy(qp_server *s)
+{
+    if (!s) return;
+    for (auto &run : s->running) {
+        bool pr = false;
+        while (!run->job.done())
+            if (run->job.advance(true, pr) != QP_OK) break;
+    }
+    for (auto &E : s->cache) qp_destroy(E.p);
+    delete s;
+}
 
 }  // extern "C"

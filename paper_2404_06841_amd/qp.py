@@ -43,7 +43,9 @@ EXPORTED = (
     "qp_dim",
     "qp_set_options", "qp_solve", "qp_solve_d", "qp_solve_multi_d", "qp_corrector",
     "qp_corrector_d",
-    "qp_homogenized", "qp_homogenized_ex", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
+    "qp_homogenized", "qp_homogenized_ex", "qp_homogenized_batch", "qp_server_create",
+    "qp_server_submit", "qp_server_progress", "qp_server_pending", "qp_server_bytes",
+    "qp_server_destroy", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
     "qp_corrector_rhs_d", "qp_multi_index_d", "qp_astar_d", "qp_coef_extrema",
     "qp_synchronize", "qp_strerror", "qp_last_error",
 )
@@ -104,6 +106,17 @@ def lib():
         "qp_corrector_d": (C.c_int, [vp, C.c_int, vp, C.c_double, C.POINTER(qp_solve_info)]),
         "qp_homogenized": (C.c_int, [vp, dp, C.c_double, C.POINTER(qp_solve_info)]),
         "qp_homogenized_ex": (C.c_int, [vp, dp, dp, C.c_double, C.POINTER(qp_solve_info)]),
+        "qp_homogenized_batch": (C.c_int, [C.POINTER(vp), C.c_int, dp, C.c_double,
+                                           C.POINTER(qp_solve_info)]),
+        "qp_server_create": (C.c_int, [C.POINTER(vp), C.c_size_t, C.POINTER(qp_options)]),
+        "qp_server_submit": (C.c_int, [vp, C.c_int, C.c_int, dp, C.c_int, ip, dp, dp, C.c_int,
+                                       C.c_double, dp, C.POINTER(qp_solve_info),
+                                       C.POINTER(C.c_int64)]),
+        "qp_server_progress": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int),
+                                         C.c_int, C.POINTER(C.c_int)]),
+        "qp_server_pending": (C.c_int, [vp]),
+        "qp_server_bytes": (C.c_size_t, [vp]),
+        "qp_server_destroy": (None, [vp]),
         "qp_matvec_d": (C.c_int, [vp, vp, vp]),
         "qp_matvec32_d": (C.c_int, [vp, vp, vp]),
         "qp_precond_d": (C.c_int, [vp, vp]),
@@ -375,3 +388,102 @@ class Problem:
 
     def synchronize(self):
         _check(lib().qp_synchronize(self.h), "qp_synchronize")
+
+
+# --------------------------------------------------------------------------
+# Batches and serving
+# --------------------------------------------------------------------------
+
+def homogenized_batch(problems, tol: float = 1e-12, check: bool = True):
+    """qp_homogenized_batch over Problem objects (each should own a distinct
+    stream for the solves to overlap).  Returns (list of d x d A*, list of
+    per-problem info lists, status)."""
+    count = len(problems)
+    ds = [pr.d for pr in problems]
+    A = np.zeros(sum(d * d for d in ds))
+    infos = (qp_solve_info * sum(ds))()
+    hs = (C.c_void_p * count)(*[pr.h for pr in problems])
+    st = lib().qp_homogenized_batch(hs, count, _dptr(A), float(tol), infos)
+    if check:
+        _check(st, "qp_homogenized_batch")
+    outA, outI, ao, io = [], [], 0, 0
+    for d in ds:
+        outA.append(A[ao:ao + d * d].reshape(d, d).copy())
+        outI.append([infos[io + j] for j in range(d)])
+        ao += d * d
+        io += d
+    return outA, outI, st
+
+
+class Server:
+    """qp_server: homogenization requests over a cache of problems bounded by
+    an HBM budget.  submit() returns a ticket; progress() returns the finished
+    tickets; result(ticket) gives (A*, infos, status) once finished."""
+
+    def __init__(self, hbm_budget: int, precision: str = "fp64", maxit: int = 10000,
+                 inner_tol: float = 1e-4):
+        opt = qp_default_options()
+        opt.precision = QP_PREC_FP32_IR if precision == "fp32ir" else QP_PREC_FP64
+        opt.maxit = int(maxit)
+        opt.inner_tol = float(inner_tol)
+        self.opt = opt
+        h = C.c_void_p()
+        _check(lib().qp_server_create(C.byref(h), int(hbm_budget), C.byref(opt)), "qp_server_create")
+        self.h = h
+        self._out = {}     # ticket -> (A buffer, infos buffer, d)
+        self._status = {}  # finished ticket -> status
+
+    def submit(self, prob, tol: float = 1e-12) -> int:
+        d, n, N = int(prob.d), int(prob.n), int(prob.N)
+        P = np.ascontiguousarray(prob.P, dtype=np.float64).reshape(-1)
+        modes = np.ascontiguousarray(prob.modes, dtype=np.int32).reshape(-1)
+        g = modes.size // n
+        coefs = getattr(prob, "coefs", None)
+        if coefs is not None:
+            c = np.ascontiguousarray(np.asarray(coefs, dtype=np.complex128).reshape(-1)).view(np.float64)
+            coef_p, coefs_p = None, _dptr(c)
+        else:
+            c = np.ascontiguousarray(np.asarray(prob.coef, dtype=np.complex128).reshape(-1)).view(np.float64)
+            coef_p, coefs_p = _dptr(c), None
+        A = np.zeros(d * d)
+        infos = (qp_solve_info * d)()
+        t = C.c_int64(0)
+        st = lib().qp_server_submit(self.h, d, n, _dptr(P), g,
+                                    modes.ctypes.data_as(C.POINTER(C.c_int32)), coef_p, coefs_p,
+                                    N, float(tol), _dptr(A), infos, C.byref(t))
+        _check(st, "qp_server_submit")
+        self._out[t.value] = (A, infos, d)
+        return t.value
+
+    def progress(self, wait_us: int = 1000, max_done: int = 64):
+        done = (C.c_int64 * max_done)()
+        stat = (C.c_int * max_done)()
+        nd = C.c_int(0)
+        _check(lib().qp_server_progress(self.h, int(wait_us), done, stat, max_done, C.byref(nd)),
+               "qp_server_progress")
+        out = []
+        for i in range(nd.value):
+            self._status[done[i]] = stat[i]
+            out.append(done[i])
+        return out
+
+    def result(self, ticket: int):
+        A, infos, d = self._out[ticket]
+        return A.reshape(d, d), [infos[j] for j in range(d)], self._status.get(ticket)
+
+    def pending(self) -> int:
+        return int(lib().qp_server_pending(self.h))
+
+    def bytes(self) -> int:
+        return int(lib().qp_server_bytes(self.h))
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lib().qp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -160,3 +160,20 @@ def test_valid_diagonal_problem_without_device_reports_device_error():
         pytest.skip("a GPU is present")
     st, h = qp.qp_create_diag(DIAG.d, DIAG.n, DIAG.P, DIAG.modes, DIAG.coefs, DIAG.N)
     assert st == qp.QP_EDEVICE and h is None
+
+
+def test_server_and_batch_argument_checks_on_host():
+    h = qp.C.c_void_p()
+    assert qp.lib().qp_server_create(qp.C.byref(h), 0, None) == qp.QP_EINVAL
+    srv = qp.Server(1 << 30)  # creating a server touches no device
+    with pytest.raises(qp.QPError):
+        srv.submit(W.eightfold(8), tol=-1.0)
+    bad = W.eightfold(8)
+    bad = W.Problem(bad.name, bad.d, bad.n, 2, bad.P, bad.modes, bad.coef)  # |m| >= N/2
+    with pytest.raises(qp.QPError):
+        srv.submit(bad, tol=1e-12)
+    with pytest.raises(qp.QPError):
+        srv.submit(W.icosahedral(16), tol=1e-12)  # needs more than the 1 GiB budget
+    assert srv.pending() == 0 and srv.bytes() == 0
+    srv.close()
+    assert qp.lib().qp_homogenized_batch(None, 0, None, 1e-12, None) == qp.QP_EINVAL
