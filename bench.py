@@ -165,6 +165,100 @@ def diagonal_workload(torch, np, qp, W, gold, steps: int, warmup: int):
     return res
 
 
+def batch_instances(torch, np, qp, W, reps: int = 3):
+    """64 seeded eightfold instances with N drawn from {8, 12, 16, 24, 32}
+    (16.2M unknowns for the default seed), two correctors each, FP32-IR:
+    homogenized together by
+    qp_homogenized_batch (each problem on its own stream) versus one after
+    another on the same problems."""
+    probs = W.eightfold_batch(64)
+    gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream()) for pr in probs]
+    solves = sum(pr.d for pr in probs)
+    qp.homogenized_batch(gps, tol=TOL)  # warm-up (graphs, caches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        As, _, st = qp.homogenized_batch(gps, tol=TOL)
+    dt_b = (time.perf_counter() - t0) / reps
+    seq = [gp.homogenized(tol=TOL, energy=False).A.copy() for gp in gps]
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for gp in gps:
+            gp.homogenized(tol=TOL, energy=False)
+    dt_s = (time.perf_counter() - t0) / reps
+    same = all(np.array_equal(a, b) for a, b in zip(As, seq))
+    for gp in gps:
+        gp.close()
+    Ns = sorted(set(int(pr.N) for pr in probs))
+    return {"workload": f"64 seeded eightfold d=2 n=4 instances, N in {Ns} "
+                        f"({sum(pr.D for pr in probs):,} unknowns), 2 correctors each, FP32-IR",
+            "value": round(solves / dt_b, 2), "unit": "corrector solves/s",
+            "ms_per_batch": round(dt_b * 1e3, 3), "status": int(st),
+            "sequential_value": round(solves / dt_s, 2),
+            "sequential_ms": round(dt_s * 1e3, 3),
+            "speedup_vs_sequential": round(dt_s / dt_b, 3),
+            "results_equal_sequential": bool(same)}
+
+
+def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):
+    """Homogenization requests served by qp_server (FP32-IR): icosahedral d=3
+    n=6 problems at N = 6, 8, 12, 16 mixed with eightfold n=4 problems at
+    N = 16, 24, 32, drawn uniformly (seeded).  Capacity is measured with all
+    requests queued at once; then the same mix arrives as a seeded Poisson
+    stream at `load` times that capacity, and each request's latency (arrival
+    to result) is recorded."""
+    configs = [W.icosahedral(6), W.icosahedral(8), W.icosahedral(12), W.icosahedral(16),
+               W.eightfold_random(16, 11), W.eightfold_random(24, 12),
+               W.eightfold_random(32, 13)]
+    rng = np.random.default_rng(W.BASE_SEED + 77)
+    mix = [int(i) for i in rng.integers(0, len(configs), size=requests)]
+    srv = qp.Server(96 << 30, precision="fp32ir")
+
+    def drain(tickets):
+        left, fin = set(tickets), {}
+        while left:
+            for t in srv.progress(wait_us=1000):
+                if t in left:
+                    left.discard(t)
+                    fin[t] = time.perf_counter()
+        return fin
+
+    drain([srv.submit(c, tol=TOL) for c in configs])  # every problem created once
+    t0 = time.perf_counter()
+    drain([srv.submit(configs[i], tol=TOL) for i in mix])
+    cap = requests / (time.perf_counter() - t0)
+    gaps = rng.exponential(1.0 / (load * cap), size=requests)
+    arrive, submitted, finish, tickets = np.cumsum(gaps), {}, {}, []
+    t0 = time.perf_counter()
+    k = 0
+    while len(finish) < requests:
+        now = time.perf_counter() - t0
+        while k < requests and arrive[k] <= now:
+            t = srv.submit(configs[mix[k]], tol=TOL)
+            submitted[t] = t0 + arrive[k]
+            tickets.append(t)
+            k += 1
+        wait = 1000 if k >= requests else int(max(50.0, min(1000.0, (arrive[k] - now) * 1e6)))
+        for t in srv.progress(wait_us=wait):
+            finish[t] = time.perf_counter()
+    span = max(finish.values()) - t0
+    lat = np.array([(finish[t] - submitted[t]) * 1e3 for t in tickets])
+    bad = sum(1 for t in tickets if srv.result(t)[2] != qp.QP_OK)
+    solves = sum(configs[i].d for i in mix)
+    cached = srv.bytes()
+    srv.close()
+    return {"workload": f"{requests} homogenization requests, icosahedral N 6/8/12/16 and eightfold "
+                        "N 16/24/32 mixed uniformly; Poisson arrivals (seeded) at "
+                        f"{load} x measured capacity; FP32-IR",
+            "capacity_requests_per_s": round(cap, 2),
+            "offered_requests_per_s": round(load * cap, 2),
+            "value": round(solves / span, 2), "unit": "corrector solves/s",
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                           "p99": round(float(np.percentile(lat, 99)), 3),
+                           "max": round(float(lat.max()), 3)},
+            "failed": bad, "cached_problem_bytes": int(cached)}
+
+
 def cpu_baseline(prob):
     """The oracle, unmodified, on this host's cores: FP64 homogenizations of the
     same workload (two corrector solves at tol 1e-12 each), repeated until at
@@ -280,6 +374,8 @@ def main():
         "diagonal_coefficient": diagonal_workload(torch, np, qp, W, gold,
                                                   max(5, args.steps // 2), args.warmup),
         "hbm_products": hbm_products(torch, qp, W),
+        "batch_instances": batch_instances(torch, np, qp, W),
+        "serving": serving(torch, np, qp, W),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
