@@ -142,6 +142,51 @@ def hbm_products(torch, qp, W):
     return out
 
 
+def per_launch_us(torch, fn, reps: int = 20, warm: int = 3) -> float:
+    """Average duration of fn() (an entry point that returns after its launch
+    completed), each call bracketed by its own HIP events on torch's current
+    stream (the library's stream)."""
+    for _ in range(warm):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    return sum(e0.elapsed_time(e1) for e0, e1 in ev) * 1e3 / reps
+
+
+def stored_matrix(torch, qp, W):
+    """The paper's compressed matrix (Alg. 1: D * g stored triples (i, j,
+    Q_ij), int32 indices and FP64 complex values) against the matrix-free
+    product, FP64, one right-hand side per launch."""
+    out = {}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    for name, prob in (("eightfold d=2 n=4 N=32", W.eightfold_random(32, 0)),
+                       ("icosahedral d=3 n=6 N=16", W.icosahedral(16))):
+        gp = qp.Problem(prob)
+        t0 = time.perf_counter()
+        coo = gp.coo_build_d()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        D, g = prob.D, prob.g
+        u = torch.randn(D, dtype=torch.complex128, device="cuda", generator=gen)
+        y = torch.empty_like(u)
+        t_coo = per_launch_us(torch, lambda: gp.coo_matvec_d(coo, u, y))
+        t_mf = per_launch_us(torch, lambda: gp.matvec_d(u, y))
+        entries = D * g
+        out[name] = {"unknowns": D, "entries": entries, "stored_bytes": entries * 24,
+                     "build_ms": round(build_ms, 2),
+                     "stored_product_us": round(t_coo, 2), "matrix_free_product_us": round(t_mf, 2),
+                     "stored_over_matrix_free": round(t_coo / t_mf, 2),
+                     "stored_GBs_read": round((entries * 20 + 32 * D) / (t_coo * 1e-6) / 1e9, 1)}
+        del coo, u, y
+        gp.close()
+    return out
+
+
 def diagonal_workload(torch, np, qp, W, gold, steps: int, warmup: int):
     """The diagonal coefficient diag(a_1, a_2) of App. D on the eightfold P at
     N=32 (an independent seeded random field per entry): homogenizations in
@@ -375,6 +420,7 @@ def main():
                                                   max(5, args.steps // 2), args.warmup),
         "hbm_products": hbm_products(torch, qp, W),
         "batch_instances": batch_instances(torch, np, qp, W),
+        "stored_matrix": stored_matrix(torch, qp, W),
         "serving": serving(torch, np, qp, W),
     }
     if not args.no_cpu_baseline:

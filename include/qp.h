@@ -308,6 +308,24 @@ size_t qp_server_bytes(const qp_server *s);
 /* Finish the running requests, release every cached problem and the server. */
 void qp_server_destroy(qp_server *s);
 
+/* ---- the compressed stiffness matrix of Alg. 1 (comparison path) ---- */
+
+/*
+ * The paper stores Q = A o W as triples (i, j, Q_ij) (Alg. 1 and the
+ * compressed matrix-vector product of Sec. 4.2).  This build keeps them as a
+ * comparison for the matrix-free product: D * g entries ordered mode-major
+ * (row i's entry for the r-th coefficient mode, in the problem's mode order,
+ * is element r*D + i; an entry whose value is zero keeps its slot), values
+ * computed in FP64 from the integer indices.  The arrays are the caller's
+ * device buffers (rows, cols: int32; vals: complex (re, im) doubles), each of
+ * qp_coo_entries(p) elements; nothing is allocated.
+ */
+int64_t qp_coo_entries(const qp_problem *p);
+qp_status qp_coo_build_d(qp_problem *p, int32_t *rows, int32_t *cols, double *vals);
+/* y = Q u from the triples of qp_coo_build_d (FP64; u, y: D complex, device). */
+qp_status qp_coo_matvec_d(qp_problem *p, const int32_t *cols, const double *vals, const double *u,
+                          double *y);
+
 /* ---- single steps of the path, device pointers (used by parity tests) ---- */
 
 /* y = Q u in FP64 (eq. linear_system; y[C(0)] = 0, u[C(0)] ignored). */

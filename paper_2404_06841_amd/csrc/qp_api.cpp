@@ -1474,6 +1474,28 @@ qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
     return QP_OK;
 }
 
+int64_t qp_coo_entries(const qp_problem *p)
+{
+    return p ? (int64_t)p->host.D * p->host.g : 0;
+}
+
+qp_status qp_coo_build_d(qp_problem *p, int32_t *rows, int32_t *cols, double *vals)
+{
+    if (!p || !rows || !cols || !vals) return fail(QP_EINVAL, "null argument");
+    QP_HIP(qp::launch_coo_build(p->tab, p->host, rows, cols, vals, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
+qp_status qp_coo_matvec_d(qp_problem *p, const int32_t *cols, const double *vals, const double *u,
+                          double *y)
+{
+    if (!p || !cols || !vals || !u || !y) return fail(QP_EINVAL, "null argument");
+    QP_HIP(qp::launch_coo_matvec(p->host, cols, vals, u, y, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
 qp_status qp_precond_d(qp_problem *p, double *M)
 {
     if (!p || !M) return fail(QP_EINVAL, "null argument");

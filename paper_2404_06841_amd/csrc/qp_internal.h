@@ -223,6 +223,13 @@ hipError_t launch_dot(const Table *tab, const Table &ht, const double *x, const 
                       const Parts &parts, double *out, hipStream_t s);
 // Signed multi-index of every entry (D x n int32).
 hipError_t launch_multi_index(const Table *tab, const Table &ht, int32_t *k, hipStream_t s);
+// The compressed stiffness matrix of Alg. 1: D * g triples (i, j, Q_ij),
+// mode-major (row i's r-th entry at r D + i, zero values kept), FP64 values.
+hipError_t launch_coo_build(const Table *tab, const Table &ht, int32_t *rows, int32_t *cols,
+                            double *vals, hipStream_t s);
+// y = Q x from those triples (FP64).
+hipError_t launch_coo_matvec(const Table &ht, const int32_t *cols, const double *vals,
+                             const double *x, double *y, hipStream_t s);
 // Reset K States (flags, counters) with a kernel (no memset node).
 hipError_t launch_state_reset(int K, State *st, hipStream_t s);
 

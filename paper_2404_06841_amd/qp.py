@@ -45,7 +45,7 @@ EXPORTED = (
     "qp_corrector_d",
     "qp_homogenized", "qp_homogenized_ex", "qp_homogenized_batch", "qp_server_create",
     "qp_server_submit", "qp_server_progress", "qp_server_pending", "qp_server_bytes",
-    "qp_server_destroy", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
+    "qp_server_destroy", "qp_coo_entries", "qp_coo_build_d", "qp_coo_matvec_d", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
     "qp_corrector_rhs_d", "qp_multi_index_d", "qp_astar_d", "qp_coef_extrema",
     "qp_synchronize", "qp_strerror", "qp_last_error",
 )
@@ -117,6 +117,9 @@ def lib():
         "qp_server_pending": (C.c_int, [vp]),
         "qp_server_bytes": (C.c_size_t, [vp]),
         "qp_server_destroy": (None, [vp]),
+        "qp_coo_entries": (C.c_int64, [vp]),
+        "qp_coo_build_d": (C.c_int, [vp, vp, vp, vp]),
+        "qp_coo_matvec_d": (C.c_int, [vp, vp, vp, vp, vp]),
         "qp_matvec_d": (C.c_int, [vp, vp, vp]),
         "qp_matvec32_d": (C.c_int, [vp, vp, vp]),
         "qp_precond_d": (C.c_int, [vp, vp]),
@@ -352,6 +355,28 @@ class Problem:
             out = torch.empty(self.D, dtype=torch.complex64, device="cuda")
         _check(lib().qp_matvec32_d(self.h, _tensor_ptr(u, torch.complex64, self.D),
                                    _tensor_ptr(out, torch.complex64, self.D)), "qp_matvec32_d")
+        return out
+
+    def coo_build_d(self):
+        """The compressed matrix of Alg. 1 as device tensors (rows, cols, vals)."""
+        import torch
+        n = int(lib().qp_coo_entries(self.h))
+        rows = torch.empty(n, dtype=torch.int32, device="cuda")
+        cols = torch.empty(n, dtype=torch.int32, device="cuda")
+        vals = torch.empty(n, dtype=torch.complex128, device="cuda")
+        _check(lib().qp_coo_build_d(self.h, _tensor_ptr(rows, torch.int32, n),
+                                    _tensor_ptr(cols, torch.int32, n),
+                                    _tensor_ptr(vals, torch.complex128, n)), "qp_coo_build_d")
+        return rows, cols, vals
+
+    def coo_matvec_d(self, coo, u, out=None):
+        import torch
+        _, cols, vals = coo
+        if out is None:
+            out = torch.empty(self.D, dtype=torch.complex128, device="cuda")
+        _check(lib().qp_coo_matvec_d(self.h, _tensor_ptr(cols, torch.int32), _tensor_ptr(vals, torch.complex128),
+                                     _tensor_ptr(u, torch.complex128, self.D),
+                                     _tensor_ptr(out, torch.complex128, self.D)), "qp_coo_matvec_d")
         return out
 
     def precond_d(self):

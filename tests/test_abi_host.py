@@ -177,3 +177,8 @@ def test_server_and_batch_argument_checks_on_host():
     assert srv.pending() == 0 and srv.bytes() == 0
     srv.close()
     assert qp.lib().qp_homogenized_batch(None, 0, None, 1e-12, None) == qp.QP_EINVAL
+
+
+def test_coo_entry_count_without_problem():
+    assert qp.lib().qp_coo_entries(None) == 0
+    assert qp.lib().qp_coo_build_d(None, None, None, None) == qp.QP_EINVAL
