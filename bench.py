@@ -187,6 +187,24 @@ def stored_matrix(torch, qp, W):
     return out
 
 
+def sampled_inputs(torch, qp):
+    """Forward DFT of grid samples (qp_dft_d: the discrete Fourier-Bohr
+    coefficients of a sampled coefficient or right-hand side), FP64 complex,
+    on the eightfold N=32 and icosahedral N=16 grids."""
+    out = {}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    for name, n, N in (("n=4 N=32", 4, 32), ("n=6 N=16", 6, 16)):
+        D = N ** n
+        x = torch.randn(D, dtype=torch.complex128, device="cuda", generator=gen)
+        y = torch.empty_like(x)
+        us = per_launch_us(torch, lambda: qp.dft_d(x, n, N, out=y), reps=10, warm=2)
+        out[name] = {"points": D, "us": round(us, 1),
+                     "GBs_per_pass": round(32.0 * D * n / (us * 1e-6) / 1e9, 1)}
+        del x, y
+    return out
+
+
 def diagonal_workload(torch, np, qp, W, gold, steps: int, warmup: int):
     """The diagonal coefficient diag(a_1, a_2) of App. D on the eightfold P at
     N=32 (an independent seeded random field per entry): homogenizations in
@@ -421,6 +439,7 @@ def main():
         "hbm_products": hbm_products(torch, qp, W),
         "batch_instances": batch_instances(torch, np, qp, W),
         "stored_matrix": stored_matrix(torch, qp, W),
+        "sampled_inputs": sampled_inputs(torch, qp),
         "serving": serving(torch, np, qp, W),
     }
     if not args.no_cpu_baseline:

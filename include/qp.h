@@ -308,6 +308,37 @@ size_t qp_server_bytes(const qp_server *s);
 /* Finish the running requests, release every cached problem and the server. */
 void qp_server_destroy(qp_server *s);
 
+/* ---- sampled inputs: discrete Fourier-Bohr coefficients (Sec. 2.3) ---- */
+
+/*
+ * n-dimensional DFT on the collocation grid T_N^n, in the storage order of
+ * Sec. 3.1.2 (which is also the sample order of y_j = 2 pi j / N, first
+ * axis slowest):
+ *   forward (inverse = 0):  out_k = (1/D) sum_j in_j exp(-i k.y_j)
+ *                           (the discrete coefficients of sampled values),
+ *   inverse (inverse != 0): out_j = sum_k in_k exp(i k.y_j)  (the samples).
+ * in, out: device, D = N^n complex (re, im) doubles; out may equal in.
+ * 1 <= n <= QP_MAX_DIM_N, 1 <= N <= 1024, N^n < 2^31.  stream: hipStream_t
+ * or NULL (the null stream); returns after the transform has finished.
+ * A forward transform of sampled right-hand-side values gives the F of
+ * qp_solve_d.
+ */
+qp_status qp_dft_d(int n, int N, const double *in, double *out, int inverse, void *stream);
+
+/*
+ * The coefficient modes of a sampled real coefficient: from its spectrum
+ * (host, D complex, e.g. qp_dft_d of the samples copied back), keep every k
+ * with |spec_k| or |spec_{-k}| above rel_tol * max|spec| (and k = 0), so
+ * that modes come in +-pairs, and store Hermitian-symmetrized coefficients
+ * (spec_k + conj(spec_{-k})) / 2.  modes (host, max_modes * n int32, signed
+ * in K_N) and coef (host, max_modes complex) receive *g entries in storage
+ * order, ready for qp_create.  QP_EINVAL when more than max_modes modes
+ * qualify, when a retained mode has a component N/2 (it would alias), or for
+ * a zero or non-finite spectrum.  Host only.
+ */
+qp_status qp_modes_from_spectrum(int n, int N, const double *spec, double rel_tol, int max_modes,
+                                 int32_t *modes, double *coef, int *g);
+
 /* ---- the compressed stiffness matrix of Alg. 1 (comparison path) ---- */
 
 /*

@@ -1474,6 +1474,80 @@ qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
     return QP_OK;
 }
 
+qp_status qp_dft_d(int n, int N, const double *in, double *out, int inverse, void *stream)
+{
+    if (!in || !out) return fail(QP_EINVAL, "null argument");
+    if (n < 1 || n > QP_MAX_DIM_N || N < 1 || N > 1024)
+        return fail(QP_EINVAL, "n=%d or N=%d outside [1, %d] x [1, 1024]", n, N, QP_MAX_DIM_N);
+    int64_t D = 1;
+    for (int t = 0; t < n; ++t) {
+        D *= N;
+        if (D >= ((int64_t)1 << 31)) return fail(QP_EINVAL, "N^n exceeds 2^31 - 1");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    QP_HIP(qp::launch_dft(n, N, in, out, inverse ? 1 : 0, s));
+    QP_HIP(hipStreamSynchronize(s));
+    return QP_OK;
+}
+
+qp_status qp_modes_from_spectrum(int n, int N, const double *spec, double rel_tol, int max_modes,
+                                 int32_t *modes, double *coef, int *g)
+{
+    if (!spec || !modes || !coef || !g) return fail(QP_EINVAL, "null argument");
+    *g = 0;
+    if (n < 1 || n > QP_MAX_DIM_N || N < 2) return fail(QP_EINVAL, "n=%d or N=%d out of range", n, N);
+    if (!(rel_tol >= 0.0) || !(rel_tol < 1.0)) return fail(QP_EINVAL, "rel_tol must be in [0, 1)");
+    if (max_modes < 1) return fail(QP_EINVAL, "max_modes < 1");
+    int64_t D = 1;
+    for (int t = 0; t < n; ++t) {
+        D *= N;
+        if (D >= ((int64_t)1 << 31)) return fail(QP_EINVAL, "N^n exceeds 2^31 - 1");
+    }
+    double amax = 0.0;
+    for (int64_t i = 0; i < D; ++i) amax = std::max(amax, std::hypot(spec[2 * i], spec[2 * i + 1]));
+    if (!(amax > 0.0) || !std::isfinite(amax)) return fail(QP_EINVAL, "spectrum is zero or not finite");
+    const double cut = rel_tol * amax;
+    // storage index of -k (digit b -> (N - b) mod N per axis)
+    auto neg = [&](int64_t i) {
+        int64_t r = 0, m = 1, rest = i;
+        for (int t = 0; t < n; ++t) {
+            const int64_t b = rest % N;
+            rest /= N;
+            r += ((N - b) % N) * m;
+            m *= N;
+        }
+        return r;
+    };
+    std::vector<int64_t> keep;
+    for (int64_t i = 0; i < D; ++i) {
+        const double a = std::max(std::hypot(spec[2 * i], spec[2 * i + 1]),
+                                  std::hypot(spec[2 * neg(i)], spec[2 * neg(i) + 1]));
+        if (a > cut || i == 0) keep.push_back(i);  // a mode and its partner together
+    }
+    if ((int64_t)keep.size() > max_modes)
+        return fail(QP_EINVAL, "%lld modes exceed rel_tol, more than max_modes = %d",
+                    (long long)keep.size(), max_modes);
+    int k = 0;
+    for (const int64_t i : keep) {
+        int64_t rest = i;
+        for (int t = n - 1; t >= 0; --t) {
+            const int b = (int)(rest % N);
+            rest /= N;
+            if (2 * b == N)
+                return fail(QP_EINVAL, "a retained mode lies on the N/2 face (would alias)");
+            modes[k * n + t] = (2 * b < N) ? b : b - N;
+        }
+        // Hermitian part: the coefficients of a real field satisfy
+        // Ahat_{-m} = conj(Ahat_m); keep their average
+        const int64_t j = neg(i);
+        coef[2 * k] = 0.5 * (spec[2 * i] + spec[2 * j]);
+        coef[2 * k + 1] = 0.5 * (spec[2 * i + 1] - spec[2 * j + 1]);
+        ++k;
+    }
+    *g = k;
+    return QP_OK;
+}
+
 int64_t qp_coo_entries(const qp_problem *p)
 {
     return p ? (int64_t)p->host.D * p->host.g : 0;

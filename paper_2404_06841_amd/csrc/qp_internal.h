@@ -230,6 +230,9 @@ hipError_t launch_coo_build(const Table *tab, const Table &ht, int32_t *rows, in
 // y = Q x from those triples (FP64).
 hipError_t launch_coo_matvec(const Table &ht, const int32_t *cols, const double *vals,
                              const double *x, double *y, hipStream_t s);
+// n-dimensional DFT on T_N^n in storage order: forward (1/D normalized) or
+// inverse, in (D complex) -> out (D complex; may equal in).
+hipError_t launch_dft(int n, int N, const double *in, double *out, int inverse, hipStream_t s);
 // Reset K States (flags, counters) with a kernel (no memset node).
 hipError_t launch_state_reset(int K, State *st, hipStream_t s);
 

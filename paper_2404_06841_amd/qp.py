@@ -45,7 +45,8 @@ EXPORTED = (
     "qp_corrector_d",
     "qp_homogenized", "qp_homogenized_ex", "qp_homogenized_batch", "qp_server_create",
     "qp_server_submit", "qp_server_progress", "qp_server_pending", "qp_server_bytes",
-    "qp_server_destroy", "qp_coo_entries", "qp_coo_build_d", "qp_coo_matvec_d", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
+    "qp_server_destroy", "qp_coo_entries", "qp_coo_build_d", "qp_coo_matvec_d", "qp_dft_d",
+    "qp_modes_from_spectrum", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
     "qp_corrector_rhs_d", "qp_multi_index_d", "qp_astar_d", "qp_coef_extrema",
     "qp_synchronize", "qp_strerror", "qp_last_error",
 )
@@ -118,6 +119,9 @@ def lib():
         "qp_server_bytes": (C.c_size_t, [vp]),
         "qp_server_destroy": (None, [vp]),
         "qp_coo_entries": (C.c_int64, [vp]),
+        "qp_dft_d": (C.c_int, [C.c_int, C.c_int, vp, vp, C.c_int, vp]),
+        "qp_modes_from_spectrum": (C.c_int, [C.c_int, C.c_int, dp, C.c_double, C.c_int, ip, dp,
+                                             C.POINTER(C.c_int)]),
         "qp_coo_build_d": (C.c_int, [vp, vp, vp, vp]),
         "qp_coo_matvec_d": (C.c_int, [vp, vp, vp, vp, vp]),
         "qp_matvec_d": (C.c_int, [vp, vp, vp]),
@@ -512,3 +516,29 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def dft_d(x, n: int, N: int, inverse: bool = False, out=None):
+    """qp_dft_d on a complex128 CUDA tensor of N^n entries (torch's current stream)."""
+    import torch
+    D = N ** n
+    if out is None:
+        out = torch.empty(D, dtype=torch.complex128, device="cuda")
+    _check(lib().qp_dft_d(int(n), int(N), _tensor_ptr(x, torch.complex128, D),
+                          _tensor_ptr(out, torch.complex128, D), 1 if inverse else 0,
+                          C.c_void_p(torch.cuda.current_stream().cuda_stream)), "qp_dft_d")
+    return out
+
+
+def modes_from_spectrum(spec: np.ndarray, n: int, N: int, rel_tol: float = 1e-12,
+                        max_modes: int = MAX_MODES):
+    """qp_modes_from_spectrum: (modes (g x n int32), coef (g complex))."""
+    sp = np.ascontiguousarray(np.asarray(spec, dtype=np.complex128).reshape(-1)).view(np.float64)
+    modes = np.zeros(max_modes * n, dtype=np.int32)
+    coef = np.zeros(2 * max_modes)
+    g = C.c_int(0)
+    _check(lib().qp_modes_from_spectrum(int(n), int(N), _dptr(sp), float(rel_tol), int(max_modes),
+                                        modes.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(coef),
+                                        C.byref(g)), "qp_modes_from_spectrum")
+    k = g.value
+    return modes[:k * n].reshape(k, n).copy(), coef[:2 * k].view(np.complex128).copy()
