@@ -468,10 +468,10 @@ qp_status enqueue_fp64(qp_problem *p, int K, double *U, int k, int ab, bool prof
     for (int it = 0; it < k; ++it) {
         QP_TRY(queue_matvec(p, qp::F64, qp::EPI_ALPHA, K, p->h(), p->q(), nullptr,
                             prof ? ab * kMaxBatch + it : -1));
-        QP_HIP(qp::launch_pcg_update(qp::F64, it, K, p->tab, p->host, U, p->r(), p->h(), p->q(),
-                                     p->M64(), parts, p->st(), p->stream));
-        QP_HIP(qp::launch_pcg_direction(qp::F64, it, K, p->tab, p->host, p->r(), p->h(), p->M64(),
-                                        parts, p->st(), p->stream));
+        QP_HIP(qp::launch_pcg_update(qp::F64, it, K, p->tab, p->host, p->r(), p->q(), p->M64(),
+                                     parts, p->st(), p->stream));
+        QP_HIP(qp::launch_pcg_direction(qp::F64, it, K, p->tab, p->host, U, p->r(), p->h(),
+                                        p->M64(), parts, p->st(), p->stream));
     }
     return QP_OK;
 }
@@ -497,10 +497,10 @@ qp_status enqueue_ir(qp_problem *p, int K, double *X, const double *rhs, int k, 
     for (int it = 0; it < k; ++it) {
         QP_TRY(queue_matvec(p, qp::F32, qp::EPI_ALPHA, K, p->h32(), p->q32(), nullptr,
                             prof ? ab * kMaxBatch + it : -1));
-        QP_HIP(qp::launch_pcg_update(qp::F32, it, K, p->tab, p->host, p->x32(), p->r32(), p->h32(),
-                                     p->q32(), p->M32(), parts, p->st(), p->stream));
-        QP_HIP(qp::launch_pcg_direction(qp::F32, it, K, p->tab, p->host, p->r32(), p->h32(),
-                                        p->M32(), parts, p->st(), p->stream));
+        QP_HIP(qp::launch_pcg_update(qp::F32, it, K, p->tab, p->host, p->r32(), p->q32(),
+                                     p->M32(), parts, p->st(), p->stream));
+        QP_HIP(qp::launch_pcg_direction(qp::F32, it, K, p->tab, p->host, p->x32(), p->r32(),
+                                        p->h32(), p->M32(), parts, p->st(), p->stream));
         if (it + 1 == k) QP_TRY(enqueue_replacement(p, K, X, rhs, it, ab, prof));
     }
     return QP_OK;

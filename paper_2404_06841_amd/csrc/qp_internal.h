@@ -174,15 +174,15 @@ hipError_t launch_pcg_init(int prec, int K, const Table *tab, const Table &ht, c
 // F32: thresh = tol^2, delta2, rr_last.  done when rr is 0; status on NaN.
 hipError_t launch_pcg_start(int prec, int K, const Table &ht, double tol, double delta,
                             int maxit, const Parts &parts, State *st, hipStream_t s);
-// Iteration j: alpha = rz[j&1] / (totals of parts.a); U += alpha h;
+// Iteration j: alpha = rz[j&1] / (totals of parts.a) (kept in the state);
 // r -= alpha q; parts.b <- ((r, M r), ||r||^2).
-hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Table &ht, void *U,
-                             void *r, const void *h, const void *q, const void *M,
-                             const Parts &parts, State *st, hipStream_t s);
-// Iteration j (right-hand sides whose update ran): beta from parts.b;
-// h = M r + beta h.  F64 stops on convergence or at maxit; F32 pauses when
-// the residual has dropped enough.
-hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const Table &ht,
+hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Table &ht, void *r,
+                             const void *q, const void *M, const Parts &parts, State *st,
+                             hipStream_t s);
+// Iteration j (right-hand sides whose update ran): U += alpha h; then, unless
+// F64 stops (convergence, maxit) or F32 pauses (the residual has dropped
+// enough): beta from parts.b, h = M r + beta h.
+hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const Table &ht, void *U,
                                 const void *r, void *h, const void *M, const Parts &parts,
                                 State *st, hipStream_t s);
 // FP32-IR start: st->rr0 = ||f'||^2, unit = sqrt(rr0) (two launches).

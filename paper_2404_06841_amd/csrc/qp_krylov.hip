@@ -2,9 +2,13 @@
 //
 // One PCG iteration j is three launches on one stream:
 //   stiffness product   q = Q h, partial sums of Re(h^H q)            (parts.a)
-//   update              alpha = rz / (Q h, h); U += alpha h; r -= alpha q;
+//   update              alpha = rz / (Q h, h); r -= alpha q;
 //                       partial sums of (r, M r) and ||r||^2          (parts.b)
-//   direction           beta = (r, M r)_new / rz; h = M r + beta h
+//   direction           U += alpha h (the h of this iteration); unless the
+//                       residual test stops the iteration:
+//                       beta = (r, M r)_new / rz; h = M r + beta h
+// The solution update sits in the direction pass, which reads h anyway, so
+// h is read once per iteration by the vector steps.
 // z = M r is never stored; it is recomputed from r and the diagonal M.
 // The scalars stay on the device; the host only polls `done`.
 //
@@ -120,9 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_start(int K, int is_ir, double t
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table *__restrict__ tab,
-                                                       cplx_t<T> *__restrict__ U,
                                                        cplx_t<T> *__restrict__ r,
-                                                       const cplx_t<T> *__restrict__ h,
                                                        const cplx_t<T> *__restrict__ q,
                                                        const T *__restrict__ M,
                                                        const double *__restrict__ part_in,
@@ -156,15 +158,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
         double acc[2] = {0.0, 0.0};
         QP_STREAM(i) {
             const size_t e = k * D + i;
-            cplx_t<T> u = U[e];
             cplx_t<T> rv = r[e];
-            const cplx_t<T> hv = h[e];
             const cplx_t<T> qv = q[e];
-            u.x += a * hv.x;
-            u.y += a * hv.y;
             rv.x -= a * qv.x;
             rv.y -= a * qv.y;
-            U[e] = u;
             r[e] = rv;
             const double n2 = (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
             acc[0] += (double)M[i] * n2;
@@ -183,6 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int K,
                                                           const Table *__restrict__ tab,
+                                                          cplx_t<T> *__restrict__ U,
                                                           const cplx_t<T> *__restrict__ r,
                                                           cplx_t<T> *__restrict__ h,
                                                           const T *__restrict__ M,
@@ -205,21 +203,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int 
         double v[2];
         load_totals<2>(part_in + k * kPartStride, gridDim.x, v);
         const double rz_new = v[0], rr = v[1];
+        // the update ran: U += alpha h with this iteration's h, whatever the
+        // residual test below decides
+        const T a = (T)st->alpha;
+        bool stop = false;
         if (!finite(rr) || !finite(rz_new)) {
             if (lead) {
                 st->status = QP_ENONFINITE;
                 st->done = 1;
             }
-            continue;
-        }
-        if (is_ir) {
+            stop = true;
+        } else if (is_ir) {
             if (rr <= fmax(st->thresh, st->delta2 * st->rr_last)) {
                 if (lead) {
                     st->rr = rr;
                     st->pause = 1;
                     st->rz[(j + 1) & 1] = rz_old;
                 }
-                continue;
+                stop = true;
             }
         } else {
             const bool conv = rr <= st->thresh;
@@ -230,8 +231,19 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int 
                     st->status = conv ? QP_OK : QP_ENOCONV;
                     st->done = 1;
                 }
-                continue;
+                stop = true;
             }
+        }
+        if (stop) {
+            QP_STREAM(i) {
+                const size_t e = k * D + i;
+                const cplx_t<T> hv = h[e];
+                cplx_t<T> u = U[e];
+                u.x += a * hv.x;
+                u.y += a * hv.y;
+                U[e] = u;
+            }
+            continue;
         }
         const double beta = rz_new / rz_old;
         const T b = (T)beta;
@@ -240,6 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int 
             const cplx_t<T> rv = r[e];
             const T m = M[i];
             cplx_t<T> hv = h[e];
+            cplx_t<T> u = U[e];
+            u.x += a * hv.x;
+            u.y += a * hv.y;
+            U[e] = u;
             hv.x = m * rv.x + b * hv.x;
             hv.y = m * rv.y + b * hv.y;
             h[e] = hv;
@@ -425,33 +441,33 @@ hipError_t launch_pcg_start(int prec, int K, const Table &ht, double tol, double
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Table &ht, void *U,
-                             void *r, const void *h, const void *q, const void *M,
-                             const Parts &parts, State *st, hipStream_t s)
+hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Table &ht, void *r,
+                             const void *q, const void *M, const Parts &parts, State *st,
+                             hipStream_t s)
 {
     const dim3 grid(ht.nblocks), block(kBlock);
     if (prec == F64)
-        hipLaunchKernelGGL(k_pcg_update<double>, grid, block, 0, s, j, K, tab, (double2 *)U,
-                           (double2 *)r, (const double2 *)h, (const double2 *)q, (const double *)M,
-                           (const double *)parts.a, parts.b, st);
+        hipLaunchKernelGGL(k_pcg_update<double>, grid, block, 0, s, j, K, tab, (double2 *)r,
+                           (const double2 *)q, (const double *)M, (const double *)parts.a, parts.b,
+                           st);
     else
-        hipLaunchKernelGGL(k_pcg_update<float>, grid, block, 0, s, j, K, tab, (float2 *)U,
-                           (float2 *)r, (const float2 *)h, (const float2 *)q, (const float *)M,
-                           (const double *)parts.a, parts.b, st);
+        hipLaunchKernelGGL(k_pcg_update<float>, grid, block, 0, s, j, K, tab, (float2 *)r,
+                           (const float2 *)q, (const float *)M, (const double *)parts.a, parts.b,
+                           st);
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const Table &ht,
+hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const Table &ht, void *U,
                                 const void *r, void *h, const void *M, const Parts &parts,
                                 State *st, hipStream_t s)
 {
     const dim3 grid(ht.nblocks), block(kBlock);
     if (prec == F64)
-        hipLaunchKernelGGL(k_pcg_direction<double>, grid, block, 0, s, j, 0, K, tab,
+        hipLaunchKernelGGL(k_pcg_direction<double>, grid, block, 0, s, j, 0, K, tab, (double2 *)U,
                            (const double2 *)r, (double2 *)h, (const double *)M,
                            (const double *)parts.b, st);
     else
-        hipLaunchKernelGGL(k_pcg_direction<float>, grid, block, 0, s, j, 1, K, tab,
+        hipLaunchKernelGGL(k_pcg_direction<float>, grid, block, 0, s, j, 1, K, tab, (float2 *)U,
                            (const float2 *)r, (float2 *)h, (const float *)M,
                            (const double *)parts.b, st);
     return hipGetLastError();
