@@ -98,9 +98,9 @@ typedef struct qp_options {
                            replayed; 0 = launch every kernel directly            */
     int gather64;       /* nonzero: the stiffness product forms 64-bit neighbour
                            addresses and serves one right-hand side per launch.
-                           Always on when N^n >= 2^28 (vectors of 4 GiB or more,
-                           beyond the 32-bit record indices of the default
-                           gathers); default 0                                   */
+                           Always on when N^n * max(2, d) * 8 >= 2^32 (a family
+                           of vectors of 4 GiB or more, beyond the 32-bit
+                           record offsets of the default gathers); default 0  */
 } qp_options;
 
 typedef struct qp_solve_info {

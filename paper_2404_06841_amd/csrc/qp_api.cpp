@@ -1227,9 +1227,13 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     if (!p) return fail(QP_ENOMEM, "host allocation failed");
     p->opt = o;
     build_table(p->host, d, n, P, g, modes, coef, coefs, N);
-    // record indices of the default gathers are scaled by the entry size in 32
-    // bits: vectors of 2^28 entries or more take 64-bit addresses
-    if (p->host.tile_s > 1 && (o.gather64 || p->host.D >= ((int64_t)1 << 28))) p->host.wide = 1;
+    // record indices of the default gathers are scaled by the record size in
+    // 32 bits; the largest records are the interleaved float families of d
+    // right-hand sides (d * 8 bytes) and FP64 entries (16 bytes): vectors
+    // reaching 4 GiB in either take 64-bit addresses
+    if (p->host.tile_s > 1 &&
+        (o.gather64 || (int64_t)p->host.D * std::max(2, d) * 8 >= ((int64_t)1 << 32)))
+        p->host.wide = 1;
     p->L = make_layout(d, n, N, p->host.D, g);
 
     auto bail = [&](qp_status st) {

@@ -57,6 +57,20 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, int stride, unsign
     return r;
 }
 
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ f32x4_t struct_load_f32x4(rsrc_t r, int index, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.buffer.load.v4f32");
+
+// Element i of right-hand side k in a family of K vectors of D entries:
+// FP64 families are vector-major (vector k starts at k D); float families
+// (the FP32-IR inner solve) interleave the right-hand sides (entry i of all
+// K together), so one gather of K * 8 bytes serves them all.
+template <typename T>
+__device__ __forceinline__ size_t vec_at(int k, int K, size_t D, size_t i)
+{
+    return (sizeof(T) == 4) ? i * (size_t)K + k : (size_t)k * D + i;
+}
+
 template <typename T> __device__ __forceinline__ cplx_t<T> gather(rsrc_t r, int index);
 template <> __device__ __forceinline__ float2 gather<float>(rsrc_t r, int index)
 {

@@ -112,6 +112,7 @@ struct State {
     double thresh;    // convergence: rr <= thresh (solve units)
     double delta2;    // FP32-IR: replace the residual once rr <= delta2 * rr_last
     double rr_last;   // FP32-IR: rr after the last residual replacement
+    double rr_pause;  // FP32-IR: recursive rr at the pause (snapshot taken by the fold)
     double unit;      // FP32-IR: ||F'||; float vectors hold (true value) / unit
     double inv_unit;
     int iters;        // update steps performed

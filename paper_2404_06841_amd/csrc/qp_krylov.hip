@@ -12,10 +12,13 @@
 // z = M r is never stored; it is recomputed from r and the diagonal M.
 // The scalars stay on the device; the host only polls `done`.
 //
-// Every kernel serves K right-hand sides at once (K <= d): vector k of a
-// family starts at element k * D, its state is st[k], its partial sums start
-// at part + k * kPartStride.  A right-hand side that has finished (or, in
-// FP32-IR, paused) is skipped by every workgroup alike.
+// Every kernel serves K right-hand sides at once (K <= d): entry i of vector
+// k of a family is at vec_at<T>(k, K, D, i) (FP64 vectors one after the
+// other, float vectors interleaved), its state is st[k], its partial sums
+// start at part + k * kPartStride.  A right-hand side that has finished (or, in
+// FP32-IR, paused) is skipped by every workgroup alike.  The FP64 kernels
+// sweep the vectors one after the other; the float kernels (further down)
+// read the K values of an entry with one load.
 //
 // FP32-IR runs the same loop with float vectors (entries scaled by 1/||F'||)
 // and FP64 scalars and dot products.  Whenever the float residual has dropped
@@ -66,9 +69,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(int K, const Table *__restr
             hv.y = m * rv.y;
             zero.x = 0;
             zero.y = 0;
-            U[k * D + i] = zero;
-            r[k * D + i] = rv;
-            h[k * D + i] = hv;
+            const size_t e = vec_at<T>(k, K, D, i);
+            U[e] = zero;
+            r[e] = rv;
+            h[e] = hv;
             if (X64) X64[k * D + i] = make_double2(0.0, 0.0);
             const double n2 = (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
             acc[0] += (double)m * n2;
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
         const T a = (T)alpha;
         double acc[2] = {0.0, 0.0};
         QP_STREAM(i) {
-            const size_t e = k * D + i;
+            const size_t e = vec_at<T>(k, K, D, i);
             cplx_t<T> rv = r[e];
             const cplx_t<T> qv = q[e];
             rv.x -= a * qv.x;
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int K,
+__global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int K,
                                                           const Table *__restrict__ tab,
                                                           cplx_t<T> *__restrict__ U,
                                                           const cplx_t<T> *__restrict__ r,
@@ -213,15 +217,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int 
                 st->done = 1;
             }
             stop = true;
-        } else if (is_ir) {
-            if (rr <= fmax(st->thresh, st->delta2 * st->rr_last)) {
-                if (lead) {
-                    st->rr = rr;
-                    st->pause = 1;
-                    st->rz[(j + 1) & 1] = rz_old;
-                }
-                stop = true;
-            }
         } else {
             const bool conv = rr <= st->thresh;
             const bool limit = st->iters >= st->maxit;  // iters counts this update
@@ -236,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int 
         }
         if (stop) {
             QP_STREAM(i) {
-                const size_t e = k * D + i;
+                const size_t e = vec_at<T>(k, K, D, i);
                 const cplx_t<T> hv = h[e];
                 cplx_t<T> u = U[e];
                 u.x += a * hv.x;
@@ -248,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int is_ir, int 
         const double beta = rz_new / rz_old;
         const T b = (T)beta;
         QP_STREAM(i) {
-            const size_t e = k * D + i;
+            const size_t e = vec_at<T>(k, K, D, i);
             const cplx_t<T> rv = r[e];
             const T m = M[i];
             cplx_t<T> hv = h[e];
@@ -301,47 +296,352 @@ __global__ __launch_bounds__(kBlock) void k_ir_unit(int K, const double *__restr
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_ir_fold(int K, const Table *__restrict__ tab,
-                                                    double2 *__restrict__ X,
-                                                    float2 *__restrict__ x,
-                                                    State *__restrict__ sts)
+// Pause every unfinished right-hand side (the forced final replacement).
+__global__ void k_ir_force(int K, State *sts)
+{
+    if (blockIdx.x == 0 && threadIdx.x < K && !sts[threadIdx.x].done) sts[threadIdx.x].pause = 1;
+}
+
+__global__ void k_state_reset(int K, State *sts)
+{
+    if (blockIdx.x != 0) return;
+    const int k = threadIdx.x;
+    if (k >= K) return;
+    State *st = sts + k;
+    st->rz[0] = st->rz[1] = 0.0;
+    st->alpha = st->beta = st->hq = 0.0;
+    st->rr = st->rr0 = st->thresh = st->delta2 = st->rr_last = st->rr_pause = 0.0;
+    st->unit = 1.0;
+    st->inv_unit = 1.0;
+    st->iters = 0;
+    st->replacements = 0;
+    st->done = 0;
+    st->pause = 0;
+    st->status = 0;
+    st->maxit = 0;
+    st->did_update = 0;
+    st->replace = 0;
+}
+
+// ---------------------------------------------------------------- float families
+//
+// The float vectors of the FP32-IR inner solve interleave their KK
+// right-hand sides (entry i of all of them at i KK .. i KK + KK - 1), so the
+// stiffness product gathers them with one load; these kernels walk entries
+// once and treat the KK right-hand sides of an entry together, each with its
+// own state, scalars and partial sums.  The arithmetic per (entry,
+// right-hand side) is that of the FP64 kernels above, with the FP32-IR
+// rules for pausing and replacing.
+
+template <int KK>
+__device__ __forceinline__ void ld_row(const float2 *__restrict__ p, size_t i, float2 (&v)[KK])
+{
+    const float2 *q = p + i * KK;
+    if constexpr (KK == 2) {
+        const float4 a = *reinterpret_cast<const float4 *>(q);
+        v[0] = make_float2(a.x, a.y);
+        v[1] = make_float2(a.z, a.w);
+    } else if constexpr (KK == 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(q);
+        const float4 b = *reinterpret_cast<const float4 *>(q + 2);
+        v[0] = make_float2(a.x, a.y);
+        v[1] = make_float2(a.z, a.w);
+        v[2] = make_float2(b.x, b.y);
+        v[3] = make_float2(b.z, b.w);
+    } else {
+#pragma unroll
+        for (int k = 0; k < KK; ++k) v[k] = q[k];
+    }
+}
+
+template <int KK>
+__device__ __forceinline__ void st_row(float2 *__restrict__ p, size_t i, const float2 (&v)[KK])
+{
+    float2 *q = p + i * KK;
+    if constexpr (KK == 2) {
+        *reinterpret_cast<float4 *>(q) = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    } else if constexpr (KK == 4) {
+        *reinterpret_cast<float4 *>(q) = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+        *reinterpret_cast<float4 *>(q + 2) = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+    } else {
+#pragma unroll
+        for (int k = 0; k < KK; ++k) q[k] = v[k];
+    }
+}
+
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_init_f(const Table *__restrict__ tab,
+                                                   const double2 *__restrict__ f,
+                                                   double2 *__restrict__ X64, float2 *__restrict__ U,
+                                                   float2 *__restrict__ r, float2 *__restrict__ h,
+                                                   const float *__restrict__ M,
+                                                   double *__restrict__ part,
+                                                   const State *__restrict__ st)
 {
     const size_t D = tab->D;
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    double scale[KK], acc[KK][2];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        scale[k] = st[k].inv_unit;
+        acc[k][0] = acc[k][1] = 0.0;
+    }
+    QP_STREAM(i) {
+        const float m = M[i];
+        float2 rv[KK], hv[KK], zero[KK];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            const double2 fv = f[k * D + i];
+            rv[k].x = (i != 0) ? (float)(fv.x * scale[k]) : 0.f;
+            rv[k].y = (i != 0) ? (float)(fv.y * scale[k]) : 0.f;
+            hv[k].x = m * rv[k].x;
+            hv[k].y = m * rv[k].y;
+            zero[k] = make_float2(0.f, 0.f);
+            if (X64) X64[k * D + i] = make_double2(0.0, 0.0);
+            const double n2 = (double)rv[k].x * (double)rv[k].x + (double)rv[k].y * (double)rv[k].y;
+            acc[k][0] += (double)m * n2;
+            acc[k][1] += n2;
+        }
+        st_row<KK>(U, i, zero);
+        st_row<KK>(r, i, rv);
+        st_row<KK>(h, i, hv);
+    }
+#pragma unroll
+    for (int k = 0; k < KK; ++k) store_partials<2>(acc[k], part + k * kPartStride);
+}
+
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restrict__ tab,
+                                                     float2 *__restrict__ r,
+                                                     const float2 *__restrict__ q,
+                                                     const float *__restrict__ M,
+                                                     const double *__restrict__ part_in,
+                                                     double *__restrict__ part_out,
+                                                     State *__restrict__ sts)
+{
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block(tab, begin, end);
-    for (int k = 0; k < K; ++k) {
-        // replaced only once paused; the decision is kept for the later
-        // replacement steps, which must not read the flags they change
-        const bool rep = !sts[k].done && sts[k].pause;
-        if (lead) sts[k].replace = rep ? 1 : 0;
-        if (!rep) continue;
-        const double unit = sts[k].unit;
-        QP_STREAM(i) {
-            const size_t e = k * D + i;
-            double2 a = X[e];
-            const float2 v = x[e];
-            a.x += unit * (double)v.x;
-            a.y += unit * (double)v.y;
-            X[e] = a;
-            x[e] = make_float2(0.f, 0.f);
+    bool act[KK];
+    float a[KK];
+    double alpha[KK], hqv[KK], acc[KK][2];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        State *st = sts + k;
+        act[k] = !(st->done || st->pause);
+        a[k] = 0.f;
+        alpha[k] = hqv[k] = 0.0;
+        acc[k][0] = acc[k][1] = 0.0;
+        if (!act[k]) {
+            if (lead) st->did_update = 0;
+            continue;
+        }
+        double hq[1];
+        load_totals<1>(part_in + k * kPartStride, tab->nb_mv, hq);  // the product's partials
+        if (!(hq[0] > 0.0)) {
+            // (Q h, h) <= 0: Q is not positive definite on this Krylov space
+            if (lead) {
+                st->hq = hq[0];
+                st->status = finite(hq[0]) ? QP_ENOTSPD : QP_ENONFINITE;
+                st->done = 1;
+                st->did_update = 0;
+            }
+            act[k] = false;
+            continue;
+        }
+        hqv[k] = hq[0];
+        alpha[k] = st->rz[j & 1] / hq[0];
+        a[k] = (float)alpha[k];
+        any = true;
+    }
+    if (!any) return;
+    QP_STREAM(i) {
+        float2 rv[KK], qv[KK];
+        ld_row<KK>(r, i, rv);
+        ld_row<KK>(q, i, qv);
+        const double m = (double)M[i];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            if (!act[k]) continue;
+            rv[k].x -= a[k] * qv[k].x;
+            rv[k].y -= a[k] * qv[k].y;
+            const double n2 = (double)rv[k].x * (double)rv[k].x + (double)rv[k].y * (double)rv[k].y;
+            acc[k][0] += m * n2;
+            acc[k][1] += n2;
+        }
+        st_row<KK>(r, i, rv);
+    }
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        if (!act[k]) continue;
+        store_partials<2>(acc[k], part_out + k * kPartStride);
+        if (lead) {
+            State *st = sts + k;
+            st->alpha = alpha[k];
+            st->hq = hqv[k];
+            st->iters = st->iters + 1;
+            st->did_update = 1;
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_ir_direction(int j, int K, const Table *__restrict__ tab,
-                                                         const float2 *__restrict__ r,
-                                                         float2 *__restrict__ h,
-                                                         const float *__restrict__ M,
-                                                         const double *__restrict__ part_in,
-                                                         State *__restrict__ sts)
+// FP32-IR direction (is_ir semantics of k_pcg_direction): U += alpha h for
+// every right-hand side whose update ran; h = M r + beta h unless it pauses.
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__restrict__ tab,
+                                                        float2 *__restrict__ U,
+                                                        const float2 *__restrict__ r,
+                                                        float2 *__restrict__ h,
+                                                        const float *__restrict__ M,
+                                                        const double *__restrict__ part_in,
+                                                        State *__restrict__ sts)
+{
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    bool did[KK], go[KK];
+    float a[KK], b[KK];
+    double rzn[KK], rrv[KK], betav[KK];
+    bool any_did = false, any_go = false;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        State *st = sts + k;
+        const double rz_old = st->rz[j & 1];
+        did[k] = st->did_update != 0;
+        go[k] = false;
+        a[k] = b[k] = 0.f;
+        rzn[k] = rrv[k] = betav[k] = 0.0;
+        if (!did[k]) {
+            // no update this iteration; a paused solve carries rz forward so
+            // iteration j+1 finds it in its slot
+            if (lead && !st->done && st->pause) st->rz[(j + 1) & 1] = rz_old;
+            continue;
+        }
+        any_did = true;
+        a[k] = (float)st->alpha;
+        double v[2];
+        load_totals<2>(part_in + k * kPartStride, gridDim.x, v);
+        const double rz_new = v[0], rr = v[1];
+        if (!finite(rr) || !finite(rz_new)) {
+            if (lead) {
+                st->status = QP_ENONFINITE;
+                st->done = 1;
+            }
+            continue;
+        }
+        if (rr <= fmax(st->thresh, st->delta2 * st->rr_last)) {
+            if (lead) {
+                st->rr = rr;
+                st->pause = 1;
+                st->rz[(j + 1) & 1] = rz_old;
+            }
+            continue;
+        }
+        go[k] = true;
+        any_go = true;
+        rzn[k] = rz_new;
+        rrv[k] = rr;
+        betav[k] = rz_new / rz_old;
+        b[k] = (float)betav[k];
+    }
+    if (!any_did) return;
+    QP_STREAM(i) {
+        float2 uv[KK], hv[KK], rv[KK];
+        ld_row<KK>(U, i, uv);
+        ld_row<KK>(h, i, hv);
+        if (any_go) ld_row<KK>(r, i, rv);
+        const float m = M[i];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            if (!did[k]) continue;
+            uv[k].x += a[k] * hv[k].x;
+            uv[k].y += a[k] * hv[k].y;
+            if (go[k]) {
+                hv[k].x = m * rv[k].x + b[k] * hv[k].x;
+                hv[k].y = m * rv[k].y + b[k] * hv[k].y;
+            }
+        }
+        st_row<KK>(U, i, uv);
+        if (any_go) st_row<KK>(h, i, hv);
+    }
+    if (lead) {
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            if (!go[k]) continue;
+            State *st = sts + k;
+            st->rr = rrv[k];
+            st->beta = betav[k];
+            st->rz[(j + 1) & 1] = rzn[k];
+        }
+    }
+}
+
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_fold_f(const Table *__restrict__ tab,
+                                                   double2 *__restrict__ X,
+                                                   float2 *__restrict__ x,
+                                                   State *__restrict__ sts)
 {
     const size_t D = tab->D;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block(tab, begin, end);
-    for (int k = 0; k < K; ++k) {
+    bool rep[KK];
+    double unit[KK];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        // replaced only once paused; the decision is kept for the later
+        // replacement steps, which must not read the flags they change
+        rep[k] = !sts[k].done && sts[k].pause;
+        if (lead) {
+            sts[k].replace = rep[k] ? 1 : 0;
+            sts[k].rr_pause = sts[k].rr;
+        }
+        unit[k] = sts[k].unit;
+        any = any || rep[k];
+    }
+    if (!any) return;
+    QP_STREAM(i) {
+        float2 v[KK];
+        ld_row<KK>(x, i, v);
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            if (!rep[k]) continue;
+            const size_t e = (size_t)k * D + i;
+            double2 s = X[e];
+            s.x += unit[k] * (double)v[k].x;
+            s.y += unit[k] * (double)v[k].y;
+            X[e] = s;
+            v[k] = make_float2(0.f, 0.f);
+        }
+        st_row<KK>(x, i, v);
+    }
+}
+
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_irdir_f(int j, const Table *__restrict__ tab,
+                                                    const float2 *__restrict__ r,
+                                                    float2 *__restrict__ h,
+                                                    const float *__restrict__ M,
+                                                    const double *__restrict__ part_in,
+                                                    State *__restrict__ sts)
+{
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    bool go[KK];
+    float b[KK];
+    double rzn[KK], rrv[KK], betav[KK];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
         State *st = sts + k;
+        go[k] = false;
+        b[k] = 0.f;
+        rzn[k] = rrv[k] = betav[k] = 0.0;
         if (!st->replace) continue;  // decided by the fold
         double v[2];
         load_totals<2>(part_in + k * kPartStride, tab->nb_mv, v);  // FP64 residual product
@@ -362,57 +662,46 @@ __global__ __launch_bounds__(kBlock) void k_ir_direction(int j, int K, const Tab
             }
             continue;
         }
-        // Keep the search direction while the float recursion tracked the true
-        // residual; restart it (beta = 0) when the true residual is well above
-        // the recursive one it replaces (the recursion has drifted).
-        const bool restart = rr > 4.0 * st->rr;
-        const double beta = restart ? 0.0 : rz_new / st->rz[j & 1];
-        const float b = (float)beta;
-        QP_STREAM(i) {
-            const size_t e = k * D + i;
-            const float2 rv = r[e];
-            const float m = M[i];
-            float2 hv = h[e];
-            hv.x = m * rv.x + b * hv.x;
-            hv.y = m * rv.y + b * hv.y;
-            h[e] = hv;
+        // keep the search direction while the float recursion tracked the
+        // true residual; restart it (beta = 0) when the true residual is well
+        // above the recursive one it replaces (the recursion has drifted)
+        // (rr_pause is the snapshot the fold took: st->rr itself is rewritten
+        // by this kernel's lead while other workgroups may still read it)
+        const bool restart = rr > 4.0 * st->rr_pause;
+        go[k] = true;
+        any = true;
+        rzn[k] = rz_new;
+        rrv[k] = rr;
+        betav[k] = restart ? 0.0 : rz_new / st->rz[j & 1];
+        b[k] = (float)betav[k];
+    }
+    if (!any) return;
+    QP_STREAM(i) {
+        float2 rv[KK], hv[KK];
+        ld_row<KK>(r, i, rv);
+        ld_row<KK>(h, i, hv);
+        const float m = M[i];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            if (!go[k]) continue;
+            hv[k].x = m * rv[k].x + b[k] * hv[k].x;
+            hv[k].y = m * rv[k].y + b[k] * hv[k].y;
         }
-        if (lead) {
-            st->rr = rr;
-            st->rr_last = rr;
-            st->beta = beta;
-            st->rz[(j + 1) & 1] = rz_new;
+        st_row<KK>(h, i, hv);
+    }
+    if (lead) {
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            if (!go[k]) continue;
+            State *st = sts + k;
+            st->rr = rrv[k];
+            st->rr_last = rrv[k];
+            st->beta = betav[k];
+            st->rz[(j + 1) & 1] = rzn[k];
             st->pause = 0;
             st->replacements = st->replacements + 1;
         }
     }
-}
-
-// Pause every unfinished right-hand side (the forced final replacement).
-__global__ void k_ir_force(int K, State *sts)
-{
-    if (blockIdx.x == 0 && threadIdx.x < K && !sts[threadIdx.x].done) sts[threadIdx.x].pause = 1;
-}
-
-__global__ void k_state_reset(int K, State *sts)
-{
-    if (blockIdx.x != 0) return;
-    const int k = threadIdx.x;
-    if (k >= K) return;
-    State *st = sts + k;
-    st->rz[0] = st->rz[1] = 0.0;
-    st->alpha = st->beta = st->hq = 0.0;
-    st->rr = st->rr0 = st->thresh = st->delta2 = st->rr_last = 0.0;
-    st->unit = 1.0;
-    st->inv_unit = 1.0;
-    st->iters = 0;
-    st->replacements = 0;
-    st->done = 0;
-    st->pause = 0;
-    st->status = 0;
-    st->maxit = 0;
-    st->did_update = 0;
-    st->replace = 0;
 }
 
 }  // namespace
@@ -424,12 +713,22 @@ hipError_t launch_pcg_init(int prec, int K, const Table *tab, const Table &ht, c
     const dim3 grid(ht.nblocks), block(kBlock);
     auto F = reinterpret_cast<const double2 *>(f);
     auto X = reinterpret_cast<double2 *>(X64);
-    if (prec == F64)
+    if (prec == F64) {
         hipLaunchKernelGGL(k_pcg_init<double>, grid, block, 0, s, K, tab, F, X, (double2 *)U,
                            (double2 *)r, (double2 *)h, (const double *)M, parts.b, st);
-    else
-        hipLaunchKernelGGL(k_pcg_init<float>, grid, block, 0, s, K, tab, F, X, (float2 *)U,
-                           (float2 *)r, (float2 *)h, (const float *)M, parts.b, st);
+        return hipGetLastError();
+    }
+    switch (K) {
+#define QP_K(KK)                                                                                   \
+    case KK:                                                                                        \
+        hipLaunchKernelGGL(k_init_f<KK>, grid, block, 0, s, tab, F, X, (float2 *)U, (float2 *)r,  \
+                           (float2 *)h, (const float *)M, parts.b, st);                             \
+        break;
+        QP_K(1) QP_K(2) QP_K(3) QP_K(4)
+#undef QP_K
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -446,14 +745,24 @@ hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Tab
                              hipStream_t s)
 {
     const dim3 grid(ht.nblocks), block(kBlock);
-    if (prec == F64)
+    if (prec == F64) {
         hipLaunchKernelGGL(k_pcg_update<double>, grid, block, 0, s, j, K, tab, (double2 *)r,
                            (const double2 *)q, (const double *)M, (const double *)parts.a, parts.b,
                            st);
-    else
-        hipLaunchKernelGGL(k_pcg_update<float>, grid, block, 0, s, j, K, tab, (float2 *)r,
-                           (const float2 *)q, (const float *)M, (const double *)parts.a, parts.b,
-                           st);
+        return hipGetLastError();
+    }
+    switch (K) {
+#define QP_K(KK)                                                                                  \
+    case KK:                                                                                       \
+        hipLaunchKernelGGL(k_update_f<KK>, grid, block, 0, s, j, tab, (float2 *)r,                \
+                           (const float2 *)q, (const float *)M, (const double *)parts.a, parts.b, \
+                           st);                                                                    \
+        break;
+        QP_K(1) QP_K(2) QP_K(3) QP_K(4)
+#undef QP_K
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -462,14 +771,24 @@ hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const 
                                 State *st, hipStream_t s)
 {
     const dim3 grid(ht.nblocks), block(kBlock);
-    if (prec == F64)
-        hipLaunchKernelGGL(k_pcg_direction<double>, grid, block, 0, s, j, 0, K, tab, (double2 *)U,
+    if (prec == F64) {
+        hipLaunchKernelGGL(k_pcg_direction<double>, grid, block, 0, s, j, K, tab, (double2 *)U,
                            (const double2 *)r, (double2 *)h, (const double *)M,
                            (const double *)parts.b, st);
-    else
-        hipLaunchKernelGGL(k_pcg_direction<float>, grid, block, 0, s, j, 1, K, tab, (float2 *)U,
-                           (const float2 *)r, (float2 *)h, (const float *)M,
-                           (const double *)parts.b, st);
+        return hipGetLastError();
+    }
+    switch (K) {
+#define QP_K(KK)                                                                                 \
+    case KK:                                                                                      \
+        hipLaunchKernelGGL(k_direction_f<KK>, grid, block, 0, s, j, tab, (float2 *)U,            \
+                           (const float2 *)r, (float2 *)h, (const float *)M,                      \
+                           (const double *)parts.b, st);                                          \
+        break;
+        QP_K(1) QP_K(2) QP_K(3) QP_K(4)
+#undef QP_K
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -488,8 +807,17 @@ hipError_t launch_ir_unit(int K, const Table *tab, const Table &ht, const double
 hipError_t launch_ir_fold(int K, const Table *tab, const Table &ht, double *X, float *x, State *st,
                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ir_fold, dim3(ht.nblocks), dim3(kBlock), 0, s, K, tab,
-                       reinterpret_cast<double2 *>(X), reinterpret_cast<float2 *>(x), st);
+    switch (K) {
+#define QP_K(KK)                                                                              \
+    case KK:                                                                                   \
+        hipLaunchKernelGGL(k_fold_f<KK>, dim3(ht.nblocks), dim3(kBlock), 0, s, tab,           \
+                           reinterpret_cast<double2 *>(X), reinterpret_cast<float2 *>(x), st); \
+        break;
+        QP_K(1) QP_K(2) QP_K(3) QP_K(4)
+#undef QP_K
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -497,9 +825,18 @@ hipError_t launch_ir_direction(int j, int K, const Table *tab, const Table &ht, 
                                float *h, const float *M, const Parts &parts, State *st,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ir_direction, dim3(ht.nblocks), dim3(kBlock), 0, s, j, K, tab,
-                       reinterpret_cast<const float2 *>(r), reinterpret_cast<float2 *>(h), M,
-                       (const double *)parts.b, st);
+    switch (K) {
+#define QP_K(KK)                                                                                \
+    case KK:                                                                                     \
+        hipLaunchKernelGGL(k_irdir_f<KK>, dim3(ht.nblocks), dim3(kBlock), 0, s, j, tab,         \
+                           reinterpret_cast<const float2 *>(r), reinterpret_cast<float2 *>(h), M, \
+                           (const double *)parts.b, st);                                         \
+        break;
+        QP_K(1) QP_K(2) QP_K(3) QP_K(4)
+#undef QP_K
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

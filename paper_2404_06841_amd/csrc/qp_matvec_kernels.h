@@ -525,9 +525,10 @@ __global__ __launch_bounds__(kBlock) void k_unit_records(const Table *__restrict
     }
 }
 
-// Epilogue of one output entry i of the stiffness product.
+// Epilogue of one output entry i of the stiffness product; ex, ey: the
+// entry's index in the families of x and y (f and M32 are indexed by i).
 template <typename T, int EPI>
-__device__ __forceinline__ void put_output(size_t i, T acc_re, T acc_im,
+__device__ __forceinline__ void put_output(size_t i, size_t ex, size_t ey, T acc_re, T acc_im,
                                            const cplx_t<T> *__restrict__ x, void *__restrict__ yv,
                                            const double2 *__restrict__ f,
                                            const float *__restrict__ M32, double inv_unit,
@@ -543,16 +544,16 @@ __device__ __forceinline__ void put_output(size_t i, T acc_re, T acc_im,
         const double rx = (i != 0) ? (fv.x - (double)acc_re) * inv_unit : 0.0;
         const double ry = (i != 0) ? (fv.y - (double)acc_im) * inv_unit : 0.0;
         const float2 o = make_float2((float)rx, (float)ry);
-        static_cast<float2 *>(yv)[i] = o;
+        static_cast<float2 *>(yv)[ey] = o;
         dots[0] += (double)M32[i] * ((double)o.x * (double)o.x + (double)o.y * (double)o.y);
         dots[1] += rx * rx + ry * ry;
     } else {
         cplx_t<T> o;
         o.x = acc_re;
         o.y = acc_im;
-        static_cast<cplx_t<T> *>(yv)[i] = o;
+        static_cast<cplx_t<T> *>(yv)[ey] = o;
         if (EPI == EPI_ALPHA) {
-            const cplx_t<T> xi = x[i];
+            const cplx_t<T> xi = x[ex];
             dots[0] += (double)xi.x * (double)acc_re + (double)xi.y * (double)acc_im;
         }
     }
@@ -651,6 +652,10 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
 #pragma unroll
     for (int k = 0; k < KR; ++k)
         xr[k] = make_rsrc(x + k * D, (int)sizeof(cplx_t<T>), act[k] ? (unsigned)D : 0u);
+    // float families interleave their right-hand sides: one resource of D
+    // records of KR entries, one gather of KR * 8 bytes per (entry, mode)
+    constexpr bool ILV = std::is_same<T, float>::value && KR > 1;
+    const rsrc_t xi = make_rsrc(x, (int)(KR * sizeof(cplx_t<T>)), (unsigned)D);
 
     // items in XCD-front order: each XCD owns a contiguous eighth, its waves
     // sweep it together
@@ -774,9 +779,23 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
                         wr[m] = REAL ? wv : Q.cr * wv;
                         wi[m] = REAL ? (T)0 : Q.ci * wv;
                     }
+                    if constexpr (ILV) {
+                        const f32x4_t v0 = struct_load_f32x4(xi, idx, 0, 0, 0);
+                        *reinterpret_cast<float2 *>(&u[m][0]) = make_float2(v0.x, v0.y);
+                        *reinterpret_cast<float2 *>(&u[m][1]) = make_float2(v0.z, v0.w);
+                        if constexpr (KR == 3) {
+                            const f32x2_t v1 = struct_load_f32x2(xi, idx, 16, 0, 0);
+                            *reinterpret_cast<float2 *>(&u[m][KR - 1]) = make_float2(v1.x, v1.y);
+                        } else if constexpr (KR == 4) {
+                            const f32x4_t v1 = struct_load_f32x4(xi, idx, 16, 0, 0);
+                            *reinterpret_cast<float2 *>(&u[m][KR - 2]) = make_float2(v1.x, v1.y);
+                            *reinterpret_cast<float2 *>(&u[m][KR - 1]) = make_float2(v1.z, v1.w);
+                        }
+                    } else {
 #pragma unroll
-                    for (int k = 0; k < KR; ++k)
-                        u[m][k] = WIDE ? x[(unsigned)idx] : gather<T>(xr[k], idx);
+                        for (int k = 0; k < KR; ++k)
+                            u[m][k] = WIDE ? x[(unsigned)idx] : gather<T>(xr[k], idx);
+                    }
                 }
 #pragma unroll
                 for (int m = 0; m < C; ++m) {
@@ -807,10 +826,10 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
 #pragma unroll
                 for (int k = 0; k < KR; ++k) {
                     if (!act[k]) continue;
-                    void *yk = (EPI == EPI_RESID)
-                                   ? (void *)(static_cast<float2 *>(yv) + k * D)
-                                   : (void *)(static_cast<cplx_t<T> *>(yv) + k * D);
-                    put_output<T, EPI>(i, acc_re[k], acc_im[k], x + k * D, yk,
+                    // the replaced residual (EPI_RESID) is a float family
+                    const size_t ex = vec_at<T>(k, KR, D, i);
+                    const size_t ey = (EPI == EPI_RESID) ? vec_at<float>(k, KR, D, i) : ex;
+                    put_output<T, EPI>(i, ex, ey, acc_re[k], acc_im[k], x, yv,
                                        f ? f + k * D : f, M32, inv_unit[k], dots[k]);
                 }
             }

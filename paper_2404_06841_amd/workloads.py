@@ -226,6 +226,13 @@ def icosahedral(N: int = 8, amplitude: float = 0.5, mean: float = 4.0) -> Proble
                    {"amplitude": amplitude, "mean": mean})
 
 
+def periodic_cubic(d: int = 4, N: int = 6, amplitude: float = 0.5, mean: float = 3.0) -> Problem:
+    """Periodic d = n problem (P = identity): A = mean + amplitude * sum_t cos(y_t)."""
+    modes, coef = cosine_field(d, mean, [amplitude] * d)
+    return Problem("periodic_cubic", d, d, int(N), np.eye(d, dtype=np.float64), modes, coef,
+                   {"amplitude": amplitude, "mean": mean})
+
+
 def anisotropic_paper_example():
     """Appendix D / Sec. 5.2 homogenization example, as two parent fields on T^4.
 

@@ -64,6 +64,8 @@ PROBLEMS = {
     "three_mode_N33_odd": lambda: W.one_d_three_mode(33),
     "random_N24": lambda: W.eightfold_random(24, 3),
     "random_N8": lambda: W.eightfold_random(8, 1),
+    "periodic_cubic_d4_N6": lambda: W.periodic_cubic(4, 6),
+    "periodic_cubic_d3_N7": lambda: W.periodic_cubic(3, 7),
 }
 
 
