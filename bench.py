@@ -213,7 +213,7 @@ def diagonal_workload(torch, np, qp, W, gold, steps: int, warmup: int):
     A_ref = np.array(gold["diag_eightfold_N32"]["A"])
     res = {"workload": "eightfold d=2 n=4 N=32, A = diag(a_1, a_2), 6 seeded random mode "
                        f"pairs per entry ({prob.g} modes)"}
-    gp = qp.Problem(prob, precision="fp32ir")
+    gp = qp.Problem(prob, precision="fp32ir", autotune=True)
     for prec in ("fp32ir", "fp64"):
         gp.set_options(precision=qp.QP_PREC_FP32_IR if prec == "fp32ir" else qp.QP_PREC_FP64)
         for _ in range(warmup):
@@ -235,7 +235,8 @@ def batch_instances(torch, np, qp, W, reps: int = 3):
     qp_homogenized_batch (each problem on its own stream) versus one after
     another on the same problems."""
     probs = W.eightfold_batch(64)
-    gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream()) for pr in probs]
+    gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream(), autotune=True)
+           for pr in probs]
     solves = sum(pr.d for pr in probs)
     qp.homogenized_batch(gps, tol=TOL)  # warm-up (graphs, caches)
     torch.cuda.synchronize()
@@ -275,7 +276,7 @@ def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):
                W.eightfold_random(32, 13)]
     rng = np.random.default_rng(W.BASE_SEED + 77)
     mix = [int(i) for i in rng.integers(0, len(configs), size=requests)]
-    srv = qp.Server(96 << 30, precision="fp32ir")
+    srv = qp.Server(96 << 30, precision="fp32ir", autotune=True)
 
     def drain(tickets):
         left, fin = set(tickets), {}
@@ -363,7 +364,7 @@ def main():
     A_ref = np.array(gold["c3_eightfold_random_N32"]["A"])
 
     # headline: FP32-IR with every full batch of iterations replayed as a HIP graph
-    gp = qp.Problem(prob, precision="fp32ir")
+    gp = qp.Problem(prob, precision="fp32ir", autotune=True)
     for _ in range(args.warmup):
         gp.homogenized(tol=TOL, energy=False)
     dt, lat, r, _ = run_steps(gp, args.steps, torch)
@@ -378,8 +379,13 @@ def main():
     dtp, _, rp, (mv_ms, mv_n, mv_rhs) = run_steps(gp, args.steps, torch)
     gp.set_options(profile=0)
 
-    # the same steps in plain FP64 (comparison, not the headline)
-    gp.set_options(precision=qp.QP_PREC_FP64, profile=0)
+    layout = gp.layout()
+    gp.close()
+
+    # the same steps in plain FP64 (comparison, not the headline), on a problem
+    # whose product layout is tuned for the FP64 launch
+    gp = qp.Problem(prob, precision="fp64", autotune=True)
+    layout64 = gp.layout()
     for _ in range(args.warmup):
         gp.homogenized(tol=TOL, energy=False)
     dt64, lat64, r64, _ = run_steps(gp, args.steps, torch)
@@ -404,7 +410,8 @@ def main():
                 "algorithmic_bytes_per_launch": round(algo_bytes),
                 "timing": "HIP events around each launch, in a second pass of the same steps "
                           "(profiled batches run without graph replay)",
-                "profiled_pass_value": round(solves / dtp, 2)}
+                "profiled_pass_value": round(solves / dtp, 2),
+                "layout": layout}
     lat_sorted = np.sort(np.array(lat))
     out = {
         "metric": METRIC,
@@ -430,7 +437,7 @@ def main():
         "fp64": {"value": round(solves / dt64, 2), "ms_per_step": round(dt64 / args.steps * 1e3, 4),
                  "astar_rel_err": err_64,
                  "p99_ms": round(float(np.percentile(np.array(lat64), 99)), 4),
-                 "iters": [i.iters for i in r64.infos]},
+                 "iters": [i.iters for i in r64.infos], "layout": layout64},
         "fp32ir_iters": [i.iters for i in r.infos],
         "fp32ir_replacements": [i.outer_iters for i in r.infos],
         "roofline": roofline,

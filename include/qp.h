@@ -101,6 +101,16 @@ typedef struct qp_options {
                            Always on when N^n * max(2, d) * 8 >= 2^32 (a family
                            of vectors of 4 GiB or more, beyond the 32-bit
                            record offsets of the default gathers); default 0  */
+    int autotune;       /* nonzero: qp_create times the candidate work layouts
+                           of the plane-tile stiffness product (tiles per wave
+                           item, workgroups, item order) on this problem and
+                           keeps the fastest (qp_product_layout reports it).
+                           The choice is kept per problem shape and precision
+                           for the life of the process and reused.  Output
+                           values of the product do not depend on the layout;
+                           which workgroup sums which partial dot product does,
+                           so iterates can differ from an untuned problem's in
+                           the last bits.  Default 0 (fixed heuristics)      */
 } qp_options;
 
 typedef struct qp_solve_info {
@@ -119,6 +129,19 @@ typedef struct qp_solve_info {
                              served (a launch serves every unfinished one)       */
     int matvec32_rhs;     /* the same for the float launches                     */
 } qp_solve_info;
+
+/* Work layout of the stiffness product (see qp_options.autotune). */
+typedef struct qp_layout {
+    int item_tiles;     /* plane tiles per wave work item (line tiles: 1)      */
+    int workgroups;     /* grid of the product launches                        */
+    int xcd_front;      /* 1: each of the 8 XCDs sweeps a contiguous share of
+                           the work items; 0: items in plain order             */
+    int tuned;          /* 0: fixed heuristics; 1: timed on this problem;
+                           2: reused from an earlier problem of the same shape */
+    int candidates;     /* layouts timed (tuned == 1)                          */
+    double default_us;  /* mean launch of the heuristic layout (tuned == 1)    */
+    double best_us;     /* mean launch of the chosen layout (tuned == 1)       */
+} qp_layout;
 
 /* Fill *opt with the defaults listed above. */
 void qp_default_options(qp_options *opt);
@@ -180,6 +203,19 @@ int64_t qp_dim(const qp_problem *p);
 /* Replace the solver options (precision, preconditioner, limits, profile).
  * The stream and workspace of a created problem cannot change. */
 qp_status qp_set_options(qp_problem *p, const qp_options *opt);
+
+/* The stiffness product's work layout of p (host-only; no device call).
+ * QP_EINVAL for null arguments. */
+qp_status qp_product_layout(const qp_problem *p, qp_layout *out);
+
+/* Set the stiffness product's work layout (item_tiles, workgroups and
+ * xcd_front of *layout; the other fields are ignored), e.g. one that
+ * qp_product_layout reported in an earlier process, so that the partial sums,
+ * and with them the iterates, repeat bitwise.  Waits for the problem's stream
+ * and drops its captured batches.  QP_EINVAL unless item_tiles is 1, 2 or 4
+ * (1 for line tiles, N > 32 or n = 1), 1 <= workgroups <= 1024 and xcd_front
+ * is 0 or 1. */
+qp_status qp_set_product_layout(qp_problem *p, const qp_layout *layout);
 
 /*
  * Solve Q U = F' by C-PCG (Alg. 2) with the diagonal preconditioner M of

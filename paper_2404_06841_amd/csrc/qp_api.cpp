@@ -10,7 +10,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -128,6 +130,7 @@ struct qp_problem {
     qp_options opt{};
     double amin = 0, amax = 0, pkmin = 0;
     int flags = 0;
+    qp_layout layout{};         // work layout of the stiffness product
     State *hstate = nullptr;   // pinned: two polling slots + final, kMaxRhs states each
     double *hsmall = nullptr;  // pinned
     int *hexec = nullptr;      // pinned copy of the execution log
@@ -1201,6 +1204,140 @@ size_t qp_workspace_bytes(int d, int n, int N, int g)
 }
 
 // coefs: null (scalar coefficient `coef`) or d x g complex (diagonal coefficient)
+// ---------------------------------------------------------------- product layout
+//
+// The work layout of the plane-tile stiffness product (tiles per wave item,
+// workgroups, item order) leaves every output value unchanged: each output
+// is summed by one lane over the modes in a fixed order.  It decides only
+// which workgroup sums which partial dot products.  With
+// qp_options.autotune the first problem of a shape times each candidate
+// layout on its own product (the launch the solve repeats: its precision,
+// all the right-hand sides one launch serves) and keeps the fastest; later
+// problems of the same shape in the process reuse that choice.
+namespace {
+
+struct LayoutPick {
+    int it, nb, xcd;
+    bool operator==(const LayoutPick &o) const { return it == o.it && nb == o.nb && xcd == o.xcd; }
+};
+
+std::mutex g_layout_mu;
+std::map<std::vector<int>, LayoutPick> g_layouts;
+
+int grid_for(int64_t want)
+{
+    int nb = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, want));
+    if (nb >= 8) nb -= nb % 8;
+    return nb;
+}
+
+// Candidate layouts of a plane-tile table: 1, 2 or 4 tiles per item; one,
+// two or four items per wave; XCD-front or linear item order.
+std::vector<LayoutPick> layout_candidates(const Table &T)
+{
+    std::vector<LayoutPick> c;
+    const int tpu = T.tiles_per_unit;
+    const int64_t units = T.ntiles / tpu;
+    for (int it : {1, 2, 4}) {
+        if (it > 1 && it / 2 >= tpu) continue;  // same items as it / 2
+        const int64_t items = units * ((tpu + it - 1) / it);
+        for (int per : {1, 2, 4}) {
+            const int nb = grid_for((items + 4 * per - 1) / (4 * per));
+            for (int xcd : {1, 0}) {
+                const LayoutPick L{it, nb, xcd};
+                if (std::find(c.begin(), c.end(), L) == c.end()) c.push_back(L);
+            }
+        }
+    }
+    return c;
+}
+
+qp_status apply_layout(qp_problem *p, const LayoutPick &L)
+{
+    p->host.item_tiles = L.it;
+    p->host.nb_mv = L.nb;
+    p->host.xcd_front = L.xcd;
+    QP_HIP(hipMemcpyAsync(p->tab, &p->host, sizeof(Table), hipMemcpyHostToDevice, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
+// Mean duration of `reps` products (after one untimed), microseconds.
+qp_status time_product(qp_problem *p, int reps, double &us)
+{
+    const bool f32 = p->opt.precision == QP_PREC_FP32_IR;
+    const int prec = f32 ? qp::F32 : qp::F64;
+    const int K = rhs_per_launch(p);
+    const void *x = f32 ? (const void *)p->h32() : (const void *)p->h();
+    void *y = f32 ? (void *)p->q32() : (void *)p->q();
+    for (int r = 0; r <= reps; ++r) {
+        if (r == 1) QP_HIP(hipEventRecord(p->ev_t0, p->stream));
+        QP_HIP(qp::launch_matvec(prec, qp::EPI_ALPHA, K, p->tab, p->host, p->recs(), p->urec(prec),
+                                 p->upku(prec), x, y, nullptr, p->M32(), p->parts(), p->st(),
+                                 nullptr, p->stream));
+    }
+    QP_HIP(hipEventRecord(p->ev_t1, p->stream));
+    QP_HIP(hipEventSynchronize(p->ev_t1));
+    float ms = 0.f;
+    QP_HIP(hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1));
+    us = 1e3 * ms / reps;
+    return QP_OK;
+}
+
+qp_status tune_layout(qp_problem *p)
+{
+    const Table &T = p->host;
+    const LayoutPick dflt{T.item_tiles, T.nb_mv, T.xcd_front};
+    p->layout = qp_layout{T.item_tiles, T.nb_mv, T.xcd_front, 0, 0, 0.0, 0.0};
+    if (T.tile_s <= 1) return QP_OK;  // line tiles: one layout
+    const std::vector<int> key = {T.d,         T.n,    T.N,       T.g,      T.aniso,
+                                  T.real_coef, T.wide, T.tile_s,  p->opt.precision};
+    {
+        std::lock_guard<std::mutex> lock(g_layout_mu);
+        const auto f = g_layouts.find(key);
+        if (f != g_layouts.end()) {
+            QP_TRY(apply_layout(p, f->second));
+            p->layout = qp_layout{f->second.it, f->second.nb, f->second.xcd, 2, 0, 0.0, 0.0};
+            return QP_OK;
+        }
+    }
+    // active states and a zero source; the product writes q and the partials
+    const int K = rhs_per_launch(p);
+    const bool f32 = p->opt.precision == QP_PREC_FP32_IR;
+    QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
+    QP_HIP(hipMemsetAsync(f32 ? (void *)p->h32() : (void *)p->h(), 0,
+                          (f32 ? 8 : 16) * (size_t)T.D * K, p->stream));
+    double est = 0.0;
+    QP_TRY(time_product(p, 3, est));
+    // about 2 ms of launches per candidate
+    const int reps = (int)std::min(50.0, std::max(3.0, std::ceil(2000.0 / std::max(est, 1.0))));
+    const std::vector<LayoutPick> cands = layout_candidates(T);
+    LayoutPick best = dflt;
+    double best_us = 0.0, dflt_us = 0.0;
+    QP_TRY(time_product(p, reps, dflt_us));
+    best_us = dflt_us;
+    for (const LayoutPick &L : cands) {
+        if (L == dflt) continue;
+        QP_TRY(apply_layout(p, L));
+        double us = 0.0;
+        QP_TRY(time_product(p, reps, us));
+        // a layout replaces the heuristic one only when clearly faster
+        if (us < 0.97 * best_us) {
+            best = L;
+            best_us = us;
+        }
+    }
+    QP_TRY(apply_layout(p, best));
+    QP_HIP(qp::launch_state_reset(qp::kMaxRhs, p->st(), p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    p->layout = qp_layout{best.it, best.nb, best.xcd, 1, (int)cands.size(), dflt_us, best_us};
+    std::lock_guard<std::mutex> lock(g_layout_mu);
+    g_layouts.emplace(key, best);
+    return QP_OK;
+}
+
+}  // namespace
+
 static qp_status create_problem(qp_problem **out, int d, int n, const double *P, int g,
                                 const int32_t *modes, const double *coef, const double *coefs,
                                 int N, const qp_options *opt)
@@ -1305,7 +1442,38 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     if (p->amin < -1e-12 * scale)
         return bail(fail(QP_ENOTELLIPTIC, "coefficient minimum on the grid is %.6g < 0", p->amin));
     if (std::fabs(p->amin) <= 1e-12 * scale) p->flags |= QP_FLAG_DEGENERATE;
+    p->layout = qp_layout{p->host.item_tiles, p->host.nb_mv, p->host.xcd_front, 0, 0, 0.0, 0.0};
+    if (o.autotune) {
+        s = tune_layout(p);
+        if (s != QP_OK) return bail(s);
+    }
     *out = p;
+    return QP_OK;
+}
+
+qp_status qp_product_layout(const qp_problem *p, qp_layout *out)
+{
+    if (!p || !out) return fail(QP_EINVAL, "null argument");
+    *out = p->layout;
+    return QP_OK;
+}
+
+qp_status qp_set_product_layout(qp_problem *p, const qp_layout *layout)
+{
+    if (!p || !layout) return fail(QP_EINVAL, "null argument");
+    const qp_layout &L = *layout;
+    const bool plane = p->host.tile_s > 1;
+    if (L.workgroups < 1 || L.workgroups > qp::kMaxBlocks)
+        return fail(QP_EINVAL, "workgroups = %d outside [1, %d]", L.workgroups, qp::kMaxBlocks);
+    if (plane ? (L.item_tiles != 1 && L.item_tiles != 2 && L.item_tiles != 4) : L.item_tiles != 1)
+        return fail(QP_EINVAL, "item_tiles = %d is not 1, 2 or 4 (1 for line tiles)", L.item_tiles);
+    if (L.xcd_front != 0 && L.xcd_front != 1) return fail(QP_EINVAL, "xcd_front must be 0 or 1");
+    // launches queued earlier read the table; captured batches hold the old grid
+    QP_HIP(hipStreamSynchronize(p->stream));
+    for (auto &G : p->graphs) (void)hipGraphExecDestroy(G.exec);
+    p->graphs.clear();
+    QP_TRY(apply_layout(p, LayoutPick{L.item_tiles, L.workgroups, L.xcd_front}));
+    p->layout = qp_layout{L.item_tiles, L.workgroups, L.xcd_front, 0, 0, 0.0, 0.0};
     return QP_OK;
 }
 

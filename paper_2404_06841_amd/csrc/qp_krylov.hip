@@ -411,6 +411,10 @@ __global__ __launch_bounds__(kBlock) void k_init_f(const Table *__restrict__ tab
     for (int k = 0; k < KK; ++k) store_partials<2>(acc[k], part + k * kPartStride);
 }
 
+// The first pass's rows of the update and the direction are requested before
+// the previous launch's partial sums are reduced, so the reduction's latency
+// overlaps the loads (a chunk is usually exactly one pass: 4 entries per
+// thread).
 template <int KK>
 __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restrict__ tab,
                                                      float2 *__restrict__ r,
@@ -424,20 +428,36 @@ __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restr
     int begin, end;
     chunk_of_block(tab, begin, end);
     bool act[KK];
-    float a[KK];
-    double alpha[KK], hqv[KK], acc[KK][2];
     bool any = false;
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
+        act[k] = !(sts[k].done || sts[k].pause);
+        if (!act[k] && lead) sts[k].did_update = 0;
+        any = any || act[k];
+    }
+    if (!any) return;
+    const int i0 = begin + threadIdx.x;
+    float2 rv[4][KK], qv[4][KK];
+    float mv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kBlock;
+        if (i < end) {
+            ld_row<KK>(r, i, rv[u]);
+            ld_row<KK>(q, i, qv[u]);
+            mv[u] = M[i];
+        }
+    }
+    float a[KK];
+    double alpha[KK], hqv[KK], acc[KK][2];
+    any = false;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
         State *st = sts + k;
-        act[k] = !(st->done || st->pause);
         a[k] = 0.f;
         alpha[k] = hqv[k] = 0.0;
         acc[k][0] = acc[k][1] = 0.0;
-        if (!act[k]) {
-            if (lead) st->did_update = 0;
-            continue;
-        }
+        if (!act[k]) continue;
         double hq[1];
         load_totals<1>(part_in + k * kPartStride, tab->nb_mv, hq);  // the product's partials
         if (!(hq[0] > 0.0)) {
@@ -457,21 +477,39 @@ __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restr
         any = true;
     }
     if (!any) return;
-    QP_STREAM(i) {
-        float2 rv[KK], qv[KK];
-        ld_row<KK>(r, i, rv);
-        ld_row<KK>(q, i, qv);
-        const double m = (double)M[i];
+    auto step = [&](int i, float2(&rw)[KK], const float2(&qw)[KK], float m) {
+        const double md = (double)m;
 #pragma unroll
         for (int k = 0; k < KK; ++k) {
             if (!act[k]) continue;
-            rv[k].x -= a[k] * qv[k].x;
-            rv[k].y -= a[k] * qv[k].y;
-            const double n2 = (double)rv[k].x * (double)rv[k].x + (double)rv[k].y * (double)rv[k].y;
-            acc[k][0] += m * n2;
+            rw[k].x -= a[k] * qw[k].x;
+            rw[k].y -= a[k] * qw[k].y;
+            const double n2 = (double)rw[k].x * (double)rw[k].x + (double)rw[k].y * (double)rw[k].y;
+            acc[k][0] += md * n2;
             acc[k][1] += n2;
         }
-        st_row<KK>(r, i, rv);
+        st_row<KK>(r, i, rw);
+    };
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kBlock;
+        if (i < end) step(i, rv[u], qv[u], mv[u]);
+    }
+    for (int ib = i0 + 4 * kBlock; ib < end; ib += 4 * kBlock) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = ib + u * kBlock;
+            if (i < end) {
+                ld_row<KK>(r, i, rv[u]);
+                ld_row<KK>(q, i, qv[u]);
+                mv[u] = M[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = ib + u * kBlock;
+            if (i < end) step(i, rv[u], qv[u], mv[u]);
+        }
     }
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
@@ -487,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restr
     }
 }
 
-// FP32-IR direction (is_ir semantics of k_pcg_direction): U += alpha h for
+// FP32-IR direction (the FP32-IR rules of k_pcg_direction): U += alpha h for
 // every right-hand side whose update ran; h = M r + beta h unless it pauses.
 template <int KK>
 __global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__restrict__ tab,
@@ -501,25 +539,43 @@ __global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__re
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block(tab, begin, end);
-    bool did[KK], go[KK];
-    float a[KK], b[KK];
-    double rzn[KK], rrv[KK], betav[KK];
-    bool any_did = false, any_go = false;
+    bool did[KK];
+    bool any_did = false;
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
         State *st = sts + k;
-        const double rz_old = st->rz[j & 1];
         did[k] = st->did_update != 0;
+        // no update this iteration; a paused solve carries rz forward so
+        // iteration j+1 finds it in its slot
+        if (!did[k] && lead && !st->done && st->pause) st->rz[(j + 1) & 1] = st->rz[j & 1];
+        any_did = any_did || did[k];
+    }
+    if (!any_did) return;
+    const int i0 = begin + threadIdx.x;
+    float2 uv[4][KK], hv[4][KK], rv[4][KK];
+    float mv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kBlock;
+        if (i < end) {
+            ld_row<KK>(U, i, uv[u]);
+            ld_row<KK>(h, i, hv[u]);
+            ld_row<KK>(r, i, rv[u]);
+            mv[u] = M[i];
+        }
+    }
+    bool go[KK];
+    float a[KK], b[KK];
+    double rzn[KK], rrv[KK], betav[KK];
+    bool any_go = false;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        State *st = sts + k;
         go[k] = false;
         a[k] = b[k] = 0.f;
         rzn[k] = rrv[k] = betav[k] = 0.0;
-        if (!did[k]) {
-            // no update this iteration; a paused solve carries rz forward so
-            // iteration j+1 finds it in its slot
-            if (lead && !st->done && st->pause) st->rz[(j + 1) & 1] = rz_old;
-            continue;
-        }
-        any_did = true;
+        if (!did[k]) continue;
+        const double rz_old = st->rz[j & 1];
         a[k] = (float)st->alpha;
         double v[2];
         load_totals<2>(part_in + k * kPartStride, gridDim.x, v);
@@ -546,25 +602,41 @@ __global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__re
         betav[k] = rz_new / rz_old;
         b[k] = (float)betav[k];
     }
-    if (!any_did) return;
-    QP_STREAM(i) {
-        float2 uv[KK], hv[KK], rv[KK];
-        ld_row<KK>(U, i, uv);
-        ld_row<KK>(h, i, hv);
-        if (any_go) ld_row<KK>(r, i, rv);
-        const float m = M[i];
+    auto step = [&](int i, float2(&uw)[KK], float2(&hw)[KK], const float2(&rw)[KK], float m) {
 #pragma unroll
         for (int k = 0; k < KK; ++k) {
             if (!did[k]) continue;
-            uv[k].x += a[k] * hv[k].x;
-            uv[k].y += a[k] * hv[k].y;
+            uw[k].x += a[k] * hw[k].x;
+            uw[k].y += a[k] * hw[k].y;
             if (go[k]) {
-                hv[k].x = m * rv[k].x + b[k] * hv[k].x;
-                hv[k].y = m * rv[k].y + b[k] * hv[k].y;
+                hw[k].x = m * rw[k].x + b[k] * hw[k].x;
+                hw[k].y = m * rw[k].y + b[k] * hw[k].y;
             }
         }
-        st_row<KK>(U, i, uv);
-        if (any_go) st_row<KK>(h, i, hv);
+        st_row<KK>(U, i, uw);
+        if (any_go) st_row<KK>(h, i, hw);
+    };
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kBlock;
+        if (i < end) step(i, uv[u], hv[u], rv[u], mv[u]);
+    }
+    for (int ib = i0 + 4 * kBlock; ib < end; ib += 4 * kBlock) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = ib + u * kBlock;
+            if (i < end) {
+                ld_row<KK>(U, i, uv[u]);
+                ld_row<KK>(h, i, hv[u]);
+                ld_row<KK>(r, i, rv[u]);
+                mv[u] = M[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = ib + u * kBlock;
+            if (i < end) step(i, uv[u], hv[u], rv[u], mv[u]);
+        }
     }
     if (lead) {
 #pragma unroll

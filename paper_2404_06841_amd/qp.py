@@ -41,7 +41,7 @@ MAX_N, MAX_D, MAX_MODES = 8, 4, 64
 EXPORTED = (
     "qp_default_options", "qp_workspace_bytes", "qp_create", "qp_create_diag", "qp_destroy",
     "qp_dim",
-    "qp_set_options", "qp_solve", "qp_solve_d", "qp_solve_multi_d", "qp_corrector",
+    "qp_set_options", "qp_product_layout", "qp_set_product_layout", "qp_solve", "qp_solve_d", "qp_solve_multi_d", "qp_corrector",
     "qp_corrector_d",
     "qp_homogenized", "qp_homogenized_ex", "qp_homogenized_batch", "qp_server_create",
     "qp_server_submit", "qp_server_progress", "qp_server_pending", "qp_server_bytes",
@@ -57,7 +57,16 @@ class qp_options(C.Structure):
                 ("inner_tol", C.c_double), ("poll_every", C.c_int),
                 ("profile", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("graphs", C.c_int),
-                ("gather64", C.c_int)]
+                ("gather64", C.c_int), ("autotune", C.c_int)]
+
+
+class qp_layout(C.Structure):
+    _fields_ = [("item_tiles", C.c_int), ("workgroups", C.c_int), ("xcd_front", C.c_int),
+                ("tuned", C.c_int), ("candidates", C.c_int), ("default_us", C.c_double),
+                ("best_us", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class qp_solve_info(C.Structure):
@@ -131,6 +140,8 @@ def lib():
         "qp_multi_index_d": (C.c_int, [vp, vp]),
         "qp_astar_d": (C.c_int, [vp, vp, dp]),
         "qp_coef_extrema": (C.c_int, [vp, dp, dp]),
+        "qp_product_layout": (C.c_int, [vp, C.POINTER(qp_layout)]),
+        "qp_set_product_layout": (C.c_int, [vp, C.POINTER(qp_layout)]),
         "qp_synchronize": (C.c_int, [vp]),
         "qp_strerror": (C.c_char_p, [C.c_int]),
         "qp_last_error": (C.c_char_p, []),
@@ -229,7 +240,7 @@ class Problem:
     def __init__(self, prob, precision: str = "fp64", precond: str = "paper",
                  maxit: int = 10000, inner_tol: float = 1e-4,
                  profile: bool = False, stream=None, poll_every: int = 0,
-                 graphs: bool = True, gather64: bool = False):
+                 graphs: bool = True, gather64: bool = False, autotune: bool = False):
         import torch
         self.d, self.n, self.N = int(prob.d), int(prob.n), int(prob.N)
         self.D = self.N ** self.n
@@ -244,6 +255,7 @@ class Problem:
         opt.poll_every = int(poll_every)
         opt.graphs = 1 if graphs else 0
         opt.gather64 = 1 if gather64 else 0
+        opt.autotune = 1 if autotune else 0
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         nbytes = qp_workspace_bytes(self.d, self.n, self.N, self.g)
@@ -410,6 +422,18 @@ class Problem:
                                 _dptr(A)), "qp_astar_d")
         return A.reshape(self.d, self.d)
 
+    def layout(self) -> dict:
+        """The stiffness product's work layout (qp_product_layout)."""
+        out = qp_layout()
+        _check(lib().qp_product_layout(self.h, C.byref(out)), "qp_product_layout")
+        return out.as_dict()
+
+    def set_layout(self, item_tiles: int, workgroups: int, xcd_front: int):
+        """Set the stiffness product's work layout (qp_set_product_layout)."""
+        L = qp_layout(item_tiles=int(item_tiles), workgroups=int(workgroups),
+                      xcd_front=int(xcd_front))
+        _check(lib().qp_set_product_layout(self.h, C.byref(L)), "qp_set_product_layout")
+
     def coef_extrema(self):
         lo, hi = C.c_double(), C.c_double()
         _check(lib().qp_coef_extrema(self.h, C.byref(lo), C.byref(hi)), "qp_coef_extrema")
@@ -450,8 +474,9 @@ class Server:
     tickets; result(ticket) gives (A*, infos, status) once finished."""
 
     def __init__(self, hbm_budget: int, precision: str = "fp64", maxit: int = 10000,
-                 inner_tol: float = 1e-4):
+                 inner_tol: float = 1e-4, autotune: bool = False):
         opt = qp_default_options()
+        opt.autotune = 1 if autotune else 0
         opt.precision = QP_PREC_FP32_IR if precision == "fp32ir" else QP_PREC_FP64
         opt.maxit = int(maxit)
         opt.inner_tol = float(inner_tol)

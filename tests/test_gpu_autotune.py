@@ -1,0 +1,131 @@
+"""The stiffness product's work layout: explicit layouts and the autotuner.
+
+The layout (plane tiles per wave work item, workgroups, XCD-front or plain
+item order) decides only which waves compute which outputs and which
+workgroup sums which partial dot product.  Every product value must therefore
+be bitwise the same under every layout, and a solve under any layout must
+meet the oracle's A* as the default layout does.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_06841_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2404_06841_amd import qp  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# (item_tiles, workgroups, xcd_front): grids below, at and above one item per
+# wave, grids that are and are not multiples of 8
+LAYOUTS = [(it, nb, x) for it in (1, 2, 4) for nb in (8, 24, 256, 1024) for x in (0, 1)]
+LAYOUTS += [(1, 1, 0), (4, 3, 1), (2, 1000, 1)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x: np.ndarray, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def key(L: dict) -> tuple:
+    return L["item_tiles"], L["workgroups"], L["xcd_front"]
+
+
+@pytest.mark.parametrize("make", [lambda: W.eightfold_random(16, 3), lambda: W.icosahedral(6)],
+                         ids=["eightfold_random_N16", "icosa_N6"])
+def test_every_layout_gives_bitwise_equal_products(make):
+    prob = make()
+    say("[case] layouts", prob.D, prob.g)
+    a = qp.Problem(prob)
+    u = W.random_vector(prob.D, seed=5)
+    u32 = dev(u.astype(np.complex64), torch.complex64)
+    y64 = a.matvec_d(dev(u))
+    y32 = a.matvec32_d(u32)
+    ref = oracle.matvec(prob, u)
+    assert np.abs(y64.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+    for L in LAYOUTS:
+        a.set_layout(*L)
+        got = a.layout()
+        assert key(got) == L and got["tuned"] == 0
+        assert torch.equal(a.matvec_d(dev(u)), y64), L
+        assert torch.equal(a.matvec32_d(u32), y32), L
+    a.close()
+
+
+def test_solves_under_other_layouts_meet_the_oracle():
+    gold = json.load(open(os.path.join(GOLDEN, "oracle_astar.json")))["c2_eightfold_N16"]
+    A_ref = np.array(gold["A"])
+    prob = W.eightfold(16)
+    a = qp.Problem(prob)
+    for L in [(1, 24, 0), (4, 1024, 1), (2, 8, 1)]:
+        a.set_layout(*L)
+        for prec in ("fp64", "fp32ir"):
+            a.set_precision(prec)
+            r = a.homogenized(tol=1e-12)
+            err = np.abs(r.A - A_ref).max() / np.abs(A_ref).max()
+            say(f"  layout {L} {prec}: iters {[i.iters for i in r.infos]} rel err {err:.2e}")
+            assert all(i.status == 0 for i in r.infos)
+            assert err <= 1e-10, (L, prec, err)
+    a.close()
+
+
+def test_autotune_chooses_a_layout_and_reuses_it_for_the_shape():
+    gold = json.load(open(os.path.join(GOLDEN, "oracle_astar.json")))["c2_eightfold_N16"]
+    A_ref = np.array(gold["A"])
+    prob = W.eightfold(16)
+    plain = qp.Problem(prob, precision="fp32ir")
+    a = qp.Problem(prob, precision="fp32ir", autotune=True)
+    La = a.layout()
+    say("  tuned layout", La)
+    assert La["tuned"] in (1, 2)
+    if La["tuned"] == 1:
+        assert La["candidates"] >= 2
+        assert 0 < La["best_us"] <= La["default_us"]
+    b = qp.Problem(prob, precision="fp32ir", autotune=True)
+    Lb = b.layout()
+    assert Lb["tuned"] == 2 and key(Lb) == key(La)
+    u = W.random_vector(prob.D, seed=9)
+    assert torch.equal(a.matvec_d(dev(u)), plain.matvec_d(dev(u)))
+    r = a.homogenized(tol=1e-12)
+    err = np.abs(r.A - A_ref).max() / np.abs(A_ref).max()
+    assert all(i.status == 0 for i in r.infos) and err <= 1e-10, err
+    # the same layout set explicitly repeats the tuned problem's A* bitwise
+    plain.set_layout(*key(La))
+    r2 = plain.homogenized(tol=1e-12)
+    assert np.array_equal(r2.A, r.A)
+    for p in (plain, a, b):
+        p.close()
+
+
+def test_invalid_layouts_are_rejected():
+    a = qp.Problem(W.eightfold(8))
+    for L in [(3, 8, 0), (1, 0, 0), (1, 1025, 0), (1, 8, 2)]:
+        with pytest.raises(qp.QPError) as e:
+            a.set_layout(*L)
+        assert e.value.status == qp.QP_EINVAL
+    line = qp.Problem(W.periodic_1d(100))  # line tiles: one item size
+    assert line.layout()["item_tiles"] == 1
+    with pytest.raises(qp.QPError):
+        line.set_layout(2, 8, 1)
+    u = W.random_vector(line.D, seed=3)
+    y = line.matvec_d(dev(u))
+    line.set_layout(1, 16, 0)
+    assert torch.equal(line.matvec_d(dev(u)), y)
+    a.close()
+    line.close()
