@@ -81,10 +81,12 @@ typedef struct qp_options {
     int maxit;          /* PCG iteration limit; default 10000                     */
     double inner_tol;   /* FP32-IR: replace the float residual once it has
                            dropped by this factor since the last replacement;
-                           default 1e-4                                          */
-    int poll_every;     /* iterations queued between convergence polls, and the
-                           longest FP32-IR run between replacements; 0 = 8,
-                           rounded up to an even count, at most 64                */
+                           default 1e-5 (float rounding limits it to about
+                           1e-6: below that the recursion drifts and restarts) */
+    int poll_every;     /* iterations queued between convergence polls (FP32-IR:
+                           each batch ends with the replacement steps, which act
+                           on the right-hand sides that reached inner_tol);
+                           0 = 12, rounded up to an even count, at most 64      */
     int profile;        /* nonzero: bracket every stiffness-product launch with
                            HIP events; totals reported in qp_solve_info.  Batches
                            are then launched directly (no graph replay)          */

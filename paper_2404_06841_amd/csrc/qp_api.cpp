@@ -425,7 +425,7 @@ struct Profile {
 
 int batch_size(const qp_options &o)
 {
-    int b = o.poll_every > 0 ? o.poll_every : 8;
+    int b = o.poll_every > 0 ? o.poll_every : 12;
     b = std::min(kMaxBatch, std::max(2, b));
     return (b + 1) & ~1;
 }
@@ -1186,7 +1186,7 @@ void qp_default_options(qp_options *opt)
     opt->precision = QP_PREC_FP64;
     opt->precond = QP_PRECOND_PAPER;
     opt->maxit = 10000;
-    opt->inner_tol = 1e-4;
+    opt->inner_tol = 1e-5;
     opt->poll_every = 0;
     opt->graphs = 1;
 }

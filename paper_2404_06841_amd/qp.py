@@ -238,7 +238,7 @@ class Problem:
     non-None attribute `coefs` (d x g) makes it a diagonal coefficient."""
 
     def __init__(self, prob, precision: str = "fp64", precond: str = "paper",
-                 maxit: int = 10000, inner_tol: float = 1e-4,
+                 maxit: int = 10000, inner_tol: float = 1e-5,
                  profile: bool = False, stream=None, poll_every: int = 0,
                  graphs: bool = True, gather64: bool = False, autotune: bool = False):
         import torch
@@ -474,7 +474,7 @@ class Server:
     tickets; result(ticket) gives (A*, infos, status) once finished."""
 
     def __init__(self, hbm_budget: int, precision: str = "fp64", maxit: int = 10000,
-                 inner_tol: float = 1e-4, autotune: bool = False):
+                 inner_tol: float = 1e-5, autotune: bool = False):
         opt = qp_default_options()
         opt.autotune = 1 if autotune else 0
         opt.precision = QP_PREC_FP32_IR if precision == "fp32ir" else QP_PREC_FP64

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_and_strings():
     o = qp.qp_default_options()
     assert o.precision == qp.QP_PREC_FP64 and o.precond == qp.QP_PRECOND_PAPER
-    assert o.maxit == 10000 and o.inner_tol == pytest.approx(1e-4) and o.poll_every == 0
+    assert o.maxit == 10000 and o.inner_tol == pytest.approx(1e-5) and o.poll_every == 0
     assert o.graphs == 1
     assert o.gather64 == 0
     assert o.stream is None and o.workspace is None
