@@ -231,9 +231,9 @@ def diagonal_workload(torch, np, qp, W, gold, steps: int, warmup: int):
 def batch_instances(torch, np, qp, W, reps: int = 3):
     """64 seeded eightfold instances with N drawn from {8, 12, 16, 24, 32}
     (16.2M unknowns for the default seed), two correctors each, FP32-IR:
-    homogenized together by
-    qp_homogenized_batch (each problem on its own stream) versus one after
-    another on the same problems."""
+    homogenized together by qp_homogenized_grouped (one launch per solver
+    step for all 64), by qp_homogenized_batch (each problem on its own
+    stream), and one after another, on the same problems."""
     probs = W.eightfold_batch(64)
     gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream(), autotune=True)
            for pr in probs]
@@ -244,6 +244,12 @@ def batch_instances(torch, np, qp, W, reps: int = 3):
     for _ in range(reps):
         As, _, st = qp.homogenized_batch(gps, tol=TOL)
     dt_b = (time.perf_counter() - t0) / reps
+    qp.homogenized_batch(gps, tol=TOL, grouped=True)  # warm-up (group tables)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Ag, _, stg = qp.homogenized_batch(gps, tol=TOL, grouped=True)
+    dt_g = (time.perf_counter() - t0) / reps
     seq = [gp.homogenized(tol=TOL, energy=False).A.copy() for gp in gps]
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -251,17 +257,22 @@ def batch_instances(torch, np, qp, W, reps: int = 3):
             gp.homogenized(tol=TOL, energy=False)
     dt_s = (time.perf_counter() - t0) / reps
     same = all(np.array_equal(a, b) for a, b in zip(As, seq))
+    same_g = all(np.array_equal(a, b) for a, b in zip(Ag, seq))
     for gp in gps:
         gp.close()
     Ns = sorted(set(int(pr.N) for pr in probs))
     return {"workload": f"64 seeded eightfold d=2 n=4 instances, N in {Ns} "
                         f"({sum(pr.D for pr in probs):,} unknowns), 2 correctors each, FP32-IR",
-            "value": round(solves / dt_b, 2), "unit": "corrector solves/s",
-            "ms_per_batch": round(dt_b * 1e3, 3), "status": int(st),
+            "value": round(solves / min(dt_g, dt_b), 2), "unit": "corrector solves/s",
+            "what": "the faster of grouped_value and streams_value",
+            "grouped_value": round(solves / dt_g, 2), "grouped_ms": round(dt_g * 1e3, 3),
+            "grouped_status": int(stg), "grouped_results_equal_sequential": bool(same_g),
+            "streams_value": round(solves / dt_b, 2), "streams_ms": round(dt_b * 1e3, 3),
+            "streams_status": int(st), "streams_results_equal_sequential": bool(same),
             "sequential_value": round(solves / dt_s, 2),
             "sequential_ms": round(dt_s * 1e3, 3),
-            "speedup_vs_sequential": round(dt_s / dt_b, 3),
-            "results_equal_sequential": bool(same)}
+            "grouped_speedup_vs_sequential": round(dt_s / dt_g, 3),
+            "streams_speedup_vs_sequential": round(dt_s / dt_b, 3)}
 
 
 def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):

@@ -291,6 +291,30 @@ qp_status qp_homogenized_ex(qp_problem *p, double *Astar, double *Astar_energy,
 qp_status qp_homogenized_batch(qp_problem *const *problems, int count, double *Astar, double tol,
                                qp_solve_info *infos);
 
+/*
+ * Homogenize several FP32-IR problems with one launch per solver step for
+ * the whole group: each launch of the float product, update, direction and
+ * of the residual replacement covers the workgroups of every problem, each
+ * workgroup computing what it computes in that problem's own launch, so
+ * every A* equals qp_homogenized's on the problem alone.  The replacement
+ * steps follow every second iteration; the host polls every poll_every
+ * iterations (problem 0's options).
+ *   problems  count distinct problems created with precision
+ *             QP_PREC_FP32_IR, the same d (2 or 3), a scalar coefficient
+ *             (all real or all complex), plane tiles (N <= 32, n >= 2) with
+ *             the default 32-bit gathers, on one device, with equal maxit;
+ *             N, n, P, modes and g may differ
+ *   Astar, infos  as for qp_homogenized_batch
+ * Runs on problem 0's stream after waiting for every problem's stream.
+ * Calls from several host threads are serialized (the group tables are
+ * shared: up to count * (160 + 4 * workgroups) bytes of device memory and
+ * 3 * count * d states of pinned memory, allocated on first use and kept).
+ * Returns QP_EINVAL (naming the problem and the reason) when a problem
+ * cannot join; otherwise the first non-QP_OK corrector status.
+ */
+qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double *Astar, double tol,
+                                 qp_solve_info *infos);
+
 /* ---- serving: a request queue over a cache of problems ---- */
 
 /*

@@ -1621,6 +1621,274 @@ qp_status qp_homogenized_batch(qp_problem *const *problems, int count, double *A
     return worst;
 }
 
+// ---------------------------------------------------------------- grouped batch
+//
+// The corrector solves of several FP32-IR problems as one launch sequence:
+// every step (float product, update, direction; fold, FP64 residual,
+// replacement direction) is one launch whose workgroups are the problems'
+// own workgroups one after the other (GroupEntry, owner tables), so the
+// device sees one launch per step for the whole batch.  Each problem's
+// workgroups compute exactly what a launch of that problem alone computes,
+// so the values equal standalone solves.  The replacement steps follow every
+// second iteration (a paused right-hand side waits at most one iteration;
+// with nothing paused they exit at once), the host polls every poll_every
+// iterations.
+namespace {
+
+std::mutex g_group_mu;  // the group buffers below serve one call at a time
+struct GroupBuffers {
+    int device = -1;
+    char *dev = nullptr;
+    size_t dev_bytes = 0;
+    State *host = nullptr;  // pinned: 3 slots of states
+    size_t host_states = 0;
+};
+GroupBuffers g_gb;
+
+qp_status group_buffers(int device, size_t dev_bytes, size_t nstates)
+{
+    if (g_gb.device != device) {
+        if (g_gb.dev) (void)hipFree(g_gb.dev);
+        if (g_gb.host) (void)hipHostFree(g_gb.host);
+        g_gb = GroupBuffers{};
+        g_gb.device = device;
+    }
+    if (dev_bytes > g_gb.dev_bytes) {
+        if (g_gb.dev) (void)hipFree(g_gb.dev);
+        g_gb.dev = nullptr;
+        g_gb.dev_bytes = 0;
+        if (hipMalloc(&g_gb.dev, dev_bytes) != hipSuccess)
+            return fail(QP_ENOMEM, "group table of %zu bytes", dev_bytes);
+        g_gb.dev_bytes = dev_bytes;
+    }
+    if (nstates > g_gb.host_states) {
+        if (g_gb.host) (void)hipHostFree(g_gb.host);
+        g_gb.host = nullptr;
+        g_gb.host_states = 0;
+        if (hipHostMalloc(&g_gb.host, 3 * nstates * sizeof(State), hipHostMallocDefault) != hipSuccess)
+            return fail(QP_ENOMEM, "pinned group states");
+        g_gb.host_states = nstates;
+    }
+    return QP_OK;
+}
+
+// Why p cannot join a group led by p0 (null: it can).
+const char *group_mismatch(const qp_problem *p, const qp_problem *p0)
+{
+    if (p->opt.precision != QP_PREC_FP32_IR) return "precision is not FP32-IR";
+    if (p->host.tile_s <= 1 || p->host.wide) return "not a plane-tile problem with 32-bit gathers";
+    if (p->host.aniso) return "diagonal coefficient";
+    if (p->host.d != 2 && p->host.d != 3) return "d is not 2 or 3";
+    if (p->host.d != p0->host.d) return "d differs from problem 0";
+    if (p->host.real_coef != p0->host.real_coef) return "real/complex coefficient differs from problem 0";
+    if (p->device != p0->device) return "device differs from problem 0";
+    if (p->opt.maxit != p0->opt.maxit) return "maxit differs from problem 0";
+    return nullptr;
+}
+
+}  // namespace
+
+qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double *Astar, double tol,
+                                 qp_solve_info *infos)
+{
+    if (!problems || !Astar || count < 1) return fail(QP_EINVAL, "null argument or empty group");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QP_EINVAL, "tol must be positive and finite");
+    for (int i = 0; i < count; ++i) {
+        if (!problems[i]) return fail(QP_EINVAL, "problem %d is null", i);
+        for (int k = 0; k < i; ++k)
+            if (problems[k] == problems[i]) return fail(QP_EINVAL, "problem %d repeats problem %d", i, k);
+        if (const char *why = group_mismatch(problems[i], problems[0]))
+            return fail(QP_EINVAL, "problem %d cannot join the group: %s", i, why);
+    }
+    qp_problem *p0 = problems[0];
+    const int G = count, d = p0->host.d, K = d;
+    const hipStream_t s = p0->stream;
+    std::lock_guard<std::mutex> lock(g_group_mu);
+    for (int i = 0; i < G; ++i) QP_HIP(hipStreamSynchronize(problems[i]->stream));
+
+    // group table and owners
+    std::vector<qp::GroupEntry> ents(G);
+    std::vector<int> own_mv, own_st;
+    int gpmax = 4;
+    for (int i = 0; i < G; ++i) {
+        qp_problem *p = problems[i];
+        const qp::Parts parts = p->parts();
+        qp::GroupEntry &e = ents[i];
+        e.tab = p->tab;
+        e.recs = p->recs();
+        e.urec32 = p->urec(qp::F32);
+        e.upku32 = p->upku(qp::F32);
+        e.urec64 = p->urec(qp::F64);
+        e.upku64 = p->upku(qp::F64);
+        e.x32 = p->x32();
+        e.r32 = p->r32();
+        e.h32 = p->h32();
+        e.q32 = p->q32();
+        e.M32 = p->M32();
+        e.X = p->chi(0);
+        e.F = p->F();
+        e.pa = parts.a;
+        e.pb = parts.b;
+        e.st = p->st();
+        e.mv0 = (int)own_mv.size();
+        e.nb_mv = p->host.nb_mv;
+        e.sv0 = (int)own_st.size();
+        e.nb_st = p->host.nblocks;
+        own_mv.insert(own_mv.end(), (size_t)e.nb_mv, i);
+        own_st.insert(own_st.end(), (size_t)e.nb_st, i);
+        gpmax = std::max(gpmax, (p->host.g + 3) & ~3);
+    }
+    int tot_mv = (int)own_mv.size(), tot_st = (int)own_st.size();
+    const size_t nst = (size_t)G * K;
+    const size_t o_own_mv = align_up(sizeof(qp::GroupEntry) * G);
+    const size_t o_own_st = align_up(o_own_mv + sizeof(int) * tot_mv);
+    const size_t o_states = align_up(o_own_st + sizeof(int) * tot_st);
+    const size_t bytes = o_states + 3 * nst * sizeof(State);
+    QP_TRY(group_buffers(p0->device, bytes, nst));
+    auto *E = reinterpret_cast<qp::GroupEntry *>(g_gb.dev);
+    auto *owner_mv = reinterpret_cast<int *>(g_gb.dev + o_own_mv);
+    auto *owner_st = reinterpret_cast<int *>(g_gb.dev + o_own_st);
+    auto *dstates = reinterpret_cast<State *>(g_gb.dev + o_states);
+    QP_HIP(hipMemcpy(E, ents.data(), sizeof(qp::GroupEntry) * G, hipMemcpyHostToDevice));
+    QP_HIP(hipMemcpy(owner_mv, own_mv.data(), sizeof(int) * tot_mv, hipMemcpyHostToDevice));
+    QP_HIP(hipMemcpy(owner_st, own_st.data(), sizeof(int) * tot_st, hipMemcpyHostToDevice));
+
+    // set-up of every problem (the launches of a standalone homogenization)
+    QP_HIP(hipEventRecord(p0->ev_t0, s));
+    for (int i = 0; i < G; ++i) {
+        qp_problem *p = problems[i];
+        const qp::Parts parts = p->parts();
+        for (int j = 0; j < d; ++j)
+            QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, p->F() + (size_t)2 * p->host.D * j, s));
+        QP_HIP(qp::launch_state_reset(K, p->st(), s));
+        QP_HIP(qp::launch_ir_unit(K, p->tab, p->host, p->F(), parts, p->st(), s));
+        QP_HIP(qp::launch_pcg_init(qp::F32, K, p->tab, p->host, p->F(), p->chi(0), p->x32(),
+                                   p->r32(), p->h32(), p->M32(), parts, p->st(), s));
+        QP_HIP(qp::launch_pcg_start(qp::F32, K, p->host, tol, p->opt.inner_tol, p->opt.maxit, parts,
+                                    p->st(), s));
+    }
+    auto replacement = [&](int j) -> qp_status {
+        QP_HIP(qp::launch_group_vec(2, j, K, tot_st, E, owner_st, s));
+        QP_HIP(qp::launch_group_matvec(qp::F64, d, p0->host.real_coef, tot_mv, gpmax, E, owner_mv, s));
+        QP_HIP(qp::launch_group_vec(3, j, K, tot_st, E, owner_st, s));
+        return QP_OK;
+    };
+    auto poll = [&](int slot, hipEvent_t ev) -> qp_status {
+        QP_HIP(qp::launch_group_states(G, K, E, dstates + slot * nst, s));
+        QP_HIP(hipMemcpyAsync(g_gb.host + slot * nst, dstates + slot * nst, nst * sizeof(State),
+                              hipMemcpyDeviceToHost, s));
+        if (ev) QP_HIP(hipEventRecord(ev, s));
+        return QP_OK;
+    };
+    const int maxit = p0->opt.maxit, full = batch_size(p0->opt);
+    int j = 0, slot = 0, inflight = 0;
+    bool fin = false;
+    std::vector<char> running(G, 1);
+    // Launches cover only the problems still running: once a poll shows
+    // problems finished, the owner tables are rebuilt without them (after the
+    // queued work has drained; a finished problem's state no longer changes).
+    auto compact = [&](const State *seen) -> qp_status {
+        bool changed = false;
+        for (int i = 0; i < G; ++i) {
+            bool done = true;
+            for (int r = 0; r < K; ++r) done = done && seen[(size_t)i * K + r].done != 0;
+            if (running[i] && done) {
+                running[i] = 0;
+                changed = true;
+            }
+        }
+        bool any = false;
+        for (int i = 0; i < G; ++i) any = any || running[i];
+        if (!changed || !any) return QP_OK;
+        own_mv.clear();
+        own_st.clear();
+        for (int i = 0; i < G; ++i) {
+            if (!running[i]) continue;
+            ents[i].mv0 = (int)own_mv.size();
+            ents[i].sv0 = (int)own_st.size();
+            own_mv.insert(own_mv.end(), (size_t)ents[i].nb_mv, i);
+            own_st.insert(own_st.end(), (size_t)ents[i].nb_st, i);
+        }
+        QP_HIP(hipStreamSynchronize(s));
+        QP_HIP(hipMemcpy(E, ents.data(), sizeof(qp::GroupEntry) * G, hipMemcpyHostToDevice));
+        QP_HIP(hipMemcpy(owner_mv, own_mv.data(), sizeof(int) * own_mv.size(), hipMemcpyHostToDevice));
+        QP_HIP(hipMemcpy(owner_st, own_st.data(), sizeof(int) * own_st.size(), hipMemcpyHostToDevice));
+        tot_mv = (int)own_mv.size();
+        tot_st = (int)own_st.size();
+        return QP_OK;
+    };
+    auto queue = [&]() -> qp_status {
+        const int k = std::min(full, maxit - j);
+        for (int it = 0; it < k; ++it) {
+            QP_HIP(qp::launch_group_matvec(qp::F32, d, p0->host.real_coef, tot_mv, gpmax, E, owner_mv, s));
+            QP_HIP(qp::launch_group_vec(0, it, K, tot_st, E, owner_st, s));
+            QP_HIP(qp::launch_group_vec(1, it, K, tot_st, E, owner_st, s));
+            if (it & 1) QP_TRY(replacement(it));
+        }
+        QP_TRY(poll(slot, p0->ev_poll[slot]));
+        j += k;
+        slot ^= 1;
+        ++inflight;
+        return QP_OK;
+    };
+    // two chunks of iterations in flight: the device runs one while the host
+    // inspects the poll of the other
+    while (!fin) {
+        while (inflight < 2 && j < maxit) QP_TRY(queue());
+        if (inflight == 0) break;
+        const int oldest = (inflight == 2) ? slot : (slot ^ 1);
+        QP_HIP(hipEventSynchronize(p0->ev_poll[oldest]));
+        --inflight;
+        fin = true;
+        for (size_t t = 0; t < nst; ++t) fin = fin && g_gb.host[oldest * nst + t].done != 0;
+        if (!fin) QP_TRY(compact(g_gb.host + oldest * nst));
+    }
+    if (!fin) {
+        // iteration limit: fold every unfinished increment into X with one
+        // forced replacement, whose true residual decides the status
+        for (int i = 0; i < G; ++i) QP_HIP(qp::launch_ir_force(K, problems[i]->st(), s));
+        QP_TRY(replacement(maxit));
+    }
+    QP_HIP(hipEventRecord(p0->ev_t1, s));
+    QP_TRY(poll(2, nullptr));
+    for (int i = 0; i < G; ++i) {
+        qp_problem *p = problems[i];
+        QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), s));
+        QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    QP_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    QP_HIP(hipEventElapsedTime(&ms, p0->ev_t0, p0->ev_t1));
+    const State *fs = g_gb.host + 2 * nst;
+    qp_status worst = QP_OK;
+    size_t ao = 0;
+    for (int i = 0; i < G; ++i) {
+        qp_problem *p = problems[i];
+        for (int e = 0; e < d * d; ++e) Astar[ao + e] = p->hsmall[e];
+        ao += (size_t)d * d;
+        for (int r = 0; r < K; ++r) {
+            const State &st = fs[(size_t)i * K + r];
+            const qp_status status = st.done ? (qp_status)st.status : QP_ENOCONV;
+            if (infos) {
+                qp_solve_info *info = infos + (size_t)i * K + r;
+                std::memset(info, 0, sizeof(*info));
+                info->flags = p->flags;
+                info->status = status;
+                info->iters = st.iters;
+                info->outer_iters = st.replacements;
+                info->rel_resid = std::sqrt(st.rr);
+                info->seconds = ms * 1e-3;
+            }
+            if (status != QP_OK && worst == QP_OK) worst = status;
+        }
+    }
+    if (worst != QP_OK) {
+        report(worst);
+        fail(worst, "a corrector solve of the group did not converge");
+    }
+    return worst;
+}
+
 qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info *info)
 {
     return qp_homogenized_ex(p, Astar, nullptr, tol, info);

@@ -83,13 +83,19 @@ template <> __device__ __forceinline__ double2 gather<double>(rsrc_t r, int inde
     return make_double2(v.x, v.y);
 }
 
-__device__ __forceinline__ void chunk_of_block(const Table *__restrict__ tab, int &begin, int &end)
+// Chunk of workgroup b of nb (a grouped launch gives each problem its own
+// range of workgroups; b and nb are then the problem's).
+__device__ __forceinline__ void chunk_of_block_at(const Table *__restrict__ tab, int b, int nb,
+                                                  int &begin, int &end)
 {
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
     const int logical = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
     begin = logical * tab->chunk;
     end = min(begin + tab->chunk, tab->D);
+}
+
+__device__ __forceinline__ void chunk_of_block(const Table *__restrict__ tab, int &begin, int &end)
+{
+    chunk_of_block_at(tab, (int)blockIdx.x, (int)gridDim.x, begin, end);
 }
 
 // floor(x / N) for 0 <= x < 2^31 by multiply-shift (magic from the host).
@@ -135,15 +141,21 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV])
     __syncthreads();
 }
 
-// Store this workgroup's totals: part[k * kMaxBlocks + blockIdx.x].
+// Store workgroup b's totals: part[k * kMaxBlocks + b].
 template <int NV, bool MIN = false>
-__device__ __forceinline__ void store_partials(double (&v)[NV], double *__restrict__ part)
+__device__ __forceinline__ void store_partials_at(double (&v)[NV], double *__restrict__ part, int b)
 {
     block_reduce<NV, MIN>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) part[k * kMaxBlocks + blockIdx.x] = v[k];
+        for (int k = 0; k < NV; ++k) part[k * kMaxBlocks + b] = v[k];
     }
+}
+
+template <int NV, bool MIN = false>
+__device__ __forceinline__ void store_partials(double (&v)[NV], double *__restrict__ part)
+{
+    store_partials_at<NV, MIN>(v, part, (int)blockIdx.x);
 }
 
 // Sum (or min) of the nb partials a previous kernel stored; same order in

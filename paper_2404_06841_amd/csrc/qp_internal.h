@@ -126,6 +126,24 @@ struct State {
 };
 
 enum Epilogue { EPI_NONE = 0, EPI_ALPHA = 1, EPI_RESID = 2 };
+
+// One problem of a grouped launch (FP32-IR steps of several problems in one
+// launch): its table, records and vectors, and the workgroups it owns.
+// Workgroup w of a grouped product launch serves problem owner_mv[w] as
+// workgroup w - mv0 of nb_mv; of a grouped vector launch, problem owner_st[w]
+// as workgroup w - sv0 of nb_st.
+struct GroupEntry {
+    const Table *tab;
+    const ModeRec *recs;
+    const void *urec32, *upku32, *urec64, *upku64;  // unit records per precision
+    float *x32, *r32, *h32, *q32;                   // float families (K interleaved)
+    const float *M32;
+    double *X;                                      // FP64 solutions (K vectors)
+    const double *F;                                // FP64 right-hand sides (K vectors)
+    double *pa, *pb;                                // partial sums (Parts a, b)
+    State *st;                                      // K states
+    int mv0, nb_mv, sv0, nb_st;
+};
 enum Precision { F64 = 0, F32 = 1 };
 
 // Partial-sum buffers: each holds kMaxRhs slices of kPartStride doubles
@@ -199,6 +217,20 @@ hipError_t launch_ir_direction(int j, int K, const Table *tab, const Table &ht, 
                                hipStream_t s);
 
 // FP32-IR: pause every unfinished right-hand side (final forced replacement).
+// Grouped FP32-IR steps over the problems of E (see GroupEntry); total: the
+// workgroups of the launch (the sum of the problems' nb_mv for the product,
+// of their nb_st for the vector steps), owner: the problem of each.
+// Product: prec F32 = float product of h into q with the alpha partials,
+// F64 = replaced FP64 residual of X into the float r; d in {2, 3}, K = d,
+// scalar coefficient (real or complex), gpmax = the largest padded mode count.
+hipError_t launch_group_matvec(int prec, int d, bool real, int total, int gpmax,
+                               const GroupEntry *E, const int *owner, hipStream_t s);
+// Vector steps of iteration j: 0 update, 1 direction, 2 fold, 3 replacement
+// direction; K in {2, 3}.
+hipError_t launch_group_vec(int step, int j, int K, int total, const GroupEntry *E, const int *owner,
+                            hipStream_t s);
+// out[g K + k] = state k of problem g (one workgroup; out in device memory).
+hipError_t launch_group_states(int G, int K, const GroupEntry *E, State *out, hipStream_t s);
 hipError_t launch_ir_force(int K, State *st, hipStream_t s);
 
 // ---- setup and single-step kernels ----

@@ -416,7 +416,8 @@ __global__ __launch_bounds__(kBlock) void k_init_f(const Table *__restrict__ tab
 // overlaps the loads (a chunk is usually exactly one pass: 4 entries per
 // thread).
 template <int KK>
-__global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restrict__ tab,
+__device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
+                                         const Table *__restrict__ tab,
                                                      float2 *__restrict__ r,
                                                      const float2 *__restrict__ q,
                                                      const float *__restrict__ M,
@@ -424,9 +425,9 @@ __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restr
                                                      double *__restrict__ part_out,
                                                      State *__restrict__ sts)
 {
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool lead = vb == 0 && threadIdx.x == 0;
     int begin, end;
-    chunk_of_block(tab, begin, end);
+    chunk_of_block_at(tab, vb, vnb, begin, end);
     bool act[KK];
     bool any = false;
 #pragma unroll
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restr
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
         if (!act[k]) continue;
-        store_partials<2>(acc[k], part_out + k * kPartStride);
+        store_partials_at<2>(acc[k], part_out + k * kPartStride, vb);
         if (lead) {
             State *st = sts + k;
             st->alpha = alpha[k];
@@ -528,7 +529,8 @@ __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restr
 // FP32-IR direction (the FP32-IR rules of k_pcg_direction): U += alpha h for
 // every right-hand side whose update ran; h = M r + beta h unless it pauses.
 template <int KK>
-__global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__restrict__ tab,
+__device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
+                                         const Table *__restrict__ tab,
                                                         float2 *__restrict__ U,
                                                         const float2 *__restrict__ r,
                                                         float2 *__restrict__ h,
@@ -536,9 +538,9 @@ __global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__re
                                                         const double *__restrict__ part_in,
                                                         State *__restrict__ sts)
 {
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool lead = vb == 0 && threadIdx.x == 0;
     int begin, end;
-    chunk_of_block(tab, begin, end);
+    chunk_of_block_at(tab, vb, vnb, begin, end);
     bool did[KK];
     bool any_did = false;
 #pragma unroll
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__re
         const double rz_old = st->rz[j & 1];
         a[k] = (float)st->alpha;
         double v[2];
-        load_totals<2>(part_in + k * kPartStride, gridDim.x, v);
+        load_totals<2>(part_in + k * kPartStride, vnb, v);
         const double rz_new = v[0], rr = v[1];
         if (!finite(rr) || !finite(rz_new)) {
             if (lead) {
@@ -651,15 +653,15 @@ __global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__re
 }
 
 template <int KK>
-__global__ __launch_bounds__(kBlock) void k_fold_f(const Table *__restrict__ tab,
+__device__ __forceinline__ void fold_f(const int vb, const int vnb, const Table *__restrict__ tab,
                                                    double2 *__restrict__ X,
                                                    float2 *__restrict__ x,
                                                    State *__restrict__ sts)
 {
     const size_t D = tab->D;
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool lead = vb == 0 && threadIdx.x == 0;
     int begin, end;
-    chunk_of_block(tab, begin, end);
+    chunk_of_block_at(tab, vb, vnb, begin, end);
     bool rep[KK];
     double unit[KK];
     bool any = false;
@@ -694,16 +696,17 @@ __global__ __launch_bounds__(kBlock) void k_fold_f(const Table *__restrict__ tab
 }
 
 template <int KK>
-__global__ __launch_bounds__(kBlock) void k_irdir_f(int j, const Table *__restrict__ tab,
+__device__ __forceinline__ void irdir_f(const int vb, const int vnb, int j,
+                                         const Table *__restrict__ tab,
                                                     const float2 *__restrict__ r,
                                                     float2 *__restrict__ h,
                                                     const float *__restrict__ M,
                                                     const double *__restrict__ part_in,
                                                     State *__restrict__ sts)
 {
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool lead = vb == 0 && threadIdx.x == 0;
     int begin, end;
-    chunk_of_block(tab, begin, end);
+    chunk_of_block_at(tab, vb, vnb, begin, end);
     bool go[KK];
     float b[KK];
     double rzn[KK], rrv[KK], betav[KK];
@@ -774,6 +777,81 @@ __global__ __launch_bounds__(kBlock) void k_irdir_f(int j, const Table *__restri
             st->replacements = st->replacements + 1;
         }
     }
+}
+
+
+// Kernels over one problem (the whole grid) and grouped over several (each
+// workgroup serves the problem owner[blockIdx.x] as one of its workgroups).
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restrict__ tab,
+                                                     float2 *__restrict__ r,
+                                                     const float2 *__restrict__ q,
+                                                     const float *__restrict__ M,
+                                                     const double *__restrict__ part_in,
+                                                     double *__restrict__ part_out,
+                                                     State *__restrict__ sts)
+{
+    update_f<KK>((int)blockIdx.x, (int)gridDim.x, j, tab, r, q, M, part_in, part_out, sts);
+}
+
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__restrict__ tab,
+                                                        float2 *__restrict__ U,
+                                                        const float2 *__restrict__ r,
+                                                        float2 *__restrict__ h,
+                                                        const float *__restrict__ M,
+                                                        const double *__restrict__ part_in,
+                                                        State *__restrict__ sts)
+{
+    direction_f<KK>((int)blockIdx.x, (int)gridDim.x, j, tab, U, r, h, M, part_in, sts);
+}
+
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_fold_f(const Table *__restrict__ tab,
+                                                   double2 *__restrict__ X,
+                                                   float2 *__restrict__ x,
+                                                   State *__restrict__ sts)
+{
+    fold_f<KK>((int)blockIdx.x, (int)gridDim.x, tab, X, x, sts);
+}
+
+template <int KK>
+__global__ __launch_bounds__(kBlock) void k_irdir_f(int j, const Table *__restrict__ tab,
+                                                    const float2 *__restrict__ r,
+                                                    float2 *__restrict__ h,
+                                                    const float *__restrict__ M,
+                                                    const double *__restrict__ part_in,
+                                                    State *__restrict__ sts)
+{
+    irdir_f<KK>((int)blockIdx.x, (int)gridDim.x, j, tab, r, h, M, part_in, sts);
+}
+
+// step: 0 update, 1 direction, 2 fold, 3 replacement direction
+template <int KK, int STEP>
+__global__ __launch_bounds__(kBlock) void k_vec_grp(int j, const GroupEntry *__restrict__ ents,
+                                                    const int *__restrict__ owner)
+{
+    const GroupEntry &e = ents[owner[blockIdx.x]];
+    const int vb = (int)blockIdx.x - e.sv0, vnb = e.nb_st;
+    float2 *x32 = reinterpret_cast<float2 *>(e.x32);
+    float2 *r32 = reinterpret_cast<float2 *>(e.r32);
+    float2 *h32 = reinterpret_cast<float2 *>(e.h32);
+    if constexpr (STEP == 0)
+        update_f<KK>(vb, vnb, j, e.tab, r32, reinterpret_cast<const float2 *>(e.q32), e.M32, e.pa,
+                     e.pb, e.st);
+    else if constexpr (STEP == 1)
+        direction_f<KK>(vb, vnb, j, e.tab, x32, r32, h32, e.M32, e.pb, e.st);
+    else if constexpr (STEP == 2)
+        fold_f<KK>(vb, vnb, e.tab, reinterpret_cast<double2 *>(e.X), x32, e.st);
+    else
+        irdir_f<KK>(vb, vnb, j, e.tab, r32, h32, e.M32, e.pb, e.st);
+}
+
+// The K states of every problem of a group, one after the other (the poll).
+__global__ void k_group_states(int G, int K, const GroupEntry *__restrict__ ents,
+                               State *__restrict__ out)
+{
+    for (int t = threadIdx.x; t < G * K; t += blockDim.x) out[t] = ents[t / K].st[t % K];
 }
 
 }  // namespace
@@ -921,6 +999,39 @@ hipError_t launch_ir_force(int K, State *st, hipStream_t s)
 hipError_t launch_state_reset(int K, State *st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, K, st);
+    return hipGetLastError();
+}
+
+}  // namespace qp
+
+namespace qp {
+
+hipError_t launch_group_vec(int step, int j, int K, int total, const GroupEntry *E, const int *owner,
+                            hipStream_t s)
+{
+    if (total < 1 || step < 0 || step > 3) return hipErrorInvalidValue;
+    const dim3 grid(total), block(kBlock);
+#define QP_STEP(KK, ST)                                                                     \
+    case ST:                                                                                 \
+        hipLaunchKernelGGL((k_vec_grp<KK, ST>), grid, block, 0, s, j, E, owner);            \
+        break;
+#define QP_K(KK)                                                                            \
+    case KK:                                                                                 \
+        switch (step) { QP_STEP(KK, 0) QP_STEP(KK, 1) QP_STEP(KK, 2) QP_STEP(KK, 3) }      \
+        break;
+    switch (K) {
+        QP_K(2) QP_K(3)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef QP_K
+#undef QP_STEP
+    return hipGetLastError();
+}
+
+hipError_t launch_group_states(int G, int K, const GroupEntry *E, State *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_group_states, dim3(1), dim3(kBlock), 0, s, G, K, E, out);
     return hipGetLastError();
 }
 

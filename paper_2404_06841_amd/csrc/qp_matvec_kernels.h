@@ -559,6 +559,18 @@ __device__ __forceinline__ void put_output(size_t i, size_t ex, size_t ey, T acc
     }
 }
 
+// Partial sums of workgroup b of a plane-tile product (no execution log).
+template <int EPI>
+__device__ __forceinline__ void put_partials_at(double (&dots)[2], double *__restrict__ part, int b)
+{
+    if (EPI == EPI_ALPHA) {
+        double v[1] = {dots[0]};
+        store_partials_at<1>(v, part, b);
+    } else if (EPI == EPI_RESID) {
+        store_partials_at<2>(dots, part, b);
+    }
+}
+
 template <int EPI>
 __device__ __forceinline__ void put_partials(double (&dots)[2], double *__restrict__ part,
                                              State *__restrict__ st, int *__restrict__ exec)
@@ -584,18 +596,21 @@ __device__ __forceinline__ void wave_sync()
 // Work items of the plane kernel: (unit, up to tab->item_tiles consecutive
 // tiles); a wave copies the unit's records to its LDS once per item.
 
+// The product as workgroup vb of vnb (the whole grid of a plain launch, a
+// problem's range of a grouped one).
 template <typename T, int DT, int EPI, bool REAL, int KR, bool WIDE, bool AN>
-__global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict__ tab,
-                                                         const ModeRec *__restrict__ recs,
-                                                         const PlaneRec<T, DT, AN> *__restrict__ urec,
-                                                         const T *__restrict__ upku,
-                                                         const cplx_t<T> *__restrict__ x,
-                                                         void *__restrict__ yv,
-                                                         const double2 *__restrict__ f,
-                                                         const float *__restrict__ M32,
-                                                         double *__restrict__ part,
-                                                         State *__restrict__ st,
-                                                         int *__restrict__ exec)
+__device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
+                                             const Table *__restrict__ tab,
+                                             const ModeRec *__restrict__ recs,
+                                             const PlaneRec<T, DT, AN> *__restrict__ urec,
+                                             const T *__restrict__ upku,
+                                             const cplx_t<T> *__restrict__ x,
+                                             void *__restrict__ yv,
+                                             const double2 *__restrict__ f,
+                                             const float *__restrict__ M32,
+                                             double *__restrict__ part,
+                                             State *__restrict__ st,
+                                             int *__restrict__ exec)
 {
     // right-hand sides served by this launch (uniform)
     bool act[KR];
@@ -662,9 +677,9 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
     const int it = tab->item_tiles;
     const int ipu = (tpu + it - 1) / it;  // items per unit
     const int nitems = (tab->ntiles / tpu) * ipu;
-    const int nw = gridDim.x * kWaves;
-    const int b = blockIdx.x;
-    const bool by_xcd = tab->xcd_front && (gridDim.x % 8 == 0);
+    const int nw = vnb * kWaves;
+    const int b = vb;
+    const bool by_xcd = tab->xcd_front && (vnb % 8 == 0);
     const int xcd = by_xcd ? b % 8 : 0;
     const int nloc = by_xcd ? nw / 8 : nw;
     const int loc = (by_xcd ? b / 8 : b) * kWaves + wave;
@@ -837,9 +852,49 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
     }
 #pragma unroll
     for (int k = 0; k < KR; ++k)
-        if (act[k]) put_partials<EPI>(dots[k], part + k * kPartStride, st, nullptr);
-    if ((EPI == EPI_ALPHA || EPI == EPI_RESID) && exec && blockIdx.x == 0 && threadIdx.x == 0)
+        if (act[k]) put_partials_at<EPI>(dots[k], part + k * kPartStride, vb);
+    if ((EPI == EPI_ALPHA || EPI == EPI_RESID) && exec && vb == 0 && threadIdx.x == 0)
         *exec = nact;
+}
+
+template <typename T, int DT, int EPI, bool REAL, int KR, bool WIDE, bool AN>
+__global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict__ tab,
+                                                         const ModeRec *__restrict__ recs,
+                                                         const PlaneRec<T, DT, AN> *__restrict__ urec,
+                                                         const T *__restrict__ upku,
+                                                         const cplx_t<T> *__restrict__ x,
+                                                         void *__restrict__ yv,
+                                                         const double2 *__restrict__ f,
+                                                         const float *__restrict__ M32,
+                                                         double *__restrict__ part,
+                                                         State *__restrict__ st,
+                                                         int *__restrict__ exec)
+{
+    matvec_plane<T, DT, EPI, REAL, KR, WIDE, AN>((int)blockIdx.x, (int)gridDim.x, tab, recs, urec,
+                                                 upku, x, yv, f, M32, part, st, exec);
+}
+
+// Grouped FP32-IR product: the float product of h into q with the alpha
+// partials (EPI_ALPHA), or the replaced FP64 residual of X into the float r
+// (EPI_RESID), of every problem of the group in one launch.
+template <typename T, int DT, int EPI, bool REAL, int KR>
+__global__ __launch_bounds__(kBlock) void k_matvec_plane_grp(const GroupEntry *__restrict__ ents,
+                                                             const int *__restrict__ owner)
+{
+    static_assert((EPI == EPI_ALPHA && sizeof(T) == 4) || (EPI == EPI_RESID && sizeof(T) == 8),
+                  "grouped launches run the FP32-IR products");
+    const GroupEntry &e = ents[owner[blockIdx.x]];
+    using Rec = PlaneRec<T, DT, false>;
+    if constexpr (EPI == EPI_ALPHA)
+        matvec_plane<T, DT, EPI, REAL, KR, false, false>(
+            (int)blockIdx.x - e.mv0, e.nb_mv, e.tab, e.recs, static_cast<const Rec *>(e.urec32),
+            static_cast<const T *>(e.upku32), reinterpret_cast<const cplx_t<T> *>(e.h32), e.q32,
+            nullptr, e.M32, e.pa, e.st, nullptr);
+    else
+        matvec_plane<T, DT, EPI, REAL, KR, false, false>(
+            (int)blockIdx.x - e.mv0, e.nb_mv, e.tab, e.recs, static_cast<const Rec *>(e.urec64),
+            static_cast<const T *>(e.upku64), reinterpret_cast<const cplx_t<T> *>(e.X), e.r32,
+            reinterpret_cast<const double2 *>(e.F), e.M32, e.pb, e.st, nullptr);
 }
 
 template <typename T, int EPI, bool REAL, int KR, bool WIDE, bool AN>
