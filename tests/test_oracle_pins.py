@@ -331,3 +331,38 @@ def test_corrector_rhs_is_derivative_of_coefficient():
             fd = (a(x + e) - a(x - e)) / (2 * h)
             series = np.sum(F * np.exp(1j * PK @ x))
             assert abs(series - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def _conjugation_gap(prob, v) -> float:
+    """max_k |v[C(rep(-k))] - conj(v[C(k)])| / max|v| over the grid."""
+    n, N = prob.n, prob.N
+    worst = 0.0
+    for i in range(N ** n):
+        k = oracle.multi_index(n, N, i)
+        j = oracle.index(n, N, tuple(oracle.rep(N, -x) for x in k))
+        worst = max(worst, abs(v[j] - np.conj(v[i])))
+    return worst / np.abs(v).max()
+
+
+@pytest.mark.parametrize("make", [lambda N: W.eightfold(N), lambda N: W.eightfold_random(N, 1)],
+                         ids=["eightfold", "eightfold_random"])
+def test_corrector_conjugation_symmetry_needs_odd_N(make):
+    """A real coefficient gives a source with F_{-k} = conj(F_k) (Sec. 5.2:
+    F_k = i (Pk)_j Ahat_k).  At odd N the grid K_N is symmetric, so the
+    discrete operator commutes with k -> -k plus conjugation and the
+    corrector inherits the symmetry (half of the unknowns would determine the
+    rest).  At even N the face k_t = -N/2 has no partner +N/2 in K_N; its
+    weights (P k).(P j) use the signed representatives, so the symmetry
+    breaks and the discrete corrector is not conjugation-symmetric: storing
+    half of the unknowns would change the discrete solution."""
+    for N, expect_sym in ((7, True), (6, False)):
+        prob = make(N)
+        F = oracle.corrector_rhs(prob, 0)
+        assert _conjugation_gap(prob, F) == 0.0
+        chi = oracle.pcg(prob, F, tol=1e-13)
+        chi = chi[0] if isinstance(chi, tuple) else chi
+        gap = _conjugation_gap(prob, chi)
+        if expect_sym:
+            assert gap <= 1e-12, (N, gap)
+        else:
+            assert gap >= 1e-3, (N, gap)
