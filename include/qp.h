@@ -203,7 +203,9 @@ void qp_destroy(qp_problem *p);
 int64_t qp_dim(const qp_problem *p);
 
 /* Replace the solver options (precision, preconditioner, limits, profile).
- * The stream and workspace of a created problem cannot change. */
+ * The stream and workspace of a created problem cannot change.  A change of
+ * precision waits for the problem's stream and re-derives the grid of the
+ * vector kernels (chosen per precision). */
 qp_status qp_set_options(qp_problem *p, const qp_options *opt);
 
 /* The stiffness product's work layout of p (host-only; no device call).

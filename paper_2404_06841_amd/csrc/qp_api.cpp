@@ -237,6 +237,25 @@ qp_status check_args(int d, int n, const double *P, int g, const int32_t *modes,
 }
 
 // coefs: null for a scalar coefficient, else d x g complex (a_l's Ahat per mode)
+// Grid of the streaming kernels: workgroups of `chunk` consecutive entries
+// (a multiple of kBlock).  Every vector kernel reduces all partial sums of
+// the previous launch in each workgroup, so the partial traffic grows with
+// the square of the workgroup count: at 1,048,576 unknowns 1024 workgroups
+// read 48 MB of partials per iteration beside 136 MB of float vectors.  The
+// cap per precision was measured there (two right-hand sides): FP32-IR best
+// at 512 workgroups (2048 entries each), FP64 at 683 (1536 entries each).
+void stream_grid(Table &T, int precision)
+{
+    const int64_t D = T.D;
+    const int cap = std::min(qp::kStreamBlocks, precision == QP_PREC_FP32_IR ? 512 : 820);
+    int nb = (int)std::min<int64_t>(cap, (D + qp::kBlock - 1) / qp::kBlock);
+    if (nb >= 64) nb -= nb % 8;
+    int64_t chunk = (D + nb - 1) / nb;
+    chunk = (chunk + qp::kBlock - 1) / qp::kBlock * qp::kBlock;
+    T.chunk = (int)chunk;
+    T.nblocks = (int)((D + chunk - 1) / chunk);
+}
+
 void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *modes,
                  const double *coef, const double *coefs, int N)
 {
@@ -357,12 +376,7 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
     int nbm = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, want));
     if (nbm >= 8) nbm -= nbm % 8;
     T.nb_mv = nbm;
-    int nb = (int)std::min<int64_t>(qp::kStreamBlocks, (D + qp::kBlock - 1) / qp::kBlock);
-    if (nb >= 64) nb -= nb % 8;
-    int64_t chunk = (D + nb - 1) / nb;
-    chunk = (chunk + qp::kBlock - 1) / qp::kBlock * qp::kBlock;
-    T.chunk = (int)chunk;
-    T.nblocks = (int)((D + chunk - 1) / chunk);
+    stream_grid(T, QP_PREC_FP64);
 }
 
 
@@ -1364,6 +1378,7 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     if (!p) return fail(QP_ENOMEM, "host allocation failed");
     p->opt = o;
     build_table(p->host, d, n, P, g, modes, coef, coefs, N);
+    stream_grid(p->host, o.precision);
     // record indices of the default gathers are scaled by the record size in
     // 32 bits; the largest records are the interleaved float families of d
     // right-hand sides (d * 8 bytes) and FP64 entries (16 bytes): vectors
@@ -1503,11 +1518,20 @@ qp_status qp_set_options(qp_problem *p, const qp_options *opt)
 {
     if (!p || !opt) return fail(QP_EINVAL, "null argument");
     QP_TRY(check_options(opt));
-    const int old_precond = p->opt.precond;
+    const int old_precond = p->opt.precond, old_precision = p->opt.precision;
     void *stream = p->opt.stream;
     p->opt = *opt;
     p->opt.stream = stream;
     p->opt.workspace = nullptr;
+    if (opt->precision != old_precision) {
+        // the streaming grid follows the precision; captured batches hold the old one
+        QP_HIP(hipStreamSynchronize(p->stream));
+        for (auto &G : p->graphs) (void)hipGraphExecDestroy(G.exec);
+        p->graphs.clear();
+        stream_grid(p->host, opt->precision);
+        QP_HIP(hipMemcpyAsync(p->tab, &p->host, sizeof(Table), hipMemcpyHostToDevice, p->stream));
+        QP_HIP(hipStreamSynchronize(p->stream));
+    }
     if (opt->precond != old_precond) return compute_setup(p);
     return QP_OK;
 }

@@ -17,7 +17,10 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 #define QP_MAX_BLOCKS 1024
 #endif
 constexpr int kMaxBlocks = QP_MAX_BLOCKS;  // grid cap (partial sums per reduction)
-constexpr int kStreamBlocks = 1024;        // grid cap of the streaming kernels: 4 per CU
+#ifndef QP_STREAM_BLOCKS
+#define QP_STREAM_BLOCKS 1024
+#endif
+constexpr int kStreamBlocks = QP_STREAM_BLOCKS;  // upper cap of the streaming kernels' grid
 
 // Problem constants, resident in device memory and read with uniform
 // (scalar) loads by every kernel.
