@@ -745,7 +745,10 @@ struct SolveJob {
 
     bool done() const { return phase == kDone; }
 
-    qp_status begin(qp_problem *p_, int K_, const double *rhs_, double *U_, double tol_)
+    // norms_ready (FP32-IR): the ||f'||^2 partials of the K right-hand sides
+    // are already in parts.c (the corrector sources stored them).
+    qp_status begin(qp_problem *p_, int K_, const double *rhs_, double *U_, double tol_,
+                    bool norms_ready = false)
     {
         p = p_;
         K = K_;
@@ -772,7 +775,10 @@ struct SolveJob {
         const qp::Parts parts = p->parts();
         QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
         if (ir) {
-            QP_HIP(qp::launch_ir_unit(K, p->tab, p->host, rhs, parts, p->st(), p->stream));
+            if (norms_ready)
+                QP_HIP(qp::launch_ir_unit_only(K, p->host, parts, p->st(), p->stream));
+            else
+                QP_HIP(qp::launch_ir_unit(K, p->tab, p->host, rhs, parts, p->st(), p->stream));
             QP_HIP(qp::launch_pcg_init(qp::F32, K, p->tab, p->host, rhs, U, p->x32(), p->r32(),
                                        p->h32(), p->M32(), parts, p->st(), p->stream));
             QP_HIP(qp::launch_pcg_start(qp::F32, K, p->host, tol, p->opt.inner_tol, p->opt.maxit,
@@ -1034,22 +1040,25 @@ struct HomJob {
         if (!(tol > 0.0) || !std::isfinite(tol))
             return fail(QP_EINVAL, "tol must be positive and finite");
         const int d = p->host.d;
-        for (int j = 0; j < d; ++j)
-            QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, p->F() + (size_t)2 * p->host.D * j,
-                                            p->stream));
         G = rhs_per_launch(p);
+        // all d sources in one pass; when one solve serves them all, that pass
+        // also stores the norms the FP32-IR start needs
+        const bool one = G >= d && p->opt.precision == QP_PREC_FP32_IR;
+        const qp::Parts parts = p->parts();
+        QP_HIP(qp::launch_corrector_rhs_all(p->tab, p->host, d, p->F(), one ? &parts : nullptr,
+                                            p->stream));
         r0 = 0;
         worst = QP_OK;
-        QP_TRY(start_group());
+        QP_TRY(start_group(one));
         phase = kSolve;
         return QP_OK;
     }
 
-    qp_status start_group()
+    qp_status start_group(bool norms_ready = false)
     {
         const size_t D2 = 2 * (size_t)p->host.D;
         const int Kg = std::min(G, p->host.d - r0);
-        return sj.begin(p, Kg, p->F() + r0 * D2, p->chi(0) + r0 * D2, tol);
+        return sj.begin(p, Kg, p->F() + r0 * D2, p->chi(0) + r0 * D2, tol, norms_ready);
     }
 
     qp_status advance(bool blocking, bool &progressed)
@@ -1782,10 +1791,9 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
     for (int i = 0; i < G; ++i) {
         qp_problem *p = problems[i];
         const qp::Parts parts = p->parts();
-        for (int j = 0; j < d; ++j)
-            QP_HIP(qp::launch_corrector_rhs(p->tab, p->host, j, p->F() + (size_t)2 * p->host.D * j, s));
+        QP_HIP(qp::launch_corrector_rhs_all(p->tab, p->host, d, p->F(), &parts, s));
         QP_HIP(qp::launch_state_reset(K, p->st(), s));
-        QP_HIP(qp::launch_ir_unit(K, p->tab, p->host, p->F(), parts, p->st(), s));
+        QP_HIP(qp::launch_ir_unit_only(K, p->host, parts, p->st(), s));
         QP_HIP(qp::launch_pcg_init(qp::F32, K, p->tab, p->host, p->F(), p->chi(0), p->x32(),
                                    p->r32(), p->h32(), p->M32(), parts, p->st(), s));
         QP_HIP(qp::launch_pcg_start(qp::F32, K, p->host, tol, p->opt.inner_tol, p->opt.maxit, parts,

@@ -251,6 +251,14 @@ hipError_t launch_extrema(const Table *tab, const Table &ht, const Parts &parts,
 // F_k = i (P k)_j Ahat_k.
 hipError_t launch_corrector_rhs(const Table *tab, const Table &ht, int j, double *F,
                                 hipStream_t s);
+// The sources of correctors 0 .. K-1 (F + j D); with parts, also the partial
+// sums of ||f'_j||^2 in parts->c (as launch_ir_unit's first launch stores
+// them).
+hipError_t launch_corrector_rhs_all(const Table *tab, const Table &ht, int K, double *F,
+                                    const Parts *parts, hipStream_t s);
+// FP32-IR unit from the ||f'||^2 partials already in parts.c (one launch).
+hipError_t launch_ir_unit_only(int K, const Table &ht, const Parts &parts, State *st,
+                               hipStream_t s);
 // A* flux form from d correctors (d*D complex): out[0..d*d) real, out[d*d..) imag.
 hipError_t launch_astar(const Table *tab, const Table &ht, const double *chi, double *out,
                         hipStream_t s);

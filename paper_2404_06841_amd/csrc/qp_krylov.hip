@@ -954,6 +954,14 @@ hipError_t launch_ir_unit(int K, const Table *tab, const Table &ht, const double
     return hipGetLastError();
 }
 
+hipError_t launch_ir_unit_only(int K, const Table &ht, const Parts &parts, State *st,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ir_unit, dim3(1), dim3(kBlock), 0, s, K, (const double *)parts.c,
+                       ht.nblocks, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_ir_fold(int K, const Table *tab, const Table &ht, double *X, float *x, State *st,
                           hipStream_t s)
 {

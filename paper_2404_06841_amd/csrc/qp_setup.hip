@@ -156,6 +156,49 @@ __global__ __launch_bounds__(kBlock) void k_corrector_rhs(const Table *__restric
     }
 }
 
+// The sources of correctors 0 .. K-1 in one pass (F + j D), and, when part
+// is given, the partial sums of ||f'_j||^2 (zero frequency excluded) for the
+// FP32-IR unit, as the separate norm pass would store them.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_corrector_rhs_all(const Table *__restrict__ tab,
+                                                              double2 *__restrict__ F,
+                                                              double *__restrict__ part)
+{
+    const int g = tab->g;
+    const size_t D = tab->D;
+    int begin, end;
+    chunk_of_block(tab, begin, end);
+    double acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = 0.0;
+    for (int i = begin + threadIdx.x; i < end; i += kBlock) {
+        double2 v[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) v[j] = make_double2(0.0, 0.0);
+        for (int r = 0; r < g; ++r) {
+            if (tab->midx[r] == i) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const double s = tab->Pm[r][j];
+                    v[j].x += -s * tab->coefl[r][j][1];
+                    v[j].y += s * tab->coefl[r][j][0];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            F[(size_t)j * D + i] = v[j];
+            if (i != 0) acc[j] += v[j].x * v[j].x + v[j].y * v[j].y;
+        }
+    }
+    if (!part) return;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double a[1] = {acc[j]};
+        store_partials<1>(a, part + j * kPartStride);
+    }
+}
+
 // A*_ij = Ahat_0 delta_ij + mean_N{ a d_i chi_j }
 //       = Ahat_0 delta_ij + sum_m Ahat_m i (P(-m))_i chi_j[C(-m)]
 // (the discrete mean keeps the frequency pairs whose sum is 0 mod N).  For a
@@ -240,6 +283,25 @@ hipError_t launch_corrector_rhs(const Table *tab, const Table &ht, int j, double
 {
     hipLaunchKernelGGL(k_corrector_rhs, dim3(ht.nblocks), dim3(kBlock), 0, s, tab, j,
                        reinterpret_cast<double2 *>(F));
+    return hipGetLastError();
+}
+
+hipError_t launch_corrector_rhs_all(const Table *tab, const Table &ht, int K, double *F,
+                                    const Parts *parts, hipStream_t s)
+{
+    double2 *f = reinterpret_cast<double2 *>(F);
+    double *c = parts ? parts->c : nullptr;
+    switch (K) {
+#define QP_K(KK)                                                                                \
+    case KK:                                                                                     \
+        hipLaunchKernelGGL(k_corrector_rhs_all<KK>, dim3(ht.nblocks), dim3(kBlock), 0, s, tab, f, \
+                           c);                                                                   \
+        break;
+        QP_K(1) QP_K(2) QP_K(3) QP_K(4)
+#undef QP_K
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
