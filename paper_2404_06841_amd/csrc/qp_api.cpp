@@ -1237,6 +1237,8 @@ size_t qp_workspace_bytes(int d, int n, int N, int g)
 // layout on its own product (the launch the solve repeats: its precision,
 // all the right-hand sides one launch serves) and keeps the fastest; later
 // problems of the same shape in the process reuse that choice.
+}  // extern "C"
+
 namespace {
 
 struct LayoutPick {
@@ -1360,6 +1362,7 @@ qp_status tune_layout(qp_problem *p)
 }
 
 }  // namespace
+extern "C" {
 
 static qp_status create_problem(qp_problem **out, int d, int n, const double *P, int g,
                                 const int32_t *modes, const double *coef, const double *coefs,
@@ -1666,6 +1669,8 @@ qp_status qp_homogenized_batch(qp_problem *const *problems, int count, double *A
 // second iteration (a paused right-hand side waits at most one iteration;
 // with nothing paused they exit at once), the host polls every poll_every
 // iterations.
+}  // extern "C"
+
 namespace {
 
 std::mutex g_group_mu;  // the group buffers below serve one call at a time
@@ -1720,6 +1725,7 @@ const char *group_mismatch(const qp_problem *p, const qp_problem *p0)
 }
 
 }  // namespace
+extern "C" {
 
 qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double *Astar, double tol,
                                  qp_solve_info *infos)
@@ -2180,6 +2186,8 @@ qp_status qp_server_submit(qp_server *s, int d, int n, const double *P, int g,
     return QP_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Admit queued requests in arrival order.  A request whose problem would
@@ -2258,6 +2266,7 @@ qp_status server_admit(qp_server *s)
 }
 
 }  // namespace
+extern "C" {
 
 qp_status qp_server_progress(qp_server *s, int wait_us, int64_t *done, qp_status *done_status,
                              int max_done, int *ndone)

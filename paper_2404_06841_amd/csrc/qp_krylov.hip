@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_unit(int K, const double *__restr
 // Pause every unfinished right-hand side (the forced final replacement).
 __global__ void k_ir_force(int K, State *sts)
 {
-    if (blockIdx.x == 0 && threadIdx.x < K && !sts[threadIdx.x].done) sts[threadIdx.x].pause = 1;
+    if (blockIdx.x == 0 && (int)threadIdx.x < K && !sts[threadIdx.x].done) sts[threadIdx.x].pause = 1;
 }
 
 __global__ void k_state_reset(int K, State *sts)

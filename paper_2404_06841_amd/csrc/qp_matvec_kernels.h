@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
             }
         }
         // ---- unit records (thread r prepares sorted mode r) ----
-        if (threadIdx.x < gp) {
+        if ((int)threadIdx.x < gp) {
             const int r = threadIdx.x;
             const int rs = (r < g) ? r : zs;  // padding: the zero mode with weight 0
             const SRec<T, DT> &M = s_mode[rs];
