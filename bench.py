@@ -112,11 +112,12 @@ def hbm_products(torch, qp, W):
     right-hand side per launch, timed with HIP events on the library's stream
     (torch's current stream).  Algorithmic bytes: read x once, write y once."""
     prob = W.icosahedral(16)
-    gp = qp.Problem(prob)
+    gp = qp.Problem(prob, autotune=True)
     D = prob.D
     gen = torch.Generator(device="cuda")
     gen.manual_seed(16)
-    out = {"workload": "icosahedral d=3 n=6 N=16 (16,777,216 unknowns, 13 modes)"}
+    out = {"workload": "icosahedral d=3 n=6 N=16 (16,777,216 unknowns, 13 modes)",
+           "layout": gp.layout()}
     for name, dtype, fn, per in (("fp64", torch.complex128, gp.matvec_d, 32.0),
                                  ("fp32", torch.complex64, gp.matvec32_d, 16.0)):
         u = torch.randn(D, dtype=dtype, device="cuda", generator=gen)

@@ -137,7 +137,10 @@ typedef struct qp_layout {
     int item_tiles;     /* plane tiles per wave work item (line tiles: 1)      */
     int workgroups;     /* grid of the product launches                        */
     int xcd_front;      /* 1: each of the 8 XCDs sweeps a contiguous share of
-                           the work items; 0: items in plain order             */
+                           the work items; 2: the same, with the slowest axis
+                           varying fastest inside each share (when the shares
+                           are whole values of it, n >= 3; else as 1);
+                           0: items in plain order                             */
     int tuned;          /* 0: fixed heuristics; 1: timed on this problem;
                            2: reused from an earlier problem of the same shape */
     int candidates;     /* layouts timed (tuned == 1)                          */
@@ -218,7 +221,7 @@ qp_status qp_product_layout(const qp_problem *p, qp_layout *out);
  * and with them the iterates, repeat bitwise.  Waits for the problem's stream
  * and drops its captured batches.  QP_EINVAL unless item_tiles is 1, 2 or 4
  * (1 for line tiles, N > 32 or n = 1), 1 <= workgroups <= 1024 and xcd_front
- * is 0 or 1. */
+ * is 0, 1 or 2. */
 qp_status qp_set_product_layout(qp_problem *p, const qp_layout *layout);
 
 /*

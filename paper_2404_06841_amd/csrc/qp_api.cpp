@@ -368,6 +368,19 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
         while (T.item_tiles < 4 && T.ntiles / (2 * T.item_tiles) >= QP_ITEM_TARGET)
             T.item_tiles *= 2;
     T.xcd_front = QP_XCD_FRONT;
+    // slab order (xcd_front 2): each eighth of the units must be whole values
+    // of the slowest uniform axis (n >= 3)
+    T.slab_units = T.slab_stride = T.slab_span = 0;
+    if (T.tile_s > 1 && n >= 3) {
+        const int64_t units_all = T.ntiles / T.tiles_per_unit;
+        int64_t S1 = 1;
+        for (int t = 1; t < n - 2; ++t) S1 *= N;
+        if (units_all % 8 == 0 && (units_all / 8) % S1 == 0 && units_all / 8 / S1 >= 2) {
+            T.slab_units = (int)(units_all / 8);
+            T.slab_stride = (int)S1;
+            T.slab_span = (int)(units_all / 8 / S1);
+        }
+    }
     const int64_t units = T.ntiles / T.tiles_per_unit;
     const int64_t items = T.tile_s > 1
                               ? units * ((T.tiles_per_unit + T.item_tiles - 1) / T.item_tiles)
@@ -1268,7 +1281,8 @@ std::vector<LayoutPick> layout_candidates(const Table &T)
         const int64_t items = units * ((tpu + it - 1) / it);
         for (int per : {1, 2, 4}) {
             const int nb = grid_for((items + 4 * per - 1) / (4 * per));
-            for (int xcd : {1, 0}) {
+            for (int xcd : {1, 0, 2}) {
+                if (xcd == 2 && T.slab_span == 0) continue;
                 const LayoutPick L{it, nb, xcd};
                 if (std::find(c.begin(), c.end(), L) == c.end()) c.push_back(L);
             }
@@ -1494,7 +1508,7 @@ qp_status qp_set_product_layout(qp_problem *p, const qp_layout *layout)
         return fail(QP_EINVAL, "workgroups = %d outside [1, %d]", L.workgroups, qp::kMaxBlocks);
     if (plane ? (L.item_tiles != 1 && L.item_tiles != 2 && L.item_tiles != 4) : L.item_tiles != 1)
         return fail(QP_EINVAL, "item_tiles = %d is not 1, 2 or 4 (1 for line tiles)", L.item_tiles);
-    if (L.xcd_front != 0 && L.xcd_front != 1) return fail(QP_EINVAL, "xcd_front must be 0 or 1");
+    if (L.xcd_front < 0 || L.xcd_front > 2) return fail(QP_EINVAL, "xcd_front must be 0, 1 or 2");
     // launches queued earlier read the table; captured batches hold the old grid
     QP_HIP(hipStreamSynchronize(p->stream));
     for (auto &G : p->graphs) (void)hipGraphExecDestroy(G.exec);

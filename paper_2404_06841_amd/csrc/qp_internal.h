@@ -57,6 +57,10 @@ struct Table {
     int nb_mv;                // grid of the stiffness product (multiple of 8 when >= 8)
     int item_tiles;           // plane tiles: consecutive tiles of a unit per wave item
     int xcd_front;            // plane tiles: each XCD sweeps its own contiguous eighth
+                              // (2: with the slowest axis innermost, slab_span > 0)
+    int slab_units;           // units (planes) per eighth, when they divide evenly
+    int slab_stride;          // units per value of the slowest axis (N^(n-3))
+    int slab_span;            // values of the slowest axis per eighth (0: no slab order)
     int wide;                 // plane tiles: 64-bit neighbour addresses, one right-hand
                               // side per launch (else 32-bit record indices)
     uint64_t slotmask[64];    // tile_s > 1: per tile of a plane, bit r when sorted mode

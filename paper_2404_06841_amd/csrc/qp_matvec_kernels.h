@@ -691,9 +691,19 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
 #pragma unroll
     for (int k = 0; k < KR; ++k) dots[k][0] = dots[k][1] = 0.0;
 
+    // xcd_front 2: inside each XCD's eighth of the units (a slab of span
+    // consecutive values of the slowest axis), that axis varies fastest, so a
+    // unit's neighbours along it are swept next to it (see Table)
+    const int span = (by_xcd && tab->xcd_front == 2) ? tab->slab_span : 0;
     for (int item = ibeg + loc; item < iend; item += nloc) {
-        const int unit = item / ipu;
+        int unit = item / ipu;
         const int tl0 = (item - unit * ipu) * it;
+        if (span > 0) {
+            const int E = tab->slab_units, S1 = tab->slab_stride;
+            const int e = unit / E, ul = unit - e * E;
+            const int rest = ul / span;
+            unit = e * E + (ul - rest * span) * S1 + rest;
+        }
         // ---- the unit's records to this wave's LDS ----
         {
             const uint4 *src = reinterpret_cast<const uint4 *>(urec + (size_t)unit * gp);

@@ -32,6 +32,9 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # wave, grids that are and are not multiples of 8
 LAYOUTS = [(it, nb, x) for it in (1, 2, 4) for nb in (8, 24, 256, 1024) for x in (0, 1)]
 LAYOUTS += [(1, 1, 0), (4, 3, 1), (2, 1000, 1)]
+# slab order (xcd_front 2): the slowest axis innermost inside each XCD's eighth
+# (identity where the eighths are not whole slabs, as for N = 6 here)
+LAYOUTS += [(4, 1024, 2), (1, 256, 2), (2, 24, 2), (1, 1, 2)]
 
 
 def say(*a):
@@ -68,12 +71,28 @@ def test_every_layout_gives_bitwise_equal_products(make):
     a.close()
 
 
+def test_slab_order_at_the_large_icosahedral_shape():
+    # 16,777,216 unknowns: each XCD's eighth is two values of the slowest axis
+    prob = W.icosahedral(16)
+    a = qp.Problem(prob)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    u = torch.randn(prob.D, dtype=torch.complex128, device="cuda", generator=gen)
+    u32 = u.to(torch.complex64)
+    y64, y32 = a.matvec_d(u), a.matvec32_d(u32)
+    for L in [(2, 1024, 2), (4, 1024, 2), (1, 512, 2)]:
+        a.set_layout(*L)
+        assert torch.equal(a.matvec_d(u), y64), L
+        assert torch.equal(a.matvec32_d(u32), y32), L
+    a.close()
+
+
 def test_solves_under_other_layouts_meet_the_oracle():
     gold = json.load(open(os.path.join(GOLDEN, "oracle_astar.json")))["c2_eightfold_N16"]
     A_ref = np.array(gold["A"])
     prob = W.eightfold(16)
     a = qp.Problem(prob)
-    for L in [(1, 24, 0), (4, 1024, 1), (2, 8, 1)]:
+    for L in [(1, 24, 0), (4, 1024, 1), (2, 8, 1), (4, 1024, 2), (1, 256, 2)]:
         a.set_layout(*L)
         for prec in ("fp64", "fp32ir"):
             a.set_precision(prec)
@@ -115,7 +134,7 @@ def test_autotune_chooses_a_layout_and_reuses_it_for_the_shape():
 
 def test_invalid_layouts_are_rejected():
     a = qp.Problem(W.eightfold(8))
-    for L in [(3, 8, 0), (1, 0, 0), (1, 1025, 0), (1, 8, 2)]:
+    for L in [(3, 8, 0), (1, 0, 0), (1, 1025, 0), (1, 8, 3)]:
         with pytest.raises(qp.QPError) as e:
             a.set_layout(*L)
         assert e.value.status == qp.QP_EINVAL
