@@ -132,10 +132,12 @@ typedef struct qp_solve_info {
     int matvec32_rhs;     /* the same for the float launches                     */
 } qp_solve_info;
 
-/* Work layout of the stiffness product (see qp_options.autotune). */
+/* Work layout of the stiffness product (see qp_options.autotune): one for
+ * the float launches and one for the FP64 launches. */
 typedef struct qp_layout {
-    int item_tiles;     /* plane tiles per wave work item (line tiles: 1)      */
-    int workgroups;     /* grid of the product launches                        */
+    int item_tiles;     /* float launches: plane tiles per wave work item
+                           (line tiles: 1)                                     */
+    int workgroups;     /* float launches: grid of the product                 */
     int xcd_front;      /* 1: each of the 8 XCDs sweeps a contiguous share of
                            the work items; 2: the same, with the slowest axis
                            varying fastest inside each share (when the shares
@@ -144,8 +146,14 @@ typedef struct qp_layout {
     int tuned;          /* 0: fixed heuristics; 1: timed on this problem;
                            2: reused from an earlier problem of the same shape */
     int candidates;     /* layouts timed (tuned == 1)                          */
-    double default_us;  /* mean launch of the heuristic layout (tuned == 1)    */
-    double best_us;     /* mean launch of the chosen layout (tuned == 1)       */
+    double default_us;  /* float product (FP32-IR problems): mean launch of the
+                           heuristic layout (tuned == 1)                       */
+    double best_us;     /* ... and of the chosen layout                        */
+    int item_tiles64;   /* the same three for the FP64 launches (FP64 solves,  */
+    int workgroups64;   /* the residual replacements of FP32-IR, qp_matvec_d); */
+    int xcd_front64;    /* workgroups64 = 0 in qp_set_product_layout: as float */
+    double default64_us;/* FP64 product (the residual product for FP32-IR):    */
+    double best64_us;   /* mean launch of the heuristic and the chosen layout  */
 } qp_layout;
 
 /* Fill *opt with the defaults listed above. */
@@ -215,8 +223,10 @@ qp_status qp_set_options(qp_problem *p, const qp_options *opt);
  * QP_EINVAL for null arguments. */
 qp_status qp_product_layout(const qp_problem *p, qp_layout *out);
 
-/* Set the stiffness product's work layout (item_tiles, workgroups and
- * xcd_front of *layout; the other fields are ignored), e.g. one that
+/* Set the stiffness product's work layouts (item_tiles, workgroups and
+ * xcd_front of *layout for the float launches; item_tiles64, workgroups64
+ * and xcd_front64 for the FP64 launches, or the float ones when workgroups64
+ * is 0; the other fields are ignored), e.g. ones that
  * qp_product_layout reported in an earlier process, so that the partial sums,
  * and with them the iterates, repeat bitwise.  Waits for the problem's stream
  * and drops its captured batches.  QP_EINVAL unless item_tiles is 1, 2 or 4

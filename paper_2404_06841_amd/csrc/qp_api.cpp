@@ -389,6 +389,9 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
     int nbm = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, want));
     if (nbm >= 8) nbm -= nbm % 8;
     T.nb_mv = nbm;
+    T.item_tiles64 = T.item_tiles;
+    T.nb_mv64 = T.nb_mv;
+    T.xcd_front64 = T.xcd_front;
     stream_grid(T, QP_PREC_FP64);
 }
 
@@ -1260,7 +1263,7 @@ struct LayoutPick {
 };
 
 std::mutex g_layout_mu;
-std::map<std::vector<int>, LayoutPick> g_layouts;
+std::map<std::vector<int>, std::pair<LayoutPick, LayoutPick>> g_layouts;  // float, FP64
 
 int grid_for(int64_t want)
 {
@@ -1291,29 +1294,46 @@ std::vector<LayoutPick> layout_candidates(const Table &T)
     return c;
 }
 
-qp_status apply_layout(qp_problem *p, const LayoutPick &L)
+// The layout of the float (prec F32) or the FP64 launches.
+qp_status apply_layout(qp_problem *p, const LayoutPick &L, int prec)
 {
-    p->host.item_tiles = L.it;
-    p->host.nb_mv = L.nb;
-    p->host.xcd_front = L.xcd;
+    if (prec == qp::F32) {
+        p->host.item_tiles = L.it;
+        p->host.nb_mv = L.nb;
+        p->host.xcd_front = L.xcd;
+    } else {
+        p->host.item_tiles64 = L.it;
+        p->host.nb_mv64 = L.nb;
+        p->host.xcd_front64 = L.xcd;
+    }
     QP_HIP(hipMemcpyAsync(p->tab, &p->host, sizeof(Table), hipMemcpyHostToDevice, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
     return QP_OK;
 }
 
-// Mean duration of `reps` products (after one untimed), microseconds.
-qp_status time_product(qp_problem *p, int reps, double &us)
+// Mean duration of `reps` products (after one untimed), microseconds, as a
+// solve launches them: the product of precision prec with its alpha
+// partials, or (resid, FP64) the residual replacement of FP32-IR.  The
+// states are set so that every launch does its work.
+qp_status time_product(qp_problem *p, int prec, bool resid, int reps, double &us)
 {
-    const bool f32 = p->opt.precision == QP_PREC_FP32_IR;
-    const int prec = f32 ? qp::F32 : qp::F64;
+    const bool f32 = prec == qp::F32;
     const int K = rhs_per_launch(p);
+    QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
+    if (resid) {
+        // paused, then marked for replacement by the fold (x is zero: X stays)
+        QP_HIP(qp::launch_ir_force(K, p->st(), p->stream));
+        QP_HIP(qp::launch_ir_fold(K, p->tab, p->host, p->h(), p->x32(), p->st(), p->stream));
+    }
+    const int epi = resid ? qp::EPI_RESID : qp::EPI_ALPHA;
     const void *x = f32 ? (const void *)p->h32() : (const void *)p->h();
-    void *y = f32 ? (void *)p->q32() : (void *)p->q();
+    void *y = resid ? (void *)p->r32() : (f32 ? (void *)p->q32() : (void *)p->q());
+    const double *f = resid ? p->F() : nullptr;
     for (int r = 0; r <= reps; ++r) {
         if (r == 1) QP_HIP(hipEventRecord(p->ev_t0, p->stream));
-        QP_HIP(qp::launch_matvec(prec, qp::EPI_ALPHA, K, p->tab, p->host, p->recs(), p->urec(prec),
-                                 p->upku(prec), x, y, nullptr, p->M32(), p->parts(), p->st(),
-                                 nullptr, p->stream));
+        QP_HIP(qp::launch_matvec(prec, epi, K, p->tab, p->host, p->recs(), p->urec(prec),
+                                 p->upku(prec), x, y, f, p->M32(), p->parts(), p->st(), nullptr,
+                                 p->stream));
     }
     QP_HIP(hipEventRecord(p->ev_t1, p->stream));
     QP_HIP(hipEventSynchronize(p->ev_t1));
@@ -1323,11 +1343,60 @@ qp_status time_product(qp_problem *p, int reps, double &us)
     return QP_OK;
 }
 
+// One layout search: each candidate timed on the launch kind given
+// (time_product's prec and resid), the heuristic layout kept unless a
+// candidate is at least 3% faster.
+qp_status search_layout(qp_problem *p, int prec, bool resid, LayoutPick &best, double &dflt_us,
+                        double &best_us, int &ncand)
+{
+    const Table &T = p->host;
+    const LayoutPick dflt = (prec == qp::F32) ? LayoutPick{T.item_tiles, T.nb_mv, T.xcd_front}
+                                              : LayoutPick{T.item_tiles64, T.nb_mv64, T.xcd_front64};
+    double est = 0.0;
+    QP_TRY(time_product(p, prec, resid, 3, est));
+    // about 2 ms of launches per candidate
+    const int reps = (int)std::min(50.0, std::max(3.0, std::ceil(2000.0 / std::max(est, 1.0))));
+    const std::vector<LayoutPick> cands = layout_candidates(T);
+    best = dflt;
+    QP_TRY(time_product(p, prec, resid, reps, dflt_us));
+    best_us = dflt_us;
+    for (const LayoutPick &L : cands) {
+        if (L == dflt) continue;
+        QP_TRY(apply_layout(p, L, prec));
+        double us = 0.0;
+        QP_TRY(time_product(p, prec, resid, reps, us));
+        // a layout replaces the heuristic one only when clearly faster
+        if (us < 0.97 * best_us) {
+            best = L;
+            best_us = us;
+        }
+    }
+    QP_TRY(apply_layout(p, best, prec));
+    ncand = (int)cands.size();
+    return QP_OK;
+}
+
+void report_layout(qp_problem *p, int tuned)
+{
+    const Table &T = p->host;
+    qp_layout &L = p->layout;
+    L.item_tiles = T.item_tiles;
+    L.workgroups = T.nb_mv;
+    L.xcd_front = T.xcd_front;
+    L.item_tiles64 = T.item_tiles64;
+    L.workgroups64 = T.nb_mv64;
+    L.xcd_front64 = T.xcd_front64;
+    L.tuned = tuned;
+}
+
+// FP32-IR problems tune the float product (the iterations) and, apart, the
+// FP64 residual product of the replacements; FP64 problems tune their FP64
+// product and keep the heuristic float layout.
 qp_status tune_layout(qp_problem *p)
 {
     const Table &T = p->host;
-    const LayoutPick dflt{T.item_tiles, T.nb_mv, T.xcd_front};
-    p->layout = qp_layout{T.item_tiles, T.nb_mv, T.xcd_front, 0, 0, 0.0, 0.0};
+    p->layout = qp_layout{};
+    report_layout(p, 0);
     if (T.tile_s <= 1) return QP_OK;  // line tiles: one layout
     const std::vector<int> key = {T.d,         T.n,    T.N,       T.g,      T.aniso,
                                   T.real_coef, T.wide, T.tile_s,  p->opt.precision};
@@ -1335,43 +1404,36 @@ qp_status tune_layout(qp_problem *p)
         std::lock_guard<std::mutex> lock(g_layout_mu);
         const auto f = g_layouts.find(key);
         if (f != g_layouts.end()) {
-            QP_TRY(apply_layout(p, f->second));
-            p->layout = qp_layout{f->second.it, f->second.nb, f->second.xcd, 2, 0, 0.0, 0.0};
+            QP_TRY(apply_layout(p, f->second.first, qp::F32));
+            QP_TRY(apply_layout(p, f->second.second, qp::F64));
+            report_layout(p, 2);
             return QP_OK;
         }
     }
-    // active states and a zero source; the product writes q and the partials
+    // zero sources; the products write q or r and the partials
     const int K = rhs_per_launch(p);
     const bool f32 = p->opt.precision == QP_PREC_FP32_IR;
-    QP_HIP(qp::launch_state_reset(K, p->st(), p->stream));
-    QP_HIP(hipMemsetAsync(f32 ? (void *)p->h32() : (void *)p->h(), 0,
-                          (f32 ? 8 : 16) * (size_t)T.D * K, p->stream));
-    double est = 0.0;
-    QP_TRY(time_product(p, 3, est));
-    // about 2 ms of launches per candidate
-    const int reps = (int)std::min(50.0, std::max(3.0, std::ceil(2000.0 / std::max(est, 1.0))));
-    const std::vector<LayoutPick> cands = layout_candidates(T);
-    LayoutPick best = dflt;
-    double best_us = 0.0, dflt_us = 0.0;
-    QP_TRY(time_product(p, reps, dflt_us));
-    best_us = dflt_us;
-    for (const LayoutPick &L : cands) {
-        if (L == dflt) continue;
-        QP_TRY(apply_layout(p, L));
-        double us = 0.0;
-        QP_TRY(time_product(p, reps, us));
-        // a layout replaces the heuristic one only when clearly faster
-        if (us < 0.97 * best_us) {
-            best = L;
-            best_us = us;
-        }
+    QP_HIP(hipMemsetAsync(p->h(), 0, 16 * (size_t)T.D * K, p->stream));
+    if (f32) {
+        QP_HIP(hipMemsetAsync(p->h32(), 0, 8 * (size_t)T.D * K, p->stream));
+        QP_HIP(hipMemsetAsync(p->x32(), 0, 8 * (size_t)T.D * K, p->stream));
+        QP_HIP(hipMemsetAsync(p->F(), 0, 16 * (size_t)T.D * K, p->stream));
     }
-    QP_TRY(apply_layout(p, best));
+    LayoutPick b32{T.item_tiles, T.nb_mv, T.xcd_front}, b64{};
+    double d32 = 0.0, s32 = 0.0, d64 = 0.0, s64 = 0.0;
+    int n32 = 0, n64 = 0;
+    if (f32) QP_TRY(search_layout(p, qp::F32, false, b32, d32, s32, n32));
+    QP_TRY(search_layout(p, qp::F64, f32, b64, d64, s64, n64));
     QP_HIP(qp::launch_state_reset(qp::kMaxRhs, p->st(), p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
-    p->layout = qp_layout{best.it, best.nb, best.xcd, 1, (int)cands.size(), dflt_us, best_us};
+    report_layout(p, 1);
+    p->layout.candidates = n32 + n64;
+    p->layout.default_us = d32;
+    p->layout.best_us = s32;
+    p->layout.default64_us = d64;
+    p->layout.best64_us = s64;
     std::lock_guard<std::mutex> lock(g_layout_mu);
-    g_layouts.emplace(key, best);
+    g_layouts.emplace(key, std::make_pair(b32, b64));
     return QP_OK;
 }
 
@@ -1483,7 +1545,8 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     if (p->amin < -1e-12 * scale)
         return bail(fail(QP_ENOTELLIPTIC, "coefficient minimum on the grid is %.6g < 0", p->amin));
     if (std::fabs(p->amin) <= 1e-12 * scale) p->flags |= QP_FLAG_DEGENERATE;
-    p->layout = qp_layout{p->host.item_tiles, p->host.nb_mv, p->host.xcd_front, 0, 0, 0.0, 0.0};
+    p->layout = qp_layout{};
+    report_layout(p, 0);
     if (o.autotune) {
         s = tune_layout(p);
         if (s != QP_OK) return bail(s);
@@ -1509,12 +1572,29 @@ qp_status qp_set_product_layout(qp_problem *p, const qp_layout *layout)
     if (plane ? (L.item_tiles != 1 && L.item_tiles != 2 && L.item_tiles != 4) : L.item_tiles != 1)
         return fail(QP_EINVAL, "item_tiles = %d is not 1, 2 or 4 (1 for line tiles)", L.item_tiles);
     if (L.xcd_front < 0 || L.xcd_front > 2) return fail(QP_EINVAL, "xcd_front must be 0, 1 or 2");
+    if (L.workgroups64 > 0) {
+        if (L.workgroups64 > qp::kMaxBlocks)
+            return fail(QP_EINVAL, "workgroups64 = %d outside [1, %d]", L.workgroups64, qp::kMaxBlocks);
+        if (plane ? (L.item_tiles64 != 1 && L.item_tiles64 != 2 && L.item_tiles64 != 4)
+                  : L.item_tiles64 != 1)
+            return fail(QP_EINVAL, "item_tiles64 = %d is not 1, 2 or 4 (1 for line tiles)",
+                        L.item_tiles64);
+        if (L.xcd_front64 < 0 || L.xcd_front64 > 2)
+            return fail(QP_EINVAL, "xcd_front64 must be 0, 1 or 2");
+    } else if (L.workgroups64 < 0) {
+        return fail(QP_EINVAL, "workgroups64 = %d is negative", L.workgroups64);
+    }
     // launches queued earlier read the table; captured batches hold the old grid
     QP_HIP(hipStreamSynchronize(p->stream));
     for (auto &G : p->graphs) (void)hipGraphExecDestroy(G.exec);
     p->graphs.clear();
-    QP_TRY(apply_layout(p, LayoutPick{L.item_tiles, L.workgroups, L.xcd_front}));
-    p->layout = qp_layout{L.item_tiles, L.workgroups, L.xcd_front, 0, 0, 0.0, 0.0};
+    QP_TRY(apply_layout(p, LayoutPick{L.item_tiles, L.workgroups, L.xcd_front}, qp::F32));
+    if (L.workgroups64 > 0)
+        QP_TRY(apply_layout(p, LayoutPick{L.item_tiles64, L.workgroups64, L.xcd_front64}, qp::F64));
+    else
+        QP_TRY(apply_layout(p, LayoutPick{L.item_tiles, L.workgroups, L.xcd_front}, qp::F64));
+    p->layout = qp_layout{};
+    report_layout(p, 0);
     return QP_OK;
 }
 
@@ -1761,7 +1841,7 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
 
     // group table and owners
     std::vector<qp::GroupEntry> ents(G);
-    std::vector<int> own_mv, own_st;
+    std::vector<int> own_mv, own_mv64, own_st;
     int gpmax = 4;
     for (int i = 0; i < G; ++i) {
         qp_problem *p = problems[i];
@@ -1785,25 +1865,31 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
         e.st = p->st();
         e.mv0 = (int)own_mv.size();
         e.nb_mv = p->host.nb_mv;
+        e.mv064 = (int)own_mv64.size();
+        e.nb_mv64 = p->host.nb_mv64;
         e.sv0 = (int)own_st.size();
         e.nb_st = p->host.nblocks;
         own_mv.insert(own_mv.end(), (size_t)e.nb_mv, i);
+        own_mv64.insert(own_mv64.end(), (size_t)e.nb_mv64, i);
         own_st.insert(own_st.end(), (size_t)e.nb_st, i);
         gpmax = std::max(gpmax, (p->host.g + 3) & ~3);
     }
-    int tot_mv = (int)own_mv.size(), tot_st = (int)own_st.size();
+    int tot_mv = (int)own_mv.size(), tot_mv64 = (int)own_mv64.size(), tot_st = (int)own_st.size();
     const size_t nst = (size_t)G * K;
     const size_t o_own_mv = align_up(sizeof(qp::GroupEntry) * G);
-    const size_t o_own_st = align_up(o_own_mv + sizeof(int) * tot_mv);
+    const size_t o_own_mv64 = align_up(o_own_mv + sizeof(int) * tot_mv);
+    const size_t o_own_st = align_up(o_own_mv64 + sizeof(int) * tot_mv64);
     const size_t o_states = align_up(o_own_st + sizeof(int) * tot_st);
     const size_t bytes = o_states + 3 * nst * sizeof(State);
     QP_TRY(group_buffers(p0->device, bytes, nst));
     auto *E = reinterpret_cast<qp::GroupEntry *>(g_gb.dev);
     auto *owner_mv = reinterpret_cast<int *>(g_gb.dev + o_own_mv);
+    auto *owner_mv64 = reinterpret_cast<int *>(g_gb.dev + o_own_mv64);
     auto *owner_st = reinterpret_cast<int *>(g_gb.dev + o_own_st);
     auto *dstates = reinterpret_cast<State *>(g_gb.dev + o_states);
     QP_HIP(hipMemcpy(E, ents.data(), sizeof(qp::GroupEntry) * G, hipMemcpyHostToDevice));
     QP_HIP(hipMemcpy(owner_mv, own_mv.data(), sizeof(int) * tot_mv, hipMemcpyHostToDevice));
+    QP_HIP(hipMemcpy(owner_mv64, own_mv64.data(), sizeof(int) * tot_mv64, hipMemcpyHostToDevice));
     QP_HIP(hipMemcpy(owner_st, own_st.data(), sizeof(int) * tot_st, hipMemcpyHostToDevice));
 
     // set-up of every problem (the launches of a standalone homogenization)
@@ -1821,7 +1907,8 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
     }
     auto replacement = [&](int j) -> qp_status {
         QP_HIP(qp::launch_group_vec(2, j, K, tot_st, E, owner_st, s));
-        QP_HIP(qp::launch_group_matvec(qp::F64, d, p0->host.real_coef, tot_mv, gpmax, E, owner_mv, s));
+        QP_HIP(qp::launch_group_matvec(qp::F64, d, p0->host.real_coef, tot_mv64, gpmax, E, owner_mv64,
+                                       s));
         QP_HIP(qp::launch_group_vec(3, j, K, tot_st, E, owner_st, s));
         return QP_OK;
     };
@@ -1853,19 +1940,25 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
         for (int i = 0; i < G; ++i) any = any || running[i];
         if (!changed || !any) return QP_OK;
         own_mv.clear();
+        own_mv64.clear();
         own_st.clear();
         for (int i = 0; i < G; ++i) {
             if (!running[i]) continue;
             ents[i].mv0 = (int)own_mv.size();
+            ents[i].mv064 = (int)own_mv64.size();
             ents[i].sv0 = (int)own_st.size();
             own_mv.insert(own_mv.end(), (size_t)ents[i].nb_mv, i);
+            own_mv64.insert(own_mv64.end(), (size_t)ents[i].nb_mv64, i);
             own_st.insert(own_st.end(), (size_t)ents[i].nb_st, i);
         }
         QP_HIP(hipStreamSynchronize(s));
         QP_HIP(hipMemcpy(E, ents.data(), sizeof(qp::GroupEntry) * G, hipMemcpyHostToDevice));
         QP_HIP(hipMemcpy(owner_mv, own_mv.data(), sizeof(int) * own_mv.size(), hipMemcpyHostToDevice));
+        QP_HIP(hipMemcpy(owner_mv64, own_mv64.data(), sizeof(int) * own_mv64.size(),
+                         hipMemcpyHostToDevice));
         QP_HIP(hipMemcpy(owner_st, own_st.data(), sizeof(int) * own_st.size(), hipMemcpyHostToDevice));
         tot_mv = (int)own_mv.size();
+        tot_mv64 = (int)own_mv64.size();
         tot_st = (int)own_st.size();
         return QP_OK;
     };

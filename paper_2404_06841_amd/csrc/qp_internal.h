@@ -61,6 +61,9 @@ struct Table {
     int slab_units;           // units (planes) per eighth, when they divide evenly
     int slab_stride;          // units per value of the slowest axis (N^(n-3))
     int slab_span;            // values of the slowest axis per eighth (0: no slab order)
+    int item_tiles64;         // the same three for the FP64 launches (tuned apart:
+    int nb_mv64;              // the float product and the FP64 one prefer different
+    int xcd_front64;          // layouts)
     int wide;                 // plane tiles: 64-bit neighbour addresses, one right-hand
                               // side per launch (else 32-bit record indices)
     uint64_t slotmask[64];    // tile_s > 1: per tile of a plane, bit r when sorted mode
@@ -150,6 +153,7 @@ struct GroupEntry {
     double *pa, *pb;                                // partial sums (Parts a, b)
     State *st;                                      // K states
     int mv0, nb_mv, sv0, nb_st;
+    int mv064, nb_mv64;  // the FP64 product's workgroups (owner_mv64)
 };
 enum Precision { F64 = 0, F32 = 1 };
 

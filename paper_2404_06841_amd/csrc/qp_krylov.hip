@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
             continue;
         }
         double hq[1];
-        load_totals<1>(part_in + k * kPartStride, tab->nb_mv, hq);  // the product's partials
+        load_totals<1>(part_in + k * kPartStride, sizeof(T) == 8 ? tab->nb_mv64 : tab->nb_mv, hq);
         if (!(hq[0] > 0.0)) {
             // (Q h, h) <= 0: Q is not positive definite on this Krylov space
             if (lead) {
@@ -719,7 +719,7 @@ __device__ __forceinline__ void irdir_f(const int vb, const int vnb, int j,
         rzn[k] = rrv[k] = betav[k] = 0.0;
         if (!st->replace) continue;  // decided by the fold
         double v[2];
-        load_totals<2>(part_in + k * kPartStride, tab->nb_mv, v);  // FP64 residual product
+        load_totals<2>(part_in + k * kPartStride, tab->nb_mv64, v);  // FP64 residual product
         const double rz_new = v[0], rr = v[1];  // true residual, scaled by 1/unit
         if (!finite(rr) || !finite(rz_new)) {
             if (lead) {

@@ -674,12 +674,14 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
 
     // items in XCD-front order: each XCD owns a contiguous eighth, its waves
     // sweep it together
-    const int it = tab->item_tiles;
+    constexpr bool F64L = sizeof(T) == 8;  // FP64 launches have their own layout
+    const int it = F64L ? tab->item_tiles64 : tab->item_tiles;
+    const int xfront = F64L ? tab->xcd_front64 : tab->xcd_front;
     const int ipu = (tpu + it - 1) / it;  // items per unit
     const int nitems = (tab->ntiles / tpu) * ipu;
     const int nw = vnb * kWaves;
     const int b = vb;
-    const bool by_xcd = tab->xcd_front && (vnb % 8 == 0);
+    const bool by_xcd = xfront && (vnb % 8 == 0);
     const int xcd = by_xcd ? b % 8 : 0;
     const int nloc = by_xcd ? nw / 8 : nw;
     const int loc = (by_xcd ? b / 8 : b) * kWaves + wave;
@@ -694,7 +696,7 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
     // xcd_front 2: inside each XCD's eighth of the units (a slab of span
     // consecutive values of the slowest axis), that axis varies fastest, so a
     // unit's neighbours along it are swept next to it (see Table)
-    const int span = (by_xcd && tab->xcd_front == 2) ? tab->slab_span : 0;
+    const int span = (by_xcd && xfront == 2) ? tab->slab_span : 0;
     for (int item = ibeg + loc; item < iend; item += nloc) {
         int unit = item / ipu;
         const int tl0 = (item - unit * ipu) * it;
@@ -902,7 +904,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane_grp(const GroupEntry *_
             nullptr, e.M32, e.pa, e.st, nullptr);
     else
         matvec_plane<T, DT, EPI, REAL, KR, false, false>(
-            (int)blockIdx.x - e.mv0, e.nb_mv, e.tab, e.recs, static_cast<const Rec *>(e.urec64),
+            (int)blockIdx.x - e.mv064, e.nb_mv64, e.tab, e.recs, static_cast<const Rec *>(e.urec64),
             static_cast<const T *>(e.upku64), reinterpret_cast<const cplx_t<T> *>(e.X), e.r32,
             reinterpret_cast<const double2 *>(e.F), e.M32, e.pb, e.st, nullptr);
 }
@@ -913,7 +915,7 @@ hipError_t launch_plane(const Table &ht, size_t lds, const Table *tab, const Mod
                         const double2 *Fv, const float *M32, double *part, State *st, int *exec,
                         hipStream_t s)
 {
-    const dim3 grid(ht.nb_mv), block(kBlock);
+    const dim3 grid(sizeof(T) == 8 ? ht.nb_mv64 : ht.nb_mv), block(kBlock);
     const size_t gp = (size_t)((ht.g + 3) & ~3);
     switch (ht.d) {
 #define QP_CASE(DD)                                                                              \
@@ -936,7 +938,7 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, cons
                     const void *upku, const void *x, void *y, const double *f, const float *M32,
                     double *part, State *st, int *exec, hipStream_t s)
 {
-    const dim3 grid(ht.nb_mv), block(kBlock);
+    const dim3 grid(sizeof(T) == 8 ? ht.nb_mv64 : ht.nb_mv), block(kBlock);
     const size_t lds = (ht.N <= kWave) ? sizeof(int2) * kWave * (size_t)((ht.g + 3) & ~3) : 0;
     auto X = static_cast<const cplx_t<T> *>(x);
     auto Fv = reinterpret_cast<const double2 *>(f);

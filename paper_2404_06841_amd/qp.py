@@ -64,7 +64,8 @@ class qp_options(C.Structure):
 class qp_layout(C.Structure):
     _fields_ = [("item_tiles", C.c_int), ("workgroups", C.c_int), ("xcd_front", C.c_int),
                 ("tuned", C.c_int), ("candidates", C.c_int), ("default_us", C.c_double),
-                ("best_us", C.c_double)]
+                ("best_us", C.c_double), ("item_tiles64", C.c_int), ("workgroups64", C.c_int),
+                ("xcd_front64", C.c_int), ("default64_us", C.c_double), ("best64_us", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -431,10 +432,13 @@ class Problem:
         _check(lib().qp_product_layout(self.h, C.byref(out)), "qp_product_layout")
         return out.as_dict()
 
-    def set_layout(self, item_tiles: int, workgroups: int, xcd_front: int):
-        """Set the stiffness product's work layout (qp_set_product_layout)."""
+    def set_layout(self, item_tiles: int, workgroups: int, xcd_front: int,
+                   item_tiles64: int = 0, workgroups64: int = 0, xcd_front64: int = 0):
+        """Set the stiffness product's work layouts (qp_set_product_layout);
+        the FP64 launches take the float layout unless workgroups64 > 0."""
         L = qp_layout(item_tiles=int(item_tiles), workgroups=int(workgroups),
-                      xcd_front=int(xcd_front))
+                      xcd_front=int(xcd_front), item_tiles64=int(item_tiles64),
+                      workgroups64=int(workgroups64), xcd_front64=int(xcd_front64))
         _check(lib().qp_set_product_layout(self.h, C.byref(L)), "qp_set_product_layout")
 
     def coef_extrema(self):

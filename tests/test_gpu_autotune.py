@@ -50,6 +50,10 @@ def key(L: dict) -> tuple:
     return L["item_tiles"], L["workgroups"], L["xcd_front"]
 
 
+def key64(L: dict) -> tuple:
+    return L["item_tiles64"], L["workgroups64"], L["xcd_front64"]
+
+
 @pytest.mark.parametrize("make", [lambda: W.eightfold_random(16, 3), lambda: W.icosahedral(6)],
                          ids=["eightfold_random_N16", "icosa_N6"])
 def test_every_layout_gives_bitwise_equal_products(make):
@@ -65,7 +69,7 @@ def test_every_layout_gives_bitwise_equal_products(make):
     for L in LAYOUTS:
         a.set_layout(*L)
         got = a.layout()
-        assert key(got) == L and got["tuned"] == 0
+        assert key(got) == L and key64(got) == L and got["tuned"] == 0
         assert torch.equal(a.matvec_d(dev(u)), y64), L
         assert torch.equal(a.matvec32_d(u32), y32), L
     a.close()
@@ -118,18 +122,39 @@ def test_autotune_chooses_a_layout_and_reuses_it_for_the_shape():
         assert 0 < La["best_us"] <= La["default_us"]
     b = qp.Problem(prob, precision="fp32ir", autotune=True)
     Lb = b.layout()
-    assert Lb["tuned"] == 2 and key(Lb) == key(La)
+    assert Lb["tuned"] == 2 and key(Lb) == key(La) and key64(Lb) == key64(La)
     u = W.random_vector(prob.D, seed=9)
     assert torch.equal(a.matvec_d(dev(u)), plain.matvec_d(dev(u)))
     r = a.homogenized(tol=1e-12)
     err = np.abs(r.A - A_ref).max() / np.abs(A_ref).max()
     assert all(i.status == 0 for i in r.infos) and err <= 1e-10, err
-    # the same layout set explicitly repeats the tuned problem's A* bitwise
-    plain.set_layout(*key(La))
+    # the same layouts set explicitly repeat the tuned problem's A* bitwise
+    plain.set_layout(*key(La), *key64(La))
     r2 = plain.homogenized(tol=1e-12)
     assert np.array_equal(r2.A, r.A)
     for p in (plain, a, b):
         p.close()
+
+
+def test_separate_fp64_layout():
+    # float and FP64 launches on different layouts: both products unchanged,
+    # and an FP32-IR solve (float iterations, FP64 replacements) meets the oracle
+    gold = json.load(open(os.path.join(GOLDEN, "oracle_astar.json")))["c2_eightfold_N16"]
+    A_ref = np.array(gold["A"])
+    prob = W.eightfold(16)
+    a = qp.Problem(prob, precision="fp32ir")
+    u = W.random_vector(prob.D, seed=11)
+    u32 = dev(u.astype(np.complex64), torch.complex64)
+    y64, y32 = a.matvec_d(dev(u)), a.matvec32_d(u32)
+    a.set_layout(4, 256, 1, 1, 1000, 2)
+    assert key(a.layout()) == (4, 256, 1) and key64(a.layout()) == (1, 1000, 2)
+    assert torch.equal(a.matvec_d(dev(u)), y64) and torch.equal(a.matvec32_d(u32), y32)
+    r = a.homogenized(tol=1e-12)
+    err = np.abs(r.A - A_ref).max() / np.abs(A_ref).max()
+    assert all(i.status == 0 for i in r.infos) and err <= 1e-10, err
+    with pytest.raises(qp.QPError):
+        a.set_layout(4, 256, 1, 3, 64, 0)  # item_tiles64 not 1, 2 or 4
+    a.close()
 
 
 def test_invalid_layouts_are_rejected():
