@@ -362,8 +362,9 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(how the path would shard is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
+                                   "(independent solves shard by problem; one large solve "
+                                   "would shard into slabs along the slowest axis)"}))
         sys.exit(2)
     import numpy as np
     import torch

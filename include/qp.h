@@ -56,7 +56,7 @@ typedef enum qp_status {
     QP_ENONFINITE = -7     /* NaN or Inf in an input or in the residual            */
 } qp_status;
 
-/* Limits of this build. */
+/* Compile-time limits of the library. */
 #define QP_MAX_DIM_N 8     /* parent dimension n  */
 #define QP_MAX_DIM_D 4     /* physical dimension d */
 #define QP_MAX_MODES 64    /* coefficient modes g  */

@@ -1,4 +1,4 @@
-// Internal interface between the host driver (qp_api.cpp) and the gfx950
+// Internal interface between the host runtime (qp_api.cpp) and the gfx950
 // kernels.  Not part of the public ABI.
 #pragma once
 

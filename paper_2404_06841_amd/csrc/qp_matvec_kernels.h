@@ -388,7 +388,9 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                 using std::integral_constant;
                 int rb = 0;
                 for (; rb + KC <= gp; rb += KC) chunk(integral_constant<int, KC>(), Gc, rb);
-                if (KC / 2 >= 4 && rb + KC / 2 <= gp) {
+                // a half chunk only when it keeps rb a multiple of 4 (gp is one,
+                // and the 4-chunks below must end exactly at gp)
+                if (KC / 2 >= 4 && (KC / 2) % 4 == 0 && rb + KC / 2 <= gp) {
                     chunk(integral_constant<int, (KC / 2 >= 4 ? KC / 2 : 4)>(), Gc, rb);
                     rb += KC / 2;
                 }
@@ -842,7 +844,9 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                 using std::integral_constant;
                 int rb = 0;
                 for (; rb + KC <= gp; rb += KC) chunk(integral_constant<int, KC>(), rb);
-                if (KC / 2 >= 4 && rb + KC / 2 <= gp) {
+                // a half chunk only when it keeps rb a multiple of 4 (gp is one,
+                // and the 4-chunks below must end exactly at gp)
+                if (KC / 2 >= 4 && (KC / 2) % 4 == 0 && rb + KC / 2 <= gp) {
                     chunk(integral_constant<int, (KC / 2 >= 4 ? KC / 2 : 4)>(), rb);
                     rb += KC / 2;
                 }
