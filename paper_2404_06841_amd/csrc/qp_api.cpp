@@ -236,18 +236,22 @@ qp_status check_args(int d, int n, const double *P, int g, const int32_t *modes,
     return QP_OK;
 }
 
-// coefs: null for a scalar coefficient, else d x g complex (a_l's Ahat per mode)
 // Grid of the streaming kernels: workgroups of `chunk` consecutive entries
 // (a multiple of kBlock).  Every vector kernel reduces all partial sums of
 // the previous launch in each workgroup, so the partial traffic grows with
 // the square of the workgroup count: at 1,048,576 unknowns 1024 workgroups
 // read 48 MB of partials per iteration beside 136 MB of float vectors.  The
 // cap per precision was measured there (two right-hand sides): FP32-IR best
-// at 512 workgroups (2048 entries each), FP64 at 683 (1536 entries each).
+// at 586 workgroups of 1792 entries (one pass of the float update and
+// direction; 384 to 768 workgroups within 0.3%), FP64 at 683 (1536 entries
+// each).
+#ifndef QP_GRID_IR
+#define QP_GRID_IR 640
+#endif
 void stream_grid(Table &T, int precision)
 {
     const int64_t D = T.D;
-    const int cap = std::min(qp::kStreamBlocks, precision == QP_PREC_FP32_IR ? 512 : 820);
+    const int cap = std::min(qp::kStreamBlocks, precision == QP_PREC_FP32_IR ? QP_GRID_IR : 820);
     int nb = (int)std::min<int64_t>(cap, (D + qp::kBlock - 1) / qp::kBlock);
     if (nb >= 64) nb -= nb % 8;
     int64_t chunk = (D + nb - 1) / nb;
@@ -256,6 +260,7 @@ void stream_grid(Table &T, int precision)
     T.nblocks = (int)((D + chunk - 1) / chunk);
 }
 
+// coefs: null for a scalar coefficient, else d x g complex (a_l's Ahat per mode)
 void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *modes,
                  const double *coef, const double *coefs, int N)
 {

@@ -413,8 +413,15 @@ __global__ __launch_bounds__(kBlock) void k_init_f(const Table *__restrict__ tab
 
 // The first pass's rows of the update and the direction are requested before
 // the previous launch's partial sums are reduced, so the reduction's latency
-// overlaps the loads (a chunk is usually exactly one pass: 4 entries per
-// thread).
+// overlaps the loads.  A pass loads kRows entries per thread; with the float
+// stream grid a chunk is at most one pass up to 1.3 M entries, so a wave makes
+// one round trip to memory instead of two (a later pass's loads of r cannot
+// move above the earlier pass's stores to r).
+#ifndef QP_VEC_ROWS
+#define QP_VEC_ROWS 8
+#endif
+constexpr int kRows = QP_VEC_ROWS;
+
 template <int KK>
 __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
                                          const Table *__restrict__ tab,
@@ -438,10 +445,10 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
     }
     if (!any) return;
     const int i0 = begin + threadIdx.x;
-    float2 rv[4][KK], qv[4][KK];
-    float mv[4];
+    float2 rv[kRows][KK], qv[kRows][KK];
+    float mv[kRows];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kRows; ++u) {
         const int i = i0 + u * kBlock;
         if (i < end) {
             ld_row<KK>(r, i, rv[u]);
@@ -492,13 +499,13 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
         st_row<KK>(r, i, rw);
     };
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kRows; ++u) {
         const int i = i0 + u * kBlock;
         if (i < end) step(i, rv[u], qv[u], mv[u]);
     }
-    for (int ib = i0 + 4 * kBlock; ib < end; ib += 4 * kBlock) {
+    for (int ib = i0 + kRows * kBlock; ib < end; ib += kRows * kBlock) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kRows; ++u) {
             const int i = ib + u * kBlock;
             if (i < end) {
                 ld_row<KK>(r, i, rv[u]);
@@ -507,7 +514,7 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kRows; ++u) {
             const int i = ib + u * kBlock;
             if (i < end) step(i, rv[u], qv[u], mv[u]);
         }
@@ -554,10 +561,10 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
     }
     if (!any_did) return;
     const int i0 = begin + threadIdx.x;
-    float2 uv[4][KK], hv[4][KK], rv[4][KK];
-    float mv[4];
+    float2 uv[kRows][KK], hv[kRows][KK], rv[kRows][KK];
+    float mv[kRows];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kRows; ++u) {
         const int i = i0 + u * kBlock;
         if (i < end) {
             ld_row<KK>(U, i, uv[u]);
@@ -619,13 +626,13 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
         if (any_go) st_row<KK>(h, i, hw);
     };
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kRows; ++u) {
         const int i = i0 + u * kBlock;
         if (i < end) step(i, uv[u], hv[u], rv[u], mv[u]);
     }
-    for (int ib = i0 + 4 * kBlock; ib < end; ib += 4 * kBlock) {
+    for (int ib = i0 + kRows * kBlock; ib < end; ib += kRows * kBlock) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kRows; ++u) {
             const int i = ib + u * kBlock;
             if (i < end) {
                 ld_row<KK>(U, i, uv[u]);
@@ -635,7 +642,7 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kRows; ++u) {
             const int i = ib + u * kBlock;
             if (i < end) step(i, uv[u], hv[u], rv[u], mv[u]);
         }
