@@ -413,16 +413,14 @@ __global__ __launch_bounds__(kBlock) void k_init_f(const Table *__restrict__ tab
 
 // The first pass's rows of the update and the direction are requested before
 // the previous launch's partial sums are reduced, so the reduction's latency
-// overlaps the loads.  A pass loads kRows entries per thread; with the float
-// stream grid a chunk is at most one pass up to 1.3 M entries, so a wave makes
-// one round trip to memory instead of two (a later pass's loads of r cannot
-// move above the earlier pass's stores to r).
-#ifndef QP_VEC_ROWS
-#define QP_VEC_ROWS 8
-#endif
-constexpr int kRows = QP_VEC_ROWS;
+// overlaps the loads.  A pass loads ROWS entries per thread.  A later pass's
+// loads of r cannot move above the earlier pass's stores to r, so each pass
+// costs a wave a round trip to memory: chunks longer than 4 * kBlock take the
+// 8-row instance (one pass up to 2048 entries), shorter ones the 4-row
+// instance, whose smaller register count keeps more waves resident when many
+// problems share the device.
 
-template <int KK>
+template <int KK, int ROWS>
 __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
                                          const Table *__restrict__ tab,
                                                      float2 *__restrict__ r,
@@ -445,10 +443,10 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
     }
     if (!any) return;
     const int i0 = begin + threadIdx.x;
-    float2 rv[kRows][KK], qv[kRows][KK];
-    float mv[kRows];
+    float2 rv[ROWS][KK], qv[ROWS][KK];
+    float mv[ROWS];
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) {
+    for (int u = 0; u < ROWS; ++u) {
         const int i = i0 + u * kBlock;
         if (i < end) {
             ld_row<KK>(r, i, rv[u]);
@@ -499,13 +497,13 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
         st_row<KK>(r, i, rw);
     };
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) {
+    for (int u = 0; u < ROWS; ++u) {
         const int i = i0 + u * kBlock;
         if (i < end) step(i, rv[u], qv[u], mv[u]);
     }
-    for (int ib = i0 + kRows * kBlock; ib < end; ib += kRows * kBlock) {
+    for (int ib = i0 + ROWS * kBlock; ib < end; ib += ROWS * kBlock) {
 #pragma unroll
-        for (int u = 0; u < kRows; ++u) {
+        for (int u = 0; u < ROWS; ++u) {
             const int i = ib + u * kBlock;
             if (i < end) {
                 ld_row<KK>(r, i, rv[u]);
@@ -514,7 +512,7 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
             }
         }
 #pragma unroll
-        for (int u = 0; u < kRows; ++u) {
+        for (int u = 0; u < ROWS; ++u) {
             const int i = ib + u * kBlock;
             if (i < end) step(i, rv[u], qv[u], mv[u]);
         }
@@ -535,7 +533,7 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
 
 // FP32-IR direction (the FP32-IR rules of k_pcg_direction): U += alpha h for
 // every right-hand side whose update ran; h = M r + beta h unless it pauses.
-template <int KK>
+template <int KK, int ROWS>
 __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
                                          const Table *__restrict__ tab,
                                                         float2 *__restrict__ U,
@@ -561,10 +559,10 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
     }
     if (!any_did) return;
     const int i0 = begin + threadIdx.x;
-    float2 uv[kRows][KK], hv[kRows][KK], rv[kRows][KK];
-    float mv[kRows];
+    float2 uv[ROWS][KK], hv[ROWS][KK], rv[ROWS][KK];
+    float mv[ROWS];
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) {
+    for (int u = 0; u < ROWS; ++u) {
         const int i = i0 + u * kBlock;
         if (i < end) {
             ld_row<KK>(U, i, uv[u]);
@@ -626,13 +624,13 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
         if (any_go) st_row<KK>(h, i, hw);
     };
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) {
+    for (int u = 0; u < ROWS; ++u) {
         const int i = i0 + u * kBlock;
         if (i < end) step(i, uv[u], hv[u], rv[u], mv[u]);
     }
-    for (int ib = i0 + kRows * kBlock; ib < end; ib += kRows * kBlock) {
+    for (int ib = i0 + ROWS * kBlock; ib < end; ib += ROWS * kBlock) {
 #pragma unroll
-        for (int u = 0; u < kRows; ++u) {
+        for (int u = 0; u < ROWS; ++u) {
             const int i = ib + u * kBlock;
             if (i < end) {
                 ld_row<KK>(U, i, uv[u]);
@@ -642,7 +640,7 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
             }
         }
 #pragma unroll
-        for (int u = 0; u < kRows; ++u) {
+        for (int u = 0; u < ROWS; ++u) {
             const int i = ib + u * kBlock;
             if (i < end) step(i, uv[u], hv[u], rv[u], mv[u]);
         }
@@ -789,7 +787,7 @@ __device__ __forceinline__ void irdir_f(const int vb, const int vnb, int j,
 
 // Kernels over one problem (the whole grid) and grouped over several (each
 // workgroup serves the problem owner[blockIdx.x] as one of its workgroups).
-template <int KK>
+template <int KK, int ROWS>
 __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restrict__ tab,
                                                      float2 *__restrict__ r,
                                                      const float2 *__restrict__ q,
@@ -798,10 +796,10 @@ __global__ __launch_bounds__(kBlock) void k_update_f(int j, const Table *__restr
                                                      double *__restrict__ part_out,
                                                      State *__restrict__ sts)
 {
-    update_f<KK>((int)blockIdx.x, (int)gridDim.x, j, tab, r, q, M, part_in, part_out, sts);
+    update_f<KK, ROWS>((int)blockIdx.x, (int)gridDim.x, j, tab, r, q, M, part_in, part_out, sts);
 }
 
-template <int KK>
+template <int KK, int ROWS>
 __global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__restrict__ tab,
                                                         float2 *__restrict__ U,
                                                         const float2 *__restrict__ r,
@@ -810,7 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_direction_f(int j, const Table *__re
                                                         const double *__restrict__ part_in,
                                                         State *__restrict__ sts)
 {
-    direction_f<KK>((int)blockIdx.x, (int)gridDim.x, j, tab, U, r, h, M, part_in, sts);
+    direction_f<KK, ROWS>((int)blockIdx.x, (int)gridDim.x, j, tab, U, r, h, M, part_in, sts);
 }
 
 template <int KK>
@@ -844,10 +842,10 @@ __global__ __launch_bounds__(kBlock) void k_vec_grp(int j, const GroupEntry *__r
     float2 *r32 = reinterpret_cast<float2 *>(e.r32);
     float2 *h32 = reinterpret_cast<float2 *>(e.h32);
     if constexpr (STEP == 0)
-        update_f<KK>(vb, vnb, j, e.tab, r32, reinterpret_cast<const float2 *>(e.q32), e.M32, e.pa,
-                     e.pb, e.st);
+        update_f<KK, 4>(vb, vnb, j, e.tab, r32, reinterpret_cast<const float2 *>(e.q32), e.M32,
+                        e.pa, e.pb, e.st);
     else if constexpr (STEP == 1)
-        direction_f<KK>(vb, vnb, j, e.tab, x32, r32, h32, e.M32, e.pb, e.st);
+        direction_f<KK, 4>(vb, vnb, j, e.tab, x32, r32, h32, e.M32, e.pb, e.st);
     else if constexpr (STEP == 2)
         fold_f<KK>(vb, vnb, e.tab, reinterpret_cast<double2 *>(e.X), x32, e.st);
     else
@@ -908,13 +906,15 @@ hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Tab
                            st);
         return hipGetLastError();
     }
+    const bool wide = ht.chunk > 4 * kBlock;
     switch (K) {
 #define QP_K(KK)                                                                                  \
     case KK:                                                                                       \
-        hipLaunchKernelGGL(k_update_f<KK>, grid, block, 0, s, j, tab, (float2 *)r,                \
-                           (const float2 *)q, (const float *)M, (const double *)parts.a, parts.b, \
-                           st);                                                                    \
-        break;
+    {                                                                                              \
+        auto kern = wide ? k_update_f<KK, 8> : k_update_f<KK, 4>;                                 \
+        hipLaunchKernelGGL(kern, grid, block, 0, s, j, tab, (float2 *)r, (const float2 *)q,       \
+                           (const float *)M, (const double *)parts.a, parts.b, st);                \
+    } break;
         QP_K(1) QP_K(2) QP_K(3) QP_K(4)
 #undef QP_K
     default:
@@ -934,13 +934,15 @@ hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const 
                            (const double *)parts.b, st);
         return hipGetLastError();
     }
+    const bool wide = ht.chunk > 4 * kBlock;
     switch (K) {
 #define QP_K(KK)                                                                                 \
     case KK:                                                                                      \
-        hipLaunchKernelGGL(k_direction_f<KK>, grid, block, 0, s, j, tab, (float2 *)U,            \
-                           (const float2 *)r, (float2 *)h, (const float *)M,                      \
-                           (const double *)parts.b, st);                                          \
-        break;
+    {                                                                                             \
+        auto kern = wide ? k_direction_f<KK, 8> : k_direction_f<KK, 4>;                          \
+        hipLaunchKernelGGL(kern, grid, block, 0, s, j, tab, (float2 *)U, (const float2 *)r,      \
+                           (float2 *)h, (const float *)M, (const double *)parts.b, st);           \
+    } break;
         QP_K(1) QP_K(2) QP_K(3) QP_K(4)
 #undef QP_K
     default:
