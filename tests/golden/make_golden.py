@@ -2,7 +2,8 @@
 the CPU oracle (and nothing else) for the full-size workloads that are too slow
 to recompute inside a test.
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py            # every case
+    python tests/golden/make_golden.py NAME ...   # only these; the others are kept
 """
 from __future__ import annotations
 
@@ -23,13 +24,25 @@ CASES = {
     # diagonal coefficient diag(a_1, a_2) (App. D): the benchmark's second workload
     "diag_eightfold_N32": lambda: W.eightfold_diagonal(32, 0),
     "paper_homogenization_N18": lambda: W.paper_homogenization(18),
+    # d = 3 icosahedral field at N = 10: 1,000,000 unknowns (not a power of two),
+    # three correctors
+    "icosa_N10": lambda: W.icosahedral(10),
 }
 
 
-def main():
+def main(names):
+    path = os.path.join(HERE, "oracle_astar.json")
     out = {"_about": "A* (flux and energy forms) of the CPU oracle at tol 1e-12, "
                      "written by tests/golden/make_golden.py"}
+    if names:
+        unknown = [n for n in names if n not in CASES]
+        if unknown:
+            raise SystemExit(f"unknown cases {unknown}; known: {sorted(CASES)}")
+        with open(path) as f:
+            out.update(json.load(f))
     for name, make in CASES.items():
+        if names and name not in names:
+            continue
         prob = make()
         t = time.time()
         r = oracle.homogenize(prob, tol=1e-12)
@@ -38,9 +51,9 @@ def main():
                      "iters": [i.iters for i in r.infos],
                      "seconds": time.time() - t}
         print(name, out[name], flush=True)
-    with open(os.path.join(HERE, "oracle_astar.json"), "w") as f:
+    with open(path, "w") as f:
         json.dump(out, f, indent=2)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

@@ -202,6 +202,29 @@ def test_c3_fullsize_matvec_sampled_rows():
     gp.close()
 
 
+def test_icosahedral_N10_fullsize_three_correctors():
+    """D = 10^6 (not a power of two): the float stream grid leaves a ragged
+    last workgroup (64 entries) and takes the eight-row update and direction
+    with three right-hand sides; the plane tiles use 60 of 64 lanes."""
+    gold = json.load(open(os.path.join(GOLDEN, "oracle_astar.json")))["icosa_N10"]
+    prob = W.icosahedral(10)
+    say(f"[case] icosahedral N=10 D={prob.D}")
+    gp = qp.Problem(prob)
+    A_ref = np.array(gold["A"])
+    for prec in ("fp64", "fp32ir"):
+        gp.set_precision(prec)
+        r = gp.homogenized(tol=1e-12)
+        err = np.abs(r.A - A_ref).max() / np.abs(A_ref).max()
+        say(f"  {prec}: iters {[i.iters for i in r.infos]} rel err {err:.2e}")
+        assert all(i.status == 0 for i in r.infos), prec
+        assert err <= 1e-10, (prec, r.A, A_ref)
+    u = W.random_vector(prob.D, seed=37)
+    y = host(gp.matvec_d(dev(u)))
+    ref = oracle.matvec(prob, u)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    gp.close()
+
+
 # ------------------------------------------------------------- error paths
 
 def test_literal_indefinite_fields_rejected():
