@@ -421,7 +421,8 @@ def main():
                 "launches": mv_n, "rhs_per_launch": round(mv_rhs / mv_n, 3) if mv_n else None,
                 "avg_launch_us": round(avg_s * 1e6, 2) if mv_n else None,
                 "algorithmic_bytes_per_launch": round(algo_bytes),
-                "timing": "HIP events around each launch, in a second pass of the same steps "
+                "timing": "HIP event pair recorded by each launch itself (hipExtLaunchKernelGGL) "
+                          "on the library's stream, in a second pass of the same steps "
                           "(profiled batches run without graph replay)",
                 "profiled_pass_value": round(solves / dtp, 2),
                 "layout": layout}

@@ -87,9 +87,10 @@ typedef struct qp_options {
                            each batch ends with the replacement steps, which act
                            on the right-hand sides that reached inner_tol);
                            0 = 12, rounded up to an even count, at most 64      */
-    int profile;        /* nonzero: bracket every stiffness-product launch with
-                           HIP events; totals reported in qp_solve_info.  Batches
-                           are then launched directly (no graph replay)          */
+    int profile;        /* nonzero: time every stiffness-product launch with a
+                           HIP event pair that the launch itself records (kernel
+                           start and end); totals reported in qp_solve_info.
+                           Batches are then launched directly (no graph replay) */
     void *stream;       /* hipStream_t to run on; NULL = a stream the library
                            creates and owns                                      */
     void *workspace;    /* optional device buffer of qp_workspace_bytes() bytes;

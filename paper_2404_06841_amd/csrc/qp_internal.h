@@ -188,12 +188,14 @@ hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table
                          const ModeRec *recs, const void *urec, const void *upku,
                          const void *x, void *y,
                          const double *f, const float *M32, const Parts &parts, State *st,
-                         int *exec, hipStream_t s);
+                         int *exec, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 // The same for a diagonal coefficient (tab.aniso; called by launch_matvec).
 hipError_t launch_matvec_diag(int prec, int epi, int K, const Table *tab, const Table &ht,
                               const ModeRec *recs, const void *urec, const void *upku,
                               const void *x, void *y, const double *f, const float *M32,
-                              const Parts &parts, State *st, int *exec, hipStream_t s);
+                              const Parts &parts, State *st, int *exec, hipStream_t s,
+                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Start of a solve.  r = f' * scale (scale = 1 for F64, st->inv_unit for F32),
 // U = 0, X64 = 0 (if given), h = M r; parts.b <- ((r, M r), ||r||^2).

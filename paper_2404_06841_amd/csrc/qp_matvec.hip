@@ -8,13 +8,14 @@ namespace qp {
 hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table &ht,
                          const ModeRec *recs, const void *urec, const void *upku, const void *x,
                          void *y, const double *f, const float *M32, const Parts &parts, State *st,
-                         int *exec, hipStream_t s)
+                         int *exec, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1)
 {
     if (ht.aniso)
         return launch_matvec_diag(prec, epi, K, tab, ht, recs, urec, upku, x, y, f, M32, parts, st,
-                                  exec, s);
+                                  exec, s, ev0, ev1);
     return matvec_entry<false>(prec, epi, K, tab, ht, recs, urec, upku, x, y, f, M32, parts, st,
-                               exec, s);
+                               exec, s, ev0, ev1);
 }
 
 hipError_t launch_unit_records(int prec, const Table *tab, const Table &ht, const ModeRec *recs,

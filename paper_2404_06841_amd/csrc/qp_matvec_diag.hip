@@ -9,10 +9,11 @@ namespace qp {
 hipError_t launch_matvec_diag(int prec, int epi, int K, const Table *tab, const Table &ht,
                               const ModeRec *recs, const void *urec, const void *upku,
                               const void *x, void *y, const double *f, const float *M32,
-                              const Parts &parts, State *st, int *exec, hipStream_t s)
+                              const Parts &parts, State *st, int *exec, hipStream_t s, hipEvent_t ev0,
+                              hipEvent_t ev1)
 {
     return matvec_entry<true>(prec, epi, K, tab, ht, recs, urec, upku, x, y, f, M32, parts, st,
-                              exec, s);
+                              exec, s, ev0, ev1);
 }
 
 hipError_t launch_unit_records_diag(int prec, const Table *tab, const Table &ht,

@@ -33,7 +33,10 @@
 // the shared Infinity Cache.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
+#include <cstdint>
 #include <type_traits>
 
 #include "qp_device.h"
@@ -913,21 +916,34 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane_grp(const GroupEntry *_
             reinterpret_cast<const double2 *>(e.F), e.M32, e.pb, e.st, nullptr);
 }
 
+// A product launch; with an event pair (profiled solves, never captured in a
+// graph) the kernel's own dispatch records its start and end, so the pair
+// times the kernel alone rather than also the dispatch gap in front of it.
+template <typename... A, typename F>
+void launch_timed(F kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t ev0,
+                  hipEvent_t ev1, A... args)
+{
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)lds, s, ev0, ev1, 0u, args...);
+    else
+        hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+}
+
 template <typename T, int EPI, bool REAL, int KR, bool WIDE, bool AN>
 hipError_t launch_plane(const Table &ht, size_t lds, const Table *tab, const ModeRec *recs,
                         const void *urec, const T *Pu, const cplx_t<T> *X, void *y,
                         const double2 *Fv, const float *M32, double *part, State *st, int *exec,
-                        hipStream_t s)
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     const dim3 grid(sizeof(T) == 8 ? ht.nb_mv64 : ht.nb_mv), block(kBlock);
     const size_t gp = (size_t)((ht.g + 3) & ~3);
     switch (ht.d) {
 #define QP_CASE(DD)                                                                              \
     case DD:                                                                                      \
-        hipLaunchKernelGGL((k_matvec_plane<T, DD, EPI, REAL, KR, WIDE, AN>), grid, block,        \
-                           lds + kWaves * gp * sizeof(PlaneRec<T, DD, AN>), s, tab, recs,        \
-                           static_cast<const PlaneRec<T, DD, AN> *>(urec), Pu, X, y, Fv, M32,    \
-                           part, st, exec);                                                      \
+        launch_timed(k_matvec_plane<T, DD, EPI, REAL, KR, WIDE, AN>, grid, block,               \
+                     lds + kWaves * gp * sizeof(PlaneRec<T, DD, AN>), s, ev0, ev1, tab, recs,   \
+                     static_cast<const PlaneRec<T, DD, AN> *>(urec), Pu, X, y, Fv, M32, part,   \
+                     st, exec);                                                                  \
         break;
         QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
 #undef QP_CASE
@@ -940,7 +956,7 @@ hipError_t launch_plane(const Table &ht, size_t lds, const Table *tab, const Mod
 template <typename T, int EPI, bool REAL, int KR, bool AN>
 hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, const void *urec,
                     const void *upku, const void *x, void *y, const double *f, const float *M32,
-                    double *part, State *st, int *exec, hipStream_t s)
+                    double *part, State *st, int *exec, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     const dim3 grid(sizeof(T) == 8 ? ht.nb_mv64 : ht.nb_mv), block(kBlock);
     const size_t lds = (ht.N <= kWave) ? sizeof(int2) * kWave * (size_t)((ht.g + 3) & ~3) : 0;
@@ -951,18 +967,18 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, cons
         if (!urec || !upku) return hipErrorInvalidValue;
         if (!ht.wide)
             return launch_plane<T, EPI, REAL, KR, false, AN>(ht, lds, tab, recs, urec, Pu, X, y, Fv,
-                                                            M32, part, st, exec, s);
+                                                            M32, part, st, exec, s, ev0, ev1);
         if constexpr (KR == 1)
             return launch_plane<T, EPI, REAL, 1, true, AN>(ht, lds, tab, recs, urec, Pu, X, y, Fv,
-                                                          M32, part, st, exec, s);
+                                                          M32, part, st, exec, s, ev0, ev1);
         return hipErrorInvalidValue;  // 64-bit gathers serve one right-hand side per launch
     }
     if (KR != 1) return hipErrorInvalidValue;  // line tiles serve one right-hand side
     switch (ht.d) {
 #define QP_CASE(DD)                                                                             \
     case DD:                                                                                     \
-        hipLaunchKernelGGL((k_matvec<T, DD, EPI, REAL, AN>), grid, block, lds, s, tab, recs, X, \
-                           y, Fv, M32, part, st, exec);                                          \
+        launch_timed(k_matvec<T, DD, EPI, REAL, AN>, grid, block, lds, s, ev0, ev1, tab, recs,  \
+                     X, y, Fv, M32, part, st, exec);                                             \
         break;
         QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
 #undef QP_CASE
@@ -975,13 +991,13 @@ hipError_t dispatch(const Table *tab, const Table &ht, const ModeRec *recs, cons
 template <typename T, int EPI, bool REAL, bool AN>
 hipError_t dispatch_k(int K, const Table *tab, const Table &ht, const ModeRec *recs,
                       const void *urec, const void *upku, const void *x, void *y, const double *f,
-                      const float *M32, double *part, State *st, int *exec, hipStream_t s)
+                      const float *M32, double *part, State *st, int *exec, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (K) {
-    case 1: return dispatch<T, EPI, REAL, 1, AN>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
-    case 2: return dispatch<T, EPI, REAL, 2, AN>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
-    case 3: return dispatch<T, EPI, REAL, 3, AN>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
-    case 4: return dispatch<T, EPI, REAL, 4, AN>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s);
+    case 1: return dispatch<T, EPI, REAL, 1, AN>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s, ev0, ev1);
+    case 2: return dispatch<T, EPI, REAL, 2, AN>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s, ev0, ev1);
+    case 3: return dispatch<T, EPI, REAL, 3, AN>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s, ev0, ev1);
+    case 4: return dispatch<T, EPI, REAL, 4, AN>(tab, ht, recs, urec, upku, x, y, f, M32, part, st, exec, s, ev0, ev1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -990,13 +1006,13 @@ template <typename T, int EPI, bool AN>
 hipError_t dispatch_coef(int K, const Table *tab, const Table &ht, const ModeRec *recs,
                          const void *urec, const void *upku, const void *x, void *y,
                          const double *f, const float *M32, double *part, State *st, int *exec,
-                         hipStream_t s)
+                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (ht.real_coef)
         return dispatch_k<T, EPI, true, AN>(K, tab, ht, recs, urec, upku, x, y, f, M32, part, st,
-                                            exec, s);
+                                            exec, s, ev0, ev1);
     return dispatch_k<T, EPI, false, AN>(K, tab, ht, recs, urec, upku, x, y, f, M32, part, st,
-                                         exec, s);
+                                         exec, s, ev0, ev1);
 }
 
 template <typename T, bool REAL, bool AN>
@@ -1026,24 +1042,24 @@ template <bool AN>
 hipError_t matvec_entry(int prec, int epi, int K, const Table *tab, const Table &ht,
                         const ModeRec *recs, const void *urec, const void *upku, const void *x,
                         void *y, const double *f, const float *M32, const Parts &parts, State *st,
-                        int *exec, hipStream_t s)
+                        int *exec, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (prec == F64) {
         if (epi == EPI_NONE)
             return dispatch_coef<double, EPI_NONE, AN>(K, tab, ht, recs, urec, upku, x, y, f, M32,
-                                                       parts.a, st, exec, s);
+                                                       parts.a, st, exec, s, ev0, ev1);
         if (epi == EPI_ALPHA)
             return dispatch_coef<double, EPI_ALPHA, AN>(K, tab, ht, recs, urec, upku, x, y, f, M32,
-                                                        parts.a, st, exec, s);
+                                                        parts.a, st, exec, s, ev0, ev1);
         return dispatch_coef<double, EPI_RESID, AN>(K, tab, ht, recs, urec, upku, x, y, f, M32,
-                                                    parts.b, st, exec, s);
+                                                    parts.b, st, exec, s, ev0, ev1);
     }
     if (epi == EPI_NONE)
         return dispatch_coef<float, EPI_NONE, AN>(K, tab, ht, recs, urec, upku, x, y, f, M32,
-                                                  parts.a, st, exec, s);
+                                                  parts.a, st, exec, s, ev0, ev1);
     if (epi == EPI_ALPHA)
         return dispatch_coef<float, EPI_ALPHA, AN>(K, tab, ht, recs, urec, upku, x, y, f, M32,
-                                                   parts.a, st, exec, s);
+                                                   parts.a, st, exec, s, ev0, ev1);
     return hipErrorInvalidValue;  // the replaced residual is always computed in FP64
 }
 
