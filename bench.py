@@ -393,6 +393,9 @@ def main():
     gp.set_options(profile=0)
 
     layout = gp.layout()
+    # outside the timed region: the correctors themselves, to compare the two
+    # precisions' solutions
+    chi32 = [gp.corrector_d(j, tol=TOL)[0] for j in range(prob.d)]
     gp.close()
 
     # the same steps in plain FP64 (comparison, not the headline), on a problem
@@ -403,7 +406,11 @@ def main():
         gp.homogenized(tol=TOL, energy=False)
     dt64, lat64, r64, _ = run_steps(gp, args.steps, torch)
     err_64 = float(np.abs(r64.A - A_ref).max() / np.abs(A_ref).max())
+    chi64 = [gp.corrector_d(j, tol=TOL)[0] for j in range(prob.d)]
     gp.close()
+    chi_diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+                   for a, b in zip(chi32, chi64))
+    del chi32, chi64
 
     D = prob.D
     # algorithmic bytes of a float product: read x once, write y once (16 B per
@@ -452,6 +459,13 @@ def main():
                  "astar_rel_err": err_64,
                  "p99_ms": round(float(np.percentile(np.array(lat64), 99)), 4),
                  "iters": [i.iters for i in r64.infos], "layout": layout64},
+        "solution": {"what": "corrector solves at tol 1e-12: final relative residual per "
+                             "corrector (FP32-IR: the true FP64 residual ||F' - Q chi|| / ||F'||; "
+                             "FP64: the PCG residual), and the largest "
+                             "||chi_fp32ir - chi_fp64|| / ||chi_fp64|| over the correctors",
+                     "rel_resid_fp32ir": [i.rel_resid for i in r.infos],
+                     "rel_resid_fp64": [i.rel_resid for i in r64.infos],
+                     "corrector_rel_diff": chi_diff},
         "fp32ir_iters": [i.iters for i in r.infos],
         "fp32ir_replacements": [i.outer_iters for i in r.infos],
         "roofline": roofline,
