@@ -119,6 +119,34 @@ def test_profiled_solves_time_every_product():
     assert counts[True] == counts[False]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+@pytest.mark.parametrize("prob", [W.one_d_two_mode(128, 6.0, 2 * np.pi), W.eightfold_diagonal(12, 1),
+                                  W.paper_four_mode_2d(6)],
+                         ids=["line_kernel_1d_N128", "diagonal_N12", "paper2d_complex_N6"])
+def test_profiled_launches_time_and_match_unprofiled(prob, prec):
+    """A profiled product launch records its own event pair; the line kernel,
+    the diagonal-coefficient and complex-coefficient plane kernels all take
+    that launch path.  The timed solve gives bitwise the same A* as the
+    unprofiled one."""
+    plain = qp.Problem(prob, precision=prec)
+    timed = qp.Problem(prob, precision=prec, profile=True)
+    ra = plain.homogenized(tol=1e-12)
+    rb = timed.homogenized(tol=1e-12)
+    i0 = rb.infos[0]
+    n64, ms64 = i0.matvec_launches, i0.matvec_ms
+    n32, ms32 = i0.matvec32_launches, i0.matvec32_ms
+    say("profiled", prec, n64, ms64, n32, ms32)
+    assert np.array_equal(ra.A, rb.A)
+    assert [i.iters for i in ra.infos] == [i.iters for i in rb.infos]
+    if prec == "fp64":
+        assert n64 > 0 and ms64 > 0 and n32 == 0
+    else:
+        assert n32 > 0 and ms32 > 0 and n64 > 0 and ms64 > 0
+    assert 0 < ms64 / max(n64, 1) < 100 and (n32 == 0 or 0 < ms32 / n32 < 100)
+    plain.close()
+    timed.close()
+
+
 @pytest.mark.parametrize("prob", [W.eightfold_random(12, 2), W.icosahedral(6), W.paper_four_mode_2d(6)],
                          ids=["eightfold_random_N12", "icosa_N6", "paper2d_complex_N6"])
 def test_multi_rhs_fp64_equals_separate_solves(prob):
