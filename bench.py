@@ -338,9 +338,9 @@ def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):
 def cpu_baseline(prob):
     """The oracle, unmodified, on this host's cores: FP64 homogenizations of the
     same workload (two corrector solves at tol 1e-12 each), repeated until at
-    least 10 s of CPU work have run."""
+    least 10 s of CPU work have run; then one corrector solve on one thread."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.max_threads()
     reps, iters = 0, None
     t0 = time.perf_counter()
     while True:
@@ -350,10 +350,30 @@ def cpu_baseline(prob):
         dt = time.perf_counter() - t0
         if dt >= 10.0 or reps >= 20:
             break
+    # effective bandwidth: 32 B per unknown per stiffness product (FP64), one
+    # product per PCG iteration
+    gbs = 32.0 * prob.D * sum(iters) * reps / dt / 1e9
+    oracle.set_threads(1)
+    F = oracle.corrector_rhs(prob, 0)
+    t1 = time.perf_counter()
+    _, _, it1, _ = oracle.pcg(prob, F, tol=TOL)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(prob.d * reps / dt, 4), "unit": "corrector solves/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{reps} homogenizations ({prob.d * reps} FP64 corrector solves, tol 1e-12, "
-                      f"{iters} PCG iterations each) of the same workload, {dt:.2f} s"}
+                      f"{iters} PCG iterations each) of the same workload, {dt:.2f} s",
+            "effective_GBs": round(gbs, 2),
+            "value_1_thread": round(1.0 / dt1, 4),
+            "sample_1_thread": f"one FP64 corrector solve (j = 1, {it1} PCG iterations), "
+                               f"{dt1:.2f} s",
+            "host": {"cpu_model": model, "logical_cpus": os.cpu_count()}}
 
 
 def main():

@@ -43,6 +43,10 @@ def _load():
     lib = C.CDLL(_LIB_PATH)
     dp = C.POINTER(C.c_double)
     pp = C.POINTER(_Problem)
+    lib.qo_set_threads.restype = None
+    lib.qo_set_threads.argtypes = [C.c_int]
+    lib.qo_max_threads.restype = C.c_int
+    lib.qo_max_threads.argtypes = []
     lib.qo_size.restype = C.c_long
     lib.qo_size.argtypes = [C.c_int, C.c_int]
     lib.qo_rep.restype = C.c_int
@@ -235,6 +239,10 @@ def homogenize(prob, tol: float = 1e-12, maxit: int = 10000, kind: int = 0):
 
 
 def set_threads(n: int) -> None:
-    """Fix the OpenMP thread count used by the oracle (via the environment of
-    the calling process; call before the first oracle routine)."""
-    os.environ["OMP_NUM_THREADS"] = str(int(n))
+    """Set the OpenMP thread count of the oracle's routines (timing only)."""
+    _load().qo_set_threads(int(n))
+
+
+def max_threads() -> int:
+    """The OpenMP thread count the oracle's routines use."""
+    return int(_load().qo_max_threads())

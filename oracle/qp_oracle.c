@@ -28,6 +28,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -45,6 +46,17 @@ typedef struct {
 } qo_problem;
 
 /* D = N^n */
+/* OpenMP threads of the routines below (timing only; no arithmetic). */
+void qo_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
+int qo_max_threads(void)
+{
+    return omp_get_max_threads();
+}
+
 long qo_size(int n, int N)
 {
     long D = 1;
