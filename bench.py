@@ -300,11 +300,11 @@ def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):
     requests queued at once; then the same mix arrives as a seeded Poisson
     stream at `load` times that capacity, and each request's latency (arrival
     to result) is recorded."""
-    configs = [W.icosahedral(6), W.icosahedral(8), W.icosahedral(12), W.icosahedral(16),
+    kinds = [W.icosahedral(6), W.icosahedral(8), W.icosahedral(12), W.icosahedral(16),
                W.eightfold_random(16, 11), W.eightfold_random(24, 12),
                W.eightfold_random(32, 13)]
     rng = np.random.default_rng(W.BASE_SEED + 77)
-    mix = [int(i) for i in rng.integers(0, len(configs), size=requests)]
+    mix = [int(i) for i in rng.integers(0, len(kinds), size=requests)]
     srv = qp.Server(96 << 30, precision="fp32ir", autotune=True)
 
     def drain(tickets):
@@ -316,9 +316,9 @@ def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):
                     fin[t] = time.perf_counter()
         return fin
 
-    drain([srv.submit(c, tol=TOL) for c in configs])  # every problem created once
+    drain([srv.submit(c, tol=TOL) for c in kinds])  # every problem created once
     t0 = time.perf_counter()
-    drain([srv.submit(configs[i], tol=TOL) for i in mix])
+    drain([srv.submit(kinds[i], tol=TOL) for i in mix])
     cap = requests / (time.perf_counter() - t0)
     gaps = rng.exponential(1.0 / (load * cap), size=requests)
     arrive, submitted, finish, tickets = np.cumsum(gaps), {}, {}, []
@@ -327,7 +327,7 @@ def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):
     while len(finish) < requests:
         now = time.perf_counter() - t0
         while k < requests and arrive[k] <= now:
-            t = srv.submit(configs[mix[k]], tol=TOL)
+            t = srv.submit(kinds[mix[k]], tol=TOL)
             submitted[t] = t0 + arrive[k]
             tickets.append(t)
             k += 1
@@ -337,7 +337,7 @@ def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):
     span = max(finish.values()) - t0
     lat = np.array([(finish[t] - submitted[t]) * 1e3 for t in tickets])
     bad = sum(1 for t in tickets if srv.result(t)[2] != qp.QP_OK)
-    solves = sum(configs[i].d for i in mix)
+    solves = sum(kinds[i].d for i in mix)
     cached = srv.bytes()
     srv.close()
     return {"workload": f"{requests} homogenization requests, icosahedral N 6/8/12/16 and eightfold "
