@@ -439,6 +439,17 @@ qp_status qp_coo_matvec_d(qp_problem *p, const int32_t *cols, const double *vals
 
 /* y = Q u in FP64 (eq. linear_system; y[C(0)] = 0, u[C(0)] ignored). */
 qp_status qp_matvec_d(qp_problem *p, const double *u, double *y);
+/* y = Q u in FP64 on Hermitian half storage (Sec. 2.3: the coefficients of a
+ * real function satisfy u_{-k} = conj(u_k); the coefficient is real, so Q
+ * keeps that symmetry).  Odd N and a scalar coefficient only (QP_EINVAL
+ * otherwise).  u, y: device, (D+1)/2 complex doubles each.  Layout: position 0
+ * holds k = 0 (ignored on input, 0 on output); then, for t = n, n-1, ..., 1,
+ * the entries of C(k) order with zero digits on axes 1..t-1 and digit
+ * a_t in [1, (N-1)/2], i.e. the index range [S_t, (N+1)/2 S_t) with
+ * S_t = N^(n-t), index i at position i - (S_t - 1)/2.  Those are the k != 0
+ * whose first nonzero component is positive; k's partner -k is implied.
+ * Reads and writes half the bytes of qp_matvec_d; synchronous. */
+qp_status qp_matvec_half_d(qp_problem *p, const double *u, double *y);
 /* y = Q u with float data and arithmetic (the FP32-IR inner product). */
 qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y);
 /* The diagonal preconditioner (eq. precond; kind per the options), D doubles. */

@@ -2056,6 +2056,18 @@ qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
     return QP_OK;
 }
 
+qp_status qp_matvec_half_d(qp_problem *p, const double *u, double *y)
+{
+    if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
+    if (p->host.N % 2 == 0)
+        return fail(QP_EINVAL, "Hermitian half storage needs odd N (N = %d)", p->host.N);
+    if (p->host.aniso)
+        return fail(QP_EINVAL, "Hermitian half storage: scalar coefficient only");
+    QP_HIP(qp::launch_matvec_half(p->tab, p->host, u, y, p->stream));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    return QP_OK;
+}
+
 qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");

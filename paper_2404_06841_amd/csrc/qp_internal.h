@@ -190,6 +190,10 @@ hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table
                          const double *f, const float *M32, const Parts &parts, State *st,
                          int *exec, hipStream_t s, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr);
+// y = Q u on Hermitian half storage ((D+1)/2 complex doubles each, the layout
+// of qp_matvec_half_d); scalar real coefficient, odd N (checked by the caller).
+hipError_t launch_matvec_half(const Table *tab, const Table &ht, const void *u, void *y,
+                              hipStream_t s);
 // The same for a diagonal coefficient (tab.aniso; called by launch_matvec).
 hipError_t launch_matvec_diag(int prec, int epi, int K, const Table *tab, const Table &ht,
                               const ModeRec *recs, const void *urec, const void *upku,

@@ -47,7 +47,7 @@ EXPORTED = (
     "qp_server_create",
     "qp_server_submit", "qp_server_progress", "qp_server_pending", "qp_server_bytes",
     "qp_server_destroy", "qp_coo_entries", "qp_coo_build_d", "qp_coo_matvec_d", "qp_dft_d",
-    "qp_modes_from_spectrum", "qp_matvec_d", "qp_matvec32_d", "qp_precond_d",
+    "qp_modes_from_spectrum", "qp_matvec_d", "qp_matvec32_d", "qp_matvec_half_d", "qp_precond_d",
     "qp_corrector_rhs_d", "qp_multi_index_d", "qp_astar_d", "qp_coef_extrema",
     "qp_synchronize", "qp_strerror", "qp_last_error",
 )
@@ -139,6 +139,7 @@ def lib():
         "qp_coo_matvec_d": (C.c_int, [vp, vp, vp, vp, vp]),
         "qp_matvec_d": (C.c_int, [vp, vp, vp]),
         "qp_matvec32_d": (C.c_int, [vp, vp, vp]),
+        "qp_matvec_half_d": (C.c_int, [vp, vp, vp]),
         "qp_precond_d": (C.c_int, [vp, vp]),
         "qp_corrector_rhs_d": (C.c_int, [vp, C.c_int, vp]),
         "qp_multi_index_d": (C.c_int, [vp, vp]),
@@ -375,6 +376,17 @@ class Problem:
             out = torch.empty(self.D, dtype=torch.complex64, device="cuda")
         _check(lib().qp_matvec32_d(self.h, _tensor_ptr(u, torch.complex64, self.D),
                                    _tensor_ptr(out, torch.complex64, self.D)), "qp_matvec32_d")
+        return out
+
+    def matvec_half_d(self, u, out=None):
+        """y = Q u on Hermitian half storage: (D+1)//2 complex128 entries each
+        (real coefficient, odd N; the layout of qp_matvec_half_d)."""
+        import torch
+        H = (self.D + 1) // 2
+        if out is None:
+            out = torch.empty(H, dtype=torch.complex128, device="cuda")
+        _check(lib().qp_matvec_half_d(self.h, _tensor_ptr(u, torch.complex128, H),
+                                      _tensor_ptr(out, torch.complex128, H)), "qp_matvec_half_d")
         return out
 
     def coo_build_d(self):
