@@ -160,6 +160,32 @@ def hbm_products(torch, qp, W):
     return out
 
 
+def half_storage(torch, qp, W):
+    """Hermitian half storage at odd N (icosahedral d=3, n=6, N=15: 11,390,625
+    unknowns, 5,695,313 stored): the FP64 product on the half against the
+    full-storage FP64 product of the same problem, each call bracketed by HIP
+    events on the library's stream.  Algorithmic bytes: 32 B per stored entry
+    (read once, write once)."""
+    prob = W.icosahedral(15)
+    gp = qp.Problem(prob, autotune=True)
+    D, H = prob.D, (prob.D + 1) // 2
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(15)
+    out = {"workload": "icosahedral d=3 n=6 N=15 (11,390,625 unknowns; 5,695,313 stored "
+                       "in half storage), FP64, one right-hand side"}
+    for name, fn, size in (("full", gp.matvec_d, D), ("half", gp.matvec_half_d, H)):
+        u = torch.randn(size, dtype=torch.complex128, device="cuda", generator=gen)
+        y = torch.empty_like(u)
+        us = per_launch_us(torch, lambda: fn(u, y))
+        gbs = 32.0 * size / (us * 1e-6) / 1e9
+        out[name] = {"avg_launch_us": round(us, 2), "algorithmic_bytes": int(32 * size),
+                     "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        del u, y
+    out["half_over_full_time"] = round(out["half"]["avg_launch_us"] / out["full"]["avg_launch_us"], 3)
+    gp.close()
+    return out
+
+
 def per_launch_us(torch, fn, reps: int = 20, warm: int = 3) -> float:
     """Average duration of fn() (an entry point that returns after its launch
     completed), each call bracketed by its own HIP events on torch's current
@@ -509,6 +535,7 @@ def main():
         "diagonal_coefficient": diagonal_workload(torch, np, qp, W, gold,
                                                   max(5, args.steps // 2), args.warmup),
         "hbm_products": hbm_products(torch, qp, W),
+        "half_storage": half_storage(torch, qp, W),
         "batch_instances": batch_instances(torch, np, qp, W),
         "stored_matrix": stored_matrix(torch, qp, W),
         "sampled_inputs": sampled_inputs(torch, qp),

@@ -24,12 +24,18 @@
 namespace qp {
 namespace {
 
+// DD, NN: d and n (the loops over them unroll); modes satisfy |m_t| < N/2,
+// so rep(k_t - m_t) needs one compare-and-shift per axis.  W is
+// (Pk).(Pk - Pm) - N sum_t c_t (Pk).p_t for the wrap c_t in {-1, 0, 1}.
+template <int DD, int NN>
 __global__ __launch_bounds__(kBlock) void k_matvec_half(const Table *__restrict__ tab,
                                                         const double2 *__restrict__ u,
                                                         double2 *__restrict__ y, int half)
 {
-    const int n = tab->n, N = tab->N, d = tab->d, g = tab->g;
+    const int N = tab->N, g = tab->g;
     const int h = (N - 1) / 2;
+    int topS = 1;  // N^(n-1)
+    for (int t = 1; t < NN; ++t) topS *= N;
     for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < half;
          pos += gridDim.x * blockDim.x) {
         if (pos == 0) {
@@ -39,49 +45,68 @@ __global__ __launch_bounds__(kBlock) void k_matvec_half(const Table *__restrict_
         // the range t holding this position: S = N^(n-t), the largest power
         // of N with 1 + (S - 1)/2 <= pos
         int S = 1;
-        while (S * N <= tab->D / N && 1 + (S * N - 1) / 2 <= pos) S *= N;
+        while (S < topS && 1 + (S * N - 1) / 2 <= pos) S *= N;
         int i = pos + (S - 1) / 2;
-        int k[kMaxN];
-        for (int t = n - 1; t >= 0; --t) {
+        int k[NN];
+#pragma unroll
+        for (int t = NN - 1; t >= 0; --t) {
             const int a = i % N;
             i /= N;
             k[t] = (a <= h) ? a : a - N;
         }
-        double pk[kMaxD];
-        for (int l = 0; l < d; ++l) {
+        double pk[DD], pkp[NN];  // P k and (P k).p_t
+        double pk2 = 0.0;
+#pragma unroll
+        for (int l = 0; l < DD; ++l) {
             double s = 0.0;
-            for (int t = 0; t < n; ++t) s += tab->P[l][t] * (double)k[t];
+#pragma unroll
+            for (int t = 0; t < NN; ++t) s += tab->P[l][t] * (double)k[t];
             pk[l] = s;
+            pk2 += s * s;
+        }
+#pragma unroll
+        for (int t = 0; t < NN; ++t) {
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < DD; ++l) s += pk[l] * tab->P[l][t];
+            pkp[t] = s;
         }
         double acc_re = 0.0, acc_im = 0.0;
         for (int r = 0; r < g; ++r) {
-            int j[kMaxN];
-            int first = -1;  // first axis with a nonzero component of rep(k - m)
-            for (int t = 0; t < n; ++t) {
-                const int v = k[t] - tab->modes[r][t];
-                const int w = ((v + h) % N + N) % N - h;
-                j[t] = w;
-                if (first < 0 && w != 0) first = t;
+            int j[NN];
+            int first = NN;  // first axis with a nonzero component of rep(k - m)
+            double wrap = 0.0;
+#pragma unroll
+            for (int t = NN - 1; t >= 0; --t) {
+                int v = k[t] - tab->modes[r][t];
+                if (v > h) {
+                    v -= N;
+                    wrap += pkp[t];
+                } else if (v < -h) {
+                    v += N;
+                    wrap -= pkp[t];
+                }
+                j[t] = v;
+                if (v != 0) first = t;
             }
-            if (first < 0) continue;  // the zero mode: W = 0
+            if (first == NN) continue;  // the zero mode: W = 0
             const bool neg = j[first] < 0;
             // stored index of j (or of -j) and its position
-            int idx = 0;
-            for (int t = 0; t < n; ++t) {
+            int idx = 0, Sj = 1;
+#pragma unroll
+            for (int t = 0; t < NN; ++t) {
                 int a = neg ? -j[t] : j[t];
                 if (a < 0) a += N;
                 idx = idx * N + a;
+                if (t > first) Sj *= N;
             }
-            int Sj = 1;
-            for (int t = first + 1; t < n; ++t) Sj *= N;
             double2 v = u[idx - (Sj - 1) / 2];
             if (neg) v.y = -v.y;
-            double w = 0.0;
-            for (int l = 0; l < d; ++l) {
-                double pj = 0.0;
-                for (int t = 0; t < n; ++t) pj += tab->P[l][t] * (double)j[t];
-                w += pk[l] * pj;
-            }
+            double pkpm = 0.0;
+#pragma unroll
+            for (int l = 0; l < DD; ++l) pkpm += pk[l] * tab->Pm[r][l];
+            // rep(k - m) = k - m + N c, c_t = -1 above the range, +1 below
+            const double w = pk2 - pkpm - (double)N * wrap;
             const double cr = tab->coef[r][0] * w, ci = tab->coef[r][1] * w;
             acc_re += cr * v.x - ci * v.y;
             acc_im += cr * v.y + ci * v.x;
@@ -97,8 +122,22 @@ hipError_t launch_matvec_half(const Table *tab, const Table &ht, const void *u, 
 {
     const int half = (ht.D + 1) / 2;
     const int grid = std::min((half + kBlock - 1) / kBlock, 65536);
-    hipLaunchKernelGGL(k_matvec_half, dim3(grid), dim3(kBlock), 0, s, tab,
-                       static_cast<const double2 *>(u), static_cast<double2 *>(y), half);
+    auto U = static_cast<const double2 *>(u);
+    auto Y = static_cast<double2 *>(y);
+    switch (ht.d * 16 + ht.n) {
+#define QP_DN(DD, NN)                                                                         \
+    case DD * 16 + NN:                                                                         \
+        hipLaunchKernelGGL((k_matvec_half<DD, NN>), dim3(grid), dim3(kBlock), 0, s, tab, U, Y, \
+                           half);                                                              \
+        break;
+#define QP_D(DD) QP_DN(DD, 1) QP_DN(DD, 2) QP_DN(DD, 3) QP_DN(DD, 4) QP_DN(DD, 5) QP_DN(DD, 6) \
+        QP_DN(DD, 7) QP_DN(DD, 8)
+        QP_D(1) QP_D(2) QP_D(3) QP_D(4)
+#undef QP_D
+#undef QP_DN
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
