@@ -64,6 +64,11 @@ def _load():
     lib.qo_pcg.restype = C.c_int
     lib.qo_pcg.argtypes = [pp, C.c_int, dp, dp, C.c_double, C.c_int,
                            C.POINTER(C.c_int), dp]
+    lib.qo_pcg_ex.restype = C.c_int
+    lib.qo_pcg_ex.argtypes = [pp, C.c_int, dp, dp, C.c_double, C.c_int,
+                              C.POINTER(C.c_int), dp, dp]
+    lib.qo_dft_rows.restype = None
+    lib.qo_dft_rows.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_long, C.POINTER(C.c_long), dp]
     lib.qo_corrector_rhs.restype = None
     lib.qo_corrector_rhs.argtypes = [pp, C.c_int, dp]
     lib.qo_astar_flux.restype = C.c_double
@@ -177,6 +182,56 @@ def pcg(prob, F, tol: float = 1e-12, maxit: int = 10000, kind: int = 0):
     st = _load().qo_pcg(b.ref, int(kind), _dptr(F.view(np.float64)), _dptr(U.view(np.float64)),
                         float(tol), int(maxit), C.byref(it), C.byref(rr))
     return U, int(st), int(it.value), float(rr.value)
+
+
+def pcg_lanczos(prob, F, tol: float = 1e-12, maxit: int = 10000, kind: int = 0):
+    """C-PCG as pcg(), also returning the scalars of every step: alpha[j] and
+    the beta[j] that follows step j (beta has iters - 1 entries)."""
+    b = _Bound(prob)
+    F = _cvec(F, b.D).copy()
+    U = np.empty(b.D, dtype=np.complex128)
+    ab = np.zeros(2 * max(1, int(maxit)), dtype=np.float64)
+    it = C.c_int(0)
+    rr = C.c_double(0.0)
+    st = _load().qo_pcg_ex(b.ref, int(kind), _dptr(F.view(np.float64)), _dptr(U.view(np.float64)),
+                           float(tol), int(maxit), C.byref(it), C.byref(rr), _dptr(ab))
+    m = int(it.value)
+    return U, int(st), m, float(rr.value), ab[0:2 * m:2].copy(), ab[1:2 * m - 1:2].copy()
+
+
+def lanczos_kappa(alpha, beta) -> float:
+    """Condition estimate of the preconditioned operator M^(1/2) Q M^(1/2)
+    from C-PCG's scalars: PCG is the Lanczos process in disguise, whose
+    tridiagonal matrix has diagonal 1/alpha_j + beta_(j-1)/alpha_(j-1) and
+    off-diagonal sqrt(beta_j)/alpha_j; the ratio of its extreme eigenvalues
+    (a library eigensolver) approaches the operator's from below."""
+    from scipy.linalg import eigvalsh_tridiagonal
+    alpha = np.asarray(alpha, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)[: max(0, alpha.size - 1)]
+    if alpha.size == 0:
+        return 0.0
+    diag = 1.0 / alpha
+    diag[1:] += beta / alpha[:-1]
+    off = np.sqrt(beta) / alpha[:-1]
+    ev = eigvalsh_tridiagonal(diag, off) if alpha.size > 1 else diag
+    return float(ev.max() / ev.min())
+
+
+def dft_rows(n: int, N: int, x, rows=None, inverse: bool = False) -> np.ndarray:
+    """Discrete Fourier-Bohr transform on T_N^n (Sec. 2.3) at the given storage
+    indices (all D when rows is None), straight from the definition:
+    forward (1/D) sum_j x_j exp(-i k.y_j), inverse sum_k x_k exp(i k.y_j)."""
+    D = int(N) ** int(n)
+    x = _cvec(x, D)
+    rows = np.arange(D, dtype=np.int64) if rows is None else \
+        np.ascontiguousarray(rows, dtype=np.int64).reshape(-1)
+    if rows.size and (rows.min() < 0 or rows.max() >= D):
+        raise ValueError("row index out of range")
+    out = np.empty(rows.size, dtype=np.complex128)
+    _load().qo_dft_rows(int(n), int(N), 1 if inverse else 0, _dptr(x.view(np.float64)),
+                        int(rows.size), rows.ctypes.data_as(C.POINTER(C.c_long)),
+                        _dptr(out.view(np.float64)))
+    return out
 
 
 def corrector_rhs(prob, j: int) -> np.ndarray:

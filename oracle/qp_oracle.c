@@ -271,9 +271,12 @@ static double complex inner(long D, const double complex *x, const double comple
  *   beta = (r+,z+)/(r,z); h = z + beta h;
  * until ||r|| <= tol ||F'||.  Returns 0 on convergence, 1 when maxit steps
  * did not converge, 2 when (Qh,h) <= 0 (Q not positive definite).
- * `iters` = number of U updates performed, `relres` = final ||r||/||F'||. */
-int qo_pcg(const qo_problem *p, int kind, const double *F_, double *U_,
-           double tol, int maxit, int *iters, double *relres)
+ * `iters` = number of U updates performed, `relres` = final ||r||/||F'||.
+ * ab (NULL or 2 maxit doubles): the scalars of every step, alpha of step j
+ * at ab[2j] and the beta that follows it at ab[2j+1] (not written after the
+ * last step). */
+int qo_pcg_ex(const qo_problem *p, int kind, const double *F_, double *U_,
+              double tol, int maxit, int *iters, double *relres, double *ab)
 {
     const long D = qo_size(p->n, p->N);
     double complex *U = (double complex *)U_;
@@ -297,6 +300,7 @@ int qo_pcg(const qo_problem *p, int kind, const double *F_, double *U_,
         const double hq = creal(inner(D, q, h));   /* (Qh, h) */
         if (!(hq > 0.0)) { status = 2; break; }
         const double alpha = rz / hq;
+        if (ab) ab[2 * it] = alpha;
         for (long i = 0; i < D; ++i) {
             U[i] += alpha * h[i];
             r[i] -= alpha * q[i];
@@ -307,6 +311,7 @@ int qo_pcg(const qo_problem *p, int kind, const double *F_, double *U_,
         if (rnorm <= tol * fnorm) { status = 0; break; }
         const double rz_new = creal(inner(D, r, z));
         const double beta = rz_new / rz;
+        if (ab) ab[2 * (it - 1) + 1] = beta;
         rz = rz_new;
         for (long i = 0; i < D; ++i) h[i] = z[i] + beta * h[i];
     }
@@ -315,6 +320,48 @@ done:
     if (relres) *relres = (fnorm > 0.0) ? rnorm / fnorm : 0.0;
     free(r); free(z); free(h); free(q); free(M);
     return status;
+}
+
+int qo_pcg(const qo_problem *p, int kind, const double *F_, double *U_,
+           double tol, int maxit, int *iters, double *relres)
+{
+    return qo_pcg_ex(p, kind, F_, U_, tol, maxit, iters, relres, NULL);
+}
+
+/* Discrete Fourier-Bohr transform on the collocation grid T_N^n (Sec. 2.3):
+ * the coefficients of values f_j sampled at y_j = 2 pi j / N (j in
+ * {0..N-1}^n) are  Fhat_k = (1/D) sum_j f_j exp(-i k.y_j),  and the samples
+ * of a coefficient vector are  f_j = sum_k Fhat_k exp(i k.y_j).  Both vectors
+ * are in the storage order of Sec. 3.1.2 (entry i holds the multi-index with
+ * digits of i in base N, first axis slowest; for coefficients the digits are
+ * k mod N, which gives the same exp(i k.y_j)).  The phase k.y_j is taken as
+ * 2 pi ((sum_t k_t j_t) mod N) / N with the integer product reduced exactly.
+ * Evaluated straight from the definition, one output at a time (O(D) per
+ * output): out[r] is the transform at storage index rows[r]. */
+void qo_dft_rows(int n, int N, int inverse, const double *in_, long nrows, const long *rows,
+                 double *out_)
+{
+    const double complex *in = (const double complex *)in_;
+    double complex *out = (double complex *)out_;
+    const long D = qo_size(n, N);
+    const double sign = inverse ? 1.0 : -1.0;
+    const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long r = 0; r < nrows; ++r) {
+        int k[8], j[8];
+        long i = rows[r];
+        for (int t = n - 1; t >= 0; --t) { k[t] = (int)(i % N); i /= N; }
+        double complex acc = 0.0;
+        for (long s = 0; s < D; ++s) {
+            long rest = s;
+            for (int t = n - 1; t >= 0; --t) { j[t] = (int)(rest % N); rest /= N; }
+            long ph = 0;
+            for (int t = 0; t < n; ++t) ph = (ph + (long)k[t] * j[t]) % N;
+            const double th = sign * two_pi * (double)ph / (double)N;
+            acc += in[s] * (cos(th) + I * sin(th));
+        }
+        out[r] = inverse ? acc : acc / (double)D;
+    }
 }
 
 /* Right-hand side of the corrector equation -div(a(e_j + grad chi)) = 0, i.e.

@@ -27,6 +27,9 @@ CASES = {
     # d = 3 icosahedral field at N = 10: 1,000,000 unknowns (not a power of two),
     # three correctors
     "icosa_N10": lambda: W.icosahedral(10),
+    # the largest serving request and the HBM-sized product shape: d = 3,
+    # n = 6, N = 16 (16,777,216 unknowns), three correctors
+    "icosa_N16": lambda: W.icosahedral(16),
 }
 
 

@@ -366,3 +366,83 @@ def test_corrector_conjugation_symmetry_needs_odd_N(make):
             assert gap <= 1e-12, (N, gap)
         else:
             assert gap >= 1e-3, (N, gap)
+
+
+# ---------------------------------------------------------------- condition estimate
+
+@pytest.mark.parametrize("prob", [W.eightfold_random(6, 1), W.one_d_two_mode(16, 2.0),
+                                  W.icosahedral(3), W.eightfold(5)],
+                         ids=lambda p: f"{p.name}_N{p.N}")
+def test_lanczos_kappa_matches_dense_spectrum(prob):
+    """The condition estimate from the PCG scalars (Lanczos tridiagonal) against
+    the eigenvalues of M^(1/2) Q M^(1/2) on k != 0, Q assembled entry by entry
+    (Alg. 1) and M the Frobenius-optimal diagonal (pinned above)."""
+    Q = ind.dense_Q(prob)[1:, 1:]
+    M = oracle.precond(prob, 0)[1:]
+    ev = np.linalg.eigvalsh(np.sqrt(M)[:, None] * Q * np.sqrt(M)[None, :])
+    exact = ev[-1] / ev[0]
+    F = W.random_vector(prob.D, seed=5)
+    _, st, it, _, al, be = oracle.pcg_lanczos(prob, F, tol=1e-12)
+    assert st == 0 and al.size == it and be.size == it - 1
+    k = oracle.lanczos_kappa(al, be)
+    # Ritz values lie inside the spectrum, and a random right-hand side run to
+    # 1e-12 resolves both ends
+    assert k <= exact * (1 + 1e-8)
+    assert k >= exact * (1 - 1e-2), (k, exact)
+
+
+def test_lanczos_kappa_constant_coefficient_is_one():
+    # constant coefficient: M is the exact inverse of the diagonal Q, one step
+    base = W.eightfold(5)
+    keep = [i for i, m in enumerate(base.modes) if not np.any(m)]
+    prob = W.Problem("const", base.d, base.n, base.N, base.P, base.modes[keep], base.coef[keep])
+    F = W.random_vector(prob.D, seed=2)
+    _, st, it, _, al, be = oracle.pcg_lanczos(prob, F, tol=1e-12)
+    assert st == 0 and it == 1
+    assert oracle.lanczos_kappa(al, be) == pytest.approx(1.0, abs=1e-12)
+    assert al[0] == pytest.approx(1.0, abs=1e-12)
+
+
+# ---------------------------------------------------------------- sampled inputs
+
+@pytest.mark.parametrize("n,N", [(1, 7), (2, 6), (3, 5), (2, 9)])
+def test_dft_matches_library_fft(n, N):
+    """The direct-sum transform (Sec. 2.3) against numpy's FFT (an independent
+    library routine), both directions."""
+    x = W.random_vector(N ** n, seed=10 * n + N)
+    f = oracle.dft_rows(n, N, x)
+    ref = np.fft.fftn(x.reshape((N,) * n)).reshape(-1) / N ** n
+    assert np.abs(f - ref).max() <= 1e-14 * np.abs(ref).max() * N
+    b = oracle.dft_rows(n, N, x, inverse=True)
+    refb = np.fft.ifftn(x.reshape((N,) * n)).reshape(-1) * N ** n
+    assert np.abs(b - refb).max() <= 1e-14 * np.abs(refb).max() * N
+
+
+@pytest.mark.parametrize("n,N,m", [(2, 8, (3, -2)), (3, 5, (-2, 0, 1)), (1, 12, (-6,))])
+def test_dft_single_mode_closed_form(n, N, m):
+    """Samples of exp(i m.y) have the one coefficient 1 at C(m) (discrete
+    orthogonality, Sec. 2.3); the inverse transform of that unit vector gives
+    the samples back."""
+    D = N ** n
+    K = ind.signed_indices(n, N)
+    y = 2 * np.pi * np.stack(np.meshgrid(*([np.arange(N)] * n), indexing="ij"), -1).reshape(D, n) / N
+    samples = np.exp(1j * (y @ np.array(m, dtype=float)))
+    f = oracle.dft_rows(n, N, samples)
+    i = oracle.index(n, N, m)
+    e = np.zeros(D, complex)
+    e[i] = 1.0
+    assert np.abs(f - e).max() <= 1e-14 * N * n
+    assert np.abs(oracle.dft_rows(n, N, e, inverse=True) - samples).max() <= 1e-14 * N * n
+    assert tuple(K[i]) == tuple(oracle.multi_index(n, N, i))
+
+
+def test_dft_round_trip_parseval_and_rows():
+    n, N = 3, 6
+    D = N ** n
+    x = W.random_vector(D, seed=77)
+    f = oracle.dft_rows(n, N, x)
+    # Parseval: sum |x_j|^2 = D sum |f_k|^2
+    assert np.sum(np.abs(x) ** 2) == pytest.approx(D * np.sum(np.abs(f) ** 2), rel=1e-13)
+    assert np.abs(oracle.dft_rows(n, N, f, inverse=True) - x).max() <= 1e-13 * np.abs(x).max()
+    rows = np.array([0, 5, 37, D - 1])
+    assert np.array_equal(oracle.dft_rows(n, N, x, rows=rows), f[rows])
