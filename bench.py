@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "corrector solves/s + matvec HBM GB/s, FP32-IR vs FP64 @1e-10; p99 latency"
 HBM_PEAK_GBS = 8000.0
 TOL = 1e-12
+LATENCY_SAMPLES = 200  # homogenizations behind the latency percentiles
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_fp32_eightfold_n4_N32.txt")
 # sources of the stiffness-product kernels (the product and its device helpers)
 MATVEC_SRC = [os.path.join(ROOT, "paper_2404_06841_amd", "csrc", f)
@@ -274,108 +275,155 @@ def diagonal_workload(torch, np, qp, W, gold, steps: int, warmup: int):
 
 def batch_instances(torch, np, qp, W, reps: int = 3):
     """64 seeded eightfold instances with N drawn from {8, 12, 16, 24, 32}
-    (16.2M unknowns for the default seed), two correctors each, FP32-IR:
+    (16.2M unknowns for the default seed), two correctors each.  FP32-IR:
     homogenized together by qp_homogenized_grouped (one launch per solver
     step for all 64), by qp_homogenized_batch (each problem on its own
-    stream), and one after another, on the same problems."""
+    stream), and one after another, on the same problems.  FP64 (the
+    comparison leg): the same instances by qp_homogenized_batch and one after
+    another.  Grouped and stream results are compared with the sequential
+    ones bitwise, and the instances with N <= 12 with the oracle."""
+    import oracle
     probs = W.eightfold_batch(64)
-    gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream(), autotune=True)
-           for pr in probs]
     solves = sum(pr.d for pr in probs)
-    qp.homogenized_batch(gps, tol=TOL)  # warm-up (graphs, caches)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        As, _, st = qp.homogenized_batch(gps, tol=TOL)
-    dt_b = (time.perf_counter() - t0) / reps
-    qp.homogenized_batch(gps, tol=TOL, grouped=True)  # warm-up (group tables)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        Ag, _, stg = qp.homogenized_batch(gps, tol=TOL, grouped=True)
-    dt_g = (time.perf_counter() - t0) / reps
-    seq = [gp.homogenized(tol=TOL, energy=False).A.copy() for gp in gps]
-    t0 = time.perf_counter()
-    for _ in range(reps):
+    out = {}
+    for prec in ("fp32ir", "fp64"):
+        gps = [qp.Problem(pr, precision=prec, stream=torch.cuda.Stream(), autotune=True)
+               for pr in probs]
+        qp.homogenized_batch(gps, tol=TOL)  # warm-up (graphs, caches)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            As, _, st = qp.homogenized_batch(gps, tol=TOL)
+        dt_b = (time.perf_counter() - t0) / reps
+        if prec == "fp32ir":
+            qp.homogenized_batch(gps, tol=TOL, grouped=True)  # warm-up (group tables)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                Ag, _, stg = qp.homogenized_batch(gps, tol=TOL, grouped=True)
+            dt_g = (time.perf_counter() - t0) / reps
+        seq = [gp.homogenized(tol=TOL, energy=False).A.copy() for gp in gps]
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for gp in gps:
+                gp.homogenized(tol=TOL, energy=False)
+        dt_s = (time.perf_counter() - t0) / reps
+        leg = {"streams_value": round(solves / dt_b, 2), "streams_ms": round(dt_b * 1e3, 3),
+               "streams_status": int(st),
+               "streams_results_equal_sequential": all(np.array_equal(a, b) for a, b in zip(As, seq)),
+               "sequential_value": round(solves / dt_s, 2), "sequential_ms": round(dt_s * 1e3, 3),
+               "streams_speedup_vs_sequential": round(dt_s / dt_b, 3)}
+        if prec == "fp32ir":
+            diff = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(Ag, seq))
+            leg.update({"grouped_value": round(solves / dt_g, 2), "grouped_ms": round(dt_g * 1e3, 3),
+                        "grouped_status": int(stg),
+                        "grouped_results_equal_sequential": all(np.array_equal(a, b)
+                                                                for a, b in zip(Ag, seq)),
+                        "grouped_max_rel_diff_vs_sequential": diff,
+                        "grouped_speedup_vs_sequential": round(dt_s / dt_g, 3)})
+            leg["value"] = round(solves / min(dt_g, dt_b), 2)
+            leg["what"] = "the faster of grouped_value and streams_value"
+            # the grouped A* against the oracle for the small instances
+            small = [i for i, pr in enumerate(probs) if pr.N <= 12][:6]
+            errs = []
+            for i in small:
+                ref = oracle.homogenize(probs[i], tol=TOL).A
+                errs.append(float(np.abs(Ag[i] - ref).max() / np.abs(ref).max()))
+            leg["grouped_astar_rel_err_vs_oracle"] = {
+                "instances": [f"#{i} N={probs[i].N}" for i in small], "max": max(errs)}
+        else:
+            leg["value"] = leg["streams_value"]
+            leg["what"] = "streams_value"
         for gp in gps:
-            gp.homogenized(tol=TOL, energy=False)
-    dt_s = (time.perf_counter() - t0) / reps
-    same = all(np.array_equal(a, b) for a, b in zip(As, seq))
-    same_g = all(np.array_equal(a, b) for a, b in zip(Ag, seq))
-    for gp in gps:
-        gp.close()
+            gp.close()
+        out[prec] = leg
     Ns = sorted(set(int(pr.N) for pr in probs))
-    return {"workload": f"64 seeded eightfold d=2 n=4 instances, N in {Ns} "
-                        f"({sum(pr.D for pr in probs):,} unknowns), 2 correctors each, FP32-IR",
-            "value": round(solves / min(dt_g, dt_b), 2), "unit": "corrector solves/s",
-            "what": "the faster of grouped_value and streams_value",
-            "grouped_value": round(solves / dt_g, 2), "grouped_ms": round(dt_g * 1e3, 3),
-            "grouped_status": int(stg), "grouped_results_equal_sequential": bool(same_g),
-            "streams_value": round(solves / dt_b, 2), "streams_ms": round(dt_b * 1e3, 3),
-            "streams_status": int(st), "streams_results_equal_sequential": bool(same),
-            "sequential_value": round(solves / dt_s, 2),
-            "sequential_ms": round(dt_s * 1e3, 3),
-            "grouped_speedup_vs_sequential": round(dt_s / dt_g, 3),
-            "streams_speedup_vs_sequential": round(dt_s / dt_b, 3)}
+    res = {"workload": f"64 seeded eightfold d=2 n=4 instances, N in {Ns} "
+                       f"({sum(pr.D for pr in probs):,} unknowns), 2 correctors each",
+           "unit": "corrector solves/s"}
+    res.update(out["fp32ir"])
+    res["fp64"] = out["fp64"]
+    res["fp32ir_over_fp64"] = round(out["fp32ir"]["value"] / out["fp64"]["value"], 3)
+    return res
 
 
-def serving(torch, np, qp, W, requests: int = 42, load: float = 0.8):
-    """Homogenization requests served by qp_server (FP32-IR): icosahedral d=3
-    n=6 problems at N = 6, 8, 12, 16 mixed with eightfold n=4 problems at
-    N = 16, 24, 32, drawn uniformly (seeded).  Capacity is measured with all
-    requests queued at once; then the same mix arrives as a seeded Poisson
-    stream at `load` times that capacity, and each request's latency (arrival
-    to result) is recorded."""
+def serving(torch, np, qp, W, requests: int = 400, load: float = 0.8):
+    """Homogenization requests served by qp_server: icosahedral d=3 n=6
+    problems at N = 6, 8, 12, 16 mixed with eightfold n=4 problems at
+    N = 16, 24, 32, drawn uniformly (seeded).  For each precision (FP32-IR,
+    then FP64 as the comparison leg): capacity with all requests queued at
+    once, then the same mix as a seeded Poisson stream at `load` times that
+    capacity, with each request's latency (arrival to result); then FP32-IR
+    again under an HBM budget that holds only a few of the problems, so that
+    admission waits for idle problems to be evicted."""
     kinds = [W.icosahedral(6), W.icosahedral(8), W.icosahedral(12), W.icosahedral(16),
-               W.eightfold_random(16, 11), W.eightfold_random(24, 12),
-               W.eightfold_random(32, 13)]
+             W.eightfold_random(16, 11), W.eightfold_random(24, 12),
+             W.eightfold_random(32, 13)]
     rng = np.random.default_rng(W.BASE_SEED + 77)
     mix = [int(i) for i in rng.integers(0, len(kinds), size=requests)]
-    srv = qp.Server(96 << 30, precision="fp32ir", autotune=True)
-
-    def drain(tickets):
-        left, fin = set(tickets), {}
-        while left:
-            for t in srv.progress(wait_us=1000):
-                if t in left:
-                    left.discard(t)
-                    fin[t] = time.perf_counter()
-        return fin
-
-    drain([srv.submit(c, tol=TOL) for c in kinds])  # every problem created once
-    t0 = time.perf_counter()
-    drain([srv.submit(kinds[i], tol=TOL) for i in mix])
-    cap = requests / (time.perf_counter() - t0)
-    gaps = rng.exponential(1.0 / (load * cap), size=requests)
-    arrive, submitted, finish, tickets = np.cumsum(gaps), {}, {}, []
-    t0 = time.perf_counter()
-    k = 0
-    while len(finish) < requests:
-        now = time.perf_counter() - t0
-        while k < requests and arrive[k] <= now:
-            t = srv.submit(kinds[mix[k]], tol=TOL)
-            submitted[t] = t0 + arrive[k]
-            tickets.append(t)
-            k += 1
-        wait = 1000 if k >= requests else int(max(50.0, min(1000.0, (arrive[k] - now) * 1e6)))
-        for t in srv.progress(wait_us=wait):
-            finish[t] = time.perf_counter()
-    span = max(finish.values()) - t0
-    lat = np.array([(finish[t] - submitted[t]) * 1e3 for t in tickets])
-    bad = sum(1 for t in tickets if srv.result(t)[2] != qp.QP_OK)
+    gaps01 = rng.exponential(1.0, size=requests)  # unit-rate arrivals, scaled per run
     solves = sum(kinds[i].d for i in mix)
-    cached = srv.bytes()
-    srv.close()
-    return {"workload": f"{requests} homogenization requests, icosahedral N 6/8/12/16 and eightfold "
-                        "N 16/24/32 mixed uniformly; Poisson arrivals (seeded) at "
-                        f"{load} x measured capacity; FP32-IR",
-            "capacity_requests_per_s": round(cap, 2),
-            "offered_requests_per_s": round(load * cap, 2),
-            "value": round(solves / span, 2), "unit": "corrector solves/s",
-            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
-                           "p99": round(float(np.percentile(lat, 99)), 3),
-                           "max": round(float(lat.max()), 3)},
-            "failed": bad, "cached_problem_bytes": int(cached)}
+
+    def run(precision: str, budget: int, capacity=None):
+        srv = qp.Server(budget, precision=precision, autotune=True)
+
+        def drain(tickets):
+            left, fin = set(tickets), {}
+            while left:
+                for t in srv.progress(wait_us=1000):
+                    if t in left:
+                        left.discard(t)
+                        fin[t] = time.perf_counter()
+            return fin
+
+        drain([srv.submit(c, tol=TOL) for c in kinds])  # every problem created once
+        if capacity is None:
+            t0 = time.perf_counter()
+            drain([srv.submit(kinds[i], tol=TOL) for i in mix])
+            capacity = requests / (time.perf_counter() - t0)
+        arrive = np.cumsum(gaps01 / (load * capacity))
+        submitted, finish, tickets = {}, {}, []
+        t0 = time.perf_counter()
+        k = 0
+        while len(finish) < requests:
+            now = time.perf_counter() - t0
+            while k < requests and arrive[k] <= now:
+                t = srv.submit(kinds[mix[k]], tol=TOL)
+                submitted[t] = t0 + arrive[k]
+                tickets.append(t)
+                k += 1
+            wait = 1000 if k >= requests else int(max(50.0, min(1000.0, (arrive[k] - now) * 1e6)))
+            for t in srv.progress(wait_us=wait):
+                finish[t] = time.perf_counter()
+        span = max(finish.values()) - t0
+        lat = np.array([(finish[t] - submitted[t]) * 1e3 for t in tickets])
+        bad = sum(1 for t in tickets if srv.result(t)[2] != qp.QP_OK)
+        cached = srv.bytes()
+        srv.close()
+        return {"capacity_requests_per_s": round(capacity, 2),
+                "capacity_solves_per_s": round(solves / requests * capacity, 2),
+                "offered_requests_per_s": round(load * capacity, 2),
+                "value": round(solves / span, 2), "unit": "corrector solves/s",
+                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                               "p99": round(float(np.percentile(lat, 99)), 3),
+                               "max": round(float(lat.max()), 3), "samples": int(lat.size)},
+                "failed": bad, "cached_problem_bytes": int(cached)}
+
+    res = {"workload": f"{requests} homogenization requests, icosahedral N 6/8/12/16 and eightfold "
+                       "N 16/24/32 mixed uniformly; Poisson arrivals (seeded) at "
+                       f"{load} x the measured capacity of each precision"}
+    r32 = run("fp32ir", 96 << 30)
+    res.update(r32)
+    res["fp64"] = run("fp64", 96 << 30)
+    res["fp32ir_over_fp64_capacity"] = round(r32["capacity_requests_per_s"] /
+                                             res["fp64"]["capacity_requests_per_s"], 3)
+    # a budget of 4 GiB holds the icosahedral N = 16 problem (2.4 GB) and a few
+    # small ones, not all seven: requests wait for evictions
+    budget = 4 << 30
+    tight = run("fp32ir", budget, capacity=r32["capacity_requests_per_s"])
+    tight["hbm_budget_bytes"] = budget
+    res["tight_budget"] = tight
+    return res
 
 
 def cpu_baseline(prob):
@@ -447,6 +495,9 @@ def main():
     err_ir = float(np.abs(r.A - A_ref).max() / np.abs(A_ref).max())
     solves = prob.d * args.steps
     value = solves / dt
+    # latency percentiles over more samples than the timed steps (outside the
+    # timed region; each homogenization timed on its own)
+    _, lat, _, _ = run_steps(gp, LATENCY_SAMPLES, torch)
 
     # the same steps with every float stiffness product bracketed by HIP events
     # on the library's stream (profiled batches are launched directly)
@@ -467,7 +518,8 @@ def main():
     layout64 = gp.layout()
     for _ in range(args.warmup):
         gp.homogenized(tol=TOL, energy=False)
-    dt64, lat64, r64, _ = run_steps(gp, args.steps, torch)
+    dt64, _, r64, _ = run_steps(gp, args.steps, torch)
+    _, lat64, _, _ = run_steps(gp, LATENCY_SAMPLES, torch)
     err_64 = float(np.abs(r64.A - A_ref).max() / np.abs(A_ref).max())
     chi64 = [gp.corrector_d(j, tol=TOL)[0] for j in range(prob.d)]
     gp.close()
@@ -515,7 +567,8 @@ def main():
                    "N": 32, "n": 4, "d": 2, "unknowns": D, "modes": int(prob.g), "tol": TOL,
                    "precision": "fp32-ir", "parallelism": "single GPU"},
         "astar_rel_err": err_ir,
-        "latency_ms": {"what": "one homogenization (both corrector solves + A*)",
+        "latency_ms": {"what": "one homogenization (both corrector solves + A*), "
+                               f"{len(lat_sorted)} samples",
                        "p50": round(float(np.percentile(lat_sorted, 50)), 4),
                        "p99": round(float(np.percentile(lat_sorted, 99)), 4)},
         "fp64": {"value": round(solves / dt64, 2), "ms_per_step": round(dt64 / args.steps * 1e3, 4),

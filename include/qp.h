@@ -67,7 +67,8 @@ enum { QP_PRECOND_PAPER = 0, QP_PRECOND_JACOBI = 1 };
 /* qp_solve_info.flags bits */
 enum {
     QP_FLAG_DEGENERATE = 1,  /* min of A on the grid is 0 (within 1e-12 max|A|)  */
-    QP_FLAG_F0_IGNORED = 2   /* |rhs[C(0)]| > 1e-14 ||rhs||; it was ignored       */
+    QP_FLAG_F0_IGNORED = 2,  /* |rhs[C(0)]| > 1e-14 ||rhs||; it was ignored       */
+    QP_FLAG_INDEFINITE = 4   /* A is negative on the grid (allow_indefinite)    */
 };
 
 typedef struct qp_options {
@@ -114,6 +115,12 @@ typedef struct qp_options {
                            which workgroup sums which partial dot product does,
                            so iterates can differ from an untuned problem's in
                            the last bits.  Default 0 (fixed heuristics)      */
+    int allow_indefinite; /* nonzero: qp_create accepts a coefficient that is
+                           negative on the collocation grid (flag
+                           QP_FLAG_INDEFINITE) instead of failing with
+                           QP_ENOTELLIPTIC.  Q is then indefinite and a solve
+                           may stop with QP_ENOTSPD ((Q h, h) <= 0, Alg. 2
+                           breakdown; u holds the last iterate); default 0  */
 } qp_options;
 
 typedef struct qp_solve_info {
@@ -131,6 +138,23 @@ typedef struct qp_solve_info {
     int matvec_rhs;       /* profile only: right-hand sides those FP64 launches
                              served (a launch serves every unfinished one)       */
     int matvec32_rhs;     /* the same for the float launches                     */
+    double kappa_est;     /* condition estimate of the preconditioned operator
+                             M^(1/2) Q M^(1/2): the ratio of the extreme
+                             eigenvalues of the Lanczos tridiagonal matrix that
+                             the PCG coefficients define (diagonal 1/alpha_j +
+                             beta_(j-1)/alpha_(j-1), off-diagonal
+                             sqrt(beta_j)/alpha_j; the first 1024 iterations;
+                             FP32-IR: the float iterations, each run between
+                             two residual replacements a separate Lanczos
+                             segment).  It approaches the true ratio from below
+                             as the iterations grow (Sec. 4.3 discusses
+                             cond(QM)); 0 when no iteration ran               */
+    double bytes_moved;   /* algorithmic device bytes of the solve's kernels for
+                             this right-hand side: each vector a kernel touches
+                             read or written once (16 B per FP64 complex entry,
+                             8 B float; 8 / 4 B per preconditioner entry), from
+                             the iteration and replacement counts; cache and
+                             refetch traffic are not counted                   */
 } qp_solve_info;
 
 /* Work layout of the stiffness product (see qp_options.autotune): one for
@@ -431,13 +455,15 @@ qp_status qp_modes_from_spectrum(int n, int N, const double *spec, double rel_to
  */
 int64_t qp_coo_entries(const qp_problem *p);
 qp_status qp_coo_build_d(qp_problem *p, int32_t *rows, int32_t *cols, double *vals);
-/* y = Q u from the triples of qp_coo_build_d (FP64; u, y: D complex, device). */
+/* y = Q u from the triples of qp_coo_build_d (FP64; u, y: D complex, device,
+ * not overlapping: QP_EINVAL). */
 qp_status qp_coo_matvec_d(qp_problem *p, const int32_t *cols, const double *vals, const double *u,
                           double *y);
 
 /* ---- single steps of the path, device pointers (used by parity tests) ---- */
 
-/* y = Q u in FP64 (eq. linear_system; y[C(0)] = 0, u[C(0)] ignored). */
+/* y = Q u in FP64 (eq. linear_system; y[C(0)] = 0, u[C(0)] ignored).  u and
+ * y must not overlap (QP_EINVAL): every output reads the neighbours of u. */
 qp_status qp_matvec_d(qp_problem *p, const double *u, double *y);
 /* y = Q u in FP64 on Hermitian half storage (Sec. 2.3: the coefficients of a
  * real function satisfy u_{-k} = conj(u_k); the coefficient is real, so Q
@@ -448,9 +474,11 @@ qp_status qp_matvec_d(qp_problem *p, const double *u, double *y);
  * a_t in [1, (N-1)/2], i.e. the index range [S_t, (N+1)/2 S_t) with
  * S_t = N^(n-t), index i at position i - (S_t - 1)/2.  Those are the k != 0
  * whose first nonzero component is positive; k's partner -k is implied.
- * Reads and writes half the bytes of qp_matvec_d; synchronous. */
+ * Its algorithmic bytes (u read once, y written once) are half those of
+ * qp_matvec_d.  u and y must not overlap (QP_EINVAL); synchronous. */
 qp_status qp_matvec_half_d(qp_problem *p, const double *u, double *y);
-/* y = Q u with float data and arithmetic (the FP32-IR inner product). */
+/* y = Q u with float data and arithmetic (the FP32-IR inner product); u and
+ * y (D float complex each) must not overlap (QP_EINVAL). */
 qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y);
 /* The diagonal preconditioner (eq. precond; kind per the options), D doubles. */
 qp_status qp_precond_d(qp_problem *p, double *M);

@@ -59,6 +59,14 @@ constexpr size_t kMaxGraphs = 16;           // instantiated batch graphs kept pe
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Whether [a, a + bytes) and [b, b + bytes) share a byte (addresses compared
+// as integers, so buffers of different allocations never match).
+bool overlaps(const void *a, const void *b, size_t bytes)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
 // The stiffness product tiles planes (S lines per wave) when n >= 2 and
 // N <= 32; its units are then the N^(n-2) planes.
 bool plane_tiles(int n, int N) { return n >= 2 && N <= 32; }
@@ -73,7 +81,8 @@ int64_t plane_units(int n, int N)
 
 // Offsets of every device buffer inside the workspace.
 struct Layout {
-    size_t F, U, r, h, q, M64, M32, x32, r32, h32, q32, chi, parts, states, small, exec, tab, recs;
+    size_t F, U, r, h, q, M64, M32, x32, r32, h32, q32, chi, parts, states, hist, small, exec, tab,
+        recs;
     size_t urec[2], upku[2];  // unit records and unit P k, by precision (plane tiles)
     size_t total;
 };
@@ -103,6 +112,7 @@ Layout make_layout(int d, int n, int N, int64_t D, int g)
     L.chi = take(c64 * (size_t)d);
     L.parts = take(3 * sizeof(double) * qp::kMaxRhs * qp::kPartStride);
     L.states = take(qp::kMaxRhs * sizeof(State));
+    L.hist = take(sizeof(double) * 2 * qp::kHist * qp::kMaxRhs);
     L.small = take(sizeof(double) * 128);
     L.exec = take(sizeof(int) * kExecInts);
     L.tab = take(sizeof(Table));
@@ -134,6 +144,7 @@ struct qp_problem {
     State *hstate = nullptr;   // pinned: two polling slots + final, kMaxRhs states each
     double *hsmall = nullptr;  // pinned
     int *hexec = nullptr;      // pinned copy of the execution log
+    double *hhist = nullptr;   // pinned copy of the Lanczos coefficients (kMaxRhs x kHist pairs)
     std::vector<hipEvent_t> ev_hot, ev_res;  // profiling events (begin, end pairs)
     struct Graph {
         bool ir;
@@ -167,6 +178,7 @@ struct qp_problem {
         return qp::Parts{p, p + stride, p + 2 * stride};
     }
     State *st() const { return at<State>(L.states); }
+    double *hist(int r) const { return at<double>(L.hist) + (size_t)2 * qp::kHist * r; }
     double *small() const { return at<double>(L.small); }
     int *exec_hot() const { return at<int>(L.exec); }
     int *exec_res() const { return at<int>(L.exec) + 2 * kMaxBatch; }
@@ -437,6 +449,7 @@ void release(qp_problem *p)
     if (p->hstate) (void)hipHostFree(p->hstate);
     if (p->hsmall) (void)hipHostFree(p->hsmall);
     if (p->hexec) (void)hipHostFree(p->hexec);
+    if (p->hhist) (void)hipHostFree(p->hhist);
     if (p->own_ws && p->ws) (void)hipFree(p->ws);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
@@ -584,6 +597,93 @@ qp_status queue_batch(qp_problem *p, bool ir, int K, double *U, const double *rh
     return QP_OK;
 }
 
+// Queue the copy of the K right-hand sides' Lanczos coefficients to pinned
+// memory (behind everything queued on the problem's stream).
+qp_status queue_hist(qp_problem *p, int K, hipStream_t s)
+{
+    QP_HIP(hipMemcpyAsync(p->hhist, p->hist(0), sizeof(double) * 2 * qp::kHist * K,
+                          hipMemcpyDeviceToHost, s));
+    return QP_OK;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a[0..m) and off-diagonal b[0..m-1) (Sturm sequence of the LDL^T
+// pivots: the count of negative pivots).
+int sturm_count(const std::vector<double> &a, const std::vector<double> &b, double x)
+{
+    const int m = (int)a.size();
+    int neg = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+        const double off = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
+        q = (a[i] - x) - ((i > 0) ? off / q : 0.0);
+        if (q == 0.0) q = -1e-300;  // a zero pivot counts as negative (x is an eigenvalue)
+        if (q < 0.0) ++neg;
+    }
+    return neg;
+}
+
+// Condition estimate of the preconditioned operator from the first m PCG
+// coefficients: the Lanczos matrix of C-PCG (Alg. 2) has diagonal
+// 1/alpha_j + beta_{j-1}/alpha_{j-1} and off-diagonal sqrt(beta_j)/alpha_j;
+// its extreme eigenvalues (by bisection) approach those of M^(1/2) Q M^(1/2)
+// from inside.  ab: (alpha_j, beta_j) pairs.  0 when m < 1 or a coefficient
+// is not positive and finite.
+double lanczos_kappa(const double *ab, int m)
+{
+    if (m < 1) return 0.0;
+    std::vector<double> a(m), b(m > 1 ? m - 1 : 0);
+    for (int j = 0; j < m; ++j) {
+        const double al = ab[2 * j];
+        if (!(al > 0.0) || !std::isfinite(al)) return 0.0;
+        a[j] = 1.0 / al;
+        if (j > 0) a[j] += ab[2 * (j - 1) + 1] / ab[2 * (j - 1)];
+        if (j + 1 < m) {
+            const double be = ab[2 * j + 1];
+            if (!(be >= 0.0) || !std::isfinite(be)) return 0.0;
+            b[j] = std::sqrt(be) / al;
+        }
+    }
+    // Gershgorin interval
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+        const double r = ((i > 0) ? std::fabs(b[i - 1]) : 0.0) + ((i + 1 < m) ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto kth = [&](int k) {  // the k-th smallest eigenvalue (k = 1 .. m)
+        double l = lo, h = hi;
+        for (int it = 0; it < 200 && h - l > 1e-15 * std::max(std::fabs(l), std::fabs(h)); ++it) {
+            const double mid = 0.5 * (l + h);
+            if (sturm_count(a, b, mid) >= k) h = mid; else l = mid;
+        }
+        return 0.5 * (l + h);
+    };
+    const double emin = kth(1), emax = kth(m);
+    return (emin > 0.0) ? emax / emin : 0.0;
+}
+
+// Algorithmic device bytes a solve's kernels move for one right-hand side of
+// D unknowns: every vector a kernel touches is read or written once (FP64
+// complex 16 B, float complex 8 B, the preconditioner 8 B / 4 B); cache and
+// refetch traffic are not included.
+double solve_bytes(bool ir, double D, int iters, int replacements)
+{
+    if (!ir) {
+        // init: read f, M; write U, r, h.  Iteration: product (read h, write
+        // q), update (read r, q, M; write r), direction (read r, M, h, U;
+        // write h, U); the last direction only adds alpha h to U.
+        double b = 72.0;
+        if (iters > 0) b += 88.0 * iters + 88.0 * (iters - 1) + 48.0;
+        return b * D;
+    }
+    // ||f'|| (read f); init (read f, M; write X, x, r, h); float iteration:
+    // product 16, update 28, direction 44; replacement: fold (read X, x;
+    // write X, x), FP64 residual (read X, f, M; write float r), direction
+    // (read r, M, h; write h).
+    return (16.0 + 60.0 + 88.0 * iters + 120.0 * replacements) * D;
+}
+
 // Double-buffered polling: after each batch the K states (and, when
 // profiling, the batch's execution log) are copied to pinned memory; the
 // batch before the newest is inspected, so the device always has queued work.
@@ -687,6 +787,7 @@ struct Poller {
     {
         QP_HIP(hipMemcpyAsync(host_states(2), p->st(), sizeof(State) * K, hipMemcpyDeviceToHost,
                               p->stream));
+        QP_TRY(queue_hist(p, K, p->stream));
         return QP_OK;
     }
     // After the final copy has arrived: account the polls never inspected.
@@ -976,6 +1077,9 @@ struct SolveJob {
             info->rel_resid =
                 ir ? std::sqrt(st[r].rr) : (st[r].rr0 > 0 ? std::sqrt(st[r].rr / st[r].rr0) : 0.0);
             info->seconds = ms * 1e-3;
+            info->kappa_est =
+                lanczos_kappa(p->hhist + (size_t)2 * qp::kHist * r, std::min(st[r].iters, qp::kHist));
+            info->bytes_moved = solve_bytes(ir, (double)p->host.D, st[r].iters, info->outer_iters);
             if (prof) {
                 if (ir) {
                     info->matvec32_ms = pf.hot_ms;
@@ -1520,7 +1624,9 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     if (hipHostMalloc(&p->hstate, 3 * qp::kMaxRhs * sizeof(State), hipHostMallocDefault) !=
             hipSuccess ||
         hipHostMalloc(&p->hsmall, 128 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&p->hexec, kExecInts * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc(&p->hexec, kExecInts * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&p->hhist, sizeof(double) * 2 * qp::kHist * qp::kMaxRhs,
+                      hipHostMallocDefault) != hipSuccess)
         return bail(fail(QP_ENOMEM, "pinned host allocation failed"));
     for (auto &e : p->ev_poll)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
@@ -1532,6 +1638,9 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     p->tab = p->at<Table>(p->L.tab);
     if (hipMemcpyAsync(p->tab, &p->host, sizeof(Table), hipMemcpyHostToDevice, p->stream) != hipSuccess)
         return bail(fail(QP_EDEVICE, "table upload failed"));
+    // each state's Lanczos-coefficient slice (the state resets keep it)
+    if (qp::launch_state_hist(p->st(), p->hist(0), p->stream) != hipSuccess)
+        return bail(fail(QP_EDEVICE, "state set-up failed"));
     build_mode_records(p->host, p->recs_host);
     if (hipMemcpyAsync(const_cast<qp::ModeRec *>(p->recs()), p->recs_host.data(),
                        sizeof(qp::ModeRec) * p->recs_host.size(), hipMemcpyHostToDevice,
@@ -1549,8 +1658,11 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     if (!(p->pkmin >= 1e-24 * pn))
         return bail(fail(QP_EINVAL, "P k = 0 for a nonzero k in the grid (dependent columns of P)"));
     const double scale = std::max(std::fabs(p->amin), std::fabs(p->amax));
-    if (p->amin < -1e-12 * scale)
-        return bail(fail(QP_ENOTELLIPTIC, "coefficient minimum on the grid is %.6g < 0", p->amin));
+    if (p->amin < -1e-12 * scale) {
+        if (!o.allow_indefinite)
+            return bail(fail(QP_ENOTELLIPTIC, "coefficient minimum on the grid is %.6g < 0", p->amin));
+        p->flags |= QP_FLAG_INDEFINITE;
+    }
     if (std::fabs(p->amin) <= 1e-12 * scale) p->flags |= QP_FLAG_DEGENERATE;
     p->layout = qp_layout{};
     report_layout(p, 0);
@@ -1652,7 +1764,7 @@ qp_status qp_set_options(qp_problem *p, const qp_options *opt)
 qp_status qp_solve_d(qp_problem *p, const double *rhs, double *u, double tol, qp_solve_info *info)
 {
     if (!p || !rhs || !u) return fail(QP_EINVAL, "null argument");
-    if (rhs == u) return fail(QP_EINVAL, "rhs and u must not overlap");
+    if (overlaps(rhs, u, 16 * (size_t)p->host.D)) return fail(QP_EINVAL, "rhs and u must not overlap");
     return solve_dispatch(p, 1, rhs, u, tol, info);
 }
 
@@ -1662,9 +1774,8 @@ qp_status qp_solve_multi_d(qp_problem *p, int K, const double *rhs, double *u, d
     if (!p || !rhs || !u) return fail(QP_EINVAL, "null argument");
     if (K < 1 || K > p->host.d)
         return fail(QP_EINVAL, "K = %d right-hand sides outside [1, d = %d]", K, p->host.d);
-    const size_t bytes = 16 * (size_t)p->host.D * K;
-    const char *a = reinterpret_cast<const char *>(rhs), *b = reinterpret_cast<const char *>(u);
-    if (a < b + bytes && b < a + bytes) return fail(QP_EINVAL, "rhs and u must not overlap");
+    if (overlaps(rhs, u, 16 * (size_t)p->host.D * K))
+        return fail(QP_EINVAL, "rhs and u must not overlap");
     return solve_dispatch(p, K, rhs, u, tol, infos);
 }
 
@@ -1876,6 +1987,7 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
         e.nb_mv64 = p->host.nb_mv64;
         e.sv0 = (int)own_st.size();
         e.nb_st = p->host.nblocks;
+        e.wide = p->host.chunk > 4 * qp::kBlock ? 1 : 0;
         own_mv.insert(own_mv.end(), (size_t)e.nb_mv, i);
         own_mv64.insert(own_mv64.end(), (size_t)e.nb_mv64, i);
         own_st.insert(own_st.end(), (size_t)e.nb_st, i);
@@ -2007,6 +2119,7 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
         qp_problem *p = problems[i];
         QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), s));
         QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (infos) QP_TRY(queue_hist(p, K, s));
     }
     QP_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
@@ -2030,6 +2143,9 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
                 info->outer_iters = st.replacements;
                 info->rel_resid = std::sqrt(st.rr);
                 info->seconds = ms * 1e-3;
+                info->kappa_est = lanczos_kappa(p->hhist + (size_t)2 * qp::kHist * r,
+                                                std::min(st.iters, qp::kHist));
+                info->bytes_moved = solve_bytes(true, (double)p->host.D, st.iters, st.replacements);
             }
             if (status != QP_OK && worst == QP_OK) worst = status;
         }
@@ -2049,6 +2165,7 @@ qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info
 qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
+    if (overlaps(u, y, 16 * (size_t)p->host.D)) return fail(QP_EINVAL, "u and y must not overlap");
     QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, 1, p->tab, p->host, p->recs(), p->urec(qp::F64),
                              p->upku(qp::F64), u, y, nullptr,
                              nullptr, p->parts(), p->st(), nullptr, p->stream));
@@ -2063,6 +2180,8 @@ qp_status qp_matvec_half_d(qp_problem *p, const double *u, double *y)
         return fail(QP_EINVAL, "Hermitian half storage needs odd N (N = %d)", p->host.N);
     if (p->host.aniso)
         return fail(QP_EINVAL, "Hermitian half storage: scalar coefficient only");
+    if (overlaps(u, y, 16 * (((size_t)p->host.D + 1) / 2)))
+        return fail(QP_EINVAL, "u and y must not overlap");
     QP_HIP(qp::launch_matvec_half(p->tab, p->host, u, y, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
     return QP_OK;
@@ -2071,6 +2190,7 @@ qp_status qp_matvec_half_d(qp_problem *p, const double *u, double *y)
 qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
+    if (overlaps(u, y, 8 * (size_t)p->host.D)) return fail(QP_EINVAL, "u and y must not overlap");
     QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, 1, p->tab, p->host, p->recs(), p->urec(qp::F32),
                              p->upku(qp::F32), u, y, nullptr,
                              nullptr, p->parts(), p->st(), nullptr, p->stream));
@@ -2169,6 +2289,7 @@ qp_status qp_coo_matvec_d(qp_problem *p, const int32_t *cols, const double *vals
                           double *y)
 {
     if (!p || !cols || !vals || !u || !y) return fail(QP_EINVAL, "null argument");
+    if (overlaps(u, y, 16 * (size_t)p->host.D)) return fail(QP_EINVAL, "u and y must not overlap");
     QP_HIP(qp::launch_coo_matvec(p->host, cols, vals, u, y, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
     return QP_OK;

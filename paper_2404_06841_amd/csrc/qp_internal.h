@@ -133,7 +133,22 @@ struct State {
     int maxit;
     int did_update;   // the update of the current iteration ran (written by the update)
     int replace;      // FP32-IR: this replacement acts (written by the fold)
+    double *hist;     // Lanczos coefficients of the solve: (alpha_j, beta_j) at
+                      // hist[2 j], hist[2 j + 1] for j < kHist (set once per
+                      // problem; the kernels' lead threads write the entries)
 };
+// Iterations whose PCG coefficients a solve keeps for its condition estimate.
+constexpr int kHist = 1024;
+
+// Store alpha of iteration `it` (0-based) / beta after it, when kept.
+__device__ __forceinline__ void hist_alpha(State *st, int it, double alpha)
+{
+    if (st->hist && it >= 0 && it < kHist) st->hist[2 * it] = alpha;
+}
+__device__ __forceinline__ void hist_beta(State *st, int it, double beta)
+{
+    if (st->hist && it >= 0 && it < kHist) st->hist[2 * it + 1] = beta;
+}
 
 enum Epilogue { EPI_NONE = 0, EPI_ALPHA = 1, EPI_RESID = 2 };
 
@@ -154,6 +169,8 @@ struct GroupEntry {
     State *st;                                      // K states
     int mv0, nb_mv, sv0, nb_st;
     int mv064, nb_mv64;  // the FP64 product's workgroups (owner_mv64)
+    int wide;            // chunk > 4 kBlock: the float update and direction load
+                         // eight rows per thread (as the problem's own launches)
 };
 enum Precision { F64 = 0, F32 = 1 };
 
@@ -293,5 +310,7 @@ hipError_t launch_coo_matvec(const Table &ht, const int32_t *cols, const double 
 hipError_t launch_dft(int n, int N, const double *in, double *out, int inverse, hipStream_t s);
 // Reset K States (flags, counters) with a kernel (no memset node).
 hipError_t launch_state_reset(int K, State *st, hipStream_t s);
+// Point state r of the kMaxRhs states at hist + 2 kHist r (once per problem).
+hipError_t launch_state_hist(State *st, double *hist, hipStream_t s);
 
 }  // namespace qp

@@ -173,6 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
         }
         store_partials<2>(acc, part_out + k * kPartStride);
         if (lead) {
+            hist_alpha(st, st->iters, alpha);
             st->alpha = alpha;
             st->hq = hq[0];
             st->iters = st->iters + 1;
@@ -256,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int K,
             h[e] = hv;
         }
         if (lead) {
+            hist_beta(st, st->iters - 1, beta);
             st->rr = rr;
             st->beta = beta;
             st->rz[(j + 1) & 1] = rz_new;
@@ -300,6 +302,12 @@ __global__ __launch_bounds__(kBlock) void k_ir_unit(int K, const double *__restr
 __global__ void k_ir_force(int K, State *sts)
 {
     if (blockIdx.x == 0 && (int)threadIdx.x < K && !sts[threadIdx.x].done) sts[threadIdx.x].pause = 1;
+}
+
+__global__ void k_state_hist(State *sts, double *hist)
+{
+    if (blockIdx.x == 0 && (int)threadIdx.x < kMaxRhs)
+        sts[threadIdx.x].hist = hist + (size_t)2 * kHist * threadIdx.x;
 }
 
 __global__ void k_state_reset(int K, State *sts)
@@ -523,6 +531,7 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
         store_partials_at<2>(acc[k], part_out + k * kPartStride, vb);
         if (lead) {
             State *st = sts + k;
+            hist_alpha(st, st->iters, alpha[k]);
             st->alpha = alpha[k];
             st->hq = hqv[k];
             st->iters = st->iters + 1;
@@ -650,6 +659,7 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
         for (int k = 0; k < KK; ++k) {
             if (!go[k]) continue;
             State *st = sts + k;
+            hist_beta(st, st->iters - 1, betav[k]);
             st->rr = rrv[k];
             st->beta = betav[k];
             st->rz[(j + 1) & 1] = rzn[k];
@@ -774,6 +784,10 @@ __device__ __forceinline__ void irdir_f(const int vb, const int vnb, int j,
         for (int k = 0; k < KK; ++k) {
             if (!go[k]) continue;
             State *st = sts + k;
+            // a replaced residual does not continue the float recursion's
+            // Lanczos relation: the condition estimate takes the float
+            // iterations between replacements as separate segments
+            hist_beta(st, st->iters - 1, 0.0);
             st->rr = rrv[k];
             st->rr_last = rrv[k];
             st->beta = betav[k];
@@ -841,11 +855,21 @@ __global__ __launch_bounds__(kBlock) void k_vec_grp(int j, const GroupEntry *__r
     float2 *x32 = reinterpret_cast<float2 *>(e.x32);
     float2 *r32 = reinterpret_cast<float2 *>(e.r32);
     float2 *h32 = reinterpret_cast<float2 *>(e.h32);
-    if constexpr (STEP == 0)
-        update_f<KK, 4>(vb, vnb, j, e.tab, r32, reinterpret_cast<const float2 *>(e.q32), e.M32,
-                        e.pa, e.pb, e.st);
-    else if constexpr (STEP == 1)
-        direction_f<KK, 4>(vb, vnb, j, e.tab, x32, r32, h32, e.M32, e.pb, e.st);
+    // the row count of the problem's own launches (launch_pcg_update and
+    // launch_pcg_direction), so that every partial sum is formed alike
+    if constexpr (STEP == 0) {
+        if (e.wide)
+            update_f<KK, 8>(vb, vnb, j, e.tab, r32, reinterpret_cast<const float2 *>(e.q32), e.M32,
+                            e.pa, e.pb, e.st);
+        else
+            update_f<KK, 4>(vb, vnb, j, e.tab, r32, reinterpret_cast<const float2 *>(e.q32), e.M32,
+                            e.pa, e.pb, e.st);
+    } else if constexpr (STEP == 1) {
+        if (e.wide)
+            direction_f<KK, 8>(vb, vnb, j, e.tab, x32, r32, h32, e.M32, e.pb, e.st);
+        else
+            direction_f<KK, 4>(vb, vnb, j, e.tab, x32, r32, h32, e.M32, e.pb, e.st);
+    }
     else if constexpr (STEP == 2)
         fold_f<KK>(vb, vnb, e.tab, reinterpret_cast<double2 *>(e.X), x32, e.st);
     else
@@ -1010,6 +1034,12 @@ hipError_t launch_ir_direction(int j, int K, const Table *tab, const Table &ht, 
 hipError_t launch_ir_force(int K, State *st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ir_force, dim3(1), dim3(64), 0, s, K, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_hist(State *st, double *hist, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_state_hist, dim3(1), dim3(64), 0, s, st, hist);
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ QP_PRECOND_PAPER = 0
 QP_PRECOND_JACOBI = 1
 QP_FLAG_DEGENERATE = 1
 QP_FLAG_F0_IGNORED = 2
+QP_FLAG_INDEFINITE = 4
 
 MAX_N, MAX_D, MAX_MODES = 8, 4, 64
 
@@ -58,7 +59,7 @@ class qp_options(C.Structure):
                 ("inner_tol", C.c_double), ("poll_every", C.c_int),
                 ("profile", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("graphs", C.c_int),
-                ("gather64", C.c_int), ("autotune", C.c_int)]
+                ("gather64", C.c_int), ("autotune", C.c_int), ("allow_indefinite", C.c_int)]
 
 
 class qp_layout(C.Structure):
@@ -76,7 +77,8 @@ class qp_solve_info(C.Structure):
                 ("flags", C.c_int), ("rel_resid", C.c_double), ("seconds", C.c_double),
                 ("matvec_launches", C.c_int), ("matvec_ms", C.c_double),
                 ("matvec32_launches", C.c_int), ("matvec32_ms", C.c_double),
-                ("matvec_rhs", C.c_int), ("matvec32_rhs", C.c_int)]
+                ("matvec_rhs", C.c_int), ("matvec32_rhs", C.c_int),
+                ("kappa_est", C.c_double), ("bytes_moved", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -245,7 +247,8 @@ class Problem:
     def __init__(self, prob, precision: str = "fp64", precond: str = "paper",
                  maxit: int = 10000, inner_tol: float = 1e-5,
                  profile: bool = False, stream=None, poll_every: int = 0,
-                 graphs: bool = True, gather64: bool = False, autotune: bool = False):
+                 graphs: bool = True, gather64: bool = False, autotune: bool = False,
+                 allow_indefinite: bool = False):
         import torch
         self.d, self.n, self.N = int(prob.d), int(prob.n), int(prob.N)
         self.D = self.N ** self.n
@@ -261,6 +264,7 @@ class Problem:
         opt.graphs = 1 if graphs else 0
         opt.gather64 = 1 if gather64 else 0
         opt.autotune = 1 if autotune else 0
+        opt.allow_indefinite = 1 if allow_indefinite else 0
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         nbytes = qp_workspace_bytes(self.d, self.n, self.N, self.g)

@@ -75,16 +75,46 @@ def test_every_layout_gives_bitwise_equal_products(make):
     a.close()
 
 
-def test_slab_order_at_the_large_icosahedral_shape():
-    # 16,777,216 unknowns: each XCD's eighth is two values of the slowest axis
+def _large_rows(prob, count: int = 1500) -> np.ndarray:
+    """Rows of the icosahedral N = 16 grid to check against the oracle: the
+    first and last planes' corners, entries on the +-N/2 faces of every axis
+    (where the neighbours wrap), and a seeded uniform sample."""
+    D, N, n = prob.D, prob.N, prob.n
+    rng = np.random.default_rng(16)
+    rows = [np.arange(64), np.arange(D - 64, D), rng.integers(0, D, count)]
+    for t in range(n):
+        stride = N ** (n - 1 - t)
+        base = rng.integers(0, D, 40)
+        digit = (base // stride) % N
+        rows.append(base + (N // 2 - digit) * stride)        # digit N/2: k_t = -N/2
+        rows.append(base + (N // 2 - 1 - digit) * stride)    # digit N/2 - 1: k_t = N/2 - 1
+    return np.unique(np.concatenate(rows))
+
+
+def test_large_icosahedral_products_against_the_oracle():
+    """16,777,216 unknowns (the largest serving request and the HBM-sized
+    product shape): the FP64 and float products at sampled rows against the
+    oracle evaluated row by row, under the default layout and the slab orders
+    (each XCD's eighth is two values of the slowest axis), bitwise equal
+    across layouts."""
     prob = W.icosahedral(16)
     a = qp.Problem(prob)
+    say("[case] icosahedral N=16 products, layout", a.layout())
     gen = torch.Generator(device="cuda")
     gen.manual_seed(3)
     u = torch.randn(prob.D, dtype=torch.complex128, device="cuda", generator=gen)
     u32 = u.to(torch.complex64)
     y64, y32 = a.matvec_d(u), a.matvec32_d(u32)
-    for L in [(2, 1024, 2), (4, 1024, 2), (1, 512, 2)]:
+    rows = _large_rows(prob)
+    ix = torch.from_numpy(rows).cuda()
+    ref = oracle.matvec_rows(prob, u.cpu().numpy(), rows)
+    ref32 = oracle.matvec_rows(prob, u32.cpu().numpy().astype(np.complex128), rows)
+    scale = np.abs(ref).max()
+    e64 = np.abs(y64[ix].cpu().numpy() - ref).max() / scale
+    e32 = np.abs(y32[ix].cpu().numpy() - ref32).max() / np.abs(ref32).max()
+    say(f"  {rows.size} rows: FP64 rel err {e64:.2e}, float {e32:.2e}")
+    assert e64 <= 1e-13 and e32 <= 2e-5
+    for L in [(2, 1024, 2), (4, 1024, 2), (1, 512, 2), (1, 1024, 1)]:
         a.set_layout(*L)
         assert torch.equal(a.matvec_d(u), y64), L
         assert torch.equal(a.matvec32_d(u32), y32), L

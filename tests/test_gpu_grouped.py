@@ -54,15 +54,26 @@ GROUPS = {
                          W.periodic_cubic(3, 12)],
     # d = 2, complex coefficients
     "complex": lambda: [W.paper_four_mode_2d(6), W.paper_four_mode_2d(9)],
+    # the largest batch size (N = 32: 1,048,576 unknowns, chunks above 1024
+    # entries, so the vector steps load eight rows per thread) beside small ones
+    "eightfold_N32_mixed": lambda: [W.eightfold_random(32, 0), W.eightfold_random(8, 1),
+                                    W.eightfold_random(24, 2)],
 }
+# groups whose problems are also created with the layout autotuner (as the
+# batch benchmark does): the grouped launches must use each problem's tuned
+# layouts and partial counts
+AUTOTUNED = {"eightfold_N32_mixed"}
+CASES = sorted(GROUPS) + [n + "+autotune" for n in sorted(AUTOTUNED)]
 
 
-@pytest.mark.parametrize("name", sorted(GROUPS))
-def test_grouped_equals_standalone(name):
+@pytest.mark.parametrize("case", CASES)
+def test_grouped_equals_standalone(case):
+    name = case.split("+")[0]
+    kw = {"autotune": True} if case.endswith("+autotune") else {}
     probs = GROUPS[name]()
-    say("[case] grouped", name, [(pr.name, pr.N) for pr in probs])
-    alone = standalone(probs)
-    gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream()) for pr in probs]
+    say("[case] grouped", case, [(pr.name, pr.N) for pr in probs])
+    alone = standalone(probs, **kw)
+    gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream(), **kw) for pr in probs]
     t = time.perf_counter()
     As, infos, st = qp.homogenized_batch(gps, tol=1e-12, grouped=True)
     say("  grouped", len(probs), "problems", round((time.perf_counter() - t) * 1e3, 2), "ms")

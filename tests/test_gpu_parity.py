@@ -127,20 +127,49 @@ def test_corrector_rhs_matches_oracle(case):
         assert np.abs(F - ref).max() <= 1e-15 * max(1.0, np.abs(ref).max()), (name, j)
 
 
+def _degenerate(prob) -> bool:
+    # the 1D field 2 + cos x + cos sqrt2 x vanishes at a grid point for even N
+    return prob.name == "1d_n2" and prob.meta.get("mean") == 2.0
+
+
 def test_solve_fp64_matches_oracle(case):
     name, prob, gp = case
-    if prob.name == "1d_n2" and prob.meta.get("mean") == 2.0:
-        pytest.skip("degenerate field: covered by the corrector test")
     F = W.random_vector(prob.D, seed=23)
     tol = 1e-12
     U, info = gp.solve_d(dev(F), tol=tol)
     ref, st, it, rr = oracle.pcg(prob, F, tol=tol)
     U = host(U)
     assert info.status == 0 and st == 0
-    assert abs(info.iters - it) <= 2, (name, info.iters, it)
     assert info.rel_resid <= tol
     assert U[0] == 0
-    assert np.linalg.norm(U - ref) <= 1e3 * tol * np.linalg.norm(ref), name
+    if not _degenerate(prob):
+        assert abs(info.iters - it) <= 2, (name, info.iters, it)
+        assert np.linalg.norm(U - ref) <= 1e3 * tol * np.linalg.norm(ref), name
+        return
+    # Degenerate field (the solve of the 1D configuration at N = 32, D = 1024):
+    # Q is positive definite on k != 0 but ill-conditioned (kappa_2(Q) ~ 6e6,
+    # about 284 PCG iterations), so rounding shifts the iteration count by a
+    # few and the two solutions are each within kappa_2(Q) * tol (relative) of
+    # the unique discrete solution.  Checked: the iteration count within 2%,
+    # the true residual of the GPU solution (oracle product) within 2 tol,
+    # and both solutions against a dense solve within that conditioning bound.
+    assert abs(info.iters - it) <= max(2, int(0.02 * it)), (name, info.iters, it)
+    res = F.copy()
+    res[0] = 0
+    true_rel = np.linalg.norm(res - oracle.matvec(prob, U)) / np.linalg.norm(res)
+    assert true_rel <= 2 * tol, true_rel
+    from tests.independent import dense_Q
+    Qd = dense_Q(prob)[1:, 1:]
+    ev = np.linalg.eigvalsh(Qd)
+    kappa = ev[-1] / ev[0]
+    exact = np.zeros(prob.D, complex)
+    exact[1:] = np.linalg.solve(Qd, F[1:])
+    e_gpu = np.linalg.norm(U - exact) / np.linalg.norm(exact)
+    e_ref = np.linalg.norm(ref - exact) / np.linalg.norm(exact)
+    say(f"  degenerate N={prob.N}: iters gpu {info.iters} oracle {it}, kappa_2(Q) {kappa:.3g}, "
+        f"true residual {true_rel:.2e}, error vs dense gpu {e_gpu:.2e} oracle {e_ref:.2e}")
+    assert e_gpu <= 2 * kappa * tol and e_ref <= 2 * kappa * tol
+    assert np.linalg.norm(U - ref) <= 4 * kappa * tol * np.linalg.norm(ref)
 
 
 def _astar_scale(prob, A):
@@ -225,12 +254,50 @@ def test_icosahedral_N10_fullsize_three_correctors():
     gp.close()
 
 
+def test_icosahedral_N16_fullsize_astar():
+    """D = 16,777,216, three correctors (the largest serving request): A* of
+    both precisions against the oracle's stored value."""
+    gold = json.load(open(os.path.join(GOLDEN, "oracle_astar.json")))["icosa_N16"]
+    prob = W.icosahedral(16)
+    say(f"[case] icosahedral N=16 D={prob.D}")
+    gp = qp.Problem(prob)
+    A_ref = np.array(gold["A"])
+    for prec in ("fp64", "fp32ir"):
+        gp.set_precision(prec)
+        r = gp.homogenized(tol=1e-12)
+        err = np.abs(r.A - A_ref).max() / np.abs(A_ref).max()
+        say(f"  {prec}: iters {[i.iters for i in r.infos]} (oracle {gold['iters']}) rel err {err:.2e}")
+        assert all(i.status == 0 for i in r.infos), prec
+        assert err <= 1e-10, (prec, r.A, A_ref)
+    gp.close()
+
+
 # ------------------------------------------------------------- error paths
 
 def test_literal_indefinite_fields_rejected():
     for prob in (W.eightfold(8, amplitude=1.0), W.icosahedral(4, amplitude=1.0)):
         st, h = qp.qp_create(prob.d, prob.n, prob.P, prob.modes, prob.coef, prob.N)
         assert st == qp.QP_ENOTELLIPTIC and h is None
+
+
+@pytest.mark.parametrize("make", [lambda: W.eightfold(8, amplitude=1.0),
+                                  lambda: W.icosahedral(4, amplitude=1.0)],
+                         ids=["eightfold_literal_N8", "icosa_literal_N4"])
+def test_indefinite_field_breaks_down_like_the_oracle(make):
+    """With allow_indefinite the literal (indefinite) fields are accepted and
+    flagged; PCG then meets (Q h, h) <= 0 (Alg. 2 breakdown) at the step where
+    the oracle's PCG does, and returns the iterate before that step."""
+    prob = make()
+    gp = qp.Problem(prob, allow_indefinite=True)
+    F = W.random_vector(prob.D, seed=1)
+    U, info = gp.solve_d(dev(F), tol=1e-12, check=False)
+    ref, st, it, rr = oracle.pcg(prob, F, tol=1e-12)
+    say(f"  {prob.name} N={prob.N}: gpu status {info.status} iters {info.iters}; oracle {st} {it}")
+    assert st == oracle.PCG_NOTSPD
+    assert info.status == qp.QP_ENOTSPD and info.flags & qp.QP_FLAG_INDEFINITE
+    assert info.iters == it
+    assert np.linalg.norm(host(U) - ref) <= 1e-10 * np.linalg.norm(ref)
+    gp.close()
 
 
 def test_dependent_projection_rejected():
@@ -305,4 +372,64 @@ def test_host_pointer_entry_points():
     assert st == 0
     rc, *_ = oracle.pcg(prob, oracle.corrector_rhs(prob, 1), tol=1e-12)
     assert np.linalg.norm(chi - rc) <= 1e-9 * np.linalg.norm(rc)
+    gp.close()
+
+
+def test_products_reject_overlapping_buffers():
+    prob = W.icosahedral(5)
+    gp = qp.Problem(prob)
+    L = qp.lib()
+    D, H = prob.D, (prob.D + 1) // 2
+    buf = torch.zeros(2 * D, dtype=torch.complex128, device="cuda")
+    base = buf.data_ptr()
+    for off in (0, 16, 16 * (D - 1)):  # in place, shifted by one entry, last entry shared
+        assert L.qp_matvec_d(gp.h, base, base + off) == qp.QP_EINVAL, off
+        assert L.qp_matvec32_d(gp.h, base, base + off // 2) == qp.QP_EINVAL, off
+        if off < 16 * H:
+            assert L.qp_matvec_half_d(gp.h, base, base + off) == qp.QP_EINVAL, off
+    # adjacent, not overlapping: accepted
+    assert L.qp_matvec_d(gp.h, base, base + 16 * D) == qp.QP_OK
+    gp.close()
+
+
+# ------------------------------------------------------------- condition estimate
+
+@pytest.mark.parametrize("make", [lambda: W.eightfold_random(8, 1), lambda: W.icosahedral(4),
+                                  lambda: W.paper_four_mode_2d(6), lambda: W.one_d_two_mode(32, 2.0)],
+                         ids=["eightfold_random_N8", "icosa_N4", "complex_coef_N6", "c1_degenerate_N32"])
+def test_kappa_est_matches_oracle_lanczos(make):
+    """qp_solve_info.kappa_est against the oracle's estimate from its own PCG
+    scalars (the same Lanczos matrix; pinned against dense eigenvalues of
+    M^(1/2) Q M^(1/2) on the CPU), and bytes_moved against its per-iteration
+    bounds."""
+    prob = make()
+    gp = qp.Problem(prob)
+    F = W.random_vector(prob.D, seed=5)
+    _, info = gp.solve_d(dev(F), tol=1e-12)
+    _, st, it, _, al, be = oracle.pcg_lanczos(prob, F, tol=1e-12)
+    k_ref = oracle.lanczos_kappa(al[:1024], be[:1023])
+    say(f"  {prob.name} N={prob.N}: kappa gpu {info.kappa_est:.10g} oracle {k_ref:.10g} "
+        f"iters {info.iters}/{it} bytes/unknown {info.bytes_moved / prob.D:.0f}")
+    tol_k = 1e-6 if abs(info.iters - it) == 0 else 1e-3
+    assert info.kappa_est == pytest.approx(k_ref, rel=tol_k)
+    assert 150 * info.iters <= info.bytes_moved / prob.D <= 200 * info.iters + 100
+    gp.set_precision("fp32ir")
+    _, info32 = gp.solve_d(dev(F), tol=1e-12)
+    say(f"    fp32ir kappa {info32.kappa_est:.6g} iters {info32.iters} "
+        f"replacements {info32.outer_iters} bytes/unknown {info32.bytes_moved / prob.D:.0f}")
+    # FP32-IR: float iterations in segments between residual replacements;
+    # each segment's Ritz values lie inside the spectrum, so the estimate is a
+    # lower bound that the shorter segments leave less converged
+    assert 0.5 * k_ref <= info32.kappa_est <= 1.02 * k_ref
+    assert 80 * info32.iters <= info32.bytes_moved / prob.D
+    gp.close()
+
+
+def test_kappa_est_in_homogenization_infos():
+    prob = W.eightfold_random(12, 2)
+    gp = qp.Problem(prob)
+    r = gp.homogenized(tol=1e-12)
+    for j, inf in enumerate(r.infos):
+        _, st, it, _, al, be = oracle.pcg_lanczos(prob, oracle.corrector_rhs(prob, j), tol=1e-12)
+        assert inf.kappa_est == pytest.approx(oracle.lanczos_kappa(al, be), rel=1e-3), j
     gp.close()
