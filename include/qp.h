@@ -146,9 +146,12 @@ typedef struct qp_solve_info {
                              sqrt(beta_j)/alpha_j; the first 1024 iterations;
                              FP32-IR: the float iterations, each run between
                              two residual replacements a separate Lanczos
-                             segment).  It approaches the true ratio from below
-                             as the iterations grow (Sec. 4.3 discusses
-                             cond(QM)); 0 when no iteration ran               */
+                             segment).  In FP64 it approaches the true ratio
+                             from below as the iterations grow (Sec. 4.3
+                             discusses cond(QM)); float rounding perturbs the
+                             FP32-IR recurrence, whose estimate can exceed the
+                             FP64 one for ill-conditioned operators (14% at a
+                             ratio of 1e4).  0 when no iteration ran           */
     double bytes_moved;   /* algorithmic device bytes of the solve's kernels for
                              this right-hand side: each vector a kernel touches
                              read or written once (16 B per FP64 complex entry,
@@ -354,6 +357,7 @@ qp_status qp_homogenized_batch(qp_problem *const *problems, int count, double *A
  */
 qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double *Astar, double tol,
                                  qp_solve_info *infos);
+
 
 /* ---- serving: a request queue over a cache of problems ---- */
 
