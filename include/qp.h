@@ -358,6 +358,30 @@ qp_status qp_homogenized_batch(qp_problem *const *problems, int count, double *A
 qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double *Astar, double tol,
                                  qp_solve_info *infos);
 
+/*
+ * qp_homogenized_grouped for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same launches and results (every A*, iteration count and status equals
+ * qp_homogenized_grouped's on the same problems), with the group table, the
+ * owner arrays and the poll words in a static device array of 4 MiB that the
+ * library holds on each device until the process ends, instead of memory
+ * allocated on first use.  The call makes no device, pinned or host heap
+ * allocation: it polls one done bit per problem into problem 0's pinned
+ * words and reads the final states into each problem's own pinned slot,
+ * all made by qp_create.
+ *   problems, count, Astar, tol, infos   as for qp_homogenized_grouped;
+ *             count <= 4096.
+ * Returns QP_EINVAL, naming the sizes, when the group table (about 170 bytes
+ * per problem plus 4 bytes per workgroup of its float product, FP64 product
+ * and vector launches) exceeds the array, and otherwise as
+ * qp_homogenized_grouped.  The array keeps the last call's contents (every
+ * call writes what it reads).  Calls from several host threads of one
+ * process are serialized with qp_homogenized_grouped's; calls that overlap
+ * on one device through another route (e.g. a second copy of the library
+ * loaded into the process) would share the array and race.
+ */
+qp_status qp_homogenized_grouped_noalloc(qp_problem *const *problems, int count, double *Astar,
+                                         double tol, qp_solve_info *infos);
 
 /* ---- serving: a request queue over a cache of problems ---- */
 

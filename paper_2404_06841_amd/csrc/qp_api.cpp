@@ -1894,6 +1894,14 @@ struct GroupBuffers {
     size_t host_states = 0;
 };
 GroupBuffers g_gb;
+// Problems per grouped call: the no-allocation variant's polls carry one done
+// bit per problem in kGroupWords words per slot (problem 0's pinned scratch
+// words hold two slots).
+constexpr int kMaxGroup = 4096;
+constexpr int kGroupWords = kMaxGroup / 32;
+// Host image of the no-allocation variant's group table (entries and owner
+// arrays), the size of the device scratch array; used under g_group_mu.
+alignas(256) char g_group_host[qp::kGroupScratchBytes];
 
 qp_status group_buffers(int device, size_t dev_bytes, size_t nstates)
 {
@@ -1937,12 +1945,20 @@ const char *group_mismatch(const qp_problem *p, const qp_problem *p0)
 }
 
 }  // namespace
-extern "C" {
 
-qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double *Astar, double tol,
-                                 qp_solve_info *infos)
+namespace {
+
+// The grouped homogenization of qp_homogenized_grouped (noalloc false: group
+// tables in library memory allocated on first use, polls copy the states to
+// pinned memory) and of qp_homogenized_grouped_noalloc (noalloc true: group
+// tables in the library's static device array, polls copy one done bit per
+// problem into problem 0's pinned scratch words; no device, pinned or host
+// heap allocation).  Both queue the same solver launches.
+qp_status grouped_run(qp_problem *const *problems, int count, double *Astar, double tol,
+                      qp_solve_info *infos, bool noalloc)
 {
     if (!problems || !Astar || count < 1) return fail(QP_EINVAL, "null argument or empty group");
+    if (count > kMaxGroup) return fail(QP_EINVAL, "%d problems exceed the group limit %d", count, kMaxGroup);
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QP_EINVAL, "tol must be positive and finite");
     for (int i = 0; i < count; ++i) {
         if (!problems[i]) return fail(QP_EINVAL, "problem %d is null", i);
@@ -1954,17 +1970,65 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
     qp_problem *p0 = problems[0];
     const int G = count, d = p0->host.d, K = d;
     const hipStream_t s = p0->stream;
+
+    // sizes of the group table: entries, then the owner of every workgroup of
+    // the float product, of the FP64 product and of the vector steps, then
+    // the poll area (three slots of states, or two slots of done words)
+    size_t tot_mv = 0, tot_mv64 = 0, tot_st = 0;
+    for (int i = 0; i < G; ++i) {
+        tot_mv += (size_t)problems[i]->host.nb_mv;
+        tot_mv64 += (size_t)problems[i]->host.nb_mv64;
+        tot_st += (size_t)problems[i]->host.nblocks;
+    }
+    const size_t nst = (size_t)G * K;
+    const size_t o_own_mv = align_up(sizeof(qp::GroupEntry) * G);
+    const size_t o_own_mv64 = align_up(o_own_mv + sizeof(int) * tot_mv);
+    const size_t o_own_st = align_up(o_own_mv64 + sizeof(int) * tot_mv64);
+    const size_t o_poll = align_up(o_own_st + sizeof(int) * tot_st);
+    const size_t bytes = o_poll + (noalloc ? sizeof(uint32_t) * 2 * kGroupWords
+                                           : 3 * nst * sizeof(State));
+
     std::lock_guard<std::mutex> lock(g_group_mu);
+    char *dev = nullptr;  // device group table
+    char *hbuf = nullptr;  // host image of its first o_poll bytes
+    std::vector<char> hvec;
+    if (noalloc) {
+        void *ptr = nullptr;
+        size_t cap = 0;
+        QP_HIP(qp::group_scratch(p0->device, &ptr, &cap));
+        if (bytes > cap || o_poll > sizeof(g_group_host))
+            return fail(QP_EINVAL, "group table of %zu bytes exceeds the %zu-byte scratch array "
+                        "(fewer or smaller problems)", bytes, cap);
+        dev = static_cast<char *>(ptr);
+        hbuf = g_group_host;
+    } else {
+        QP_TRY(group_buffers(p0->device, bytes, nst));
+        dev = g_gb.dev;
+        hvec.resize(o_poll);
+        hbuf = hvec.data();
+    }
     for (int i = 0; i < G; ++i) QP_HIP(hipStreamSynchronize(problems[i]->stream));
 
-    // group table and owners
-    std::vector<qp::GroupEntry> ents(G);
-    std::vector<int> own_mv, own_mv64, own_st;
+    auto *ents = reinterpret_cast<qp::GroupEntry *>(hbuf);
+    int *own_mv = reinterpret_cast<int *>(hbuf + o_own_mv);
+    int *own_mv64 = reinterpret_cast<int *>(hbuf + o_own_mv64);
+    int *own_st = reinterpret_cast<int *>(hbuf + o_own_st);
+    auto *E = reinterpret_cast<qp::GroupEntry *>(dev);
+    auto *owner_mv = reinterpret_cast<int *>(dev + o_own_mv);
+    auto *owner_mv64 = reinterpret_cast<int *>(dev + o_own_mv64);
+    auto *owner_st = reinterpret_cast<int *>(dev + o_own_st);
+    auto *dstates = reinterpret_cast<State *>(dev + o_poll);     // noalloc false
+    auto *dwords = reinterpret_cast<uint32_t *>(dev + o_poll);   // noalloc true
+    // problem 0's pinned scratch words: two slots of kGroupWords done words
+    auto *hwords = reinterpret_cast<uint32_t *>(p0->hsmall);
+    static_assert(2 * kGroupWords * sizeof(uint32_t) <= 128 * sizeof(double), "poll words");
+
     int gpmax = 4;
     for (int i = 0; i < G; ++i) {
         qp_problem *p = problems[i];
         const qp::Parts parts = p->parts();
         qp::GroupEntry &e = ents[i];
+        e = qp::GroupEntry{};
         e.tab = p->tab;
         e.recs = p->recs();
         e.urec32 = p->urec(qp::F32);
@@ -1981,35 +2045,35 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
         e.pa = parts.a;
         e.pb = parts.b;
         e.st = p->st();
-        e.mv0 = (int)own_mv.size();
         e.nb_mv = p->host.nb_mv;
-        e.mv064 = (int)own_mv64.size();
         e.nb_mv64 = p->host.nb_mv64;
-        e.sv0 = (int)own_st.size();
         e.nb_st = p->host.nblocks;
         e.wide = p->host.chunk > 4 * qp::kBlock ? 1 : 0;
-        own_mv.insert(own_mv.end(), (size_t)e.nb_mv, i);
-        own_mv64.insert(own_mv64.end(), (size_t)e.nb_mv64, i);
-        own_st.insert(own_st.end(), (size_t)e.nb_st, i);
         gpmax = std::max(gpmax, (p->host.g + 3) & ~3);
     }
-    int tot_mv = (int)own_mv.size(), tot_mv64 = (int)own_mv64.size(), tot_st = (int)own_st.size();
-    const size_t nst = (size_t)G * K;
-    const size_t o_own_mv = align_up(sizeof(qp::GroupEntry) * G);
-    const size_t o_own_mv64 = align_up(o_own_mv + sizeof(int) * tot_mv);
-    const size_t o_own_st = align_up(o_own_mv64 + sizeof(int) * tot_mv64);
-    const size_t o_states = align_up(o_own_st + sizeof(int) * tot_st);
-    const size_t bytes = o_states + 3 * nst * sizeof(State);
-    QP_TRY(group_buffers(p0->device, bytes, nst));
-    auto *E = reinterpret_cast<qp::GroupEntry *>(g_gb.dev);
-    auto *owner_mv = reinterpret_cast<int *>(g_gb.dev + o_own_mv);
-    auto *owner_mv64 = reinterpret_cast<int *>(g_gb.dev + o_own_mv64);
-    auto *owner_st = reinterpret_cast<int *>(g_gb.dev + o_own_st);
-    auto *dstates = reinterpret_cast<State *>(g_gb.dev + o_states);
-    QP_HIP(hipMemcpy(E, ents.data(), sizeof(qp::GroupEntry) * G, hipMemcpyHostToDevice));
-    QP_HIP(hipMemcpy(owner_mv, own_mv.data(), sizeof(int) * tot_mv, hipMemcpyHostToDevice));
-    QP_HIP(hipMemcpy(owner_mv64, own_mv64.data(), sizeof(int) * tot_mv64, hipMemcpyHostToDevice));
-    QP_HIP(hipMemcpy(owner_st, own_st.data(), sizeof(int) * tot_st, hipMemcpyHostToDevice));
+    unsigned char running[kMaxGroup];
+    for (int i = 0; i < G; ++i) running[i] = 1;
+    int n_mv = 0, n_mv64 = 0, n_st = 0;  // workgroups of the current launches
+    // owners of the running problems' workgroups, uploaded with the entries
+    auto build_owners = [&]() -> qp_status {
+        n_mv = n_mv64 = n_st = 0;
+        for (int i = 0; i < G; ++i) {
+            if (!running[i]) continue;
+            qp::GroupEntry &e = ents[i];
+            e.mv0 = n_mv;
+            e.mv064 = n_mv64;
+            e.sv0 = n_st;
+            for (int w = 0; w < e.nb_mv; ++w) own_mv[n_mv++] = i;
+            for (int w = 0; w < e.nb_mv64; ++w) own_mv64[n_mv64++] = i;
+            for (int w = 0; w < e.nb_st; ++w) own_st[n_st++] = i;
+        }
+        QP_HIP(hipMemcpy(E, ents, sizeof(qp::GroupEntry) * G, hipMemcpyHostToDevice));
+        QP_HIP(hipMemcpy(owner_mv, own_mv, sizeof(int) * n_mv, hipMemcpyHostToDevice));
+        QP_HIP(hipMemcpy(owner_mv64, own_mv64, sizeof(int) * n_mv64, hipMemcpyHostToDevice));
+        QP_HIP(hipMemcpy(owner_st, own_st, sizeof(int) * n_st, hipMemcpyHostToDevice));
+        return QP_OK;
+    };
+    QP_TRY(build_owners());
 
     // set-up of every problem (the launches of a standalone homogenization)
     QP_HIP(hipEventRecord(p0->ev_t0, s));
@@ -2025,68 +2089,57 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
                                     p->st(), s));
     }
     auto replacement = [&](int j) -> qp_status {
-        QP_HIP(qp::launch_group_vec(2, j, K, tot_st, E, owner_st, s));
-        QP_HIP(qp::launch_group_matvec(qp::F64, d, p0->host.real_coef, tot_mv64, gpmax, E, owner_mv64,
+        QP_HIP(qp::launch_group_vec(2, j, K, n_st, E, owner_st, s));
+        QP_HIP(qp::launch_group_matvec(qp::F64, d, p0->host.real_coef, n_mv64, gpmax, E, owner_mv64,
                                        s));
-        QP_HIP(qp::launch_group_vec(3, j, K, tot_st, E, owner_st, s));
+        QP_HIP(qp::launch_group_vec(3, j, K, n_st, E, owner_st, s));
         return QP_OK;
     };
     auto poll = [&](int slot, hipEvent_t ev) -> qp_status {
-        QP_HIP(qp::launch_group_states(G, K, E, dstates + slot * nst, s));
-        QP_HIP(hipMemcpyAsync(g_gb.host + slot * nst, dstates + slot * nst, nst * sizeof(State),
-                              hipMemcpyDeviceToHost, s));
+        if (noalloc) {
+            QP_HIP(qp::launch_group_done(G, K, E, dwords + slot * kGroupWords, s));
+            QP_HIP(hipMemcpyAsync(hwords + slot * kGroupWords, dwords + slot * kGroupWords,
+                                  sizeof(uint32_t) * kGroupWords, hipMemcpyDeviceToHost, s));
+        } else {
+            QP_HIP(qp::launch_group_states(G, K, E, dstates + slot * nst, s));
+            QP_HIP(hipMemcpyAsync(g_gb.host + slot * nst, dstates + slot * nst, nst * sizeof(State),
+                                  hipMemcpyDeviceToHost, s));
+        }
         if (ev) QP_HIP(hipEventRecord(ev, s));
         return QP_OK;
+    };
+    // whether every right-hand side of problem i was done at the poll of slot
+    auto problem_done = [&](int slot, int i) -> bool {
+        if (noalloc) return (hwords[slot * kGroupWords + i / 32] >> (i % 32)) & 1u;
+        bool done = true;
+        for (int r = 0; r < K; ++r) done = done && g_gb.host[slot * nst + (size_t)i * K + r].done != 0;
+        return done;
     };
     const int maxit = p0->opt.maxit, full = batch_size(p0->opt);
     int j = 0, slot = 0, inflight = 0;
     bool fin = false;
-    std::vector<char> running(G, 1);
     // Launches cover only the problems still running: once a poll shows
     // problems finished, the owner tables are rebuilt without them (after the
     // queued work has drained; a finished problem's state no longer changes).
-    auto compact = [&](const State *seen) -> qp_status {
-        bool changed = false;
+    auto compact = [&](int seen) -> qp_status {
+        bool changed = false, any = false;
         for (int i = 0; i < G; ++i) {
-            bool done = true;
-            for (int r = 0; r < K; ++r) done = done && seen[(size_t)i * K + r].done != 0;
-            if (running[i] && done) {
+            if (running[i] && problem_done(seen, i)) {
                 running[i] = 0;
                 changed = true;
             }
+            any = any || running[i];
         }
-        bool any = false;
-        for (int i = 0; i < G; ++i) any = any || running[i];
         if (!changed || !any) return QP_OK;
-        own_mv.clear();
-        own_mv64.clear();
-        own_st.clear();
-        for (int i = 0; i < G; ++i) {
-            if (!running[i]) continue;
-            ents[i].mv0 = (int)own_mv.size();
-            ents[i].mv064 = (int)own_mv64.size();
-            ents[i].sv0 = (int)own_st.size();
-            own_mv.insert(own_mv.end(), (size_t)ents[i].nb_mv, i);
-            own_mv64.insert(own_mv64.end(), (size_t)ents[i].nb_mv64, i);
-            own_st.insert(own_st.end(), (size_t)ents[i].nb_st, i);
-        }
         QP_HIP(hipStreamSynchronize(s));
-        QP_HIP(hipMemcpy(E, ents.data(), sizeof(qp::GroupEntry) * G, hipMemcpyHostToDevice));
-        QP_HIP(hipMemcpy(owner_mv, own_mv.data(), sizeof(int) * own_mv.size(), hipMemcpyHostToDevice));
-        QP_HIP(hipMemcpy(owner_mv64, own_mv64.data(), sizeof(int) * own_mv64.size(),
-                         hipMemcpyHostToDevice));
-        QP_HIP(hipMemcpy(owner_st, own_st.data(), sizeof(int) * own_st.size(), hipMemcpyHostToDevice));
-        tot_mv = (int)own_mv.size();
-        tot_mv64 = (int)own_mv64.size();
-        tot_st = (int)own_st.size();
-        return QP_OK;
+        return build_owners();
     };
     auto queue = [&]() -> qp_status {
         const int k = std::min(full, maxit - j);
         for (int it = 0; it < k; ++it) {
-            QP_HIP(qp::launch_group_matvec(qp::F32, d, p0->host.real_coef, tot_mv, gpmax, E, owner_mv, s));
-            QP_HIP(qp::launch_group_vec(0, it, K, tot_st, E, owner_st, s));
-            QP_HIP(qp::launch_group_vec(1, it, K, tot_st, E, owner_st, s));
+            QP_HIP(qp::launch_group_matvec(qp::F32, d, p0->host.real_coef, n_mv, gpmax, E, owner_mv, s));
+            QP_HIP(qp::launch_group_vec(0, it, K, n_st, E, owner_st, s));
+            QP_HIP(qp::launch_group_vec(1, it, K, n_st, E, owner_st, s));
             if (it & 1) QP_TRY(replacement(it));
         }
         QP_TRY(poll(slot, p0->ev_poll[slot]));
@@ -2104,8 +2157,8 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
         QP_HIP(hipEventSynchronize(p0->ev_poll[oldest]));
         --inflight;
         fin = true;
-        for (size_t t = 0; t < nst; ++t) fin = fin && g_gb.host[oldest * nst + t].done != 0;
-        if (!fin) QP_TRY(compact(g_gb.host + oldest * nst));
+        for (int i = 0; i < G && fin; ++i) fin = problem_done(oldest, i);
+        if (!fin) QP_TRY(compact(oldest));
     }
     if (!fin) {
         // iteration limit: fold every unfinished increment into X with one
@@ -2114,9 +2167,11 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
         QP_TRY(replacement(maxit));
     }
     QP_HIP(hipEventRecord(p0->ev_t1, s));
-    QP_TRY(poll(2, nullptr));
     for (int i = 0; i < G; ++i) {
         qp_problem *p = problems[i];
+        // final states into the problem's own pinned slot 2
+        QP_HIP(hipMemcpyAsync(p->hstate + 2 * qp::kMaxRhs, p->st(), sizeof(State) * K,
+                              hipMemcpyDeviceToHost, s));
         QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), s));
         QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double), hipMemcpyDeviceToHost, s));
         if (infos) QP_TRY(queue_hist(p, K, s));
@@ -2124,15 +2179,15 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
     QP_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     QP_HIP(hipEventElapsedTime(&ms, p0->ev_t0, p0->ev_t1));
-    const State *fs = g_gb.host + 2 * nst;
     qp_status worst = QP_OK;
     size_t ao = 0;
     for (int i = 0; i < G; ++i) {
         qp_problem *p = problems[i];
+        const State *fs = p->hstate + 2 * qp::kMaxRhs;
         for (int e = 0; e < d * d; ++e) Astar[ao + e] = p->hsmall[e];
         ao += (size_t)d * d;
         for (int r = 0; r < K; ++r) {
-            const State &st = fs[(size_t)i * K + r];
+            const State &st = fs[r];
             const qp_status status = st.done ? (qp_status)st.status : QP_ENOCONV;
             if (infos) {
                 qp_solve_info *info = infos + (size_t)i * K + r;
@@ -2155,6 +2210,21 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
         fail(worst, "a corrector solve of the group did not converge");
     }
     return worst;
+}
+
+}  // namespace
+extern "C" {
+
+qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double *Astar, double tol,
+                                 qp_solve_info *infos)
+{
+    return grouped_run(problems, count, Astar, tol, infos, false);
+}
+
+qp_status qp_homogenized_grouped_noalloc(qp_problem *const *problems, int count, double *Astar,
+                                         double tol, qp_solve_info *infos)
+{
+    return grouped_run(problems, count, Astar, tol, infos, true);
 }
 
 qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info *info)

@@ -265,6 +265,14 @@ hipError_t launch_group_vec(int step, int j, int K, int total, const GroupEntry 
                             hipStream_t s);
 // out[g K + k] = state k of problem g (one workgroup; out in device memory).
 hipError_t launch_group_states(int G, int K, const GroupEntry *E, State *out, hipStream_t s);
+// Bit i % 32 of words[i / 32] = every one of problem i's K states is done, for
+// i < G; the other bits of the (G + 31) / 32 words are 0 (one workgroup).
+hipError_t launch_group_done(int G, int K, const GroupEntry *E, uint32_t *words, hipStream_t s);
+// Bytes of the grouped launches' static device scratch array.
+constexpr size_t kGroupScratchBytes = (size_t)4 << 20;
+// The address of that array on `device` (looked up once per device with the
+// device current) and its size.
+hipError_t group_scratch(int device, void **ptr, size_t *bytes);
 hipError_t launch_ir_force(int K, State *st, hipStream_t s);
 
 // ---- setup and single-step kernels ----

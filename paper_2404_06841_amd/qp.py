@@ -45,7 +45,7 @@ EXPORTED = (
     "qp_set_options", "qp_product_layout", "qp_set_product_layout", "qp_solve", "qp_solve_d", "qp_solve_multi_d", "qp_corrector",
     "qp_corrector_d",
     "qp_homogenized", "qp_homogenized_ex", "qp_homogenized_batch", "qp_homogenized_grouped",
-    "qp_server_create",
+    "qp_homogenized_grouped_noalloc", "qp_server_create",
     "qp_server_submit", "qp_server_progress", "qp_server_pending", "qp_server_bytes",
     "qp_server_destroy", "qp_coo_entries", "qp_coo_build_d", "qp_coo_matvec_d", "qp_dft_d",
     "qp_modes_from_spectrum", "qp_matvec_d", "qp_matvec32_d", "qp_matvec_half_d", "qp_precond_d",
@@ -124,6 +124,8 @@ def lib():
                                            C.POINTER(qp_solve_info)]),
         "qp_homogenized_grouped": (C.c_int, [C.POINTER(vp), C.c_int, dp, C.c_double,
                                            C.POINTER(qp_solve_info)]),
+        "qp_homogenized_grouped_noalloc": (C.c_int, [C.POINTER(vp), C.c_int, dp, C.c_double,
+                                                   C.POINTER(qp_solve_info)]),
         "qp_server_create": (C.c_int, [C.POINTER(vp), C.c_size_t, C.POINTER(qp_options)]),
         "qp_server_submit": (C.c_int, [vp, C.c_int, C.c_int, dp, C.c_int, ip, dp, dp, C.c_int,
                                        C.c_double, dp, C.POINTER(qp_solve_info),
@@ -470,17 +472,20 @@ class Problem:
 # Batches and serving
 # --------------------------------------------------------------------------
 
-def homogenized_batch(problems, tol: float = 1e-12, check: bool = True, grouped: bool = False):
+def homogenized_batch(problems, tol: float = 1e-12, check: bool = True, grouped: bool = False,
+                      noalloc: bool = False):
     """qp_homogenized_batch over Problem objects (each should own a distinct
     stream for the solves to overlap), or with grouped=True
-    qp_homogenized_grouped (one launch per solver step for all of them).
+    qp_homogenized_grouped (one launch per solver step for all of them), or
+    with noalloc=True as well qp_homogenized_grouped_noalloc.
     Returns (list of d x d A*, list of per-problem info lists, status)."""
     count = len(problems)
     ds = [pr.d for pr in problems]
     A = np.zeros(sum(d * d for d in ds))
     infos = (qp_solve_info * sum(ds))()
     hs = (C.c_void_p * count)(*[pr.h for pr in problems])
-    name = "qp_homogenized_grouped" if grouped else "qp_homogenized_batch"
+    name = ("qp_homogenized_grouped_noalloc" if noalloc else "qp_homogenized_grouped") \
+        if grouped else "qp_homogenized_batch"
     st = getattr(lib(), name)(hs, count, _dptr(A), float(tol), infos)
     if check:
         _check(st, name)
