@@ -28,6 +28,7 @@ HBM_PEAK_GBS = 8000.0
 TOL = 1e-12
 LATENCY_SAMPLES = 200  # homogenizations behind the latency percentiles
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_fp32_eightfold_n4_N32.txt")
+TRAFFIC_FILE_HBM = os.path.join(ROOT, "profiles", "matvec_icosahedral_n6_N16_dram.txt")
 # sources of the stiffness-product kernels (the product and its device helpers)
 MATVEC_SRC = [os.path.join(ROOT, "paper_2404_06841_amd", "csrc", f)
               for f in ("qp_matvec.hip", "qp_matvec_kernels.h", "qp_device.h")]
@@ -41,6 +42,10 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--product-probe", action="store_true",
+                    help="only run the HBM-sized stiffness products (icosahedral N=16, FP64 and "
+                         "float, five launches each after two warm-up launches) and the plain "
+                         "copies of --copy-probe, for counter runs")
     return ap.parse_args()
 
 
@@ -61,6 +66,31 @@ def copy_probe():
                       "kernels": ["runtime copy", "elementwise mul"]}), flush=True)
 
 
+def product_probe():
+    """The launches that the HBM-sized roofline is taken on: the icosahedral
+    N = 16 products (one right-hand side, FP64 then float, the layout the
+    autotuner picks for this shape), five of each after two warm-up launches,
+    then the copies of copy_probe."""
+    import torch
+
+    from paper_2404_06841_amd import qp
+    from paper_2404_06841_amd import workloads as W
+    prob = W.icosahedral(16)
+    gp = qp.Problem(prob, autotune=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(16)
+    for dtype, fn in ((torch.complex128, gp.matvec_d), (torch.complex64, gp.matvec32_d)):
+        u = torch.randn(prob.D, dtype=dtype, device="cuda", generator=gen)
+        y = torch.empty_like(u)
+        for _ in range(7):
+            fn(u, y)
+        del u, y
+    torch.cuda.synchronize()
+    print(json.dumps({"product_probe": prob.D, "layout": gp.layout(), "launches": 7}), flush=True)
+    gp.close()
+    copy_probe()
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for path in MATVEC_SRC:
@@ -69,20 +99,21 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(D: int):
-    """HBM bytes per float stiffness-product launch from the committed rocprofv3
-    counter summary, or None when it was taken on another kernel version."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path: str = TRAFFIC_FILE, key: str = "hbm_bytes_per_launch"):
+    """Memory-side bytes per stiffness-product launch from a committed
+    rocprofv3 counter summary (sized read and write requests), or None when
+    it was taken on another kernel version."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_hash") != kernel_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
@@ -121,20 +152,26 @@ def hbm_products(torch, qp, W):
     gen.manual_seed(16)
     out = {"workload": "icosahedral d=3 n=6 N=16 (16,777,216 unknowns, 13 modes)",
            "layout": gp.layout()}
-    # second denominator: a plain device-to-device copy of 512 MiB (read + write)
+    # second denominator: plain copies of 512 MiB (read + write): the runtime's
+    # device-to-device copy and an elementwise kernel (y = x * 1); the faster
     xc = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
     yc = torch.empty_like(xc)
-    for _ in range(2):
-        yc.copy_(xc)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record()
-    for _ in range(5):
-        yc.copy_(xc)
-    c1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2.0 * xc.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    rates = {}
+    for name, fn in (("runtime_copy", lambda: yc.copy_(xc)),
+                     ("elementwise", lambda: torch.mul(xc, 1.0, out=yc))):
+        for _ in range(2):
+            fn()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            fn()
+        c1.record()
+        torch.cuda.synchronize()
+        rates[name] = round(2.0 * xc.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9, 1)
     del xc, yc
-    out["copy_GBs"] = round(copy_gbs, 1)
+    copy_gbs = max(rates.values())
+    out["copy_GBs"] = copy_gbs
+    out["copy_GBs_by_kind"] = rates
     for name, dtype, fn, per in (("fp64", torch.complex128, gp.matvec_d, 32.0),
                                  ("fp32", torch.complex64, gp.matvec32_d, 16.0)):
         u = torch.randn(D, dtype=dtype, device="cuda", generator=gen)
@@ -161,29 +198,52 @@ def hbm_products(torch, qp, W):
     return out
 
 
-def half_storage(torch, qp, W):
-    """Hermitian half storage at odd N (icosahedral d=3, n=6, N=15: 11,390,625
-    unknowns, 5,695,313 stored): the FP64 product on the half against the
-    full-storage FP64 product of the same problem, each call bracketed by HIP
-    events on the library's stream.  Algorithmic bytes: 32 B per stored entry
-    (read once, write once)."""
+def half_storage(torch, np, qp, W, gold, steps: int = 5):
+    """Hermitian half storage at odd N (icosahedral d=3, n=6, N=15:
+    11,390,625 unknowns, 5,695,313 stored): the stiffness products of a
+    half-storage problem against the full-storage ones (each call bracketed
+    by HIP events on the library's stream; algorithmic bytes 32 B FP64 / 16 B
+    float per stored entry), and homogenizations on both storages in both
+    precisions, A* against the oracle's stored value."""
     prob = W.icosahedral(15)
-    gp = qp.Problem(prob, autotune=True)
+    A_ref = np.array(gold["icosa_N15"]["A"])
     D, H = prob.D, (prob.D + 1) // 2
     gen = torch.Generator(device="cuda")
     gen.manual_seed(15)
-    out = {"workload": "icosahedral d=3 n=6 N=15 (11,390,625 unknowns; 5,695,313 stored "
-                       "in half storage), FP64, one right-hand side"}
-    for name, fn, size in (("full", gp.matvec_d, D), ("half", gp.matvec_half_d, H)):
-        u = torch.randn(size, dtype=torch.complex128, device="cuda", generator=gen)
-        y = torch.empty_like(u)
-        us = per_launch_us(torch, lambda: fn(u, y))
-        gbs = 32.0 * size / (us * 1e-6) / 1e9
-        out[name] = {"avg_launch_us": round(us, 2), "algorithmic_bytes": int(32 * size),
-                     "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
-        del u, y
-    out["half_over_full_time"] = round(out["half"]["avg_launch_us"] / out["full"]["avg_launch_us"], 3)
-    gp.close()
+    out = {"workload": "icosahedral d=3 n=6 N=15 (11,390,625 unknowns; 5,695,313 stored in "
+                       "half storage), three correctors per homogenization"}
+    for storage in ("full", "half"):
+        res = {}
+        for prec in ("fp32ir", "fp64"):
+            gp = qp.Problem(prob, precision=prec, autotune=True, half_storage=(storage == "half"))
+            if prec == "fp32ir":
+                # the products (the FP64 and float kernels of this storage)
+                for name, dtype, fn, per in (("fp64", torch.complex128, gp.matvec_d, 32.0),
+                                             ("fp32", torch.complex64, gp.matvec32_d, 16.0)):
+                    u = torch.randn(gp.D, dtype=dtype, device="cuda", generator=gen)
+                    y = torch.empty_like(u)
+                    us = per_launch_us(torch, lambda: fn(u, y))
+                    res["product_" + name] = {
+                        "avg_launch_us": round(us, 2), "algorithmic_bytes": int(per * gp.D),
+                        "achieved_GBs": round(per * gp.D / (us * 1e-6) / 1e9, 1),
+                        "frac_of_hbm_peak": round(per * gp.D / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                    del u, y
+                res["layout"] = gp.layout()
+            gp.homogenized(tol=TOL, energy=False)  # warm-up
+            dt, _, r, _ = run_steps(gp, steps, torch)
+            res[prec] = {"value": round(prob.d * steps / dt, 2), "unit": "corrector solves/s",
+                         "ms_per_step": round(dt / steps * 1e3, 3),
+                         "astar_rel_err": float(np.abs(r.A - A_ref).max() / np.abs(A_ref).max()),
+                         "iters": [i.iters for i in r.infos]}
+            gp.close()
+        out[storage] = res
+    f, h = out["full"], out["half"]
+    out["half_over_full_product_time_fp64"] = round(
+        h["product_fp64"]["avg_launch_us"] / f["product_fp64"]["avg_launch_us"], 3)
+    out["half_over_full_product_time_fp32"] = round(
+        h["product_fp32"]["avg_launch_us"] / f["product_fp32"]["avg_launch_us"], 3)
+    out["half_speedup_fp32ir_solves"] = round(h["fp32ir"]["value"] / f["fp32ir"]["value"], 3)
+    out["half_speedup_fp64_solves"] = round(h["fp64"]["value"] / f["fp64"]["value"], 3)
     return out
 
 
@@ -473,6 +533,9 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+    if args.product_probe:
+        product_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
                                    "(independent solves shard by problem; one large solve "
@@ -534,7 +597,7 @@ def main():
     algo_bytes = 16.0 * D * (mv_rhs / mv_n) if mv_n else 16.0 * D
     avg_s = (mv_ms / mv_n) * 1e-3 if mv_n else float("nan")
     achieved = algo_bytes / avg_s / 1e9 if mv_n else None
-    traffic = measured_traffic(D)
+    traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
@@ -550,6 +613,24 @@ def main():
                 "profiled_pass_value": round(solves / dtp, 2),
                 "layout": layout}
     lat_sorted = np.sort(np.array(lat))
+    # the same roofline for the product at the HBM-sized shape (icosahedral
+    # N = 16, FP64, one right-hand side), where the vectors do not fit the
+    # caches; traffic from the committed sized-request counter summary
+    hbm = hbm_products(torch, qp, W)
+    h64 = hbm["fp64"]
+    traffic64 = measured_traffic(TRAFFIC_FILE_HBM, "fp64_bytes_per_launch")
+    roofline_hbm = {"bound": "hbm", "achieved": h64["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(h64["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                    "traffic": traffic64,
+                    "kernel": "k_matvec_plane<double> (FP64 stiffness product, one right-hand side), "
+                              "icosahedral d=3 n=6 N=16 (16,777,216 unknowns)",
+                    "avg_launch_us": h64["avg_launch_us"],
+                    "algorithmic_bytes_per_launch": h64["algorithmic_bytes"],
+                    "memory_side_GBs": (round(traffic64 / (h64["avg_launch_us"] * 1e-6) / 1e9, 1)
+                                        if traffic64 else None),
+                    "copy_GBs": hbm["copy_GBs"], "frac_of_copy": h64["frac_of_copy"],
+                    "timing": "HIP events around each call on the library's stream (the call "
+                              "returns after its launch)"}
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -588,8 +669,9 @@ def main():
         "roofline": roofline,
         "diagonal_coefficient": diagonal_workload(torch, np, qp, W, gold,
                                                   max(5, args.steps // 2), args.warmup),
-        "hbm_products": hbm_products(torch, qp, W),
-        "half_storage": half_storage(torch, qp, W),
+        "hbm_products": hbm,
+        "roofline_hbm": roofline_hbm,
+        "half_storage": half_storage(torch, np, qp, W, gold),
         "batch_instances": batch_instances(torch, np, qp, W),
         "stored_matrix": stored_matrix(torch, qp, W),
         "sampled_inputs": sampled_inputs(torch, qp),

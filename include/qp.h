@@ -121,6 +121,22 @@ typedef struct qp_options {
                            QP_ENOTELLIPTIC.  Q is then indefinite and a solve
                            may stop with QP_ENOTSPD ((Q h, h) <= 0, Alg. 2
                            breakdown; u holds the last iterate); default 0  */
+    int half_storage;   /* nonzero: Hermitian half storage (Sec. 2.3: the
+                           coefficients of a real function satisfy
+                           u_{-k} = conj(u_k), and with a real coefficient Q
+                           keeps that symmetry).  Odd N, a real scalar
+                           coefficient and n >= 2, N <= 32 (QP_EINVAL
+                           otherwise).  Every vector of the problem's calls
+                           (right-hand sides, solutions, correctors, products,
+                           preconditioner, multi-indices) then holds the
+                           (N^n + 1)/2 stored entries in the half layout of
+                           qp_matvec_half_d, qp_dim returns that count, and
+                           the solves move about half the bytes.  A
+                           right-hand side must be the half of a Hermitian
+                           vector (e.g. the coefficients of a real source).
+                           The stored-matrix calls are not available, the
+                           problem cannot join grouped calls, and a server
+                           rejects the option.  Fixed at creation; default 0 */
 } qp_options;
 
 typedef struct qp_solve_info {
@@ -169,7 +185,10 @@ typedef struct qp_layout {
     int xcd_front;      /* 1: each of the 8 XCDs sweeps a contiguous share of
                            the work items; 2: the same, with the slowest axis
                            varying fastest inside each share (when the shares
-                           are whole values of it, n >= 3; else as 1);
+                           are whole values of it, n >= 3; else as 1); 3: the
+                           same shares swept in blocks of the axes after the
+                           second one, each block through every value of the
+                           second axis (n >= 5; else as 2);
                            0: items in plain order                             */
     int tuned;          /* 0: fixed heuristics; 1: timed on this problem;
                            2: reused from an earlier problem of the same shape */
@@ -238,11 +257,13 @@ qp_status qp_create_diag(qp_problem **out, int d, int n, const double *P, int g,
 /* Release the problem and everything it owns.  NULL is ignored. */
 void qp_destroy(qp_problem *p);
 
-/* D = N^n. */
+/* Entries of the problem's vectors: D = N^n, or (N^n + 1)/2 with half
+ * storage. */
 int64_t qp_dim(const qp_problem *p);
 
 /* Replace the solver options (precision, preconditioner, limits, profile).
- * The stream and workspace of a created problem cannot change.  A change of
+ * The stream, workspace and half_storage of a created problem cannot change
+ * (the values passed for them are ignored).  A change of
  * precision waits for the problem's stream and re-derives the grid of the
  * vector kernels (chosen per precision). */
 qp_status qp_set_options(qp_problem *p, const qp_options *opt);
@@ -259,7 +280,7 @@ qp_status qp_product_layout(const qp_problem *p, qp_layout *out);
  * and with them the iterates, repeat bitwise.  Waits for the problem's stream
  * and drops its captured batches.  QP_EINVAL unless item_tiles is 1, 2 or 4
  * (1 for line tiles, N > 32 or n = 1), 1 <= workgroups <= 1024 and xcd_front
- * is 0, 1 or 2. */
+ * is 0, 1, 2 or 3. */
 qp_status qp_set_product_layout(qp_problem *p, const qp_layout *layout);
 
 /*

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqp.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(CSRC, f) for f in (
-    "qp_matvec.hip", "qp_matvec_diag.hip", "qp_group.hip", "qp_krylov.hip", "qp_setup.hip",
+    "qp_matvec.hip", "qp_matvec_diag.hip", "qp_matvec_half.hip", "qp_group.hip", "qp_krylov.hip", "qp_setup.hip",
     "qp_coo.hip", "qp_dft.hip", "qp_half.hip",
     "qp_api.cpp")]
 

@@ -87,7 +87,8 @@ struct Layout {
     size_t total;
 };
 
-Layout make_layout(int d, int n, int N, int64_t D, int g)
+// units: the plane-tile product's units (planes), 0 without plane tiles
+Layout make_layout(int d, int64_t D, int g, int64_t units)
 {
     Layout L{};
     size_t o = 0;
@@ -117,10 +118,10 @@ Layout make_layout(int d, int n, int N, int64_t D, int g)
     L.exec = take(sizeof(int) * kExecInts);
     L.tab = take(sizeof(Table));
     L.recs = take(sizeof(qp::ModeRec) * qp::kMaxG);
-    const size_t urecs = (size_t)plane_units(n, N) * (size_t)((g + 3) & ~3);
+    const size_t urecs = (size_t)units * (size_t)((g + 3) & ~3);
     for (int prec = 0; prec < 2; ++prec) {
         L.urec[prec] = take(qp::kUnitRecBytes[prec] * urecs);
-        L.upku[prec] = take((prec == qp::F64 ? 8 : 4) * (size_t)qp::kMaxD * plane_units(n, N));
+        L.upku[prec] = take((prec == qp::F64 ? 8 : 4) * (size_t)qp::kMaxD * (size_t)units);
     }
     L.total = o;
     return L;
@@ -272,6 +273,23 @@ void stream_grid(Table &T, int precision)
     T.nblocks = (int)((D + chunk - 1) / chunk);
 }
 
+// Default grid of the stiffness product from its work items: (unit,
+// consecutive tiles of the unit), about four per workgroup for plane tiles.
+void default_product_grid(Table &T)
+{
+    const int64_t units = T.ntiles / T.tiles_per_unit;
+    const int64_t items = T.tile_s > 1
+                              ? units * ((T.tiles_per_unit + T.item_tiles - 1) / T.item_tiles)
+                              : units * ((T.tiles_per_unit + 3) / 4);
+    const int64_t want = T.tile_s > 1 ? (items + 3) / 4 : items;
+    int nbm = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, want));
+    if (nbm >= 8) nbm -= nbm % 8;
+    T.nb_mv = nbm;
+    T.item_tiles64 = T.item_tiles;
+    T.nb_mv64 = T.nb_mv;
+    T.xcd_front64 = T.xcd_front;
+}
+
 // coefs: null for a scalar coefficient, else d x g complex (a_l's Ahat per mode)
 void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *modes,
                  const double *coef, const double *coefs, int N)
@@ -398,17 +416,34 @@ void build_table(Table &T, int d, int n, const double *P, int g, const int32_t *
             T.slab_span = (int)(units_all / 8 / S1);
         }
     }
+    default_product_grid(T);
+    stream_grid(T, QP_PREC_FP64);
+}
+
+// Hermitian half storage (real scalar coefficient, odd N, plane tiles): the
+// vectors hold the (N^n + 1)/2 stored entries (see qp_internal.h), the
+// product's units are the stored planes, and the mode indices become
+// positions: midx = the position of m when m is stored, else -1 (the
+// corrector source there is implied by its conjugate at -m); nidx = the
+// position of -m, or of m with nconj set when -m is not stored.
+void make_half(Table &T)
+{
+    const int N = T.N, n = T.n;
+    T.half = 1;
+    T.Dgrid = T.D;
+    T.D = (T.Dgrid + 1) / 2;
     const int64_t units = T.ntiles / T.tiles_per_unit;
-    const int64_t items = T.tile_s > 1
-                              ? units * ((T.tiles_per_unit + T.item_tiles - 1) / T.item_tiles)
-                              : units * ((T.tiles_per_unit + 3) / 4);
-    const int64_t want = T.tile_s > 1 ? (items + 3) / 4 : items;
-    int nbm = (int)std::min<int64_t>(qp::kMaxBlocks, std::max<int64_t>(1, want));
-    if (nbm >= 8) nbm -= nbm % 8;
-    T.nb_mv = nbm;
-    T.item_tiles64 = T.item_tiles;
-    T.nb_mv64 = T.nb_mv;
-    T.xcd_front64 = T.xcd_front;
+    T.half_units = (int)((units + 1) / 2);
+    T.ntiles = T.half_units * T.tiles_per_unit;
+    T.slab_units = T.slab_stride = T.slab_span = 0;
+    for (int r = 0; r < T.g; ++r) {
+        const long long mi = T.midx[r], ni = T.nidx[r];
+        T.midx[r] = qp::half_stored(mi, N, n) ? (int)qp::half_position(mi, N, n) : -1;
+        const bool neg_stored = qp::half_stored(ni, N, n);
+        T.nidx[r] = (int)qp::half_position(neg_stored ? ni : mi, N, n);
+        T.nconj[r] = neg_stored ? 0 : 1;
+    }
+    default_product_grid(T);
     stream_grid(T, QP_PREC_FP64);
 }
 
@@ -1308,6 +1343,8 @@ qp_status check_options(const qp_options *o)
     if (o->maxit < 1 || !(o->inner_tol > 0.0) || o->inner_tol >= 1.0 ||
         o->poll_every < 0 || o->poll_every > kMaxBatch)
         return fail(QP_EINVAL, "invalid iteration limits or inner tolerance");
+    if (o->half_storage && o->gather64)
+        return fail(QP_EINVAL, "half storage uses the 32-bit gathers (gather64 must be 0)");
     return QP_OK;
 }
 
@@ -1350,7 +1387,7 @@ size_t qp_workspace_bytes(int d, int n, int N, int g)
         if (D >= ((int64_t)1 << 31)) return 0;
     }
     if (g < 1 || g > QP_MAX_MODES) return 0;
-    return make_layout(d, n, N, D, g).total;
+    return make_layout(d, D, g, plane_units(n, N)).total;
 }
 
 // coefs: null (scalar coefficient `coef`) or d x g complex (diagonal coefficient)
@@ -1395,8 +1432,9 @@ std::vector<LayoutPick> layout_candidates(const Table &T)
         const int64_t items = units * ((tpu + it - 1) / it);
         for (int per : {1, 2, 4}) {
             const int nb = grid_for((items + 4 * per - 1) / (4 * per));
-            for (int xcd : {1, 0, 2}) {
+            for (int xcd : {1, 0, 2, 3}) {
                 if (xcd == 2 && T.slab_span == 0) continue;
+                if (xcd == 3 && (T.slab_span == 0 || T.n < 5)) continue;  // blocks need 3 uniform axes
                 const LayoutPick L{it, nb, xcd};
                 if (std::find(c.begin(), c.end(), L) == c.end()) c.push_back(L);
             }
@@ -1509,8 +1547,8 @@ qp_status tune_layout(qp_problem *p)
     p->layout = qp_layout{};
     report_layout(p, 0);
     if (T.tile_s <= 1) return QP_OK;  // line tiles: one layout
-    const std::vector<int> key = {T.d,         T.n,    T.N,       T.g,      T.aniso,
-                                  T.real_coef, T.wide, T.tile_s,  p->opt.precision};
+    const std::vector<int> key = {T.d,         T.n,    T.N,      T.g,              T.aniso,
+                                  T.real_coef, T.wide, T.tile_s, p->opt.precision, T.half};
     {
         std::lock_guard<std::mutex> lock(g_layout_mu);
         const auto f = g_layouts.find(key);
@@ -1577,6 +1615,21 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     if (!p) return fail(QP_ENOMEM, "host allocation failed");
     p->opt = o;
     build_table(p->host, d, n, P, g, modes, coef, coefs, N);
+    if (o.half_storage) {
+        if (N % 2 == 0) {
+            delete p;
+            return fail(QP_EINVAL, "half storage needs odd N (N = %d)", N);
+        }
+        if (coefs || !p->host.real_coef) {
+            delete p;
+            return fail(QP_EINVAL, "half storage needs a real scalar coefficient");
+        }
+        if (!plane_tiles(n, N)) {
+            delete p;
+            return fail(QP_EINVAL, "half storage needs plane tiles (n >= 2, N <= 32)");
+        }
+        make_half(p->host);
+    }
     stream_grid(p->host, o.precision);
     // record indices of the default gathers are scaled by the record size in
     // 32 bits; the largest records are the interleaved float families of d
@@ -1585,7 +1638,8 @@ static qp_status create_problem(qp_problem **out, int d, int n, const double *P,
     if (p->host.tile_s > 1 &&
         (o.gather64 || (int64_t)p->host.D * std::max(2, d) * 8 >= ((int64_t)1 << 32)))
         p->host.wide = 1;
-    p->L = make_layout(d, n, N, p->host.D, g);
+    p->L = make_layout(d, p->host.D, g,
+                       p->host.tile_s > 1 ? p->host.ntiles / p->host.tiles_per_unit : 0);
 
     auto bail = [&](qp_status st) {
         release(p);
@@ -1690,7 +1744,7 @@ qp_status qp_set_product_layout(qp_problem *p, const qp_layout *layout)
         return fail(QP_EINVAL, "workgroups = %d outside [1, %d]", L.workgroups, qp::kMaxBlocks);
     if (plane ? (L.item_tiles != 1 && L.item_tiles != 2 && L.item_tiles != 4) : L.item_tiles != 1)
         return fail(QP_EINVAL, "item_tiles = %d is not 1, 2 or 4 (1 for line tiles)", L.item_tiles);
-    if (L.xcd_front < 0 || L.xcd_front > 2) return fail(QP_EINVAL, "xcd_front must be 0, 1 or 2");
+    if (L.xcd_front < 0 || L.xcd_front > 3) return fail(QP_EINVAL, "xcd_front must be 0, 1, 2 or 3");
     if (L.workgroups64 > 0) {
         if (L.workgroups64 > qp::kMaxBlocks)
             return fail(QP_EINVAL, "workgroups64 = %d outside [1, %d]", L.workgroups64, qp::kMaxBlocks);
@@ -1698,8 +1752,8 @@ qp_status qp_set_product_layout(qp_problem *p, const qp_layout *layout)
                   : L.item_tiles64 != 1)
             return fail(QP_EINVAL, "item_tiles64 = %d is not 1, 2 or 4 (1 for line tiles)",
                         L.item_tiles64);
-        if (L.xcd_front64 < 0 || L.xcd_front64 > 2)
-            return fail(QP_EINVAL, "xcd_front64 must be 0, 1 or 2");
+        if (L.xcd_front64 < 0 || L.xcd_front64 > 3)
+            return fail(QP_EINVAL, "xcd_front64 must be 0, 1, 2 or 3");
     } else if (L.workgroups64 < 0) {
         return fail(QP_EINVAL, "workgroups64 = %d is negative", L.workgroups64);
     }
@@ -1744,10 +1798,12 @@ qp_status qp_set_options(qp_problem *p, const qp_options *opt)
     if (!p || !opt) return fail(QP_EINVAL, "null argument");
     QP_TRY(check_options(opt));
     const int old_precond = p->opt.precond, old_precision = p->opt.precision;
+    const int half = p->opt.half_storage;
     void *stream = p->opt.stream;
     p->opt = *opt;
     p->opt.stream = stream;
     p->opt.workspace = nullptr;
+    p->opt.half_storage = half;  // the storage is fixed at creation
     if (opt->precision != old_precision) {
         // the streaming grid follows the precision; captured batches hold the old one
         QP_HIP(hipStreamSynchronize(p->stream));
@@ -1936,6 +1992,7 @@ const char *group_mismatch(const qp_problem *p, const qp_problem *p0)
     if (p->opt.precision != QP_PREC_FP32_IR) return "precision is not FP32-IR";
     if (p->host.tile_s <= 1 || p->host.wide) return "not a plane-tile problem with 32-bit gathers";
     if (p->host.aniso) return "diagonal coefficient";
+    if (p->host.half) return "Hermitian half storage";
     if (p->host.d != 2 && p->host.d != 3) return "d is not 2 or 3";
     if (p->host.d != p0->host.d) return "d differs from problem 0";
     if (p->host.real_coef != p0->host.real_coef) return "real/complex coefficient differs from problem 0";
@@ -2246,6 +2303,7 @@ qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 qp_status qp_matvec_half_d(qp_problem *p, const double *u, double *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
+    if (p->host.half) return qp_matvec_d(p, u, y);  // its vectors are the half already
     if (p->host.N % 2 == 0)
         return fail(QP_EINVAL, "Hermitian half storage needs odd N (N = %d)", p->host.N);
     if (p->host.aniso)
@@ -2344,12 +2402,13 @@ qp_status qp_modes_from_spectrum(int n, int N, const double *spec, double rel_to
 
 int64_t qp_coo_entries(const qp_problem *p)
 {
-    return p ? (int64_t)p->host.D * p->host.g : 0;
+    return (p && !p->host.half) ? (int64_t)p->host.D * p->host.g : 0;
 }
 
 qp_status qp_coo_build_d(qp_problem *p, int32_t *rows, int32_t *cols, double *vals)
 {
     if (!p || !rows || !cols || !vals) return fail(QP_EINVAL, "null argument");
+    if (p->host.half) return fail(QP_EINVAL, "the stored matrix is built on full storage");
     QP_HIP(qp::launch_coo_build(p->tab, p->host, rows, cols, vals, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
     return QP_OK;
@@ -2359,6 +2418,7 @@ qp_status qp_coo_matvec_d(qp_problem *p, const int32_t *cols, const double *vals
                           double *y)
 {
     if (!p || !cols || !vals || !u || !y) return fail(QP_EINVAL, "null argument");
+    if (p->host.half) return fail(QP_EINVAL, "the stored matrix is built on full storage");
     if (overlaps(u, y, 16 * (size_t)p->host.D)) return fail(QP_EINVAL, "u and y must not overlap");
     QP_HIP(qp::launch_coo_matvec(p->host, cols, vals, u, y, p->stream));
     QP_HIP(hipStreamSynchronize(p->stream));
@@ -2445,6 +2505,8 @@ qp_status qp_server_create(qp_server **out, size_t hbm_budget, const qp_options 
     qp_default_options(&o);
     if (opt) o = *opt;
     QP_TRY(check_options(&o));
+    if (o.half_storage)
+        return fail(QP_EINVAL, "the server's problems use full storage (half_storage must be 0)");
     o.stream = nullptr;     // every cached problem gets a stream of its own
     o.workspace = nullptr;  // and a workspace of its own
     o.workspace_bytes = 0;

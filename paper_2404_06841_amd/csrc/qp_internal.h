@@ -68,7 +68,64 @@ struct Table {
                               // side per launch (else 32-bit record indices)
     uint64_t slotmask[64];    // tile_s > 1: per tile of a plane, bit r when sorted mode
                               // r's neighbour leaves [0, N) or K_N in axis n-2 for some line
+    // ---- Hermitian half storage (real scalar coefficient, odd N, plane tiles):
+    // vectors hold the (N^n + 1)/2 stored entries of the half layout below,
+    // D is that count, and the product's units are the stored planes ----
+    int half;                 // 1: half storage
+    int Dgrid;                // N^n (= D without half storage)
+    int half_units;           // stored planes: (N^(n-2) + 1)/2, the center plane first
+    int nconj[kMaxG];         // half storage: chi at C(-m) is conj(chi[nidx[r]])
 };
+
+// ---- Hermitian half layout (odd N) ----
+// The stored half of an m-dimensional grid (digits b_t in [0, N), first
+// axis slowest) is k = 0 and every k whose first nonzero signed component is
+// positive: the index ranges [S, (N+1)/2 S) for S = 1, N, ..., N^(m-1) (the
+// first nonzero digit at place S lies in [1, (N-1)/2]).  Position 0 holds
+// k = 0; index i of range S sits at position i - (S - 1)/2; positions run to
+// (N^m + 1)/2.  For the n-dimensional vectors the layout is the center plane
+// (uniform digits 0; its own half, positions [0, (N^2+1)/2)) followed by whole
+// planes in the half order of the (n-2)-dimensional plane grid: stored plane
+// hu >= 1 starts at position (N^2 + 1)/2 + (hu - 1) N^2.
+__host__ __device__ inline long long half_index(long long pos, int N, int m)
+{
+    if (pos == 0) return 0;
+    long long S = 1, top = 1;
+    for (int t = 1; t < m; ++t) top *= N;
+    while (S < top && (S * N + 1) / 2 <= pos) S *= N;
+    return pos + (S - 1) / 2;
+}
+// Position of index i, which must lie in the stored half (i = 0 or its first
+// nonzero digit in [1, (N-1)/2]).
+__host__ __device__ inline long long half_position(long long i, int N, int m)
+{
+    if (i == 0) return 0;
+    long long S = 1;
+    for (int t = 1; t < m; ++t) S *= N;
+    while (S > i) S /= N;
+    return i - (S - 1) / 2;
+}
+// Whether index i of an m-dimensional grid lies in the stored half.
+__host__ __device__ inline bool half_stored(long long i, int N, int m)
+{
+    if (i == 0) return true;
+    long long S = 1;
+    for (int t = 1; t < m; ++t) S *= N;
+    while (S > i) S /= N;
+    return (i / S) % N <= (N - 1) / 2;
+}
+// Index of -k for index i (every digit b -> (N - b) mod N).
+__host__ __device__ inline long long mirror_index(long long i, int N, int m)
+{
+    long long out = 0, S = 1;
+    for (int t = 0; t < m; ++t) {
+        const long long b = i % N;
+        i /= N;
+        out += ((N - b) % N) * S;
+        S *= N;
+    }
+    return out;
+}
 
 // Per-mode record of the tiled stiffness product, in sorted order.
 struct alignas(128) ModeRec {
@@ -105,6 +162,22 @@ struct alignas(16) UnitRecA {
     T ai[DT];   // Im(Ahat of a_l at m); 0 for padding
     int lb;     // as UnitRec
     int mslot;
+};
+// Unit record of the plane-tile product on Hermitian half storage: as
+// UnitRec, with the source plane's place in the half layout.  kind 0: the
+// source plane is stored, lb as UnitRec's relative to its first position;
+// kind 1: its mirror (every digit negated) is stored from position lb, read
+// at the mirrored in-plane digits and conjugated; kind 2: the source is the
+// center plane (stored as its own half), resolved per lane.
+template <typename T, int DT>
+struct alignas(16) HalfRec {
+    T apm[DT];
+    T a;
+    T cr, ci;
+    int lb;
+    int mslot;
+    int kind;
+    int pad;
 };
 // bytes reserved per record (at least the size of either record for d =
 // kMaxD), by Precision
@@ -211,6 +284,16 @@ hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table
 // of qp_matvec_half_d); scalar real coefficient, odd N (checked by the caller).
 hipError_t launch_matvec_half(const Table *tab, const Table &ht, const void *u, void *y,
                               hipStream_t s);
+// The same on Hermitian half storage (tab.half; called by launch_matvec): x and
+// y hold the tab.D stored entries; the unit records are those of
+// launch_unit_records on a half-storage table.
+hipError_t launch_matvec_tiled_half(int prec, int epi, int K, const Table *tab, const Table &ht,
+                                    const ModeRec *recs, const void *urec, const void *upku,
+                                    const void *x, void *y, const double *f, const float *M32,
+                                    const Parts &parts, State *st, int *exec, hipStream_t s,
+                                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_unit_records_half(int prec, const Table *tab, const Table &ht,
+                                    const ModeRec *recs, void *urec, void *upku, hipStream_t s);
 // The same for a diagonal coefficient (tab.aniso; called by launch_matvec).
 hipError_t launch_matvec_diag(int prec, int epi, int K, const Table *tab, const Table &ht,
                               const ModeRec *recs, const void *urec, const void *upku,

@@ -11,6 +11,9 @@ hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table
                          int *exec, hipStream_t s, hipEvent_t ev0,
                          hipEvent_t ev1)
 {
+    if (ht.half)
+        return launch_matvec_tiled_half(prec, epi, K, tab, ht, recs, urec, upku, x, y, f, M32,
+                                        parts, st, exec, s, ev0, ev1);
     if (ht.aniso)
         return launch_matvec_diag(prec, epi, K, tab, ht, recs, urec, upku, x, y, f, M32, parts, st,
                                   exec, s, ev0, ev1);
@@ -21,6 +24,7 @@ hipError_t launch_matvec(int prec, int epi, int K, const Table *tab, const Table
 hipError_t launch_unit_records(int prec, const Table *tab, const Table &ht, const ModeRec *recs,
                                void *urec, void *upku, hipStream_t s)
 {
+    if (ht.half) return launch_unit_records_half(prec, tab, ht, recs, urec, upku, s);
     if (ht.aniso) return launch_unit_records_diag(prec, tab, ht, recs, urec, upku, s);
     return unit_records_entry<false>(prec, tab, ht, recs, urec, upku, s);
 }

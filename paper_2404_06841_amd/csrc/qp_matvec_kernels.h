@@ -455,10 +455,15 @@ static_assert(sizeof(UnitRec<double, kMaxD>) <= kUnitRecBytes[F64], "unit record
 static_assert(sizeof(UnitRec<float, kMaxD>) <= kUnitRecBytes[F32], "unit record size");
 static_assert(sizeof(UnitRecA<double, kMaxD>) <= kUnitRecBytes[F64], "unit record size");
 static_assert(sizeof(UnitRecA<float, kMaxD>) <= kUnitRecBytes[F32], "unit record size");
+static_assert(sizeof(HalfRec<double, kMaxD>) <= kUnitRecBytes[F64], "unit record size");
+static_assert(sizeof(HalfRec<float, kMaxD>) <= kUnitRecBytes[F32], "unit record size");
 
 // Record type of the plane kernel: scalar coefficient or diagonal (App. D).
 template <typename T, int DT, bool AN>
 using PlaneRec = typename std::conditional<AN, UnitRecA<T, DT>, UnitRec<T, DT>>::type;
+// ... and of its Hermitian half-storage variant (scalar coefficient only).
+template <typename T, int DT, bool AN, bool HALF>
+using TileRec = typename std::conditional<HALF, HalfRec<T, DT>, PlaneRec<T, DT, AN>>::type;
 
 // One thread per (unit, padded mode): the record of sorted mode r (padding:
 // the zero mode with weight 0), computed in FP64 and rounded once.
@@ -525,6 +530,82 @@ __global__ __launch_bounds__(kBlock) void k_unit_records(const Table *__restrict
                 double pu = 0.0;
                 for (int t = 0; t < nu; ++t) pu += tab->P[l][t] * (double)ku[t];
                 upku[(size_t)unit * DT + l] = (T)pu;
+            }
+        }
+    }
+}
+
+// Unit records on Hermitian half storage: one thread per (stored plane hu,
+// padded mode).  The weight fields are those of k_unit_records for the
+// plane's unit index (the neighbour's signed representative does not depend
+// on storage); the source fields place the neighbour plane in the half
+// layout: stored (kind 0), mirrored (kind 1) or the center plane (kind 2).
+template <typename T, int DT>
+__global__ __launch_bounds__(kBlock) void k_unit_records_half(const Table *__restrict__ tab,
+                                                              const ModeRec *__restrict__ recs,
+                                                              HalfRec<T, DT> *__restrict__ out,
+                                                              T *__restrict__ upku)
+{
+    const int N = tab->N, n = tab->n, g = tab->g;
+    const int gp = (g + 3) & ~3;
+    const int nu = n - 2;  // uniform axes (the plane grid's dimension)
+    const int lo = -(N / 2), hi = N - 1 - N / 2;
+    const int c0 = (N * N + 1) / 2;
+    const long long total = (long long)tab->half_units * gp;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total;
+         e += (long long)gridDim.x * kBlock) {
+        const int hu = (int)(e / gp);
+        const int r = (int)(e - (long long)hu * gp);
+        const long long unit = half_index(hu, N, nu);
+        int ibu[kMaxN], ku[kMaxN];
+        long long rest = unit;
+        for (int t = nu - 1; t >= 0; --t) {
+            const long long q = rest / N;
+            ibu[t] = (int)(rest - q * N);
+            ku[t] = (2 * ibu[t] < N) ? ibu[t] : ibu[t] - N;
+            rest = q;
+        }
+        const ModeRec &M = recs[r < g ? r : tab->zero_sorted];
+        double v[DT];
+        for (int l = 0; l < DT; ++l) v[l] = M.pm[l];
+        long long src = 0;  // the neighbour plane's unit index
+        for (int t = 0; t < nu; ++t) {
+            const int m = M.mt[t];
+            int jb = ibu[t] - m;
+            jb += (jb < 0) ? N : 0;
+            jb -= (jb >= N) ? N : 0;
+            src = src * N + jb;
+            const int kd = ku[t] - m;
+            const int c = (kd < lo) ? 1 : ((kd > hi) ? -1 : 0);
+            for (int l = 0; l < DT; ++l) v[l] -= (double)c * N * tab->P[l][t];
+        }
+        HalfRec<T, DT> R;
+        const double a = (r >= g) ? 0.0 : M.c[0];
+        for (int l = 0; l < DT; ++l) R.apm[l] = (T)(a * v[l]);
+        R.a = (T)a;
+        R.cr = (r >= g) ? (T)0 : (T)M.c[0];
+        R.ci = (T)0;
+        R.mslot = M.mt[n - 2];
+        R.pad = 0;
+        if (r >= g) {
+            R.kind = 0;
+            R.lb = kNoNeighbour;  // reads zero
+        } else if (src == 0) {
+            R.kind = 2;
+            R.lb = 0;
+        } else if (half_stored(src, N, nu)) {
+            R.kind = 0;
+            R.lb = c0 + (int)(half_position(src, N, nu) - 1) * N * N - R.mslot * N;
+        } else {
+            R.kind = 1;
+            R.lb = c0 + (int)(half_position(mirror_index(src, N, nu), N, nu) - 1) * N * N;
+        }
+        out[e] = R;
+        if (r == 0) {
+            for (int l = 0; l < DT; ++l) {
+                double pu = 0.0;
+                for (int t = 0; t < nu; ++t) pu += tab->P[l][t] * (double)ku[t];
+                upku[(size_t)hu * DT + l] = (T)pu;
             }
         }
     }
@@ -603,11 +684,11 @@ __device__ __forceinline__ void wave_sync()
 
 // The product as workgroup vb of vnb (the whole grid of a plain launch, a
 // problem's range of a grouped one).
-template <typename T, int DT, int EPI, bool REAL, int KR, bool WIDE, bool AN>
+template <typename T, int DT, int EPI, bool REAL, int KR, bool WIDE, bool AN, bool HALF = false>
 __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                                              const Table *__restrict__ tab,
                                              const ModeRec *__restrict__ recs,
-                                             const PlaneRec<T, DT, AN> *__restrict__ urec,
+                                             const TileRec<T, DT, AN, HALF> *__restrict__ urec,
                                              const T *__restrict__ upku,
                                              const cplx_t<T> *__restrict__ x,
                                              void *__restrict__ yv,
@@ -628,9 +709,10 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
     }
     if (nact == 0) return;
     static_assert(!WIDE || KR == 1, "64-bit gathers serve one right-hand side");
+    static_assert(!HALF || (REAL && !AN && !WIDE), "half storage: real scalar coefficient");
     // neighbour loads in flight per chunk: about Inflight<T> over all right-hand sides
     constexpr int KC = (Inflight<T>::v / KR >= 8) ? (Inflight<T>::v / KR) / 4 * 4 : 4;
-    using Rec = PlaneRec<T, DT, AN>;
+    using Rec = TileRec<T, DT, AN, HALF>;
     // dynamic LDS: gp * kWave lane-geometry entries (column, face factor),
     // then kWaves * gp unit records
     extern __shared__ int2 s_geo[];
@@ -683,7 +765,9 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
     const int it = F64L ? tab->item_tiles64 : tab->item_tiles;
     const int xfront = F64L ? tab->xcd_front64 : tab->xcd_front;
     const int ipu = (tpu + it - 1) / it;  // items per unit
-    const int nitems = (tab->ntiles / tpu) * ipu;
+    const int nitems = (tab->ntiles / tpu) * ipu;  // half storage: the stored planes'
+    const int hh = (N - 1) / 2;                    // half storage: largest stored digit
+    const int c0 = (N * N + 1) / 2;                // half storage: first whole plane
     const int nw = vnb * kWaves;
     const int b = vb;
     const bool by_xcd = xfront && (vnb % 8 == 0);
@@ -700,16 +784,34 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
 
     // xcd_front 2: inside each XCD's eighth of the units (a slab of span
     // consecutive values of the slowest axis), that axis varies fastest, so a
-    // unit's neighbours along it are swept next to it (see Table)
-    const int span = (by_xcd && xfront == 2) ? tab->slab_span : 0;
+    // unit's neighbours along it are swept next to it (see Table).
+    // xcd_front 3: the eighth is swept in blocks of the axes after the second
+    // one (a quarter of them for FP64, half for float), each block through
+    // every value of the second axis, so the neighbour layers along that axis
+    // stay in the XCD's L2 while the block advances
+    const int span = (by_xcd && (xfront == 2 || xfront == 3) && !HALF) ? tab->slab_span : 0;
     for (int item = ibeg + loc; item < iend; item += nloc) {
         int unit = item / ipu;
         const int tl0 = (item - unit * ipu) * it;
         if (span > 0) {
             const int E = tab->slab_units, S1 = tab->slab_stride;
             const int e = unit / E, ul = unit - e * E;
-            const int rest = ul / span;
-            unit = e * E + (ul - rest * span) * S1 + rest;
+            if (xfront == 2) {
+                const int rest = ul / span;
+                unit = e * E + (ul - rest * span) * S1 + rest;
+            } else {
+                // ul = ((block * N + a1) * span + a0) * B + r, with R = S1 / N
+                // units per (a0, a1) and blocks of B of them
+                const int R = S1 / N;
+                int B = R / (F64L ? 4 : 2);
+                if (B < 1 || R % B != 0) B = R;
+                const int r = ul % B;
+                int q = ul / B;
+                const int a0 = q % span;
+                q /= span;
+                const int a1 = q % N;
+                unit = e * E + a0 * S1 + a1 * R + (q / N) * B + r;
+            }
         }
         // ---- the unit's records to this wave's LDS ----
         {
@@ -811,6 +913,27 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                         wr[m] = REAL ? wv : Q.cr * wv;
                         wi[m] = REAL ? (T)0 : Q.ci * wv;
                     }
+                    T sgn_im = (T)1;  // half storage: -1 reads the stored conjugate
+                    if constexpr (HALF) {
+                        if (Q.kind != 0) {
+                            // the neighbour's in-plane digits (slot, column)
+                            int sp = ibs - Q.mslot;
+                            sp += (sp < 0) ? N : 0;
+                            sp -= (sp >= N) ? N : 0;
+                            const int cp = ge.x;
+                            if (Q.kind == 1) {  // mirrored plane: digits negated
+                                idx = Q.lb + (sp ? N - sp : 0) * N + (cp ? N - cp : 0);
+                                sgn_im = (T)-1;
+                            } else if (sp >= 1 && sp <= hh) {  // center plane, stored
+                                idx = sp * N + cp - hh;
+                            } else if (sp == 0 && cp <= hh) {
+                                idx = cp;
+                            } else {  // center plane, mirrored
+                                idx = (sp ? (N - sp) * N - hh : 0) + (cp ? N - cp : 0);
+                                sgn_im = (T)-1;
+                            }
+                        }
+                    }
                     if constexpr (ILV) {
                         const f32x4_t v0 = struct_load_f32x4(xi, idx, 0, 0, 0);
                         *reinterpret_cast<float2 *>(&u[m][0]) = make_float2(v0.x, v0.y);
@@ -827,6 +950,10 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
 #pragma unroll
                         for (int k = 0; k < KR; ++k)
                             u[m][k] = WIDE ? x[(unsigned)idx] : gather<T>(xr[k], idx);
+                    }
+                    if constexpr (HALF) {
+#pragma unroll
+                        for (int k = 0; k < KR; ++k) u[m][k].y *= sgn_im;
                     }
                 }
 #pragma unroll
@@ -855,8 +982,22 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                 }
                 for (; rb < gp; rb += 4) chunk(integral_constant<int, 4>(), rb);
             }
-            if (active) {
-                const size_t i = (size_t)(L0 + s) * N + p;
+            bool store = active;
+            size_t i = (size_t)(L0 + s) * N + p;
+            if constexpr (HALF) {
+                // unit = stored plane hu: whole planes from c0; the center plane
+                // stores k = 0 and the (slot, position) with a positive first
+                // nonzero component
+                if (unit > 0) {
+                    i = (size_t)c0 + (size_t)(unit - 1) * N * N + (size_t)ibs * N + p;
+                } else if (ibs >= 1 && ibs <= hh) {
+                    i = (size_t)ibs * N + p - hh;
+                } else {
+                    i = (size_t)p;
+                    store = store && ibs == 0 && p <= hh;
+                }
+            }
+            if (store) {
 #pragma unroll
                 for (int k = 0; k < KR; ++k) {
                     if (!act[k]) continue;
@@ -876,10 +1017,10 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
         *exec = nact;
 }
 
-template <typename T, int DT, int EPI, bool REAL, int KR, bool WIDE, bool AN>
+template <typename T, int DT, int EPI, bool REAL, int KR, bool WIDE, bool AN, bool HALF = false>
 __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict__ tab,
                                                          const ModeRec *__restrict__ recs,
-                                                         const PlaneRec<T, DT, AN> *__restrict__ urec,
+                                                         const TileRec<T, DT, AN, HALF> *__restrict__ urec,
                                                          const T *__restrict__ upku,
                                                          const cplx_t<T> *__restrict__ x,
                                                          void *__restrict__ yv,
@@ -889,8 +1030,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec_plane(const Table *__restrict
                                                          State *__restrict__ st,
                                                          int *__restrict__ exec)
 {
-    matvec_plane<T, DT, EPI, REAL, KR, WIDE, AN>((int)blockIdx.x, (int)gridDim.x, tab, recs, urec,
-                                                 upku, x, yv, f, M32, part, st, exec);
+    matvec_plane<T, DT, EPI, REAL, KR, WIDE, AN, HALF>((int)blockIdx.x, (int)gridDim.x, tab, recs,
+                                                       urec, upku, x, yv, f, M32, part, st, exec);
 }
 
 // Grouped FP32-IR product: the float product of h into q with the alpha
@@ -929,7 +1070,7 @@ void launch_timed(F kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipE
         hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
 }
 
-template <typename T, int EPI, bool REAL, int KR, bool WIDE, bool AN>
+template <typename T, int EPI, bool REAL, int KR, bool WIDE, bool AN, bool HALF = false>
 hipError_t launch_plane(const Table &ht, size_t lds, const Table *tab, const ModeRec *recs,
                         const void *urec, const T *Pu, const cplx_t<T> *X, void *y,
                         const double2 *Fv, const float *M32, double *part, State *st, int *exec,
@@ -940,10 +1081,10 @@ hipError_t launch_plane(const Table &ht, size_t lds, const Table *tab, const Mod
     switch (ht.d) {
 #define QP_CASE(DD)                                                                              \
     case DD:                                                                                      \
-        launch_timed(k_matvec_plane<T, DD, EPI, REAL, KR, WIDE, AN>, grid, block,               \
-                     lds + kWaves * gp * sizeof(PlaneRec<T, DD, AN>), s, ev0, ev1, tab, recs,   \
-                     static_cast<const PlaneRec<T, DD, AN> *>(urec), Pu, X, y, Fv, M32, part,   \
-                     st, exec);                                                                  \
+        launch_timed(k_matvec_plane<T, DD, EPI, REAL, KR, WIDE, AN, HALF>, grid, block,         \
+                     lds + kWaves * gp * sizeof(TileRec<T, DD, AN, HALF>), s, ev0, ev1, tab,     \
+                     recs, static_cast<const TileRec<T, DD, AN, HALF> *>(urec), Pu, X, y, Fv,   \
+                     M32, part, st, exec);                                                       \
         break;
         QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
 #undef QP_CASE
@@ -1073,6 +1214,79 @@ hipError_t unit_records_entry(int prec, const Table *tab, const Table &ht, const
                             : unit_records<double, false, AN>(tab, ht, recs, urec, upku, s);
     return ht.real_coef ? unit_records<float, true, AN>(tab, ht, recs, urec, upku, s)
                         : unit_records<float, false, AN>(tab, ht, recs, urec, upku, s);
+}
+
+// Entry points of the Hermitian half-storage product (real scalar
+// coefficient, plane tiles, 32-bit gathers), by precision and epilogue.
+template <typename T, int EPI>
+hipError_t dispatch_half(int K, const Table *tab, const Table &ht, const ModeRec *recs,
+                         const void *urec, const void *upku, const void *x, void *y,
+                         const double *f, const float *M32, double *part, State *st, int *exec,
+                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (!ht.half || !ht.real_coef || ht.aniso || ht.tile_s <= 1 || !urec || !upku)
+        return hipErrorInvalidValue;
+    const size_t lds = sizeof(int2) * kWave * (size_t)((ht.g + 3) & ~3);
+    auto X = static_cast<const cplx_t<T> *>(x);
+    auto Fv = reinterpret_cast<const double2 *>(f);
+    auto Pu = static_cast<const T *>(upku);
+    switch (K) {
+#define QP_K(KK)                                                                                \
+    case KK:                                                                                     \
+        return launch_plane<T, EPI, true, KK, false, false, true>(ht, lds, tab, recs, urec, Pu, X, \
+                                                                  y, Fv, M32, part, st, exec, s,  \
+                                                                  ev0, ev1);
+        QP_K(1) QP_K(2) QP_K(3) QP_K(4)
+#undef QP_K
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+inline hipError_t matvec_half_entry(int prec, int epi, int K, const Table *tab, const Table &ht,
+                                    const ModeRec *recs, const void *urec, const void *upku,
+                                    const void *x, void *y, const double *f, const float *M32,
+                                    const Parts &parts, State *st, int *exec, hipStream_t s,
+                                    hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (prec == F64) {
+        if (epi == EPI_NONE)
+            return dispatch_half<double, EPI_NONE>(K, tab, ht, recs, urec, upku, x, y, f, M32,
+                                                   parts.a, st, exec, s, ev0, ev1);
+        if (epi == EPI_ALPHA)
+            return dispatch_half<double, EPI_ALPHA>(K, tab, ht, recs, urec, upku, x, y, f, M32,
+                                                    parts.a, st, exec, s, ev0, ev1);
+        return dispatch_half<double, EPI_RESID>(K, tab, ht, recs, urec, upku, x, y, f, M32,
+                                                parts.b, st, exec, s, ev0, ev1);
+    }
+    if (epi == EPI_NONE)
+        return dispatch_half<float, EPI_NONE>(K, tab, ht, recs, urec, upku, x, y, f, M32, parts.a,
+                                              st, exec, s, ev0, ev1);
+    if (epi == EPI_ALPHA)
+        return dispatch_half<float, EPI_ALPHA>(K, tab, ht, recs, urec, upku, x, y, f, M32, parts.a,
+                                               st, exec, s, ev0, ev1);
+    return hipErrorInvalidValue;  // the replaced residual is always computed in FP64
+}
+
+template <typename T>
+hipError_t unit_records_half(const Table *tab, const Table &ht, const ModeRec *recs, void *urec,
+                             void *upku, hipStream_t s)
+{
+    const long long total = (long long)ht.half_units * ((ht.g + 3) & ~3);
+    const int grid = (int)std::min<long long>(4096, (total + kBlock - 1) / kBlock);
+    auto Pu = static_cast<T *>(upku);
+    switch (ht.d) {
+#define QP_CASE(DD)                                                                          \
+    case DD:                                                                                  \
+        hipLaunchKernelGGL((k_unit_records_half<T, DD>), dim3(grid), dim3(kBlock), 0, s, tab,   \
+                           recs, static_cast<HalfRec<T, DD> *>(urec), Pu);                     \
+        break;
+        QP_CASE(1) QP_CASE(2) QP_CASE(3) QP_CASE(4)
+#undef QP_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace

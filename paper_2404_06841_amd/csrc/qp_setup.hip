@@ -6,11 +6,13 @@
 namespace qp {
 namespace {
 
-// Storage digits of entry i (last digit fastest) and its signed index.
+// Storage digits of entry i (last digit fastest) and its signed index; on
+// Hermitian half storage entry i is the stored position i, whose grid index
+// half_index gives.
 __device__ __forceinline__ void digits(const Table *__restrict__ tab, int i, int *ib)
 {
     const int N = tab->N;
-    int rest = i;
+    int rest = tab->half ? (int)half_index(i, N, tab->n) : i;
     for (int t = tab->n - 1; t >= 0; --t) {
         const int q = div_n(tab, rest);
         ib[t] = rest - q * N;
@@ -215,7 +217,8 @@ __global__ void k_astar(const Table *__restrict__ tab, const double2 *__restrict
     double re = (i == j) ? tab->a0l[i] : 0.0;
     double im = 0.0;
     for (int r = 0; r < g; ++r) {
-        const double2 c = cj[tab->nidx[r]];
+        double2 c = cj[tab->nidx[r]];
+        if (tab->nconj[r]) c.y = -c.y;  // half storage: chi at -m is conj(chi at m)
         const double ar = tab->coefl[r][i][0], ai = tab->coefl[r][i][1];
         const double pr = ar * c.x - ai * c.y;  // Ahat_m chi
         const double pi = ar * c.y + ai * c.x;

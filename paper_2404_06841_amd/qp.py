@@ -59,7 +59,8 @@ class qp_options(C.Structure):
                 ("inner_tol", C.c_double), ("poll_every", C.c_int),
                 ("profile", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("graphs", C.c_int),
-                ("gather64", C.c_int), ("autotune", C.c_int), ("allow_indefinite", C.c_int)]
+                ("gather64", C.c_int), ("autotune", C.c_int), ("allow_indefinite", C.c_int),
+                ("half_storage", C.c_int)]
 
 
 class qp_layout(C.Structure):
@@ -250,10 +251,13 @@ class Problem:
                  maxit: int = 10000, inner_tol: float = 1e-5,
                  profile: bool = False, stream=None, poll_every: int = 0,
                  graphs: bool = True, gather64: bool = False, autotune: bool = False,
-                 allow_indefinite: bool = False):
+                 allow_indefinite: bool = False, half_storage: bool = False):
         import torch
         self.d, self.n, self.N = int(prob.d), int(prob.n), int(prob.N)
-        self.D = self.N ** self.n
+        self.Dgrid = self.N ** self.n
+        # entries of every vector: the grid, or its Hermitian half
+        self.D = (self.Dgrid + 1) // 2 if half_storage else self.Dgrid
+        self.half = bool(half_storage)
         modes = np.asarray(prob.modes, dtype=np.int32).reshape(-1, self.n)
         self.g = modes.shape[0]
         opt = qp_default_options()
@@ -267,6 +271,7 @@ class Problem:
         opt.gather64 = 1 if gather64 else 0
         opt.autotune = 1 if autotune else 0
         opt.allow_indefinite = 1 if allow_indefinite else 0
+        opt.half_storage = 1 if half_storage else 0
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         nbytes = qp_workspace_bytes(self.d, self.n, self.N, self.g)
@@ -388,7 +393,7 @@ class Problem:
         """y = Q u on Hermitian half storage: (D+1)//2 complex128 entries each
         (real coefficient, odd N; the layout of qp_matvec_half_d)."""
         import torch
-        H = (self.D + 1) // 2
+        H = (self.Dgrid + 1) // 2
         if out is None:
             out = torch.empty(H, dtype=torch.complex128, device="cuda")
         _check(lib().qp_matvec_half_d(self.h, _tensor_ptr(u, torch.complex128, H),

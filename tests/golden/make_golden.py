@@ -30,6 +30,8 @@ CASES = {
     # the largest serving request and the HBM-sized product shape: d = 3,
     # n = 6, N = 16 (16,777,216 unknowns), three correctors
     "icosa_N16": lambda: W.icosahedral(16),
+    # odd N = 15 (11,390,625 unknowns): the Hermitian half-storage workload
+    "icosa_N15": lambda: W.icosahedral(15),
 }
 
 

@@ -35,6 +35,8 @@ LAYOUTS += [(1, 1, 0), (4, 3, 1), (2, 1000, 1)]
 # slab order (xcd_front 2): the slowest axis innermost inside each XCD's eighth
 # (identity where the eighths are not whole slabs, as for N = 6 here)
 LAYOUTS += [(4, 1024, 2), (1, 256, 2), (2, 24, 2), (1, 1, 2)]
+# blocked slab order (xcd_front 3; as the slab order below five axes)
+LAYOUTS += [(4, 1024, 3), (1, 256, 3), (2, 8, 3)]
 
 
 def say(*a):
@@ -114,7 +116,8 @@ def test_large_icosahedral_products_against_the_oracle():
     e32 = np.abs(y32[ix].cpu().numpy() - ref32).max() / np.abs(ref32).max()
     say(f"  {rows.size} rows: FP64 rel err {e64:.2e}, float {e32:.2e}")
     assert e64 <= 1e-13 and e32 <= 2e-5
-    for L in [(2, 1024, 2), (4, 1024, 2), (1, 512, 2), (1, 1024, 1)]:
+    for L in [(2, 1024, 2), (4, 1024, 2), (1, 512, 2), (1, 1024, 1), (4, 1024, 3), (2, 1024, 3),
+              (1, 512, 3)]:
         a.set_layout(*L)
         assert torch.equal(a.matvec_d(u), y64), L
         assert torch.equal(a.matvec32_d(u32), y32), L
@@ -189,7 +192,7 @@ def test_separate_fp64_layout():
 
 def test_invalid_layouts_are_rejected():
     a = qp.Problem(W.eightfold(8))
-    for L in [(3, 8, 0), (1, 0, 0), (1, 1025, 0), (1, 8, 3)]:
+    for L in [(3, 8, 0), (1, 0, 0), (1, 1025, 0), (1, 8, 4)]:
         with pytest.raises(qp.QPError) as e:
             a.set_layout(*L)
         assert e.value.status == qp.QP_EINVAL

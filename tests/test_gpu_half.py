@@ -125,3 +125,144 @@ def test_half_product_rejects_even_N_and_diagonal_coefficients():
         gp.matvec_half_d(u)
     assert e.value.status == qp.QP_EINVAL
     gp.close()
+
+
+# ------------------------------------------------------------- half-storage problems
+#
+# A problem created with half_storage keeps every vector in the half layout:
+# its product, preconditioner, corrector sources and solves run on the
+# (D+1)/2 stored entries.  Each is compared with the oracle's full-storage
+# result at the stored indices.
+
+REAL_CASES = {
+    "icosa_N5": lambda: W.icosahedral(5),
+    "icosa_N7": lambda: W.icosahedral(7),
+    "eightfold_random_N9": lambda: W.eightfold_random(9, 3),
+    "eightfold_N5": lambda: W.eightfold(5),
+    "cubic_d3_n3_N7": lambda: W.periodic_cubic(3, 7),
+    "three_mode_1d_N9": lambda: W.one_d_three_mode(9),   # n = 2: the center plane only
+}
+
+
+@pytest.fixture(scope="module", params=sorted(REAL_CASES))
+def half_case(request):
+    prob = REAL_CASES[request.param]()
+    say(f"[case] half {request.param} n={prob.n} N={prob.N} D={prob.D} g={prob.g}")
+    gp = qp.Problem(prob, half_storage=True)
+    assert gp.D == (prob.D + 1) // 2 and qp.lib().qp_dim(gp.h) == gp.D
+    yield request.param, prob, gp
+    gp.close()
+
+
+def test_half_problem_products_match_oracle(half_case):
+    name, prob, gp = half_case
+    idx, uh, full = hermitian_pair(prob, seed=prob.N + 1)
+    ref = oracle.matvec(prob, full)[idx]
+    y = gp.matvec_d(torch.from_numpy(uh).cuda()).cpu().numpy()
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    # float data and arithmetic
+    uh32 = uh.astype(np.complex64)
+    ref32 = oracle.matvec(prob, hermitian_full(prob, idx, uh32.astype(np.complex128)))[idx]
+    y32 = gp.matvec32_d(torch.from_numpy(uh32).cuda()).cpu().numpy()
+    e32 = np.abs(y32 - ref32).max() / np.abs(ref32).max()
+    say(f"  FP64 rel err {err:.2e}, float {e32:.2e}")
+    assert err <= 1e-13 and e32 <= 2e-5
+    assert y[0] == 0
+
+
+def hermitian_full(prob, idx, uh):
+    full = np.zeros(prob.D, dtype=np.complex128)
+    full[idx] = uh
+    full[negated(prob.n, prob.N, idx[1:])] = np.conj(uh[1:])
+    return full
+
+
+def test_half_problem_setup_matches_oracle(half_case):
+    name, prob, gp = half_case
+    idx = half_indices(prob.n, prob.N)
+    M = gp.precond_d().cpu().numpy()
+    refM = oracle.precond(prob, 0)[idx]
+    assert np.abs(M - refM).max() <= 1e-13 * np.abs(refM).max()
+    k = gp.multi_index_d().cpu().numpy()
+    for p in np.unique(np.concatenate([np.arange(min(idx.size, 600)), [idx.size - 1]])):
+        assert tuple(k[p]) == oracle.multi_index(prob.n, prob.N, int(idx[p])), p
+    for j in range(prob.d):
+        F = gp.corrector_rhs_d(j).cpu().numpy()
+        refF = oracle.corrector_rhs(prob, j)[idx]
+        assert np.abs(F - refF).max() <= 1e-15 * max(1.0, np.abs(refF).max()), j
+    lo, hi = gp.coef_extrema()
+    rlo, rhi = oracle.coef_extrema(prob)
+    assert lo == pytest.approx(rlo, abs=1e-12) and hi == pytest.approx(rhi, abs=1e-12)
+
+
+def test_half_problem_solves_match_oracle(half_case):
+    name, prob, gp = half_case
+    idx, Fh, Ffull = hermitian_pair(prob, seed=40 + prob.N)
+    U, info = gp.solve_d(torch.from_numpy(Fh).cuda(), tol=1e-12)
+    ref, st, it, _ = oracle.pcg(prob, Ffull, tol=1e-12)
+    U = U.cpu().numpy()
+    say(f"  solve iters {info.iters} (oracle {it}) rel resid {info.rel_resid:.2e}")
+    assert info.status == 0 and st == 0 and abs(info.iters - it) <= 2
+    assert np.linalg.norm(U - ref[idx]) <= 1e3 * 1e-12 * np.linalg.norm(ref[idx])
+    r0 = oracle.homogenize(prob, tol=1e-12)
+    for prec in ("fp64", "fp32ir"):
+        gp.set_precision(prec)
+        r = gp.homogenized(tol=1e-12)
+        scale = max(np.abs(r0.A).max(), 1.0)
+        err = np.abs(r.A - r0.A).max() / scale
+        say(f"  {prec} A* rel err {err:.2e} iters {[i.iters for i in r.infos]} "
+            f"(oracle {[i.iters for i in r0.infos]})")
+        assert all(i.status == 0 and i.rel_resid <= 1e-12 for i in r.infos), prec
+        assert err <= 1e-10, (prec, r.A, r0.A)
+    gp.set_precision("fp64")
+
+
+def test_half_problem_large_icosahedral():
+    """Icosahedral N = 15: 11,390,625 unknowns, 5,695,313 stored.  The FP64
+    and float products at sampled positions against the oracle row by row;
+    A* of both precisions against the oracle's stored value."""
+    import json
+    import os
+    prob = W.icosahedral(15)
+    gp = qp.Problem(prob, half_storage=True)
+    say(f"[case] half icosahedral N=15 H={gp.D} layout {gp.layout()}")
+    idx, uh, full = hermitian_pair(prob, seed=15)
+    y = gp.matvec_d(torch.from_numpy(uh).cuda()).cpu().numpy()
+    y32 = gp.matvec32_d(torch.from_numpy(uh.astype(np.complex64)).cuda()).cpu().numpy()
+    rng = np.random.default_rng(5)
+    pos = np.unique(np.concatenate([rng.integers(1, idx.size, 3000), [1, idx.size - 1],
+                                    np.arange(1, 200), np.arange(113 * 113 // 2, 113 * 113 // 2 + 40)]))
+    ref = oracle.matvec_rows(prob, full, idx[pos])
+    full32 = hermitian_full(prob, idx, uh.astype(np.complex64).astype(np.complex128))
+    ref32 = oracle.matvec_rows(prob, full32, idx[pos])
+    err = np.abs(y[pos] - ref).max() / np.abs(ref).max()
+    e32 = np.abs(y32[pos] - ref32).max() / np.abs(ref32).max()
+    say(f"  sampled rel err FP64 {err:.2e} float {e32:.2e}")
+    assert err <= 1e-13 and e32 <= 2e-5
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "oracle_astar.json")))["icosa_N15"]
+    A_ref = np.array(gold["A"])
+    for prec in ("fp64", "fp32ir"):
+        gp.set_precision(prec)
+        r = gp.homogenized(tol=1e-12)
+        e = np.abs(r.A - A_ref).max() / np.abs(A_ref).max()
+        say(f"  {prec}: iters {[i.iters for i in r.infos]} (oracle {gold['iters']}) A* rel err {e:.2e}")
+        assert all(i.status == 0 for i in r.infos) and e <= 1e-10, prec
+    gp.close()
+
+
+def test_half_storage_rejections():
+    for prob, why in ((W.eightfold(8), "odd N"), (W.paper_four_mode_2d(7), "real scalar"),
+                      (W.eightfold_diagonal(9, 1), "real scalar"),
+                      (W.one_d_two_mode(33, 6.0), "plane tiles")):
+        with pytest.raises(qp.QPError) as e:
+            qp.Problem(prob, half_storage=True)
+        assert e.value.status == qp.QP_EINVAL and why in str(e.value), (prob.name, str(e.value))
+    a = qp.Problem(W.eightfold(7), precision="fp32ir", half_storage=True)
+    b = qp.Problem(W.eightfold(9), precision="fp32ir")
+    with pytest.raises(qp.QPError) as e:
+        qp.homogenized_batch([b, a], tol=1e-12, grouped=True)
+    assert e.value.status == qp.QP_EINVAL
+    assert qp.lib().qp_coo_entries(a.h) == 0
+    a.close()
+    b.close()
