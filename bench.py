@@ -31,7 +31,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_fp32_eightfold_n4_
 TRAFFIC_FILE_HBM = os.path.join(ROOT, "profiles", "matvec_icosahedral_n6_N16_dram.txt")
 # sources of the stiffness-product kernels (the product and its device helpers)
 MATVEC_SRC = [os.path.join(ROOT, "paper_2404_06841_amd", "csrc", f)
-              for f in ("qp_matvec.hip", "qp_matvec_kernels.h", "qp_device.h")]
+              for f in ("qp_matvec.hip", "qp_matvec_half.hip", "qp_matvec_kernels.h",
+                        "qp_device.h")]
 
 
 def parse_args():
@@ -44,8 +45,11 @@ def parse_args():
                     help="only run a plain device copy of known size (counter calibration)")
     ap.add_argument("--product-probe", action="store_true",
                     help="only run the HBM-sized stiffness products (icosahedral N=16, FP64 and "
-                         "float, five launches each after two warm-up launches) and the plain "
-                         "copies of --copy-probe, for counter runs")
+                         "float; icosahedral N=15 FP64 on full and on half storage; seven "
+                         "launches each) and the plain copies of --copy-probe, for counter runs")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only run the headline FP32-IR homogenizations (warm-up and timed "
+                         "steps) and print their rate, for counter runs")
     return ap.parse_args()
 
 
@@ -88,6 +92,20 @@ def product_probe():
     torch.cuda.synchronize()
     print(json.dumps({"product_probe": prob.D, "layout": gp.layout(), "launches": 7}), flush=True)
     gp.close()
+    # Hermitian half storage at odd N: the FP64 product on the full and on the
+    # half problem (each with the layout the autotuner picks for it)
+    prob = W.icosahedral(15)
+    for half in (False, True):
+        gp = qp.Problem(prob, autotune=True, half_storage=half)
+        u = torch.randn(gp.D, dtype=torch.complex128, device="cuda", generator=gen)
+        y = torch.empty_like(u)
+        for _ in range(7):
+            gp.matvec_d(u, y)
+        torch.cuda.synchronize()
+        print(json.dumps({"product_probe": gp.D, "half_storage": half, "layout": gp.layout(),
+                          "launches": 7}), flush=True)
+        del u, y
+        gp.close()
     copy_probe()
 
 
@@ -559,6 +577,11 @@ def main():
     err_ir = float(np.abs(r.A - A_ref).max() / np.abs(A_ref).max())
     solves = prob.d * args.steps
     value = solves / dt
+    if args.headline_only:
+        print(json.dumps({"headline_only": round(value, 2), "steps": args.steps,
+                          "astar_rel_err": err_ir, "layout": gp.layout()}), flush=True)
+        gp.close()
+        return
     # latency percentiles over more samples than the timed steps (outside the
     # timed region; each homogenization timed on its own)
     _, lat, _, _ = run_steps(gp, LATENCY_SAMPLES, torch)
