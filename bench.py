@@ -652,6 +652,7 @@ def main():
                     "memory_side_GBs": (round(traffic64 / (h64["avg_launch_us"] * 1e-6) / 1e9, 1)
                                         if traffic64 else None),
                     "copy_GBs": hbm["copy_GBs"], "frac_of_copy": h64["frac_of_copy"],
+                    "profile_mean_us": measured_traffic(TRAFFIC_FILE_HBM, "fp64_mean_duration_us"),
                     "timing": "HIP events around each call on the library's stream (the call "
                               "returns after its launch)"}
     out = {

@@ -336,27 +336,6 @@ def random_vector(D: int, seed: int, dtype=np.complex128) -> np.ndarray:
     return v.astype(dtype)
 
 
-def sparse_vector(n: int, N: int, table: dict) -> np.ndarray:
-    """Dense length-N^n vector holding table[k] at k (signed index, stored k mod N)."""
-    D = N ** n
-    v = np.zeros(D, dtype=np.complex128)
-    for k, val in table.items():
-        i = 0
-        for t in range(n):
-            i = i * N + (int(k[t]) % N)
-        v[i] += val
-    return v
-
-
-def sine_source(n: int, N: int, axes) -> np.ndarray:
-    """F for f = sum_{t in axes} sin(y_t): Fhat_{+e_t} = -i/2, Fhat_{-e_t} = +i/2."""
-    table = {}
-    for t in axes:
-        table[_unit(n, t, 1)] = -0.5j
-        table[_unit(n, t, -1)] = 0.5j
-    return sparse_vector(n, N, table)
-
-
 def exponential_solution_modes(n_axes: int = 2, half: int = 32) -> dict:
     """Coefficients uhat_k = exp(-(|k1|+|k2|)) for -half <= k1,k2 < half (Sec. 5.1.2)."""
     out = {}

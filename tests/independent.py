@@ -157,3 +157,25 @@ def fits_strictly(keys, n: int, N: int) -> bool:
 def all_signed(n: int, N: int):
     lo = -(N // 2)
     return itertools.product(range(lo, lo + N), repeat=n)
+
+
+def sparse_vector(n: int, N: int, table: dict) -> np.ndarray:
+    """Dense vector of the grid K_N^n holding table[k] at signed index k
+    (storage position from numpy's row-major raveling of k mod N, the FFT
+    order of every axis)."""
+    v = np.zeros(N ** n, dtype=np.complex128)
+    for k, val in table.items():
+        v[np.ravel_multi_index(tuple(int(x) % N for x in k), (N,) * n)] += val
+    return v
+
+
+def sine_source(n: int, N: int, axes) -> np.ndarray:
+    """F for f = sum_{t in axes} sin(y_t): Fhat_{+e_t} = -i/2, Fhat_{-e_t} = +i/2."""
+    table = {}
+    for t in axes:
+        e = [0] * n
+        e[t] = 1
+        table[tuple(e)] = -0.5j
+        e[t] = -1
+        table[tuple(e)] = 0.5j
+    return sparse_vector(n, N, table)

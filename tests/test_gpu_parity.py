@@ -21,6 +21,7 @@ import pytest
 
 import oracle
 from paper_2404_06841_amd import workloads as W
+from tests.independent import sine_source
 
 pytestmark = pytest.mark.gpu
 
@@ -310,7 +311,7 @@ def test_dependent_projection_rejected():
 def test_degenerate_field_flag_and_solve():
     prob = W.one_d_two_mode(8, 2.0)  # A = 0 at the grid point (pi, pi)
     gp = qp.Problem(prob)
-    F = W.sine_source(2, 8, [0, 1])
+    F = sine_source(2, 8, [0, 1])
     U, info = gp.solve_d(dev(F), tol=1e-12)
     assert info.flags & qp.QP_FLAG_DEGENERATE
     ref, st, it, rr = oracle.pcg(prob, F, tol=1e-12)

@@ -182,7 +182,7 @@ def test_ex1_iterations_soft_pin():
     ref = GOLD["ex1_cpcg"]
     for N, iters in zip(ref["N"][:5], ref["iterations"][:5]):
         prob, u = _ex1(N)
-        F = W.sparse_vector(2, N, ind.continuum_rhs(prob, u))
+        F = ind.sparse_vector(2, N, ind.continuum_rhs(prob, u))
         _, st, it, _ = oracle.pcg(prob, F, tol=1e-10)
         assert st == 0 and abs(it - iters) <= 1, (N, it, iters)
 
@@ -191,9 +191,9 @@ def test_ex1_iterations_soft_pin():
 def test_ex1_machine_precision(N):
     # Paper, Sec. 5.1.1: e_N ~ 3e-16..6e-16 once N >= 8 (all modes resolved).
     prob, u = _ex1(N)
-    F = W.sparse_vector(2, N, ind.continuum_rhs(prob, u))
+    F = ind.sparse_vector(2, N, ind.continuum_rhs(prob, u))
     U, st, it, rr = oracle.pcg(prob, F, tol=1e-15, maxit=200)
-    e = np.linalg.norm(U - W.sparse_vector(2, N, u))  # l2 of coefficients = L2_QP norm (Parseval)
+    e = np.linalg.norm(U - ind.sparse_vector(2, N, u))  # l2 of coefficients = L2_QP norm (Parseval)
     paper = dict(zip(GOLD["ex1_cpcg"]["N"], GOLD["ex1_cpcg"]["e_N"]))[N]
     assert e <= 20 * paper, (e, paper)
 
@@ -205,8 +205,8 @@ def test_manufactured_solution_2d_n4():
          (0, 0, 1, 0): -0.5j, (0, 0, -1, 0): 0.5j, (0, 0, 0, 1): 0.5, (0, 0, 0, -1): 0.5}
     f = ind.continuum_rhs(prob, u)
     assert ind.fits_strictly(f.keys(), 4, 6)
-    U, st, it, rr = oracle.pcg(prob, W.sparse_vector(4, 6, f), tol=1e-15, maxit=300)
-    e = np.linalg.norm(U - W.sparse_vector(4, 6, u))
+    U, st, it, rr = oracle.pcg(prob, ind.sparse_vector(4, 6, f), tol=1e-15, maxit=300)
+    e = np.linalg.norm(U - ind.sparse_vector(4, 6, u))
     assert e <= 50 * GOLD["ex_2d_n4"]["e_N"][1]
 
 
@@ -222,8 +222,8 @@ def test_manufactured_solution_random_modes_and_faces():
             u[k] = complex(rng.standard_normal(), rng.standard_normal())
     f = ind.continuum_rhs(prob, u)
     assert ind.fits_strictly(f.keys(), 4, 12)
-    U, st, it, rr = oracle.pcg(prob, W.sparse_vector(4, 12, f), tol=1e-14, maxit=500)
-    ue = W.sparse_vector(4, 12, u)
+    U, st, it, rr = oracle.pcg(prob, ind.sparse_vector(4, 12, f), tol=1e-14, maxit=500)
+    ue = ind.sparse_vector(4, 12, u)
     assert np.linalg.norm(U - ue) <= 1e-12 * np.linalg.norm(ue)
 
 
@@ -237,9 +237,9 @@ def test_spectral_decay_ex2():
         prob = W.one_d_two_mode(N, mean=6.0, scale=2 * np.pi)
         f = ind.continuum_rhs(prob, uhat)
         f = {k: v for k, v in f.items() if ind.fits_strictly([k], 2, N)}  # truncation T_N
-        U, st, it, rr = oracle.pcg(prob, W.sparse_vector(2, N, f), tol=1e-15, maxit=400)
+        U, st, it, rr = oracle.pcg(prob, ind.sparse_vector(2, N, f), tol=1e-15, maxit=400)
         exact = {k: v for k, v in uhat.items() if any(k)}  # u_N has zero mean
-        ue = W.sparse_vector(2, N, {k: v for k, v in exact.items() if ind.fits_strictly([k], 2, N)})
+        ue = ind.sparse_vector(2, N, {k: v for k, v in exact.items() if ind.fits_strictly([k], 2, N)})
         tail = sum(abs(v) ** 2 for k, v in exact.items() if not ind.fits_strictly([k], 2, N))
         errs.append(np.sqrt(np.linalg.norm(U - ue) ** 2 + tail))
     assert all(b < a for a, b in zip(errs, errs[1:]))
