@@ -634,10 +634,22 @@ __device__ __forceinline__ void put_output(size_t i, size_t ex, size_t ey, T acc
         dots[0] += (double)M32[i] * ((double)o.x * (double)o.x + (double)o.y * (double)o.y);
         dots[1] += rx * rx + ry * ry;
     } else {
-        cplx_t<T> o;
-        o.x = acc_re;
-        o.y = acc_im;
-        static_cast<cplx_t<T> *>(yv)[ey] = o;
+        if constexpr (sizeof(T) == 8) {
+            // FP64 outputs are written nontemporally (no later read in this
+            // kernel): faster at vectors larger than the caches, with the
+            // same memory-side traffic; float outputs stay ordinary stores,
+            // since the next kernel reads them while they are still cached
+            typedef double v2d __attribute__((ext_vector_type(2)));
+            v2d o;
+            o.x = acc_re;
+            o.y = acc_im;
+            __builtin_nontemporal_store(o, reinterpret_cast<v2d *>(static_cast<cplx_t<T> *>(yv) + ey));
+        } else {
+            cplx_t<T> o;
+            o.x = acc_re;
+            o.y = acc_im;
+            static_cast<cplx_t<T> *>(yv)[ey] = o;
+        }
         if (EPI == EPI_ALPHA) {
             const cplx_t<T> xi = x[ex];
             dots[0] += (double)xi.x * (double)acc_re + (double)xi.y * (double)acc_im;
