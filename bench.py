@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 METRIC = "corrector solves/s + matvec HBM GB/s, FP32-IR vs FP64 @1e-10; p99 latency"
 HBM_PEAK_GBS = 8000.0
 TOL = 1e-12
+# batch instances with at most this many unknowns run grouped beside the
+# per-problem streams of the larger ones (qp_homogenized_batch_mixed)
+MIXED_GROUP_DIM = 1 << 15
 LATENCY_SAMPLES = 200  # homogenizations behind the latency percentiles
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_fp32_eightfold_n4_N32.txt")
 TRAFFIC_FILE_HBM = os.path.join(ROOT, "profiles", "matvec_icosahedral_n6_N16_dram.txt")
@@ -50,7 +53,68 @@ def parse_args():
     ap.add_argument("--headline-only", action="store_true",
                     help="only run the headline FP32-IR homogenizations (warm-up and timed "
                          "steps) and print their rate, for counter runs")
+    ap.add_argument("--batch-breakdown", action="store_true",
+                    help="only time the 64-instance FP32-IR batch by size class (instances "
+                         "alone, on streams, grouped) and print one line per class")
     return ap.parse_args()
+
+
+def batch_breakdown():
+    """The FP32-IR batch of batch_instances split by instance size: for all
+    instances, the N = 32 ones and the smaller ones, the sum of the times each
+    instance takes alone, the time on per-problem streams and the time grouped;
+    then the whole batch with the instances up to several size limits grouped
+    beside the streams of the others (median of three runs after a warm-up)."""
+    import torch
+
+    from paper_2404_06841_amd import qp
+    from paper_2404_06841_amd import workloads as W
+    probs = W.eightfold_batch(64)
+    gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream(), autotune=True)
+           for pr in probs]
+    alone = []
+    for gp in gps:
+        gp.homogenized(tol=TOL, energy=False)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            gp.homogenized(tol=TOL, energy=False)
+            ts.append(time.perf_counter() - t0)
+        alone.append(sorted(ts)[1])
+
+    def timed(sub, grouped):
+        qp.homogenized_batch(sub, tol=TOL, grouped=grouped)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            qp.homogenized_batch(sub, tol=TOL, grouped=grouped)
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[1]
+
+    for name, keep in (("all", lambda N: True), ("N=32", lambda N: N == 32),
+                       ("N<=24", lambda N: N <= 24), ("N<=16", lambda N: N <= 16)):
+        idx = [i for i, pr in enumerate(probs) if keep(pr.N)]
+        sub = [gps[i] for i in idx]
+        print(json.dumps({"batch_breakdown": name, "instances": len(idx),
+                          "unknowns": int(sum(probs[i].D for i in idx)),
+                          "alone_sum_ms": round(sum(alone[i] for i in idx) * 1e3, 2),
+                          "streams_ms": round(timed(sub, False) * 1e3, 2),
+                          "grouped_ms": round(timed(sub, True) * 1e3, 2)}), flush=True)
+    # the whole batch with the instances up to a size limit grouped
+    for limit in (4096, 20736, 1 << 15, 65536, 331776):
+        qp.homogenized_batch(gps, tol=TOL, group_max_dim=limit)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            qp.homogenized_batch(gps, tol=TOL, group_max_dim=limit)
+            ts.append(time.perf_counter() - t0)
+        print(json.dumps({"batch_breakdown": "mixed", "group_max_dim": limit,
+                          "grouped_instances": sum(1 for pr in probs if pr.D <= limit),
+                          "ms": round(sorted(ts)[1] * 1e3, 2)}), flush=True)
+    for gp in gps:
+        gp.close()
 
 
 def copy_probe():
@@ -359,7 +423,9 @@ def batch_instances(torch, np, qp, W, reps: int = 3):
     stream), and one after another, on the same problems.  FP64 (the
     comparison leg): the same instances by qp_homogenized_batch and one after
     another.  Grouped and stream results are compared with the sequential
-    ones bitwise, and the instances with N <= 12 with the oracle."""
+    ones bitwise, and the instances with N <= 12 with the oracle.  The work
+    bound is the time of all instances' iterations at the best rate (per
+    unknown and iteration) that an instance reaches when solved alone."""
     import oracle
     probs = W.eightfold_batch(64)
     solves = sum(pr.d for pr in probs)
@@ -380,17 +446,37 @@ def batch_instances(torch, np, qp, W, reps: int = 3):
             for _ in range(reps):
                 Ag, _, stg = qp.homogenized_batch(gps, tol=TOL, grouped=True)
             dt_g = (time.perf_counter() - t0) / reps
+            # the instances up to MIXED_GROUP_DIM unknowns grouped, the rest on streams
+            qp.homogenized_batch(gps, tol=TOL, group_max_dim=MIXED_GROUP_DIM)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                Am, _, stm = qp.homogenized_batch(gps, tol=TOL, group_max_dim=MIXED_GROUP_DIM)
+            dt_m = (time.perf_counter() - t0) / reps
         seq = [gp.homogenized(tol=TOL, energy=False).A.copy() for gp in gps]
-        t0 = time.perf_counter()
+        # one after another, each homogenization timed on its own (it returns
+        # A* to the host, so it has finished when the call returns)
+        per = [0.0] * len(gps)
+        iters = [0] * len(gps)
         for _ in range(reps):
-            for gp in gps:
-                gp.homogenized(tol=TOL, energy=False)
-        dt_s = (time.perf_counter() - t0) / reps
+            for i, gp in enumerate(gps):
+                t1 = time.perf_counter()
+                r = gp.homogenized(tol=TOL, energy=False)
+                per[i] += time.perf_counter() - t1
+                iters[i] = max(int(x.iters) for x in r.infos)
+        dt_s = sum(per) / reps
+        # work bound: every instance's iterations at the best rate per
+        # unknown and iteration that any instance reaches alone
+        rate = min(per[i] / reps / (probs[i].D * iters[i]) for i in range(len(gps)))
+        bound = sum(probs[i].D * iters[i] for i in range(len(gps))) * rate
         leg = {"streams_value": round(solves / dt_b, 2), "streams_ms": round(dt_b * 1e3, 3),
                "streams_status": int(st),
                "streams_results_equal_sequential": all(np.array_equal(a, b) for a, b in zip(As, seq)),
                "sequential_value": round(solves / dt_s, 2), "sequential_ms": round(dt_s * 1e3, 3),
-               "streams_speedup_vs_sequential": round(dt_s / dt_b, 3)}
+               "streams_speedup_vs_sequential": round(dt_s / dt_b, 3),
+               "iterations_min_max": [min(iters), max(iters)],
+               "work_bound_ms": round(bound * 1e3, 3),
+               "streams_time_over_work_bound": round(dt_b / bound, 3)}
         if prec == "fp32ir":
             diff = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(Ag, seq))
             leg.update({"grouped_value": round(solves / dt_g, 2), "grouped_ms": round(dt_g * 1e3, 3),
@@ -398,9 +484,18 @@ def batch_instances(torch, np, qp, W, reps: int = 3):
                         "grouped_results_equal_sequential": all(np.array_equal(a, b)
                                                                 for a, b in zip(Ag, seq)),
                         "grouped_max_rel_diff_vs_sequential": diff,
-                        "grouped_speedup_vs_sequential": round(dt_s / dt_g, 3)})
-            leg["value"] = round(solves / min(dt_g, dt_b), 2)
-            leg["what"] = "the faster of grouped_value and streams_value"
+                        "grouped_speedup_vs_sequential": round(dt_s / dt_g, 3),
+                        "mixed_group_max_dim": MIXED_GROUP_DIM,
+                        "mixed_grouped_instances": sum(1 for pr in probs
+                                                       if pr.D <= MIXED_GROUP_DIM),
+                        "mixed_value": round(solves / dt_m, 2), "mixed_ms": round(dt_m * 1e3, 3),
+                        "mixed_status": int(stm),
+                        "mixed_results_equal_sequential": all(np.array_equal(a, b)
+                                                              for a, b in zip(Am, seq)),
+                        "mixed_speedup_vs_sequential": round(dt_s / dt_m, 3),
+                        "mixed_time_over_work_bound": round(dt_m / bound, 3)})
+            leg["value"] = round(solves / min(dt_g, dt_b, dt_m), 2)
+            leg["what"] = "the fastest of grouped_value, streams_value and mixed_value"
             # the grouped A* against the oracle for the small instances
             small = [i for i, pr in enumerate(probs) if pr.N <= 12][:6]
             errs = []
@@ -553,6 +648,9 @@ def main():
         return
     if args.product_probe:
         product_probe()
+        return
+    if args.batch_breakdown:
+        batch_breakdown()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "

@@ -404,6 +404,28 @@ qp_status qp_homogenized_grouped(qp_problem *const *problems, int count, double 
 qp_status qp_homogenized_grouped_noalloc(qp_problem *const *problems, int count, double *Astar,
                                          double tol, qp_solve_info *infos);
 
+/*
+ * A batch with its small problems grouped: the problems with at most
+ * group_max_dim unknowns (qp_dim) that can join a group with the first of
+ * them (the conditions of qp_homogenized_grouped) run as one group, with one
+ * launch per solver step on that first problem's stream, while every other
+ * problem runs on its own stream as in qp_homogenized_batch; the host
+ * advances the group and the other problems together.  Small problems are
+ * bound by launch latency, which the group shares out, and large ones by
+ * memory traffic, which per-problem streams keep cache-resident.  Every A*,
+ * iteration count and status equals qp_homogenized's on the problem alone.
+ *   problems, count, Astar, tol, infos   as for qp_homogenized_batch
+ *   group_max_dim  the size limit of the group's members; with 0, or with
+ *             fewer than two problems that qualify, no group is formed and
+ *             the call is qp_homogenized_batch
+ * Allocates as qp_homogenized_grouped does (shared group tables; calls from
+ * several host threads are serialized while a group runs).  Returns
+ * QP_EINVAL for a null or repeated problem or a negative group_max_dim;
+ * otherwise the first non-QP_OK status in problem order.
+ */
+qp_status qp_homogenized_batch_mixed(qp_problem *const *problems, int count, double *Astar,
+                                     double tol, qp_solve_info *infos, int64_t group_max_dim);
+
 /* ---- serving: a request queue over a cache of problems ---- */
 
 /*

@@ -2010,109 +2010,204 @@ namespace {
 // pinned memory) and of qp_homogenized_grouped_noalloc (noalloc true: group
 // tables in the library's static device array, polls copy one done bit per
 // problem into problem 0's pinned scratch words; no device, pinned or host
-// heap allocation).  Both queue the same solver launches.
-qp_status grouped_run(qp_problem *const *problems, int count, double *Astar, double tol,
-                      qp_solve_info *infos, bool noalloc)
-{
-    if (!problems || !Astar || count < 1) return fail(QP_EINVAL, "null argument or empty group");
-    if (count > kMaxGroup) return fail(QP_EINVAL, "%d problems exceed the group limit %d", count, kMaxGroup);
-    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QP_EINVAL, "tol must be positive and finite");
-    for (int i = 0; i < count; ++i) {
-        if (!problems[i]) return fail(QP_EINVAL, "problem %d is null", i);
-        for (int k = 0; k < i; ++k)
-            if (problems[k] == problems[i]) return fail(QP_EINVAL, "problem %d repeats problem %d", i, k);
-        if (const char *why = group_mismatch(problems[i], problems[0]))
-            return fail(QP_EINVAL, "problem %d cannot join the group: %s", i, why);
-    }
-    qp_problem *p0 = problems[0];
-    const int G = count, d = p0->host.d, K = d;
-    const hipStream_t s = p0->stream;
-
-    // sizes of the group table: entries, then the owner of every workgroup of
-    // the float product, of the FP64 product and of the vector steps, then
-    // the poll area (three slots of states, or two slots of done words)
-    size_t tot_mv = 0, tot_mv64 = 0, tot_st = 0;
-    for (int i = 0; i < G; ++i) {
-        tot_mv += (size_t)problems[i]->host.nb_mv;
-        tot_mv64 += (size_t)problems[i]->host.nb_mv64;
-        tot_st += (size_t)problems[i]->host.nblocks;
-    }
-    const size_t nst = (size_t)G * K;
-    const size_t o_own_mv = align_up(sizeof(qp::GroupEntry) * G);
-    const size_t o_own_mv64 = align_up(o_own_mv + sizeof(int) * tot_mv);
-    const size_t o_own_st = align_up(o_own_mv64 + sizeof(int) * tot_mv64);
-    const size_t o_poll = align_up(o_own_st + sizeof(int) * tot_st);
-    const size_t bytes = o_poll + (noalloc ? sizeof(uint32_t) * 2 * kGroupWords
-                                           : 3 * nst * sizeof(State));
-
-    std::lock_guard<std::mutex> lock(g_group_mu);
-    char *dev = nullptr;  // device group table
-    char *hbuf = nullptr;  // host image of its first o_poll bytes
+// heap allocation).  Both queue the same solver launches.  As a job:
+// begin() validates, builds the group table and queues every problem's
+// set-up; advance() keeps two chunks of iterations in flight and consumes
+// their polls; once every problem is done (or at the iteration limit) it
+// queues the final steps, waits for them and writes A* and the infos.  The
+// group buffers stay locked from begin() until the job ends.
+struct GroupJob {
+    std::vector<qp_problem *> probs;
+    double *Astar = nullptr;
+    qp_solve_info *infos = nullptr;
+    double tol = 0.0;
+    bool noalloc = false;
+    int G = 0, d = 0, K = 0;
+    hipStream_t s = nullptr;
+    std::unique_lock<std::mutex> lock;
     std::vector<char> hvec;
-    if (noalloc) {
-        void *ptr = nullptr;
-        size_t cap = 0;
-        QP_HIP(qp::group_scratch(p0->device, &ptr, &cap));
-        if (bytes > cap || o_poll > sizeof(g_group_host))
-            return fail(QP_EINVAL, "group table of %zu bytes exceeds the %zu-byte scratch array "
-                        "(fewer or smaller problems)", bytes, cap);
-        dev = static_cast<char *>(ptr);
-        hbuf = g_group_host;
-    } else {
-        QP_TRY(group_buffers(p0->device, bytes, nst));
-        dev = g_gb.dev;
-        hvec.resize(o_poll);
-        hbuf = hvec.data();
-    }
-    for (int i = 0; i < G; ++i) QP_HIP(hipStreamSynchronize(problems[i]->stream));
-
-    auto *ents = reinterpret_cast<qp::GroupEntry *>(hbuf);
-    int *own_mv = reinterpret_cast<int *>(hbuf + o_own_mv);
-    int *own_mv64 = reinterpret_cast<int *>(hbuf + o_own_mv64);
-    int *own_st = reinterpret_cast<int *>(hbuf + o_own_st);
-    auto *E = reinterpret_cast<qp::GroupEntry *>(dev);
-    auto *owner_mv = reinterpret_cast<int *>(dev + o_own_mv);
-    auto *owner_mv64 = reinterpret_cast<int *>(dev + o_own_mv64);
-    auto *owner_st = reinterpret_cast<int *>(dev + o_own_st);
-    auto *dstates = reinterpret_cast<State *>(dev + o_poll);     // noalloc false
-    auto *dwords = reinterpret_cast<uint32_t *>(dev + o_poll);   // noalloc true
-    // problem 0's pinned scratch words: two slots of kGroupWords done words
-    auto *hwords = reinterpret_cast<uint32_t *>(p0->hsmall);
-    static_assert(2 * kGroupWords * sizeof(uint32_t) <= 128 * sizeof(double), "poll words");
-
+    qp::GroupEntry *ents = nullptr, *E = nullptr;
+    int *own_mv = nullptr, *own_mv64 = nullptr, *own_st = nullptr;
+    int *owner_mv = nullptr, *owner_mv64 = nullptr, *owner_st = nullptr;
+    State *dstates = nullptr;     // noalloc false
+    uint32_t *dwords = nullptr;   // noalloc true
+    uint32_t *hwords = nullptr;   // problem 0's pinned scratch words: two slots of done words
+    size_t nst = 0;
     int gpmax = 4;
-    for (int i = 0; i < G; ++i) {
-        qp_problem *p = problems[i];
-        const qp::Parts parts = p->parts();
-        qp::GroupEntry &e = ents[i];
-        e = qp::GroupEntry{};
-        e.tab = p->tab;
-        e.recs = p->recs();
-        e.urec32 = p->urec(qp::F32);
-        e.upku32 = p->upku(qp::F32);
-        e.urec64 = p->urec(qp::F64);
-        e.upku64 = p->upku(qp::F64);
-        e.x32 = p->x32();
-        e.r32 = p->r32();
-        e.h32 = p->h32();
-        e.q32 = p->q32();
-        e.M32 = p->M32();
-        e.X = p->chi(0);
-        e.F = p->F();
-        e.pa = parts.a;
-        e.pb = parts.b;
-        e.st = p->st();
-        e.nb_mv = p->host.nb_mv;
-        e.nb_mv64 = p->host.nb_mv64;
-        e.nb_st = p->host.nblocks;
-        e.wide = p->host.chunk > 4 * qp::kBlock ? 1 : 0;
-        gpmax = std::max(gpmax, (p->host.g + 3) & ~3);
-    }
-    unsigned char running[kMaxGroup];
-    for (int i = 0; i < G; ++i) running[i] = 1;
+    std::vector<unsigned char> running;
     int n_mv = 0, n_mv64 = 0, n_st = 0;  // workgroups of the current launches
+    int maxit = 0, full = 0, j = 0, slot = 0, inflight = 0;
+    bool fin = false, finished = false;
+    qp_status worst = QP_OK;
+
+    bool done() const { return finished; }
+
+    qp_status begin(qp_problem *const *problems, int count, double *Astar_, double tol_,
+                    qp_solve_info *infos_, bool noalloc_)
+    {
+        if (!problems || !Astar_ || count < 1) return fail(QP_EINVAL, "null argument or empty group");
+        if (count > kMaxGroup)
+            return fail(QP_EINVAL, "%d problems exceed the group limit %d", count, kMaxGroup);
+        if (!(tol_ > 0.0) || !std::isfinite(tol_)) return fail(QP_EINVAL, "tol must be positive and finite");
+        for (int i = 0; i < count; ++i) {
+            if (!problems[i]) return fail(QP_EINVAL, "problem %d is null", i);
+            for (int k = 0; k < i; ++k)
+                if (problems[k] == problems[i]) return fail(QP_EINVAL, "problem %d repeats problem %d", i, k);
+            if (const char *why = group_mismatch(problems[i], problems[0]))
+                return fail(QP_EINVAL, "problem %d cannot join the group: %s", i, why);
+        }
+        probs.assign(problems, problems + count);
+        Astar = Astar_;
+        infos = infos_;
+        tol = tol_;
+        noalloc = noalloc_;
+        qp_problem *p0 = probs[0];
+        G = count;
+        d = p0->host.d;
+        K = d;
+        s = p0->stream;
+
+        // sizes of the group table: entries, then the owner of every workgroup
+        // of the float product, of the FP64 product and of the vector steps,
+        // then the poll area (three slots of states, or two slots of done words)
+        size_t tot_mv = 0, tot_mv64 = 0, tot_st = 0;
+        for (int i = 0; i < G; ++i) {
+            tot_mv += (size_t)probs[i]->host.nb_mv;
+            tot_mv64 += (size_t)probs[i]->host.nb_mv64;
+            tot_st += (size_t)probs[i]->host.nblocks;
+        }
+        nst = (size_t)G * K;
+        const size_t o_own_mv = align_up(sizeof(qp::GroupEntry) * G);
+        const size_t o_own_mv64 = align_up(o_own_mv + sizeof(int) * tot_mv);
+        const size_t o_own_st = align_up(o_own_mv64 + sizeof(int) * tot_mv64);
+        const size_t o_poll = align_up(o_own_st + sizeof(int) * tot_st);
+        const size_t bytes = o_poll + (noalloc ? sizeof(uint32_t) * 2 * kGroupWords
+                                               : 3 * nst * sizeof(State));
+
+        lock = std::unique_lock<std::mutex>(g_group_mu);
+        char *dev = nullptr;   // device group table
+        char *hbuf = nullptr;  // host image of its first o_poll bytes
+        if (noalloc) {
+            void *ptr = nullptr;
+            size_t cap = 0;
+            QP_HIP(qp::group_scratch(p0->device, &ptr, &cap));
+            if (bytes > cap || o_poll > sizeof(g_group_host))
+                return fail(QP_EINVAL, "group table of %zu bytes exceeds the %zu-byte scratch array "
+                            "(fewer or smaller problems)", bytes, cap);
+            dev = static_cast<char *>(ptr);
+            hbuf = g_group_host;
+        } else {
+            QP_TRY(group_buffers(p0->device, bytes, nst));
+            dev = g_gb.dev;
+            hvec.resize(o_poll);
+            hbuf = hvec.data();
+        }
+        for (int i = 0; i < G; ++i) QP_HIP(hipStreamSynchronize(probs[i]->stream));
+
+        ents = reinterpret_cast<qp::GroupEntry *>(hbuf);
+        own_mv = reinterpret_cast<int *>(hbuf + o_own_mv);
+        own_mv64 = reinterpret_cast<int *>(hbuf + o_own_mv64);
+        own_st = reinterpret_cast<int *>(hbuf + o_own_st);
+        E = reinterpret_cast<qp::GroupEntry *>(dev);
+        owner_mv = reinterpret_cast<int *>(dev + o_own_mv);
+        owner_mv64 = reinterpret_cast<int *>(dev + o_own_mv64);
+        owner_st = reinterpret_cast<int *>(dev + o_own_st);
+        dstates = reinterpret_cast<State *>(dev + o_poll);
+        dwords = reinterpret_cast<uint32_t *>(dev + o_poll);
+        hwords = reinterpret_cast<uint32_t *>(p0->hsmall);
+        static_assert(2 * kGroupWords * sizeof(uint32_t) <= 128 * sizeof(double), "poll words");
+
+        gpmax = 4;
+        for (int i = 0; i < G; ++i) {
+            qp_problem *p = probs[i];
+            const qp::Parts parts = p->parts();
+            qp::GroupEntry &e = ents[i];
+            e = qp::GroupEntry{};
+            e.tab = p->tab;
+            e.recs = p->recs();
+            e.urec32 = p->urec(qp::F32);
+            e.upku32 = p->upku(qp::F32);
+            e.urec64 = p->urec(qp::F64);
+            e.upku64 = p->upku(qp::F64);
+            e.x32 = p->x32();
+            e.r32 = p->r32();
+            e.h32 = p->h32();
+            e.q32 = p->q32();
+            e.M32 = p->M32();
+            e.X = p->chi(0);
+            e.F = p->F();
+            e.pa = parts.a;
+            e.pb = parts.b;
+            e.st = p->st();
+            e.nb_mv = p->host.nb_mv;
+            e.nb_mv64 = p->host.nb_mv64;
+            e.nb_st = p->host.nblocks;
+            e.wide = p->host.chunk > 4 * qp::kBlock ? 1 : 0;
+            gpmax = std::max(gpmax, (p->host.g + 3) & ~3);
+        }
+        running.assign(G, 1);
+        QP_TRY(build_owners());
+
+        // set-up of every problem (the launches of a standalone homogenization)
+        QP_HIP(hipEventRecord(p0->ev_t0, s));
+        for (int i = 0; i < G; ++i) {
+            qp_problem *p = probs[i];
+            const qp::Parts parts = p->parts();
+            QP_HIP(qp::launch_corrector_rhs_all(p->tab, p->host, d, p->F(), &parts, s));
+            QP_HIP(qp::launch_state_reset(K, p->st(), s));
+            QP_HIP(qp::launch_ir_unit_only(K, p->host, parts, p->st(), s));
+            QP_HIP(qp::launch_pcg_init(qp::F32, K, p->tab, p->host, p->F(), p->chi(0), p->x32(),
+                                       p->r32(), p->h32(), p->M32(), parts, p->st(), s));
+            QP_HIP(qp::launch_pcg_start(qp::F32, K, p->host, tol, p->opt.inner_tol, p->opt.maxit,
+                                        parts, p->st(), s));
+        }
+        maxit = p0->opt.maxit;
+        full = batch_size(p0->opt);
+        j = slot = inflight = 0;
+        fin = finished = false;
+        worst = QP_OK;
+        return QP_OK;
+    }
+
+    // Two chunks of iterations in flight: the device runs one while the host
+    // inspects the poll of the other.  A non-blocking call returns when the
+    // poll it needs has not arrived.
+    qp_status advance(bool blocking, bool &progressed)
+    {
+        progressed = false;
+        if (finished) return QP_OK;
+        if (!fin) {
+            while (inflight < 2 && j < maxit) {
+                QP_TRY(queue());
+                progressed = true;
+            }
+            if (inflight > 0) {
+                const int oldest = (inflight == 2) ? slot : (slot ^ 1);
+                const hipEvent_t ev = probs[0]->ev_poll[oldest];
+                if (blocking) {
+                    QP_HIP(hipEventSynchronize(ev));
+                } else {
+                    const hipError_t q = hipEventQuery(ev);
+                    if (q == hipErrorNotReady) return QP_OK;
+                    QP_HIP(q);
+                }
+                progressed = true;
+                --inflight;
+                bool all = true;
+                for (int i = 0; i < G && all; ++i) all = problem_done(oldest, i);
+                if (!all) return compact(oldest);
+                fin = true;
+            }
+            // else: the iteration limit, nothing in flight, not every problem done
+        }
+        progressed = true;
+        return finish();
+    }
+
+  private:
     // owners of the running problems' workgroups, uploaded with the entries
-    auto build_owners = [&]() -> qp_status {
+    qp_status build_owners()
+    {
         n_mv = n_mv64 = n_st = 0;
         for (int i = 0; i < G; ++i) {
             if (!running[i]) continue;
@@ -2129,56 +2224,46 @@ qp_status grouped_run(qp_problem *const *problems, int count, double *Astar, dou
         QP_HIP(hipMemcpy(owner_mv64, own_mv64, sizeof(int) * n_mv64, hipMemcpyHostToDevice));
         QP_HIP(hipMemcpy(owner_st, own_st, sizeof(int) * n_st, hipMemcpyHostToDevice));
         return QP_OK;
-    };
-    QP_TRY(build_owners());
-
-    // set-up of every problem (the launches of a standalone homogenization)
-    QP_HIP(hipEventRecord(p0->ev_t0, s));
-    for (int i = 0; i < G; ++i) {
-        qp_problem *p = problems[i];
-        const qp::Parts parts = p->parts();
-        QP_HIP(qp::launch_corrector_rhs_all(p->tab, p->host, d, p->F(), &parts, s));
-        QP_HIP(qp::launch_state_reset(K, p->st(), s));
-        QP_HIP(qp::launch_ir_unit_only(K, p->host, parts, p->st(), s));
-        QP_HIP(qp::launch_pcg_init(qp::F32, K, p->tab, p->host, p->F(), p->chi(0), p->x32(),
-                                   p->r32(), p->h32(), p->M32(), parts, p->st(), s));
-        QP_HIP(qp::launch_pcg_start(qp::F32, K, p->host, tol, p->opt.inner_tol, p->opt.maxit, parts,
-                                    p->st(), s));
     }
-    auto replacement = [&](int j) -> qp_status {
-        QP_HIP(qp::launch_group_vec(2, j, K, n_st, E, owner_st, s));
-        QP_HIP(qp::launch_group_matvec(qp::F64, d, p0->host.real_coef, n_mv64, gpmax, E, owner_mv64,
-                                       s));
-        QP_HIP(qp::launch_group_vec(3, j, K, n_st, E, owner_st, s));
+
+    qp_status replacement(int it)
+    {
+        QP_HIP(qp::launch_group_vec(2, it, K, n_st, E, owner_st, s));
+        QP_HIP(qp::launch_group_matvec(qp::F64, d, probs[0]->host.real_coef, n_mv64, gpmax, E,
+                                       owner_mv64, s));
+        QP_HIP(qp::launch_group_vec(3, it, K, n_st, E, owner_st, s));
         return QP_OK;
-    };
-    auto poll = [&](int slot, hipEvent_t ev) -> qp_status {
+    }
+
+    qp_status poll(int sl, hipEvent_t ev)
+    {
         if (noalloc) {
-            QP_HIP(qp::launch_group_done(G, K, E, dwords + slot * kGroupWords, s));
-            QP_HIP(hipMemcpyAsync(hwords + slot * kGroupWords, dwords + slot * kGroupWords,
+            QP_HIP(qp::launch_group_done(G, K, E, dwords + sl * kGroupWords, s));
+            QP_HIP(hipMemcpyAsync(hwords + sl * kGroupWords, dwords + sl * kGroupWords,
                                   sizeof(uint32_t) * kGroupWords, hipMemcpyDeviceToHost, s));
         } else {
-            QP_HIP(qp::launch_group_states(G, K, E, dstates + slot * nst, s));
-            QP_HIP(hipMemcpyAsync(g_gb.host + slot * nst, dstates + slot * nst, nst * sizeof(State),
+            QP_HIP(qp::launch_group_states(G, K, E, dstates + sl * nst, s));
+            QP_HIP(hipMemcpyAsync(g_gb.host + sl * nst, dstates + sl * nst, nst * sizeof(State),
                                   hipMemcpyDeviceToHost, s));
         }
         if (ev) QP_HIP(hipEventRecord(ev, s));
         return QP_OK;
-    };
-    // whether every right-hand side of problem i was done at the poll of slot
-    auto problem_done = [&](int slot, int i) -> bool {
-        if (noalloc) return (hwords[slot * kGroupWords + i / 32] >> (i % 32)) & 1u;
-        bool done = true;
-        for (int r = 0; r < K; ++r) done = done && g_gb.host[slot * nst + (size_t)i * K + r].done != 0;
-        return done;
-    };
-    const int maxit = p0->opt.maxit, full = batch_size(p0->opt);
-    int j = 0, slot = 0, inflight = 0;
-    bool fin = false;
+    }
+
+    // whether every right-hand side of problem i was done at the poll of slot sl
+    bool problem_done(int sl, int i) const
+    {
+        if (noalloc) return (hwords[sl * kGroupWords + i / 32] >> (i % 32)) & 1u;
+        bool dn = true;
+        for (int r = 0; r < K; ++r) dn = dn && g_gb.host[sl * nst + (size_t)i * K + r].done != 0;
+        return dn;
+    }
+
     // Launches cover only the problems still running: once a poll shows
     // problems finished, the owner tables are rebuilt without them (after the
     // queued work has drained; a finished problem's state no longer changes).
-    auto compact = [&](int seen) -> qp_status {
+    qp_status compact(int seen)
+    {
         bool changed = false, any = false;
         for (int i = 0; i < G; ++i) {
             if (running[i] && problem_done(seen, i)) {
@@ -2190,83 +2275,92 @@ qp_status grouped_run(qp_problem *const *problems, int count, double *Astar, dou
         if (!changed || !any) return QP_OK;
         QP_HIP(hipStreamSynchronize(s));
         return build_owners();
-    };
-    auto queue = [&]() -> qp_status {
+    }
+
+    qp_status queue()
+    {
         const int k = std::min(full, maxit - j);
         for (int it = 0; it < k; ++it) {
-            QP_HIP(qp::launch_group_matvec(qp::F32, d, p0->host.real_coef, n_mv, gpmax, E, owner_mv, s));
+            QP_HIP(qp::launch_group_matvec(qp::F32, d, probs[0]->host.real_coef, n_mv, gpmax, E,
+                                           owner_mv, s));
             QP_HIP(qp::launch_group_vec(0, it, K, n_st, E, owner_st, s));
             QP_HIP(qp::launch_group_vec(1, it, K, n_st, E, owner_st, s));
             if (it & 1) QP_TRY(replacement(it));
         }
-        QP_TRY(poll(slot, p0->ev_poll[slot]));
+        QP_TRY(poll(slot, probs[0]->ev_poll[slot]));
         j += k;
         slot ^= 1;
         ++inflight;
         return QP_OK;
-    };
-    // two chunks of iterations in flight: the device runs one while the host
-    // inspects the poll of the other
-    while (!fin) {
-        while (inflight < 2 && j < maxit) QP_TRY(queue());
-        if (inflight == 0) break;
-        const int oldest = (inflight == 2) ? slot : (slot ^ 1);
-        QP_HIP(hipEventSynchronize(p0->ev_poll[oldest]));
-        --inflight;
-        fin = true;
-        for (int i = 0; i < G && fin; ++i) fin = problem_done(oldest, i);
-        if (!fin) QP_TRY(compact(oldest));
     }
-    if (!fin) {
-        // iteration limit: fold every unfinished increment into X with one
-        // forced replacement, whose true residual decides the status
-        for (int i = 0; i < G; ++i) QP_HIP(qp::launch_ir_force(K, problems[i]->st(), s));
-        QP_TRY(replacement(maxit));
-    }
-    QP_HIP(hipEventRecord(p0->ev_t1, s));
-    for (int i = 0; i < G; ++i) {
-        qp_problem *p = problems[i];
-        // final states into the problem's own pinned slot 2
-        QP_HIP(hipMemcpyAsync(p->hstate + 2 * qp::kMaxRhs, p->st(), sizeof(State) * K,
-                              hipMemcpyDeviceToHost, s));
-        QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), s));
-        QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double), hipMemcpyDeviceToHost, s));
-        if (infos) QP_TRY(queue_hist(p, K, s));
-    }
-    QP_HIP(hipStreamSynchronize(s));
-    float ms = 0.f;
-    QP_HIP(hipEventElapsedTime(&ms, p0->ev_t0, p0->ev_t1));
-    qp_status worst = QP_OK;
-    size_t ao = 0;
-    for (int i = 0; i < G; ++i) {
-        qp_problem *p = problems[i];
-        const State *fs = p->hstate + 2 * qp::kMaxRhs;
-        for (int e = 0; e < d * d; ++e) Astar[ao + e] = p->hsmall[e];
-        ao += (size_t)d * d;
-        for (int r = 0; r < K; ++r) {
-            const State &st = fs[r];
-            const qp_status status = st.done ? (qp_status)st.status : QP_ENOCONV;
-            if (infos) {
-                qp_solve_info *info = infos + (size_t)i * K + r;
-                std::memset(info, 0, sizeof(*info));
-                info->flags = p->flags;
-                info->status = status;
-                info->iters = st.iters;
-                info->outer_iters = st.replacements;
-                info->rel_resid = std::sqrt(st.rr);
-                info->seconds = ms * 1e-3;
-                info->kappa_est = lanczos_kappa(p->hhist + (size_t)2 * qp::kHist * r,
-                                                std::min(st.iters, qp::kHist));
-                info->bytes_moved = solve_bytes(true, (double)p->host.D, st.iters, st.replacements);
-            }
-            if (status != QP_OK && worst == QP_OK) worst = status;
+
+    qp_status finish()
+    {
+        finished = true;
+        qp_problem *p0 = probs[0];
+        if (!fin) {
+            // iteration limit: fold every unfinished increment into X with one
+            // forced replacement, whose true residual decides the status
+            for (int i = 0; i < G; ++i) QP_HIP(qp::launch_ir_force(K, probs[i]->st(), s));
+            QP_TRY(replacement(maxit));
         }
+        QP_HIP(hipEventRecord(p0->ev_t1, s));
+        for (int i = 0; i < G; ++i) {
+            qp_problem *p = probs[i];
+            // final states into the problem's own pinned slot 2
+            QP_HIP(hipMemcpyAsync(p->hstate + 2 * qp::kMaxRhs, p->st(), sizeof(State) * K,
+                                  hipMemcpyDeviceToHost, s));
+            QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), s));
+            QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double), hipMemcpyDeviceToHost,
+                                  s));
+            if (infos) QP_TRY(queue_hist(p, K, s));
+        }
+        QP_HIP(hipStreamSynchronize(s));
+        lock = std::unique_lock<std::mutex>();  // the group buffers are free again
+        float ms = 0.f;
+        QP_HIP(hipEventElapsedTime(&ms, p0->ev_t0, p0->ev_t1));
+        worst = QP_OK;
+        size_t ao = 0;
+        for (int i = 0; i < G; ++i) {
+            qp_problem *p = probs[i];
+            const State *fs = p->hstate + 2 * qp::kMaxRhs;
+            for (int e = 0; e < d * d; ++e) Astar[ao + e] = p->hsmall[e];
+            ao += (size_t)d * d;
+            for (int r = 0; r < K; ++r) {
+                const State &st = fs[r];
+                const qp_status status = st.done ? (qp_status)st.status : QP_ENOCONV;
+                if (infos) {
+                    qp_solve_info *info = infos + (size_t)i * K + r;
+                    std::memset(info, 0, sizeof(*info));
+                    info->flags = p->flags;
+                    info->status = status;
+                    info->iters = st.iters;
+                    info->outer_iters = st.replacements;
+                    info->rel_resid = std::sqrt(st.rr);
+                    info->seconds = ms * 1e-3;
+                    info->kappa_est = lanczos_kappa(p->hhist + (size_t)2 * qp::kHist * r,
+                                                    std::min(st.iters, qp::kHist));
+                    info->bytes_moved = solve_bytes(true, (double)p->host.D, st.iters, st.replacements);
+                }
+                if (status != QP_OK && worst == QP_OK) worst = status;
+            }
+        }
+        if (worst != QP_OK) {
+            report(worst);
+            fail(worst, "a corrector solve of the group did not converge");
+        }
+        return QP_OK;
     }
-    if (worst != QP_OK) {
-        report(worst);
-        fail(worst, "a corrector solve of the group did not converge");
-    }
-    return worst;
+};
+
+qp_status grouped_run(qp_problem *const *problems, int count, double *Astar, double tol,
+                      qp_solve_info *infos, bool noalloc)
+{
+    GroupJob job;
+    QP_TRY(job.begin(problems, count, Astar, tol, infos, noalloc));
+    bool progressed = false;
+    while (!job.done()) QP_TRY(job.advance(true, progressed));
+    return job.worst;
 }
 
 }  // namespace
@@ -2282,6 +2376,108 @@ qp_status qp_homogenized_grouped_noalloc(qp_problem *const *problems, int count,
                                          double tol, qp_solve_info *infos)
 {
     return grouped_run(problems, count, Astar, tol, infos, true);
+}
+
+qp_status qp_homogenized_batch_mixed(qp_problem *const *problems, int count, double *Astar,
+                                     double tol, qp_solve_info *infos, int64_t group_max_dim)
+{
+    if (!problems || !Astar || count < 1) return fail(QP_EINVAL, "null argument or empty batch");
+    if (group_max_dim < 0) return fail(QP_EINVAL, "group_max_dim must not be negative");
+    for (int i = 0; i < count; ++i) {
+        if (!problems[i]) return fail(QP_EINVAL, "problem %d is null", i);
+        for (int k = 0; k < i; ++k)
+            if (problems[k] == problems[i]) return fail(QP_EINVAL, "problem %d repeats problem %d", i, k);
+    }
+    // the group: the small problems that can join one led by the first of them
+    std::vector<int> member;
+    int lead = -1;
+    for (int i = 0; i < count && (int)member.size() < kMaxGroup; ++i) {
+        qp_problem *p = problems[i];
+        if ((int64_t)p->host.D > group_max_dim) continue;
+        if (lead < 0) {
+            if (group_mismatch(p, p)) continue;
+            lead = i;
+        } else if (group_mismatch(p, problems[lead])) {
+            continue;
+        }
+        member.push_back(i);
+    }
+    if (member.size() < 2) return qp_homogenized_batch(problems, count, Astar, tol, infos);
+    std::vector<char> grouped(count, 0);
+    for (int i : member) grouped[i] = 1;
+    // offsets of every problem's A* and infos in the caller's arrays
+    std::vector<size_t> ao(count), io(count);
+    for (int i = 0, a = 0, b = 0; i < count; ++i) {
+        ao[i] = a;
+        io[i] = b;
+        a += problems[i]->host.d * problems[i]->host.d;
+        b += problems[i]->host.d;
+    }
+    const int d = problems[lead]->host.d;
+    std::vector<qp_problem *> gp;
+    for (int i : member) gp.push_back(problems[i]);
+    std::vector<double> gA(member.size() * d * d);
+    std::vector<qp_solve_info> gI(member.size() * d);
+
+    GroupJob group;
+    QP_TRY(group.begin(gp.data(), (int)gp.size(), gA.data(), tol, gI.data(), false));
+    std::vector<HomJob> jobs(count);
+    for (int i = 0; i < count; ++i) {
+        if (grouped[i]) continue;
+        QP_TRY(jobs[i].begin(problems[i], Astar + ao[i], nullptr, tol, infos ? infos + io[i] : nullptr));
+    }
+    // round robin over the group and the other problems' jobs
+    auto drain = [&]() {
+        for (int i = 0; i < count; ++i) (void)hipStreamSynchronize(problems[i]->stream);
+    };
+    for (;;) {
+        bool all = true, any = false;
+        for (int i = 0; i < count; ++i) {
+            if (grouped[i] || jobs[i].done()) continue;
+            bool pr = false;
+            const qp_status st = jobs[i].advance(false, pr);
+            if (st != QP_OK) {
+                drain();
+                return st;
+            }
+            any = any || pr;
+            all = all && jobs[i].done();
+        }
+        if (!group.done()) {
+            bool pr = false;
+            const qp_status st = group.advance(false, pr);
+            if (st != QP_OK) {
+                drain();
+                return st;
+            }
+            any = any || pr;
+            all = all && group.done();
+        }
+        if (all) break;
+        if (!any) std::this_thread::yield();
+    }
+    for (size_t m = 0; m < member.size(); ++m) {
+        const int i = member[m];
+        for (int e = 0; e < d * d; ++e) Astar[ao[i] + e] = gA[m * d * d + e];
+        if (infos)
+            for (int r = 0; r < d; ++r) infos[io[i] + r] = gI[m * d + r];
+    }
+    // the first non-QP_OK status in problem order
+    qp_status worst = QP_OK;
+    for (int i = 0; i < count && worst == QP_OK; ++i) {
+        if (!grouped[i]) {
+            worst = jobs[i].worst;
+            continue;
+        }
+        for (size_t m = 0; m < member.size(); ++m)
+            if (member[m] == i)
+                for (int r = 0; r < d && worst == QP_OK; ++r) {
+                    const qp_status st = (qp_status)gI[m * d + r].status;
+                    if (st != QP_OK) worst = st;
+                }
+    }
+    if (worst != QP_OK) fail(worst, "a corrector solve of the batch did not converge");
+    return worst;
 }
 
 qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info *info)

@@ -45,7 +45,7 @@ EXPORTED = (
     "qp_set_options", "qp_product_layout", "qp_set_product_layout", "qp_solve", "qp_solve_d", "qp_solve_multi_d", "qp_corrector",
     "qp_corrector_d",
     "qp_homogenized", "qp_homogenized_ex", "qp_homogenized_batch", "qp_homogenized_grouped",
-    "qp_homogenized_grouped_noalloc", "qp_server_create",
+    "qp_homogenized_grouped_noalloc", "qp_homogenized_batch_mixed", "qp_server_create",
     "qp_server_submit", "qp_server_progress", "qp_server_pending", "qp_server_bytes",
     "qp_server_destroy", "qp_coo_entries", "qp_coo_build_d", "qp_coo_matvec_d", "qp_dft_d",
     "qp_modes_from_spectrum", "qp_matvec_d", "qp_matvec32_d", "qp_matvec_half_d", "qp_precond_d",
@@ -127,6 +127,8 @@ def lib():
                                            C.POINTER(qp_solve_info)]),
         "qp_homogenized_grouped_noalloc": (C.c_int, [C.POINTER(vp), C.c_int, dp, C.c_double,
                                                    C.POINTER(qp_solve_info)]),
+        "qp_homogenized_batch_mixed": (C.c_int, [C.POINTER(vp), C.c_int, dp, C.c_double,
+                                               C.POINTER(qp_solve_info), C.c_int64]),
         "qp_server_create": (C.c_int, [C.POINTER(vp), C.c_size_t, C.POINTER(qp_options)]),
         "qp_server_submit": (C.c_int, [vp, C.c_int, C.c_int, dp, C.c_int, ip, dp, dp, C.c_int,
                                        C.c_double, dp, C.POINTER(qp_solve_info),
@@ -478,20 +480,27 @@ class Problem:
 # --------------------------------------------------------------------------
 
 def homogenized_batch(problems, tol: float = 1e-12, check: bool = True, grouped: bool = False,
-                      noalloc: bool = False):
+                      noalloc: bool = False, group_max_dim: int = 0):
     """qp_homogenized_batch over Problem objects (each should own a distinct
     stream for the solves to overlap), or with grouped=True
     qp_homogenized_grouped (one launch per solver step for all of them), or
-    with noalloc=True as well qp_homogenized_grouped_noalloc.
+    with noalloc=True as well qp_homogenized_grouped_noalloc, or with
+    group_max_dim > 0 qp_homogenized_batch_mixed (the problems with at most
+    that many unknowns grouped, the others on their streams).
     Returns (list of d x d A*, list of per-problem info lists, status)."""
     count = len(problems)
     ds = [pr.d for pr in problems]
     A = np.zeros(sum(d * d for d in ds))
     infos = (qp_solve_info * sum(ds))()
     hs = (C.c_void_p * count)(*[pr.h for pr in problems])
-    name = ("qp_homogenized_grouped_noalloc" if noalloc else "qp_homogenized_grouped") \
-        if grouped else "qp_homogenized_batch"
-    st = getattr(lib(), name)(hs, count, _dptr(A), float(tol), infos)
+    if group_max_dim and not grouped:
+        name = "qp_homogenized_batch_mixed"
+        st = lib().qp_homogenized_batch_mixed(hs, count, _dptr(A), float(tol), infos,
+                                              int(group_max_dim))
+    else:
+        name = ("qp_homogenized_grouped_noalloc" if noalloc else "qp_homogenized_grouped") \
+            if grouped else "qp_homogenized_batch"
+        st = getattr(lib(), name)(hs, count, _dptr(A), float(tol), infos)
     if check:
         _check(st, name)
     outA, outI, ao, io = [], [], 0, 0

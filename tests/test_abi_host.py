@@ -177,6 +177,12 @@ def test_server_and_batch_argument_checks_on_host():
     assert srv.pending() == 0 and srv.bytes() == 0
     srv.close()
     assert qp.lib().qp_homogenized_batch(None, 0, None, 1e-12, None) == qp.QP_EINVAL
+    assert qp.lib().qp_homogenized_batch_mixed(None, 0, None, 1e-12, None, 1024) == qp.QP_EINVAL
+    # the size limit is checked before any problem is read
+    A = np.zeros(4)
+    dummy = (qp.C.c_void_p * 1)(1)
+    assert qp.lib().qp_homogenized_batch_mixed(dummy, 1, qp._dptr(A), 1e-12, None, -1) == qp.QP_EINVAL
+    assert "group_max_dim" in qp.qp_last_error()
 
 
 def test_coo_entry_count_without_problem():

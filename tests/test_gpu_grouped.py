@@ -134,3 +134,50 @@ def test_grouped_rejects_what_cannot_join():
             qp.homogenized_batch(grp, tol=1e-12, grouped=True)
         assert e.value.status == qp.QP_EINVAL
     a.close()
+
+
+def test_mixed_batch_equals_standalone():
+    """qp_homogenized_batch_mixed: the small FP32-IR d = 2 real problems
+    (at most 12^4 unknowns) form the group; the larger ones and those that
+    cannot join it (FP64, d = 3, complex coefficient) run on their own
+    streams; every result equals the standalone one bitwise."""
+    spec = [(W.eightfold_random(32, 0), "fp32ir"), (W.eightfold_random(8, 1), "fp32ir"),
+            (W.icosahedral(6), "fp32ir"), (W.eightfold(8), "fp64"),
+            (W.eightfold_random(12, 2), "fp32ir"), (W.eightfold_random(24, 4), "fp32ir"),
+            (W.eightfold(10), "fp32ir"), (W.paper_four_mode_2d(6), "fp32ir")]
+    say("[case] mixed batch", [(pr.name, pr.N, prec) for pr, prec in spec])
+    alone = []
+    for pr, prec in spec:
+        gp = qp.Problem(pr, precision=prec)
+        r = gp.homogenized(tol=1e-12, energy=False)
+        alone.append((r.A.copy(), [i.iters for i in r.infos], [i.outer_iters for i in r.infos]))
+        gp.close()
+    gps = [qp.Problem(pr, precision=prec, stream=torch.cuda.Stream()) for pr, prec in spec]
+    for limit in (12 ** 4, 0):
+        t = time.perf_counter()
+        As, infos, st = qp.homogenized_batch(gps, tol=1e-12, group_max_dim=limit)
+        say("  mixed, limit", limit, round((time.perf_counter() - t) * 1e3, 2), "ms")
+        assert st == qp.QP_OK
+        for (pr, _), (A0, it0, out0), A, inf in zip(spec, alone, As, infos):
+            assert np.array_equal(A, A0), (pr.name, pr.N, limit)
+            assert [i.iters for i in inf] == it0, (pr.name, pr.N, limit)
+            assert [i.outer_iters for i in inf] == out0, (pr.name, pr.N, limit)
+            assert all(i.status == 0 and i.rel_resid <= 1e-12 for i in inf)
+    for gp in gps:
+        gp.close()
+
+
+def test_mixed_batch_reports_the_first_failure_in_problem_order():
+    # the grouped problems stop at their iteration limit; the large one converges
+    small = [qp.Problem(W.eightfold_random(8, 1), precision="fp32ir", maxit=6,
+                        stream=torch.cuda.Stream()),
+             qp.Problem(W.eightfold_random(12, 2), precision="fp32ir", maxit=6,
+                        stream=torch.cuda.Stream())]
+    big = qp.Problem(W.eightfold_random(24, 4), precision="fp32ir", stream=torch.cuda.Stream())
+    As, infos, st = qp.homogenized_batch([big] + small, tol=1e-12, group_max_dim=12 ** 4,
+                                         check=False)
+    assert st == qp.QP_ENOCONV
+    assert all(i.status == 0 for i in infos[0])
+    assert all(i.status == qp.QP_ENOCONV for inf in infos[1:] for i in inf)
+    for gp in small + [big]:
+        gp.close()
