@@ -35,7 +35,7 @@ TRAFFIC_FILE_HBM = os.path.join(ROOT, "profiles", "matvec_icosahedral_n6_N16_dra
 # sources of the stiffness-product kernels (the product and its device helpers)
 MATVEC_SRC = [os.path.join(ROOT, "paper_2404_06841_amd", "csrc", f)
               for f in ("qp_matvec.hip", "qp_matvec_half.hip", "qp_matvec_kernels.h",
-                        "qp_device.h")]
+                        "qp_chunk_walk.h", "qp_device.h")]
 
 
 def parse_args():
@@ -53,6 +53,10 @@ def parse_args():
     ap.add_argument("--headline-only", action="store_true",
                     help="only run the headline FP32-IR homogenizations (warm-up and timed "
                          "steps) and print their rate, for counter runs")
+    ap.add_argument("--layout", type=str, default=None,
+                    help="with --headline-only: IT,WG,XF,IT64,WG64,XF64, the product layouts "
+                         "to use instead of the autotuner's choice (counter runs perturb the "
+                         "tuner's timings, so they pin the layout the timed run chose)")
     ap.add_argument("--batch-breakdown", action="store_true",
                     help="only time the 64-instance FP32-IR batch by size class (instances "
                          "alone, on streams, grouped) and print one line per class")
@@ -136,15 +140,18 @@ def copy_probe():
 
 def product_probe():
     """The launches that the HBM-sized roofline is taken on: the icosahedral
-    N = 16 products (one right-hand side, FP64 then float, the layout the
-    autotuner picks for this shape), five of each after two warm-up launches,
-    then the copies of copy_probe."""
+    N = 16 products (one right-hand side, FP64 then float, the default
+    layout, as hbm_products times them), seven of each; then the FP64
+    products of icosahedral N = 15 on full and on half storage (default
+    layouts, as half_storage times them); then the copies of copy_probe.
+    The layouts are fixed because a counter run perturbs the autotuner's
+    timings."""
     import torch
 
     from paper_2404_06841_amd import qp
     from paper_2404_06841_amd import workloads as W
     prob = W.icosahedral(16)
-    gp = qp.Problem(prob, autotune=True)
+    gp = qp.Problem(prob)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(16)
     for dtype, fn in ((torch.complex128, gp.matvec_d), (torch.complex64, gp.matvec32_d)):
@@ -157,10 +164,10 @@ def product_probe():
     print(json.dumps({"product_probe": prob.D, "layout": gp.layout(), "launches": 7}), flush=True)
     gp.close()
     # Hermitian half storage at odd N: the FP64 product on the full and on the
-    # half problem (each with the layout the autotuner picks for it)
+    # half problem
     prob = W.icosahedral(15)
     for half in (False, True):
-        gp = qp.Problem(prob, autotune=True, half_storage=half)
+        gp = qp.Problem(prob, half_storage=half)
         u = torch.randn(gp.D, dtype=torch.complex128, device="cuda", generator=gen)
         y = torch.empty_like(u)
         for _ in range(7):
@@ -181,10 +188,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path: str = TRAFFIC_FILE, key: str = "hbm_bytes_per_launch"):
+def measured_traffic(path: str = TRAFFIC_FILE, key: str = "hbm_bytes_per_launch",
+                     layout=None):
     """Memory-side bytes per stiffness-product launch from a committed
     rocprofv3 counter summary (sized read and write requests), or None when
-    it was taken on another kernel version."""
+    it was taken on another kernel version or, given `layout` (item tiles,
+    workgroups, XCD order of the product), on another work layout."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -193,6 +202,8 @@ def measured_traffic(path: str = TRAFFIC_FILE, key: str = "hbm_bytes_per_launch"
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_hash") != kernel_hash():
+        return None
+    if layout is not None and kv.get("layout") != ",".join(str(int(v)) for v in layout):
         return None
     try:
         return float(kv[key])
@@ -228,7 +239,7 @@ def hbm_products(torch, qp, W):
     Each figure is given against the nominal HBM peak and against a measured
     512 MiB device copy (2 x 512 MiB moved per copy)."""
     prob = W.icosahedral(16)
-    gp = qp.Problem(prob, autotune=True)
+    gp = qp.Problem(prob)  # the default layout, as in the counter runs of --product-probe
     D = prob.D
     gen = torch.Generator(device="cuda")
     gen.manual_seed(16)
@@ -296,20 +307,25 @@ def half_storage(torch, np, qp, W, gold, steps: int = 5):
                        "half storage), three correctors per homogenization"}
     for storage in ("full", "half"):
         res = {}
+        # the products (the FP64 and float kernels of this storage), in the
+        # default layout as in the counter runs of --product-probe
+        gp = qp.Problem(prob, half_storage=(storage == "half"))
+        for name, dtype, fn, per in (("fp64", torch.complex128, gp.matvec_d, 32.0),
+                                     ("fp32", torch.complex64, gp.matvec32_d, 16.0)):
+            u = torch.randn(gp.D, dtype=dtype, device="cuda", generator=gen)
+            y = torch.empty_like(u)
+            us = per_launch_us(torch, lambda: fn(u, y))
+            res["product_" + name] = {
+                "avg_launch_us": round(us, 2), "algorithmic_bytes": int(per * gp.D),
+                "achieved_GBs": round(per * gp.D / (us * 1e-6) / 1e9, 1),
+                "frac_of_hbm_peak": round(per * gp.D / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+            del u, y
+        res["product_layout"] = gp.layout()
+        gp.close()
+        # the homogenizations, each on a problem with the autotuner's layouts
         for prec in ("fp32ir", "fp64"):
             gp = qp.Problem(prob, precision=prec, autotune=True, half_storage=(storage == "half"))
             if prec == "fp32ir":
-                # the products (the FP64 and float kernels of this storage)
-                for name, dtype, fn, per in (("fp64", torch.complex128, gp.matvec_d, 32.0),
-                                             ("fp32", torch.complex64, gp.matvec32_d, 16.0)):
-                    u = torch.randn(gp.D, dtype=dtype, device="cuda", generator=gen)
-                    y = torch.empty_like(u)
-                    us = per_launch_us(torch, lambda: fn(u, y))
-                    res["product_" + name] = {
-                        "avg_launch_us": round(us, 2), "algorithmic_bytes": int(per * gp.D),
-                        "achieved_GBs": round(per * gp.D / (us * 1e-6) / 1e9, 1),
-                        "frac_of_hbm_peak": round(per * gp.D / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
-                    del u, y
                 res["layout"] = gp.layout()
             gp.homogenized(tol=TOL, energy=False)  # warm-up
             dt, _, r, _ = run_steps(gp, steps, torch)
@@ -668,7 +684,14 @@ def main():
     A_ref = np.array(gold["c3_eightfold_random_N32"]["A"])
 
     # headline: FP32-IR with every full batch of iterations replayed as a HIP graph
-    gp = qp.Problem(prob, precision="fp32ir", autotune=True)
+    if args.layout:
+        pin = [int(v) for v in args.layout.split(",")]
+        if len(pin) != 6:
+            raise SystemExit("--layout takes six integers: IT,WG,XF,IT64,WG64,XF64")
+        gp = qp.Problem(prob, precision="fp32ir")
+        gp.set_layout(*pin)
+    else:
+        gp = qp.Problem(prob, precision="fp32ir", autotune=True)
     for _ in range(args.warmup):
         gp.homogenized(tol=TOL, energy=False)
     dt, lat, r, _ = run_steps(gp, args.steps, torch)
@@ -718,7 +741,8 @@ def main():
     algo_bytes = 16.0 * D * (mv_rhs / mv_n) if mv_n else 16.0 * D
     avg_s = (mv_ms / mv_n) * 1e-3 if mv_n else float("nan")
     achieved = algo_bytes / avg_s / 1e9 if mv_n else None
-    traffic = measured_traffic()
+    float_layout = (layout["item_tiles"], layout["workgroups"], layout["xcd_front"])
+    traffic = measured_traffic(layout=float_layout)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
@@ -739,7 +763,9 @@ def main():
     # caches; traffic from the committed sized-request counter summary
     hbm = hbm_products(torch, qp, W)
     h64 = hbm["fp64"]
-    traffic64 = measured_traffic(TRAFFIC_FILE_HBM, "fp64_bytes_per_launch")
+    hl = hbm["layout"]
+    traffic64 = measured_traffic(TRAFFIC_FILE_HBM, "fp64_bytes_per_launch",
+                                 (hl["item_tiles64"], hl["workgroups64"], hl["xcd_front64"]))
     roofline_hbm = {"bound": "hbm", "achieved": h64["achieved_GBs"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(h64["achieved_GBs"] / HBM_PEAK_GBS, 4),
                     "traffic": traffic64,
@@ -750,7 +776,9 @@ def main():
                     "memory_side_GBs": (round(traffic64 / (h64["avg_launch_us"] * 1e-6) / 1e9, 1)
                                         if traffic64 else None),
                     "copy_GBs": hbm["copy_GBs"], "frac_of_copy": h64["frac_of_copy"],
-                    "profile_mean_us": measured_traffic(TRAFFIC_FILE_HBM, "fp64_mean_duration_us"),
+                    "profile_mean_us": measured_traffic(
+                        TRAFFIC_FILE_HBM, "fp64_mean_duration_us",
+                        (hl["item_tiles64"], hl["workgroups64"], hl["xcd_front64"])),
                     "timing": "HIP events around each call on the library's stream (the call "
                               "returns after its launch)"}
     out = {

@@ -39,6 +39,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "qp_chunk_walk.h"
 #include "qp_device.h"
 
 namespace qp {
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
     if (EPI == EPI_ALPHA && (st->done || st->pause)) return;
     if (EPI == EPI_RESID && !st->replace) return;  // replaced only once paused (fold decides)
     constexpr int KC = Inflight<T>::v;
+    static_assert(chunk_walk_exact(KC, (kMaxG + 3) & ~3), "the chunk walk must end at the last record");
     // per padded mode and lane: (wrapped column, face factor as float); gp * kWave
     // entries of dynamic LDS when N <= kWave
     extern __shared__ int2 s_geo[];
@@ -393,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                 for (; rb + KC <= gp; rb += KC) chunk(integral_constant<int, KC>(), Gc, rb);
                 // a half chunk only when it keeps rb a multiple of 4 (gp is one,
                 // and the 4-chunks below must end exactly at gp)
-                if (KC / 2 >= 4 && (KC / 2) % 4 == 0 && rb + KC / 2 <= gp) {
+                if (take_half_chunk(KC, rb, gp)) {
                     chunk(integral_constant<int, (KC / 2 >= 4 ? KC / 2 : 4)>(), Gc, rb);
                     rb += KC / 2;
                 }
@@ -724,6 +726,7 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
     static_assert(!HALF || (REAL && !AN && !WIDE), "half storage: real scalar coefficient");
     // neighbour loads in flight per chunk: about Inflight<T> over all right-hand sides
     constexpr int KC = (Inflight<T>::v / KR >= 8) ? (Inflight<T>::v / KR) / 4 * 4 : 4;
+    static_assert(chunk_walk_exact(KC, (kMaxG + 3) & ~3), "the chunk walk must end at the last record");
     using Rec = TileRec<T, DT, AN, HALF>;
     // dynamic LDS: gp * kWave lane-geometry entries (column, face factor),
     // then kWaves * gp unit records
@@ -988,7 +991,7 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                 for (; rb + KC <= gp; rb += KC) chunk(integral_constant<int, KC>(), rb);
                 // a half chunk only when it keeps rb a multiple of 4 (gp is one,
                 // and the 4-chunks below must end exactly at gp)
-                if (KC / 2 >= 4 && (KC / 2) % 4 == 0 && rb + KC / 2 <= gp) {
+                if (take_half_chunk(KC, rb, gp)) {
                     chunk(integral_constant<int, (KC / 2 >= 4 ? KC / 2 : 4)>(), rb);
                     rb += KC / 2;
                 }
