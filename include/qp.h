@@ -551,6 +551,12 @@ qp_status qp_matvec_half_d(qp_problem *p, const double *u, double *y);
 /* y = Q u with float data and arithmetic (the FP32-IR inner product); u and
  * y (D float complex each) must not overlap (QP_EINVAL). */
 qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y);
+/* Kernel time of the last qp_matvec_d or qp_matvec32_d call on p, in ms:
+ * with the profile option on, those calls launch their kernel with a HIP
+ * event pair that the launch itself records (so the time excludes the
+ * dispatch gap in front of the kernel); *ms = -1 when the last call was not
+ * timed.  QP_EINVAL for a null argument. */
+qp_status qp_last_product_ms(const qp_problem *p, double *ms);
 /* The diagonal preconditioner (eq. precond; kind per the options), D doubles. */
 qp_status qp_precond_d(qp_problem *p, double *M);
 /* Corrector right-hand side F_k = i (P k)_j Ahat_k, D complex doubles. */

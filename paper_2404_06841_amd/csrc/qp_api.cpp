@@ -147,6 +147,7 @@ struct qp_problem {
     int *hexec = nullptr;      // pinned copy of the execution log
     double *hhist = nullptr;   // pinned copy of the Lanczos coefficients (kMaxRhs x kHist pairs)
     std::vector<hipEvent_t> ev_hot, ev_res;  // profiling events (begin, end pairs)
+    double last_product_ms = -1.0;  // the last single product's kernel time (profile on)
     struct Graph {
         bool ir;
         int K, k, ab;
@@ -2485,14 +2486,45 @@ qp_status qp_homogenized(qp_problem *p, double *Astar, double tol, qp_solve_info
     return qp_homogenized_ex(p, Astar, nullptr, tol, info);
 }
 
+}  // extern "C"
+
+// One product of the single-product entry points; with the profile option on,
+// the launch records an event pair around its kernel and the duration is kept
+// for qp_last_product_ms.
+static qp_status single_product(qp_problem *p, int prec, const void *u, void *y)
+{
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    p->last_product_ms = -1.0;
+    if (p->opt.profile) {
+        QP_TRY(events_ready(p));
+        ev0 = p->ev_hot[0];
+        ev1 = p->ev_hot[1];
+    }
+    QP_HIP(qp::launch_matvec(prec, qp::EPI_NONE, 1, p->tab, p->host, p->recs(), p->urec(prec),
+                             p->upku(prec), u, y, nullptr, nullptr, p->parts(), p->st(), nullptr,
+                             p->stream, ev0, ev1));
+    QP_HIP(hipStreamSynchronize(p->stream));
+    if (ev0) {
+        float ms = 0.f;
+        QP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        p->last_product_ms = ms;
+    }
+    return QP_OK;
+}
+
+extern "C" {
+
 qp_status qp_matvec_d(qp_problem *p, const double *u, double *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
     if (overlaps(u, y, 16 * (size_t)p->host.D)) return fail(QP_EINVAL, "u and y must not overlap");
-    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, 1, p->tab, p->host, p->recs(), p->urec(qp::F64),
-                             p->upku(qp::F64), u, y, nullptr,
-                             nullptr, p->parts(), p->st(), nullptr, p->stream));
-    QP_HIP(hipStreamSynchronize(p->stream));
+    return single_product(p, qp::F64, u, y);
+}
+
+qp_status qp_last_product_ms(const qp_problem *p, double *ms)
+{
+    if (!p || !ms) return fail(QP_EINVAL, "null argument");
+    *ms = p->last_product_ms;
     return QP_OK;
 }
 
@@ -2515,11 +2547,7 @@ qp_status qp_matvec32_d(qp_problem *p, const float *u, float *y)
 {
     if (!p || !u || !y) return fail(QP_EINVAL, "null argument");
     if (overlaps(u, y, 8 * (size_t)p->host.D)) return fail(QP_EINVAL, "u and y must not overlap");
-    QP_HIP(qp::launch_matvec(qp::F32, qp::EPI_NONE, 1, p->tab, p->host, p->recs(), p->urec(qp::F32),
-                             p->upku(qp::F32), u, y, nullptr,
-                             nullptr, p->parts(), p->st(), nullptr, p->stream));
-    QP_HIP(hipStreamSynchronize(p->stream));
-    return QP_OK;
+    return single_product(p, qp::F32, u, y);
 }
 
 qp_status qp_dft_d(int n, int N, const double *in, double *out, int inverse, void *stream)

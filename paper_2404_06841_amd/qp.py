@@ -48,7 +48,7 @@ EXPORTED = (
     "qp_homogenized_grouped_noalloc", "qp_homogenized_batch_mixed", "qp_server_create",
     "qp_server_submit", "qp_server_progress", "qp_server_pending", "qp_server_bytes",
     "qp_server_destroy", "qp_coo_entries", "qp_coo_build_d", "qp_coo_matvec_d", "qp_dft_d",
-    "qp_modes_from_spectrum", "qp_matvec_d", "qp_matvec32_d", "qp_matvec_half_d", "qp_precond_d",
+    "qp_modes_from_spectrum", "qp_matvec_d", "qp_matvec32_d", "qp_matvec_half_d", "qp_last_product_ms", "qp_precond_d",
     "qp_corrector_rhs_d", "qp_multi_index_d", "qp_astar_d", "qp_coef_extrema",
     "qp_synchronize", "qp_strerror", "qp_last_error",
 )
@@ -146,6 +146,7 @@ def lib():
         "qp_coo_matvec_d": (C.c_int, [vp, vp, vp, vp, vp]),
         "qp_matvec_d": (C.c_int, [vp, vp, vp]),
         "qp_matvec32_d": (C.c_int, [vp, vp, vp]),
+        "qp_last_product_ms": (C.c_int, [vp, dp]),
         "qp_matvec_half_d": (C.c_int, [vp, vp, vp]),
         "qp_precond_d": (C.c_int, [vp, vp]),
         "qp_corrector_rhs_d": (C.c_int, [vp, C.c_int, vp]),
@@ -390,6 +391,13 @@ class Problem:
         _check(lib().qp_matvec32_d(self.h, _tensor_ptr(u, torch.complex64, self.D),
                                    _tensor_ptr(out, torch.complex64, self.D)), "qp_matvec32_d")
         return out
+
+    def last_product_ms(self) -> float:
+        """Kernel time of the last matvec_d / matvec32_d call (profile option
+        on; -1 otherwise), from the launch's own event pair."""
+        ms = C.c_double()
+        _check(lib().qp_last_product_ms(self.h, C.byref(ms)), "qp_last_product_ms")
+        return ms.value
 
     def matvec_half_d(self, u, out=None):
         """y = Q u on Hermitian half storage: (D+1)//2 complex128 entries each

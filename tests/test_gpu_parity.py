@@ -393,6 +393,35 @@ def test_products_reject_overlapping_buffers():
     gp.close()
 
 
+def test_single_product_kernel_time():
+    """qp_last_product_ms: -1 unless the profile option is on; then the
+    kernel time of the last single product, within the time of the call
+    bracketed by events (which also holds the dispatch gap), and the timed
+    product's values are those of an untimed one."""
+    prob = W.icosahedral(8)
+    gp = qp.Problem(prob)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    for dtype, fn in ((torch.complex128, gp.matvec_d), (torch.complex64, gp.matvec32_d)):
+        u = torch.randn(prob.D, dtype=dtype, device="cuda", generator=gen)
+        y0, y1 = torch.empty_like(u), torch.empty_like(u)
+        fn(u, y0)
+        assert gp.last_product_ms() == -1.0
+        gp.set_options(profile=1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn(u, y1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = gp.last_product_ms()
+        assert 0.0 < ms <= e0.elapsed_time(e1) + 1e-3, (ms, e0.elapsed_time(e1))
+        assert torch.equal(y0, y1)
+        gp.set_options(profile=0)
+        fn(u, y1)
+        assert gp.last_product_ms() == -1.0
+    gp.close()
+
+
 # ------------------------------------------------------------- condition estimate
 
 @pytest.mark.parametrize("make", [lambda: W.eightfold_random(8, 1), lambda: W.icosahedral(4),
