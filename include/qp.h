@@ -546,7 +546,12 @@ qp_status qp_matvec_d(qp_problem *p, const double *u, double *y);
  * S_t = N^(n-t), index i at position i - (S_t - 1)/2.  Those are the k != 0
  * whose first nonzero component is positive; k's partner -k is implied.
  * Its algorithmic bytes (u read once, y written once) are half those of
- * qp_matvec_d.  u and y must not overlap (QP_EINVAL); synchronous. */
+ * qp_matvec_d.  On a problem created with the half_storage option this is
+ * qp_matvec_d (the plane-tile product on the stored half, about 0.6x the
+ * full product's time); on a full-storage problem it runs a plain kernel,
+ * one thread per stored entry, which re-reads its neighbours from memory
+ * and takes longer than the full product (for speed create the problem
+ * with half_storage).  u and y must not overlap (QP_EINVAL); synchronous. */
 qp_status qp_matvec_half_d(qp_problem *p, const double *u, double *y);
 /* y = Q u with float data and arithmetic (the FP32-IR inner product); u and
  * y (D float complex each) must not overlap (QP_EINVAL). */
