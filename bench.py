@@ -57,6 +57,9 @@ def parse_args():
                     help="with --headline-only: IT,WG,XF,IT64,WG64,XF64, the product layouts "
                          "to use instead of the autotuner's choice (counter runs perturb the "
                          "tuner's timings, so they pin the layout the timed run chose)")
+    ap.add_argument("--config-table", action="store_true",
+                    help="only time every workload configuration on the GPU (FP32-IR and "
+                         "FP64) beside the oracle on all host threads, one line each")
     ap.add_argument("--batch-breakdown", action="store_true",
                     help="only time the 64-instance FP32-IR batch by size class (instances "
                          "alone, on streams, grouped) and print one line per class")
@@ -119,6 +122,101 @@ def batch_breakdown():
                           "ms": round(sorted(ts)[1] * 1e3, 2)}), flush=True)
     for gp in gps:
         gp.close()
+
+
+def config_table():
+    """Corrector solves per second for every workload configuration: on the
+    GPU (FP32-IR and FP64 homogenizations, autotuned layouts, at least five
+    runs or one second after a warm-up) and by the oracle on all host threads
+    (its corrector solves, A* excluded): the degenerate one-dimensional field
+    at N = 32 (d = 1, n = 2), the eightfold field at N = 16 and the seeded
+    eightfold field at N = 32 in full; the 64-instance batch as the sum over
+    its instances (GPU: the mixed batch); the icosahedral field at N = 6, 8,
+    12 in full and at N = 16 from three oracle iterations per corrector,
+    scaled to the GPU's FP64 iteration counts."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2404_06841_amd import qp
+    from paper_2404_06841_amd import workloads as W
+
+    def gpu_rate(prob, prec):
+        gp = qp.Problem(prob, precision=prec, autotune=True)
+        r = gp.homogenized(tol=TOL, energy=False)
+        torch.cuda.synchronize()
+        n, t0 = 0, time.perf_counter()
+        while n < 5 or time.perf_counter() - t0 < 1.0:
+            r = gp.homogenized(tol=TOL, energy=False)
+            n += 1
+        dt = time.perf_counter() - t0
+        gp.close()
+        return prob.d * n / dt, [int(i.iters) for i in r.infos]
+
+    def oracle_solves(prob, maxit=10000):
+        t0 = time.perf_counter()
+        its = []
+        for j in range(prob.d):
+            _, _, it, _ = oracle.pcg(prob, oracle.corrector_rhs(prob, j), tol=TOL, maxit=maxit)
+            its.append(it)
+        return time.perf_counter() - t0, its
+
+    threads = oracle.max_threads()
+    cases = [("C1 one-dimensional degenerate d=1 n=2 N=32", W.one_d_two_mode(32, 2.0)),
+             ("C2 eightfold d=2 n=4 N=16", W.eightfold(16)),
+             ("C3 seeded eightfold d=2 n=4 N=32", W.eightfold_random(32, 0)),
+             ("C5 icosahedral d=3 n=6 N=6", W.icosahedral(6)),
+             ("C5 icosahedral d=3 n=6 N=8", W.icosahedral(8)),
+             ("C5 icosahedral d=3 n=6 N=12", W.icosahedral(12))]
+    for name, prob in cases:
+        r32, it32 = gpu_rate(prob, "fp32ir")
+        r64, it64 = gpu_rate(prob, "fp64")
+        dt, its = oracle_solves(prob)
+        print(json.dumps({"config": name, "unknowns": int(prob.D), "gpu_fp32ir_solves_per_s": round(r32, 2),
+                          "gpu_fp64_solves_per_s": round(r64, 2), "gpu_iters_fp64": it64,
+                          "oracle_solves_per_s": round(prob.d / dt, 4), "oracle_iters": its,
+                          "oracle_threads": threads,
+                          "gpu_fp32ir_over_oracle": round(r32 * dt / prob.d, 1)}), flush=True)
+    # icosahedral N = 16: three oracle iterations per corrector, scaled
+    prob = W.icosahedral(16)
+    r32, it32 = gpu_rate(prob, "fp32ir")
+    r64, it64 = gpu_rate(prob, "fp64")
+    dt3, _ = oracle_solves(prob, maxit=3)
+    est = dt3 * (sum(it64) / (3.0 * prob.d))
+    print(json.dumps({"config": "C5 icosahedral d=3 n=6 N=16", "unknowns": int(prob.D),
+                      "gpu_fp32ir_solves_per_s": round(r32, 2), "gpu_fp64_solves_per_s": round(r64, 2),
+                      "gpu_iters_fp64": it64,
+                      "oracle_solves_per_s": round(prob.d / est, 5),
+                      "oracle_sample": f"3 iterations per corrector in {dt3:.2f} s, scaled to "
+                                       f"{sum(it64)} iterations",
+                      "oracle_threads": threads,
+                      "gpu_fp32ir_over_oracle": round(r32 * est / prob.d, 1)}), flush=True)
+    # the 64-instance batch: GPU mixed batch; oracle summed over the instances
+    probs = W.eightfold_batch(64)
+    gps = [qp.Problem(pr, precision="fp32ir", stream=torch.cuda.Stream(), autotune=True)
+           for pr in probs]
+    qp.homogenized_batch(gps, tol=TOL, group_max_dim=MIXED_GROUP_DIM)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        qp.homogenized_batch(gps, tol=TOL, group_max_dim=MIXED_GROUP_DIM)
+    dtg = (time.perf_counter() - t0) / 3
+    for gp in gps:
+        gp.close()
+    solves = sum(pr.d for pr in probs)
+    tot = 0.0
+    for i, pr in enumerate(probs):
+        dt, _ = oracle_solves(pr)
+        tot += dt
+        if i % 16 == 15:
+            print(json.dumps({"config_progress": f"oracle over batch instances {i + 1}/64",
+                              "seconds": round(tot, 1)}), flush=True)
+    print(json.dumps({"config": "C4 64 seeded eightfold instances, N in {8, 12, 16, 24, 32}",
+                      "unknowns": int(sum(pr.D for pr in probs)),
+                      "gpu_fp32ir_solves_per_s": round(solves / dtg, 2),
+                      "gpu_path": "qp_homogenized_batch_mixed",
+                      "oracle_solves_per_s": round(solves / tot, 4), "oracle_threads": threads,
+                      "gpu_fp32ir_over_oracle": round(tot / dtg, 1)}), flush=True)
 
 
 def copy_probe():
@@ -669,6 +767,9 @@ def main():
         return
     if args.batch_breakdown:
         batch_breakdown()
+        return
+    if args.config_table:
+        config_table()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
