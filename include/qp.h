@@ -137,6 +137,18 @@ typedef struct qp_options {
                            The stored-matrix calls are not available, the
                            problem cannot join grouped calls, and a server
                            rejects the option.  Fixed at creation; default 0 */
+    int small_dim;      /* FP64 solves of problems with at most this many
+                           unknowns (and at most 2048; scalar coefficient,
+                           full storage) run the whole PCG loop in one launch,
+                           one workgroup per right-hand side holding its
+                           vectors in registers and LDS, instead of three
+                           launches per iteration: the same recurrences and
+                           state (status, iterations, condition estimate),
+                           with the sums formed in the workgroup's order.  Not
+                           with the profile option (which times every product
+                           launch).  0 = never; default 2048 (above about
+                           that size the three-launch loop, spread over the
+                           whole device, is faster)                         */
 } qp_options;
 
 typedef struct qp_solve_info {

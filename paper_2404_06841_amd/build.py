@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libqp.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(CSRC, f) for f in (
     "qp_matvec.hip", "qp_matvec_diag.hip", "qp_matvec_half.hip", "qp_group.hip", "qp_krylov.hip", "qp_setup.hip",
-    "qp_coo.hip", "qp_dft.hip", "qp_half.hip",
+    "qp_coo.hip", "qp_dft.hip", "qp_half.hip", "qp_small.hip",
     "qp_api.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

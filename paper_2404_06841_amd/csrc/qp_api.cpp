@@ -896,6 +896,7 @@ struct SolveJob {
     double *U = nullptr;
     double tol = 0.0;
     bool ir = false, prof = false;
+    bool one_launch = false;  // FP64 loop in one launch (small problems)
     enum Phase { kQueue, kWait, kFinal, kForce, kDone } phase = kDone;
     Profile pf;
     Poller poll;
@@ -917,6 +918,8 @@ struct SolveJob {
         tol = tol_;
         ir = p->opt.precision == QP_PREC_FP32_IR;
         prof = p->opt.profile != 0;
+        one_launch = !ir && !prof && !p->host.aniso && !p->host.half &&
+                     p->host.D <= std::min(p->opt.small_dim, qp::kSmallMax);
         pf = Profile{};
         poll = Poller{};
         poll.p = p;
@@ -1016,6 +1019,15 @@ struct SolveJob {
             switch (phase) {
             case kQueue: {
                 if (j >= p->opt.maxit) {
+                    QP_TRY(begin_final());
+                    progressed = true;
+                    continue;
+                }
+                if (one_launch) {
+                    // every iteration in one launch; then the final states
+                    QP_HIP(qp::launch_pcg_wg(K, p->tab, p->host, U, p->r(), p->h(), p->M64(),
+                                             p->st(), p->stream));
+                    j = p->opt.maxit;
                     QP_TRY(begin_final());
                     progressed = true;
                     continue;
@@ -1346,6 +1358,7 @@ qp_status check_options(const qp_options *o)
         return fail(QP_EINVAL, "invalid iteration limits or inner tolerance");
     if (o->half_storage && o->gather64)
         return fail(QP_EINVAL, "half storage uses the 32-bit gathers (gather64 must be 0)");
+    if (o->small_dim < 0) return fail(QP_EINVAL, "small_dim must not be negative");
     return QP_OK;
 }
 
@@ -1377,6 +1390,7 @@ void qp_default_options(qp_options *opt)
     opt->inner_tol = 1e-5;
     opt->poll_every = 0;
     opt->graphs = 1;
+    opt->small_dim = 2048;
 }
 
 size_t qp_workspace_bytes(int d, int n, int N, int g)

@@ -321,6 +321,12 @@ hipError_t launch_pcg_update(int prec, int j, int K, const Table *tab, const Tab
 hipError_t launch_pcg_direction(int prec, int j, int K, const Table *tab, const Table &ht, void *U,
                                 const void *r, void *h, const void *M, const Parts &parts,
                                 State *st, hipStream_t s);
+// FP64 C-PCG of K right-hand sides to the end, one workgroup each, from the
+// vectors and states of launch_pcg_init / launch_pcg_start (scalar
+// coefficient, full storage, at most kSmallMax unknowns).
+constexpr int kSmallMax = 2048;
+hipError_t launch_pcg_wg(int K, const Table *tab, const Table &ht, double *U, double *r, double *h,
+                         const double *M, State *st, hipStream_t s);
 // FP32-IR start: st->rr0 = ||f'||^2, unit = sqrt(rr0) (two launches).
 hipError_t launch_ir_unit(int K, const Table *tab, const Table &ht, const double *f,
                           const Parts &parts, State *st, hipStream_t s);

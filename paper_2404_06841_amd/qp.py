@@ -60,7 +60,7 @@ class qp_options(C.Structure):
                 ("profile", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("graphs", C.c_int),
                 ("gather64", C.c_int), ("autotune", C.c_int), ("allow_indefinite", C.c_int),
-                ("half_storage", C.c_int)]
+                ("half_storage", C.c_int), ("small_dim", C.c_int)]
 
 
 class qp_layout(C.Structure):
@@ -254,7 +254,8 @@ class Problem:
                  maxit: int = 10000, inner_tol: float = 1e-5,
                  profile: bool = False, stream=None, poll_every: int = 0,
                  graphs: bool = True, gather64: bool = False, autotune: bool = False,
-                 allow_indefinite: bool = False, half_storage: bool = False):
+                 allow_indefinite: bool = False, half_storage: bool = False,
+                 small_dim=None):
         import torch
         self.d, self.n, self.N = int(prob.d), int(prob.n), int(prob.N)
         self.Dgrid = self.N ** self.n
@@ -275,6 +276,8 @@ class Problem:
         opt.autotune = 1 if autotune else 0
         opt.allow_indefinite = 1 if allow_indefinite else 0
         opt.half_storage = 1 if half_storage else 0
+        if small_dim is not None:
+            opt.small_dim = int(small_dim)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         nbytes = qp_workspace_bytes(self.d, self.n, self.N, self.g)

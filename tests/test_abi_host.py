@@ -36,6 +36,7 @@ def test_default_options_and_strings():
     assert o.maxit == 10000 and o.inner_tol == pytest.approx(1e-5) and o.poll_every == 0
     assert o.graphs == 1
     assert o.gather64 == 0
+    assert o.small_dim == 2048
     assert o.stream is None and o.workspace is None
     for s in range(0, -8, -1):
         assert qp.qp_strerror(s)
@@ -110,6 +111,13 @@ def test_invalid_problems_rejected_on_host(case):
     st, h = _create(p, **over)
     assert st == qp.QP_EINVAL and h is None, (st, qp.qp_last_error())
     assert qp.qp_last_error()
+
+
+def test_invalid_options_rejected_on_host():
+    o = qp.qp_default_options()
+    o.small_dim = -1
+    st, h = qp.qp_create(BASE.d, BASE.n, BASE.P, BASE.modes, BASE.coef, BASE.N, o)
+    assert st == qp.QP_EINVAL and h is None and "small_dim" in qp.qp_last_error()
 
 
 def test_valid_problem_without_device_reports_device_error():

@@ -59,10 +59,12 @@ def test_graph_replays_equal_direct_launches(prec):
     gp.close()
 
 
+# The FP64 tests below keep small problems on the multi-launch loop
+# (small_dim 0): its batches are what they test.
 def test_graph_cache_follows_the_output_buffer():
     prob = W.eightfold(8)
     F = dev(W.random_vector(prob.D, seed=3))
-    gp = qp.Problem(prob)
+    gp = qp.Problem(prob, small_dim=0)
     outs = [torch.empty(prob.D, dtype=torch.complex128, device="cuda") for _ in range(3)]
     res = []
     for rep in range(2):
@@ -80,7 +82,7 @@ def test_partial_last_batch_stops_at_the_limit():
     F = W.random_vector(prob.D, seed=1)
     ref, st, it, rr = oracle.pcg(prob, F, tol=1e-14, maxit=11)
     for graphs in (True, False):
-        gp = qp.Problem(prob, maxit=11, graphs=graphs)
+        gp = qp.Problem(prob, maxit=11, graphs=graphs, small_dim=0)
         u, info = gp.solve_d(dev(F), tol=1e-14, check=False)
         assert info.status == qp.QP_ENOCONV and info.iters == 11
         assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
@@ -90,8 +92,8 @@ def test_partial_last_batch_stops_at_the_limit():
 def test_batch_length_does_not_change_fp64_iterates():
     prob = W.eightfold_random(8, 1)
     F = dev(W.random_vector(prob.D, seed=2))
-    a = qp.Problem(prob)
-    b = qp.Problem(prob, poll_every=5)  # rounded up to 6
+    a = qp.Problem(prob, small_dim=0)
+    b = qp.Problem(prob, poll_every=5, small_dim=0)  # rounded up to 6
     ua, ia = a.solve_d(F, tol=1e-12)
     ub, ib = b.solve_d(F, tol=1e-12)
     assert ia.iters == ib.iters and torch.equal(ua, ub)
@@ -127,8 +129,9 @@ def test_profiled_launches_time_and_match_unprofiled(prob, prec):
     """A profiled product launch records its own event pair; the line kernel,
     the diagonal-coefficient and complex-coefficient plane kernels all take
     that launch path.  The timed solve gives bitwise the same A* as the
-    unprofiled one."""
-    plain = qp.Problem(prob, precision=prec)
+    unprofiled one on the same path (small_dim 0: a profiled FP64 solve never
+    takes the one-launch loop of small problems)."""
+    plain = qp.Problem(prob, precision=prec, small_dim=0)
     timed = qp.Problem(prob, precision=prec, profile=True)
     ra = plain.homogenized(tol=1e-12)
     rb = timed.homogenized(tol=1e-12)
