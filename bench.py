@@ -133,7 +133,9 @@ def config_table():
     eightfold field at N = 32 in full; the 64-instance batch as the sum over
     its instances (GPU: the mixed batch); the icosahedral field at N = 6, 8,
     12 in full and at N = 16 from three oracle iterations per corrector,
-    scaled to the GPU's FP64 iteration counts."""
+    scaled to the GPU's FP64 iteration counts.  First, the paper's first
+    example at N = 32, 64, 128: the FP64 solve of a manufactured solution,
+    its time and relative error."""
     import numpy as np
     import torch
 
@@ -162,6 +164,28 @@ def config_table():
         return time.perf_counter() - t0, its
 
     threads = oracle.max_threads()
+    # the paper's first example (Sec. 5.1.1): a = 6 + cos y1 + cos y2 on
+    # P = 2 pi (1, sqrt 2), manufactured solution u = sin y1 + sin y2 (its
+    # coefficients -i/2 at +e_t and +i/2 at -e_t lie in the grid), F = Q U
+    for N in (32, 64, 128):
+        prob = W.one_d_two_mode(N, 6.0, 2 * np.pi)
+        Ux = torch.zeros(prob.D, dtype=torch.complex128, device="cuda")
+        for stride in (N, 1):  # the two axes of the grid
+            Ux[1 * stride] = -0.5j
+            Ux[(N - 1) * stride] = 0.5j
+        gp = qp.Problem(prob)
+        F = gp.matvec_d(Ux).clone()
+        U, info = gp.solve_d(F, tol=TOL)
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            U, info = gp.solve_d(F, tol=TOL)
+            ts.append(time.perf_counter() - t0)
+        err = float(torch.linalg.vector_norm(U - Ux) / torch.linalg.vector_norm(Ux))
+        print(json.dumps({"config": f"paper example 1 (d=1 n=2, a = 6 + cos + cos) N={N}",
+                          "unknowns": int(prob.D), "gpu_fp64_solve_ms": round(sorted(ts)[2] * 1e3, 3),
+                          "iters": int(info.iters), "relative_error": err}), flush=True)
+        gp.close()
     cases = [("C1 one-dimensional degenerate d=1 n=2 N=32", W.one_d_two_mode(32, 2.0)),
              ("C2 eightfold d=2 n=4 N=16", W.eightfold(16)),
              ("C3 seeded eightfold d=2 n=4 N=32", W.eightfold_random(32, 0)),
