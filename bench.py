@@ -60,6 +60,9 @@ def parse_args():
     ap.add_argument("--config-table", action="store_true",
                     help="only time every workload configuration on the GPU (FP32-IR and "
                          "FP64) beside the oracle on all host threads, one line each")
+    ap.add_argument("--small-sweep", action="store_true",
+                    help="only compare FP64 homogenizations of small problems in one launch "
+                         "(small_dim) with the three-launch loop, one line per problem")
     ap.add_argument("--batch-breakdown", action="store_true",
                     help="only time the 64-instance FP32-IR batch by size class (instances "
                          "alone, on streams, grouped) and print one line per class")
@@ -241,6 +244,42 @@ def config_table():
                       "gpu_path": "qp_homogenized_batch_mixed",
                       "oracle_solves_per_s": round(solves / tot, 4), "oracle_threads": threads,
                       "gpu_fp32ir_over_oracle": round(tot / dtg, 1)}), flush=True)
+
+
+def small_sweep():
+    """FP64 homogenizations of problems of at most 2048 unknowns with the
+    whole PCG loop in one launch (the default small_dim) and with three
+    launches per iteration (small_dim 0): corrector solves per second and
+    microseconds per iteration (at least ten homogenizations or half a
+    second each, after a warm-up)."""
+    import numpy as np
+    import torch
+
+    from paper_2404_06841_amd import qp
+    from paper_2404_06841_amd import workloads as W
+    cases = [("one-dimensional degenerate N=32", W.one_d_two_mode(32, 2.0)),
+             ("one-dimensional periodic N=100", W.periodic_1d(100)),
+             ("one-dimensional N=45", W.one_d_two_mode(45, 6.0, 2 * np.pi)),
+             ("eightfold N=6", W.eightfold(6)), ("seeded eightfold N=5", W.eightfold_random(5, 7)),
+             ("seeded eightfold N=6", W.eightfold_random(6, 2)), ("icosahedral N=3", W.icosahedral(3)),
+             ("cubic d=3 N=7", W.periodic_cubic(3, 7)), ("cubic d=3 N=12", W.periodic_cubic(3, 12)),
+             ("cubic d=4 N=6", W.periodic_cubic(4, 6))]
+    for name, prob in cases:
+        out = {"small_sweep": name, "unknowns": int(prob.D), "modes": int(prob.g)}
+        for label, sd in (("one_launch", None), ("three_launches", 0)):
+            gp = qp.Problem(prob, small_dim=sd)
+            r = gp.homogenized(tol=TOL, energy=False)
+            torch.cuda.synchronize()
+            n, t0 = 0, time.perf_counter()
+            while n < 10 or time.perf_counter() - t0 < 0.5:
+                r = gp.homogenized(tol=TOL, energy=False)
+                n += 1
+            dt = (time.perf_counter() - t0) / n
+            it = max(int(i.iters) for i in r.infos)
+            out[label] = {"solves_per_s": round(prob.d / dt, 1), "iters": it,
+                          "us_per_iteration": round(dt * 1e6 / it, 2)}
+            gp.close()
+        print(json.dumps(out), flush=True)
 
 
 def copy_probe():
@@ -794,6 +833,9 @@ def main():
         return
     if args.config_table:
         config_table()
+        return
+    if args.small_sweep:
+        small_sweep()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
