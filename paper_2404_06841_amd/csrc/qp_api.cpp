@@ -897,6 +897,12 @@ struct SolveJob {
     double tol = 0.0;
     bool ir = false, prof = false;
     bool one_launch = false;  // FP64 loop in one launch (small problems)
+    // Called once the final states are queued (and again after a forced
+    // replacement), before the final event is recorded: a homogenization
+    // queues its A* there, behind the solve, instead of after the host has
+    // seen the solve finish.  Set after begin().
+    qp_status (*after_final)(void *) = nullptr;
+    void *after_ctx = nullptr;
     enum Phase { kQueue, kWait, kFinal, kForce, kDone } phase = kDone;
     Profile pf;
     Poller poll;
@@ -916,6 +922,8 @@ struct SolveJob {
         rhs = rhs_;
         U = U_;
         tol = tol_;
+        after_final = nullptr;
+        after_ctx = nullptr;
         ir = p->opt.precision == QP_PREC_FP32_IR;
         prof = p->opt.profile != 0;
         one_launch = !ir && !prof && !p->host.aniso && !p->host.half &&
@@ -1080,6 +1088,7 @@ struct SolveJob {
                         QP_TRY(enqueue_replacement(p, K, U, rhs, p->opt.maxit, 0, false));
                         QP_HIP(hipEventRecord(p->ev_t1, p->stream));
                         QP_TRY(poll.queue_final());
+                        if (after_final) QP_TRY(after_final(after_ctx));
                         QP_HIP(hipEventRecord(p->ev_fin, p->stream));
                         phase = kForce;
                         continue;
@@ -1104,6 +1113,7 @@ struct SolveJob {
     {
         QP_HIP(hipEventRecord(p->ev_t1, p->stream));
         QP_TRY(poll.queue_final());
+        if (after_final) QP_TRY(after_final(after_ctx));
         QP_HIP(hipEventRecord(p->ev_fin, p->stream));
         phase = kFinal;
         return QP_OK;
@@ -1233,7 +1243,37 @@ struct HomJob {
     {
         const size_t D2 = 2 * (size_t)p->host.D;
         const int Kg = std::min(G, p->host.d - r0);
-        return sj.begin(p, Kg, p->F() + r0 * D2, p->chi(0) + r0 * D2, tol, norms_ready);
+        QP_TRY(sj.begin(p, Kg, p->F() + r0 * D2, p->chi(0) + r0 * D2, tol, norms_ready));
+        if (r0 + Kg >= p->host.d) {
+            // the last group: A* goes behind its final states
+            sj.after_final = &HomJob::astar_hook;
+            sj.after_ctx = this;
+        }
+        return QP_OK;
+    }
+
+    static qp_status astar_hook(void *ctx) { return static_cast<HomJob *>(ctx)->queue_astar(); }
+
+    // A* (flux form, and the energy form on request) of the correctors and
+    // its copy to the host, queued on the problem's stream.
+    qp_status queue_astar()
+    {
+        const int d = p->host.d;
+        QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), p->stream));
+        if (Aenergy) {
+            const qp::Parts parts = p->parts();
+            for (int j = 0; j < d; ++j) {
+                QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, 1, p->tab, p->host, p->recs(),
+                                         p->urec(qp::F64), p->upku(qp::F64), p->chi(j), p->q(),
+                                         nullptr, nullptr, parts, p->st(), nullptr, p->stream));
+                for (int i = 0; i < d; ++i)
+                    QP_HIP(qp::launch_dot(p->tab, p->host, p->chi(i), p->q(), parts,
+                                          p->small() + 64 + i * d + j, p->stream));
+            }
+        }
+        QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream));
+        return QP_OK;
     }
 
     qp_status advance(bool blocking, bool &progressed)
@@ -1254,21 +1294,8 @@ struct HomJob {
                 continue;
             }
             if (worst == QP_EDEVICE || worst == QP_EINVAL) return worst;
-            QP_HIP(qp::launch_astar(p->tab, p->host, p->chi(0), p->small(), p->stream));
-            if (Aenergy) {
-                const qp::Parts parts = p->parts();
-                for (int j = 0; j < d; ++j) {
-                    QP_HIP(qp::launch_matvec(qp::F64, qp::EPI_NONE, 1, p->tab, p->host, p->recs(),
-                                             p->urec(qp::F64), p->upku(qp::F64), p->chi(j), p->q(),
-                                             nullptr, nullptr, parts, p->st(), nullptr, p->stream));
-                    for (int i = 0; i < d; ++i)
-                        QP_HIP(qp::launch_dot(p->tab, p->host, p->chi(i), p->q(), parts,
-                                              p->small() + 64 + i * d + j, p->stream));
-                }
-            }
-            QP_HIP(hipMemcpyAsync(p->hsmall, p->small(), 128 * sizeof(double),
-                                  hipMemcpyDeviceToHost, p->stream));
-            QP_HIP(hipEventRecord(p->ev_fin, p->stream));
+            // A* and its copy were queued behind the last group's final
+            // states (astar_hook), before that solve's final event
             phase = kAstar;
             progressed = true;
         }
