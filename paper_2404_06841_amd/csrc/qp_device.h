@@ -158,23 +158,58 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double *__restri
     store_partials_at<NV, MIN>(v, part, (int)blockIdx.x);
 }
 
-// Sum (or min) of the nb partials a previous kernel stored; same order in
-// every workgroup, result in every thread.
+// Partial sums a thread takes of each value: b = threadIdx.x + t kBlock.
+constexpr int kPartPer = kMaxBlocks / kBlock;
+static_assert(kMaxBlocks % kBlock == 0, "partials are dealt evenly over a workgroup");
+
+// Issues the loads of this thread's partials of NV values at once (every
+// slot below kMaxBlocks exists; slots at or beyond the count are not used),
+// so that they cost one round trip to memory rather than one each.
+template <int NV>
+__device__ __forceinline__ void fetch_partials(const double *__restrict__ part,
+                                               double (&p)[NV][kPartPer])
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int t = 0; t < kPartPer; ++t) p[k][t] = part[k * kMaxBlocks + threadIdx.x + t * kBlock];
+}
+
+// Sum (or min) of the first nb partials fetched above; same order in every
+// workgroup, result in every thread.
 template <int NV, bool MIN = false>
-__device__ __forceinline__ void load_totals(const double *__restrict__ part, int nb, double (&v)[NV])
+__device__ __forceinline__ void sum_partials(const double (&p)[NV][kPartPer], int nb, double (&v)[NV])
 {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double s = MIN ? INFINITY : 0.0;
-        for (int b = threadIdx.x; b < nb; b += kBlock) {
-            const double p = part[k * kMaxBlocks + b];
-            s = MIN ? fmin(s, p) : s + p;
-        }
+#pragma unroll
+        for (int t = 0; t < kPartPer; ++t)
+            if ((int)threadIdx.x + t * kBlock < nb) s = MIN ? fmin(s, p[k][t]) : s + p[k][t];
         v[k] = s;
     }
     block_reduce<NV, MIN>(v);
 }
 
+// Sum (or min) of the nb partials a previous kernel stored.
+template <int NV, bool MIN = false>
+__device__ __forceinline__ void load_totals(const double *__restrict__ part, int nb, double (&v)[NV])
+{
+    double p[NV][kPartPer];
+    fetch_partials<NV>(part, p);
+    sum_partials<NV, MIN>(p, nb, v);
+}
+
 __device__ __forceinline__ bool finite(double x) { return x == x && fabs(x) != INFINITY; }
+
+// Keeps a uniform value's load at this point of the program (an empty asm
+// statement that reads it from a scalar register).  A kernel's state flags,
+// scalars and table fields were written by earlier launches, so each load
+// is a round trip to memory; loaded together before the first branch they
+// cost one, where the compiler would otherwise sink each below the branch
+// that first needs it and chain them one after the other.
+__device__ __forceinline__ void pin(int v) { asm volatile("" : : "s"(v)); }
+__device__ __forceinline__ void pin(float v) { asm volatile("" : : "s"(v)); }
+__device__ __forceinline__ void pin(double v) { asm volatile("" : : "s"(v)); }
 
 }  // namespace qp

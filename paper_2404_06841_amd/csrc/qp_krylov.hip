@@ -441,26 +441,57 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
     const bool lead = vb == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block_at(tab, vb, vnb, begin, end);
+    const int nbp = tab->nb_mv;
+    // every flag and scalar of the right-hand sides, with the table fields,
+    // in one round trip before the first branch
+    int done[KK], pause[KK];
+    double rz[KK];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        done[k] = sts[k].done;
+        pause[k] = sts[k].pause;
+        rz[k] = sts[k].rz[j & 1];
+    }
+#pragma unroll
+    for (int k = 0; k < KK; ++k) pin(rz[k]);
+    pin(begin);
+    pin(end);
+    pin(nbp);
     bool act[KK];
     bool any = false;
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
-        act[k] = !(sts[k].done || sts[k].pause);
+        act[k] = !(done[k] | pause[k]);
         if (!act[k] && lead) sts[k].did_update = 0;
         any = any || act[k];
     }
     if (!any) return;
     const int i0 = begin + threadIdx.x;
+    // rows past the chunk load its last entry (and are never stored), so the
+    // loads of every row are issued back to back without branches
+    const int last = max(end - 1, 0);
     float2 rv[ROWS][KK], qv[ROWS][KK];
     float mv[ROWS];
 #pragma unroll
     for (int u = 0; u < ROWS; ++u) {
-        const int i = i0 + u * kBlock;
-        if (i < end) {
-            ld_row<KK>(r, i, rv[u]);
-            ld_row<KK>(q, i, qv[u]);
-            mv[u] = M[i];
+        const int i = min(i0 + u * kBlock, last);
+        ld_row<KK>(r, i, rv[u]);
+        ld_row<KK>(q, i, qv[u]);
+        mv[u] = M[i];
+    }
+    // the product's partials of every right-hand side, fetched together and
+    // reduced in one pass (each value as load_totals reduces it)
+    double hq_all[KK];
+    {
+        double p[KK][kPartPer];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            double pk[1][kPartPer];
+            fetch_partials<1>(part_in + k * kPartStride, pk);
+#pragma unroll
+            for (int t = 0; t < kPartPer; ++t) p[k][t] = pk[0][t];
         }
+        sum_partials<KK>(p, nbp, hq_all);
     }
     float a[KK];
     double alpha[KK], hqv[KK], acc[KK][2];
@@ -472,8 +503,7 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
         alpha[k] = hqv[k] = 0.0;
         acc[k][0] = acc[k][1] = 0.0;
         if (!act[k]) continue;
-        double hq[1];
-        load_totals<1>(part_in + k * kPartStride, tab->nb_mv, hq);  // the product's partials
+        const double hq[1] = {hq_all[k]};
         if (!(hq[0] > 0.0)) {
             // (Q h, h) <= 0: Q is not positive definite on this Krylov space
             if (lead) {
@@ -486,7 +516,7 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
             continue;
         }
         hqv[k] = hq[0];
-        alpha[k] = st->rz[j & 1] / hq[0];
+        alpha[k] = rz[k] / hq[0];
         a[k] = (float)alpha[k];
         any = true;
     }
@@ -512,12 +542,10 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
     for (int ib = i0 + ROWS * kBlock; ib < end; ib += ROWS * kBlock) {
 #pragma unroll
         for (int u = 0; u < ROWS; ++u) {
-            const int i = ib + u * kBlock;
-            if (i < end) {
-                ld_row<KK>(r, i, rv[u]);
-                ld_row<KK>(q, i, qv[u]);
-                mv[u] = M[i];
-            }
+            const int i = min(ib + u * kBlock, last);
+            ld_row<KK>(r, i, rv[u]);
+            ld_row<KK>(q, i, qv[u]);
+            mv[u] = M[i];
         }
 #pragma unroll
         for (int u = 0; u < ROWS; ++u) {
@@ -525,10 +553,27 @@ __device__ __forceinline__ void update_f(const int vb, const int vnb, int j,
             if (i < end) step(i, rv[u], qv[u], mv[u]);
         }
     }
+    // this launch's partials of every right-hand side in one reduction pass
+    {
+        double v[2 * KK];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            v[2 * k] = acc[k][0];
+            v[2 * k + 1] = acc[k][1];
+        }
+        block_reduce<2 * KK>(v);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < KK; ++k) {
+                if (!act[k]) continue;
+                part_out[k * kPartStride + vb] = v[2 * k];
+                part_out[k * kPartStride + kMaxBlocks + vb] = v[2 * k + 1];
+            }
+        }
+    }
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
         if (!act[k]) continue;
-        store_partials_at<2>(acc[k], part_out + k * kPartStride, vb);
         if (lead) {
             State *st = sts + k;
             hist_alpha(st, st->iters, alpha[k]);
@@ -555,30 +600,72 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
     const bool lead = vb == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block_at(tab, vb, vnb, begin, end);
+    // every flag and scalar of the right-hand sides in one round trip before
+    // the first branch (this launch's lead writes none of them)
+    int did_up[KK], done[KK], pause[KK];
+    double rz_old[KK], alpha[KK], thresh[KK], delta2[KK], rr_last[KK];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        const State *st = sts + k;
+        did_up[k] = st->did_update;
+        done[k] = st->done;
+        pause[k] = st->pause;
+        rz_old[k] = st->rz[j & 1];
+        alpha[k] = st->alpha;
+        thresh[k] = st->thresh;
+        delta2[k] = st->delta2;
+        rr_last[k] = st->rr_last;
+    }
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        pin(rz_old[k]);
+        pin(alpha[k]);
+        pin(thresh[k]);
+        pin(delta2[k]);
+        pin(rr_last[k]);
+    }
+    pin(begin);
+    pin(end);
     bool did[KK];
     bool any_did = false;
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
-        State *st = sts + k;
-        did[k] = st->did_update != 0;
+        did[k] = did_up[k] != 0;
         // no update this iteration; a paused solve carries rz forward so
         // iteration j+1 finds it in its slot
-        if (!did[k] && lead && !st->done && st->pause) st->rz[(j + 1) & 1] = st->rz[j & 1];
+        if (!did[k] && lead && !done[k] && pause[k]) sts[k].rz[(j + 1) & 1] = rz_old[k];
         any_did = any_did || did[k];
     }
     if (!any_did) return;
     const int i0 = begin + threadIdx.x;
+    // rows past the chunk load its last entry (and are never stored)
+    const int last = max(end - 1, 0);
     float2 uv[ROWS][KK], hv[ROWS][KK], rv[ROWS][KK];
     float mv[ROWS];
 #pragma unroll
     for (int u = 0; u < ROWS; ++u) {
-        const int i = i0 + u * kBlock;
-        if (i < end) {
-            ld_row<KK>(U, i, uv[u]);
-            ld_row<KK>(h, i, hv[u]);
-            ld_row<KK>(r, i, rv[u]);
-            mv[u] = M[i];
+        const int i = min(i0 + u * kBlock, last);
+        ld_row<KK>(U, i, uv[u]);
+        ld_row<KK>(h, i, hv[u]);
+        ld_row<KK>(r, i, rv[u]);
+        mv[u] = M[i];
+    }
+    // the update's partials (r, M r) and (r, r) of every right-hand side,
+    // fetched together and reduced in one pass
+    double tot[2 * KK];
+    {
+        double p[2 * KK][kPartPer];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            double pk[2][kPartPer];
+            fetch_partials<2>(part_in + k * kPartStride, pk);
+#pragma unroll
+            for (int t = 0; t < kPartPer; ++t) {
+                p[2 * k][t] = pk[0][t];
+                p[2 * k + 1][t] = pk[1][t];
+            }
         }
+        sum_partials<2 * KK>(p, vnb, tot);
     }
     bool go[KK];
     float a[KK], b[KK];
@@ -591,11 +678,8 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
         a[k] = b[k] = 0.f;
         rzn[k] = rrv[k] = betav[k] = 0.0;
         if (!did[k]) continue;
-        const double rz_old = st->rz[j & 1];
-        a[k] = (float)st->alpha;
-        double v[2];
-        load_totals<2>(part_in + k * kPartStride, vnb, v);
-        const double rz_new = v[0], rr = v[1];
+        a[k] = (float)alpha[k];
+        const double rz_new = tot[2 * k], rr = tot[2 * k + 1];
         if (!finite(rr) || !finite(rz_new)) {
             if (lead) {
                 st->status = QP_ENONFINITE;
@@ -603,11 +687,11 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
             }
             continue;
         }
-        if (rr <= fmax(st->thresh, st->delta2 * st->rr_last)) {
+        if (rr <= fmax(thresh[k], delta2[k] * rr_last[k])) {
             if (lead) {
                 st->rr = rr;
                 st->pause = 1;
-                st->rz[(j + 1) & 1] = rz_old;
+                st->rz[(j + 1) & 1] = rz_old[k];
             }
             continue;
         }
@@ -615,7 +699,7 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
         any_go = true;
         rzn[k] = rz_new;
         rrv[k] = rr;
-        betav[k] = rz_new / rz_old;
+        betav[k] = rz_new / rz_old[k];
         b[k] = (float)betav[k];
     }
     auto step = [&](int i, float2(&uw)[KK], float2(&hw)[KK], const float2(&rw)[KK], float m) {
@@ -640,13 +724,11 @@ __device__ __forceinline__ void direction_f(const int vb, const int vnb, int j,
     for (int ib = i0 + ROWS * kBlock; ib < end; ib += ROWS * kBlock) {
 #pragma unroll
         for (int u = 0; u < ROWS; ++u) {
-            const int i = ib + u * kBlock;
-            if (i < end) {
-                ld_row<KK>(U, i, uv[u]);
-                ld_row<KK>(h, i, hv[u]);
-                ld_row<KK>(r, i, rv[u]);
-                mv[u] = M[i];
-            }
+            const int i = min(ib + u * kBlock, last);
+            ld_row<KK>(U, i, uv[u]);
+            ld_row<KK>(h, i, hv[u]);
+            ld_row<KK>(r, i, rv[u]);
+            mv[u] = M[i];
         }
 #pragma unroll
         for (int u = 0; u < ROWS; ++u) {
@@ -678,18 +760,32 @@ __device__ __forceinline__ void fold_f(const int vb, const int vnb, const Table 
     int begin, end;
     chunk_of_block_at(tab, vb, vnb, begin, end);
     bool rep[KK];
-    double unit[KK];
+    int done[KK], pause[KK];
+    double unit[KK], rr[KK];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {  // one round trip before the first branch
+        done[k] = sts[k].done;
+        pause[k] = sts[k].pause;
+        unit[k] = sts[k].unit;
+        rr[k] = sts[k].rr;
+    }
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        pin(unit[k]);
+        pin(rr[k]);
+    }
+    pin(begin);
+    pin(end);
     bool any = false;
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
         // replaced only once paused; the decision is kept for the later
         // replacement steps, which must not read the flags they change
-        rep[k] = !sts[k].done && sts[k].pause;
+        rep[k] = !done[k] && pause[k];
         if (lead) {
             sts[k].replace = rep[k] ? 1 : 0;
-            sts[k].rr_pause = sts[k].rr;
+            sts[k].rr_pause = rr[k];
         }
-        unit[k] = sts[k].unit;
         any = any || rep[k];
     }
     if (!any) return;
@@ -725,6 +821,43 @@ __device__ __forceinline__ void irdir_f(const int vb, const int vnb, int j,
     bool go[KK];
     float b[KK];
     double rzn[KK], rrv[KK], betav[KK];
+    int replace[KK];
+    double thresh[KK], rr_pause[KK], rz_old[KK];
+    const int nbp = tab->nb_mv64;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {  // one round trip before the first branch
+        const State *st = sts + k;
+        replace[k] = st->replace;
+        thresh[k] = st->thresh;
+        rr_pause[k] = st->rr_pause;
+        rz_old[k] = st->rz[j & 1];
+    }
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+        pin(thresh[k]);
+        pin(rr_pause[k]);
+        pin(rz_old[k]);
+    }
+    pin(begin);
+    pin(end);
+    pin(nbp);
+    // the FP64 residual product's partials of every right-hand side, fetched
+    // together and reduced in one pass
+    double tot[2 * KK];
+    {
+        double p[2 * KK][kPartPer];
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            double pk[2][kPartPer];
+            fetch_partials<2>(part_in + k * kPartStride, pk);
+#pragma unroll
+            for (int t = 0; t < kPartPer; ++t) {
+                p[2 * k][t] = pk[0][t];
+                p[2 * k + 1][t] = pk[1][t];
+            }
+        }
+        sum_partials<2 * KK>(p, nbp, tot);
+    }
     bool any = false;
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
@@ -732,10 +865,8 @@ __device__ __forceinline__ void irdir_f(const int vb, const int vnb, int j,
         go[k] = false;
         b[k] = 0.f;
         rzn[k] = rrv[k] = betav[k] = 0.0;
-        if (!st->replace) continue;  // decided by the fold
-        double v[2];
-        load_totals<2>(part_in + k * kPartStride, tab->nb_mv64, v);  // FP64 residual product
-        const double rz_new = v[0], rr = v[1];  // true residual, scaled by 1/unit
+        if (!replace[k]) continue;  // decided by the fold
+        const double rz_new = tot[2 * k], rr = tot[2 * k + 1];  // true residual, scaled by 1/unit
         if (!finite(rr) || !finite(rz_new)) {
             if (lead) {
                 st->status = QP_ENONFINITE;
@@ -743,7 +874,7 @@ __device__ __forceinline__ void irdir_f(const int vb, const int vnb, int j,
             }
             continue;
         }
-        if (rr <= st->thresh) {
+        if (rr <= thresh[k]) {
             if (lead) {
                 st->rr = rr;
                 st->status = QP_OK;
@@ -757,12 +888,12 @@ __device__ __forceinline__ void irdir_f(const int vb, const int vnb, int j,
         // above the recursive one it replaces (the recursion has drifted)
         // (rr_pause is the snapshot the fold took: st->rr itself is rewritten
         // by this kernel's lead while other workgroups may still read it)
-        const bool restart = rr > 4.0 * st->rr_pause;
+        const bool restart = rr > 4.0 * rr_pause[k];
         go[k] = true;
         any = true;
         rzn[k] = rz_new;
         rrv[k] = rr;
-        betav[k] = restart ? 0.0 : rz_new / st->rz[j & 1];
+        betav[k] = restart ? 0.0 : rz_new / rz_old[k];
         b[k] = (float)betav[k];
     }
     if (!any) return;

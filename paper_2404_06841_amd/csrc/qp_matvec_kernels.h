@@ -712,15 +712,34 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                                              State *__restrict__ st,
                                              int *__restrict__ exec)
 {
-    // right-hand sides served by this launch (uniform)
+    // right-hand sides served by this launch (uniform); their flags and the
+    // table's sizes in one round trip before the first branch
+    const int N = tab->N;
+    const int n = tab->n;
+    const int g = tab->g;
+    pin(N);
+    pin(n);
+    pin(g);
     bool act[KR];
     int nact = 0;
+    double inv_unit[KR];
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
-        act[k] = (EPI == EPI_ALPHA) ? !(st[k].done || st[k].pause)
-                                    : ((EPI == EPI_RESID) ? (st[k].replace != 0) : true);
+        if constexpr (EPI == EPI_ALPHA) {
+            const int dn = st[k].done, ps = st[k].pause;
+            act[k] = !(dn | ps);
+        } else if constexpr (EPI == EPI_RESID) {
+            const int rp = st[k].replace;
+            act[k] = rp != 0;
+        } else {
+            act[k] = true;
+        }
+        inv_unit[k] = (EPI == EPI_RESID) ? st[k].inv_unit : 1.0;
         nact += act[k] ? 1 : 0;
     }
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+        if constexpr (EPI == EPI_RESID) pin(inv_unit[k]);
     if (nact == 0) return;
     static_assert(!WIDE || KR == 1, "64-bit gathers serve one right-hand side");
     static_assert(!HALF || (REAL && !AN && !WIDE), "half storage: real scalar coefficient");
@@ -732,9 +751,6 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
     // then kWaves * gp unit records
     extern __shared__ int2 s_geo[];
 
-    const int N = tab->N;
-    const int n = tab->n;
-    const int g = tab->g;
     const int gp = (g + 3) & ~3;
     const int S = tab->tile_s;
     const int tpu = tab->tiles_per_unit;
@@ -759,9 +775,6 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
         ps_[l] = (T)tab->P[l][n - 2];
     }
     __syncthreads();
-    double inv_unit[KR];
-#pragma unroll
-    for (int k = 0; k < KR; ++k) inv_unit[k] = (EPI == EPI_RESID) ? st[k].inv_unit : 1.0;
     const T NT = (T)N;
     // one gather resource per right-hand side; a right-hand side not served
     // by this launch has no records, so its gathers read zero without traffic
@@ -828,6 +841,13 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                 unit = e * E + a0 * S1 + a1 * R + (q / N) * B + r;
             }
         }
+        // P k of the unit's uniform axes, loaded beside its records
+        T pku[DT];
+#pragma unroll
+        for (int l = 0; l < DT; ++l) {
+            pku[l] = upku[(size_t)unit * DT + l];
+            pin(pku[l]);
+        }
         // ---- the unit's records to this wave's LDS ----
         {
             const uint4 *src = reinterpret_cast<const uint4 *>(urec + (size_t)unit * gp);
@@ -836,9 +856,6 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
             for (int v = lane; v < nvec; v += kWave) dst[v] = src[v];
             wave_sync();
         }
-        T pku[DT];
-#pragma unroll
-        for (int l = 0; l < DT; ++l) pku[l] = upku[(size_t)unit * DT + l];
 
         for (int tl = tl0; tl < min(tl0 + it, tpu); ++tl) {
             const int slot0 = tl * S;
