@@ -139,14 +139,45 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block(tab, begin, end);
-    for (int k = 0; k < K; ++k) {
+    const int nbp = sizeof(T) == 8 ? tab->nb_mv64 : tab->nb_mv;
+    // the flags, scalars and product partials of every right-hand side, in
+    // one round trip before the first branch
+    int skip[kMaxRhs];
+    double rz[kMaxRhs], p[kMaxRhs][kPartPer];
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k) {
+        if (k >= K) break;
+        skip[k] = sts[k].done | sts[k].pause;
+        rz[k] = sts[k].rz[j & 1];
+        double pk[1][kPartPer];
+        fetch_partials<1>(part_in + k * kPartStride, pk);
+#pragma unroll
+        for (int t = 0; t < kPartPer; ++t) p[k][t] = pk[0][t];
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k) {
+        if (k >= K) break;
+        pin(skip[k]);
+        pin(rz[k]);
+    }
+    pin(begin);
+    pin(end);
+    pin(nbp);
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k) {
+        if (k >= K) break;
         State *st = sts + k;
-        if (st->done || st->pause) {
+        if (skip[k]) {
             if (lead) st->did_update = 0;
             continue;
         }
         double hq[1];
-        load_totals<1>(part_in + k * kPartStride, sizeof(T) == 8 ? tab->nb_mv64 : tab->nb_mv, hq);
+        {
+            double pk[1][kPartPer];
+#pragma unroll
+            for (int t = 0; t < kPartPer; ++t) pk[0][t] = p[k][t];
+            sum_partials<1>(pk, nbp, hq);
+        }
         if (!(hq[0] > 0.0)) {
             // (Q h, h) <= 0: Q is not positive definite on this Krylov space
             if (lead) {
@@ -157,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int j, int K, const Table
             }
             continue;
         }
-        const double alpha = st->rz[j & 1] / hq[0];
+        const double alpha = rz[k] / hq[0];
         const T a = (T)alpha;
         double acc[2] = {0.0, 0.0};
         QP_STREAM(i) {
@@ -196,21 +227,51 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int K,
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int begin, end;
     chunk_of_block(tab, begin, end);
-    for (int k = 0; k < K; ++k) {
+    // the flags, scalars and update partials of every right-hand side, in one
+    // round trip before the first branch (this launch's lead writes none of
+    // the fields read here)
+    int did[kMaxRhs], carry[kMaxRhs], limit_hit[kMaxRhs];
+    double rz_old[kMaxRhs], alpha[kMaxRhs], thresh[kMaxRhs], p[kMaxRhs][2][kPartPer];
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k) {
+        if (k >= K) break;
+        const State *st = sts + k;
+        did[k] = st->did_update;
+        carry[k] = !st->done & (st->pause != 0);
+        limit_hit[k] = st->iters >= st->maxit;  // iters counts this update
+        rz_old[k] = st->rz[j & 1];
+        alpha[k] = st->alpha;
+        thresh[k] = st->thresh;
+        fetch_partials<2>(part_in + k * kPartStride, p[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k) {
+        if (k >= K) break;
+        pin(did[k]);
+        pin(carry[k]);
+        pin(limit_hit[k]);
+        pin(rz_old[k]);
+        pin(alpha[k]);
+        pin(thresh[k]);
+    }
+    pin(begin);
+    pin(end);
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k) {
+        if (k >= K) break;
         State *st = sts + k;
-        const double rz_old = st->rz[j & 1];
-        if (!st->did_update) {
+        if (!did[k]) {
             // no update this iteration; a paused solve carries rz forward so
             // iteration j+1 finds it in its slot
-            if (lead && !st->done && st->pause) st->rz[(j + 1) & 1] = rz_old;
+            if (lead && carry[k]) st->rz[(j + 1) & 1] = rz_old[k];
             continue;
         }
         double v[2];
-        load_totals<2>(part_in + k * kPartStride, gridDim.x, v);
+        sum_partials<2>(p[k], gridDim.x, v);
         const double rz_new = v[0], rr = v[1];
         // the update ran: U += alpha h with this iteration's h, whatever the
         // residual test below decides
-        const T a = (T)st->alpha;
+        const T a = (T)alpha[k];
         bool stop = false;
         if (!finite(rr) || !finite(rz_new)) {
             if (lead) {
@@ -219,8 +280,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int K,
             }
             stop = true;
         } else {
-            const bool conv = rr <= st->thresh;
-            const bool limit = st->iters >= st->maxit;  // iters counts this update
+            const bool conv = rr <= thresh[k];
+            const bool limit = limit_hit[k] != 0;
             if (conv || limit) {
                 if (lead) {
                     st->rr = rr;
@@ -241,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_direction(int j, int K,
             }
             continue;
         }
-        const double beta = rz_new / rz_old;
+        const double beta = rz_new / rz_old[k];
         const T b = (T)beta;
         QP_STREAM(i) {
             const size_t e = vec_at<T>(k, K, D, i);
