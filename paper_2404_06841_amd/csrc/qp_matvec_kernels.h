@@ -755,18 +755,42 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
     const int S = tab->tile_s;
     const int tpu = tab->tiles_per_unit;
     const size_t D = tab->D;
+    // the work layout, loaded beside the mode shifts below (one round trip)
+    constexpr bool F64L = sizeof(T) == 8;  // FP64 launches have their own layout
+    const int it = F64L ? tab->item_tiles64 : tab->item_tiles;
+    const int xfront = F64L ? tab->xcd_front64 : tab->xcd_front;
+    const int ntiles = tab->ntiles;
+    pin(S);
+    pin(tpu);
+    pin(it);
+    pin(xfront);
+    pin(ntiles);
     const int lane = threadIdx.x % kWave;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int s = lane / N;
     const int p = lane - s * N;
     const int lo = -(N / 2), hi = N - 1 - N / 2;
     Rec *s_rec = reinterpret_cast<Rec *>(s_geo + gp * kWave) + wave * gp;
-    for (int e = threadIdx.x; e < gp * kWave; e += kBlock) {
-        const int r = e / kWave, l = e - (e / kWave) * kWave;
-        const int pl = l - (l / N) * N;  // position of lane l
-        int colw, c;
-        last_axis(N, lo, hi, r < g ? recs[r].mt[n - 1] : 0, pl, colw, c);
-        s_geo[e] = make_int2(colw, __float_as_int((float)c));
+    {
+        // lane geometry of every padded mode: entry r * kWave + lane belongs
+        // to the thread of wave r % kWaves, which loads the last-axis shifts
+        // of all its modes at once (one round trip) before using them
+        constexpr int kPer = ((kMaxG + 3) & ~3) / kWaves;
+        const int pl = lane - (lane / N) * N;  // position of this lane
+        int mt[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int r = wave + k * kWaves;
+            mt[k] = r < g ? recs[r].mt[n - 1] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int r = wave + k * kWaves;
+            if (r >= gp) break;
+            int colw, c;
+            last_axis(N, lo, hi, mt[k], pl, colw, c);
+            s_geo[r * kWave + lane] = make_int2(colw, __float_as_int((float)c));
+        }
     }
     T pl_[DT], ps_[DT];  // p_{n-1}, p_{n-2}
 #pragma unroll
@@ -774,7 +798,11 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
         pl_[l] = (T)tab->P[l][n - 1];
         ps_[l] = (T)tab->P[l][n - 2];
     }
-    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < DT; ++l) {
+        pin(pl_[l]);
+        pin(ps_[l]);
+    }
     const T NT = (T)N;
     // one gather resource per right-hand side; a right-hand side not served
     // by this launch has no records, so its gathers read zero without traffic
@@ -789,11 +817,8 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
 
     // items in XCD-front order: each XCD owns a contiguous eighth, its waves
     // sweep it together
-    constexpr bool F64L = sizeof(T) == 8;  // FP64 launches have their own layout
-    const int it = F64L ? tab->item_tiles64 : tab->item_tiles;
-    const int xfront = F64L ? tab->xcd_front64 : tab->xcd_front;
     const int ipu = (tpu + it - 1) / it;  // items per unit
-    const int nitems = (tab->ntiles / tpu) * ipu;  // half storage: the stored planes'
+    const int nitems = (ntiles / tpu) * ipu;  // half storage: the stored planes'
     const int hh = (N - 1) / 2;                    // half storage: largest stored digit
     const int c0 = (N * N + 1) / 2;                // half storage: first whole plane
     const int nw = vnb * kWaves;
@@ -818,6 +843,7 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
     // every value of the second axis, so the neighbour layers along that axis
     // stay in the XCD's L2 while the block advances
     const int span = (by_xcd && (xfront == 2 || xfront == 3) && !HALF) ? tab->slab_span : 0;
+    __syncthreads();
     for (int item = ibeg + loc; item < iend; item += nloc) {
         int unit = item / ipu;
         const int tl0 = (item - unit * ipu) * it;
@@ -841,20 +867,19 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                 unit = e * E + a0 * S1 + a1 * R + (q / N) * B + r;
             }
         }
-        // P k of the unit's uniform axes, loaded beside its records
+        // ---- the unit's records to this wave's LDS, and P k of the unit's
+        // uniform axes loaded beside them ----
         T pku[DT];
-#pragma unroll
-        for (int l = 0; l < DT; ++l) {
-            pku[l] = upku[(size_t)unit * DT + l];
-            pin(pku[l]);
-        }
-        // ---- the unit's records to this wave's LDS ----
         {
             const uint4 *src = reinterpret_cast<const uint4 *>(urec + (size_t)unit * gp);
             uint4 *dst = reinterpret_cast<uint4 *>(s_rec);
             wave_sync();  // the previous item's records have been read
+#pragma unroll
+            for (int l = 0; l < DT; ++l) pku[l] = upku[(size_t)unit * DT + l];
             for (int v = lane; v < nvec; v += kWave) dst[v] = src[v];
             wave_sync();
+#pragma unroll
+            for (int l = 0; l < DT; ++l) pin(pku[l]);
         }
 
         for (int tl = tl0; tl < min(tl0 + it, tpu); ++tl) {
