@@ -155,12 +155,23 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
         s_mode[r] = M;
     }
     if (cached) {
-        for (int e = threadIdx.x; e < gp * kWave; e += kBlock) {
-            const int r = e / kWave, l = e - (e / kWave) * kWave;
-            const int pl = l - (l / P) * P;  // position of lane l
+        // entry r * kWave + lane belongs to the thread of wave r % kWaves,
+        // which loads the last-axis shifts of all its modes at once
+        constexpr int kPer = ((kMaxG + 3) & ~3) / kWaves;
+        const int pl = lane - (lane / P) * P;  // position of this lane
+        int mt[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int r = wave + k * kWaves;
+            mt[k] = r < g ? recs[r].mt[n - 1] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int r = wave + k * kWaves;
+            if (r >= gp) break;
             int colw, c;
-            last_axis(N, lo, hi, r < g ? recs[r].mt[n - 1] : 0, pl, colw, c);
-            s_geo[e] = make_int2(colw, __float_as_int((float)c));
+            last_axis(N, lo, hi, mt[k], pl, colw, c);
+            s_geo[r * kWave + lane] = make_int2(colw, __float_as_int((float)c));
         }
     }
     if (threadIdx.x < kMaxN * DT) {
