@@ -30,22 +30,45 @@ __device__ __forceinline__ int signed_of(int b, int N) { return (2 * b < N) ? b 
 // M_0 = 0.  Partials of min_{k != 0} |P k|^2 (dependent columns of P).
 // Diagonal coefficient (App. D): q_kk = sum_l Ahat^l_0 (P k)_l^2 and the
 // column entry of mode m is sum_l Ahat^l_m (P rep(k + m))_l (P k)_l.
+// The problem's modes, coefficients and projection, copied to LDS once per
+// workgroup: the set-up kernels read them in their innermost loops with
+// indices that vary per mode and axis.
+struct SetupLds {
+    double P[kMaxD][kMaxN];
+    double coefl[kMaxG][kMaxD][2];
+    int modes[kMaxG][kMaxN];
+};
+
+__device__ __forceinline__ void setup_lds(const Table *__restrict__ tab, SetupLds &L)
+{
+    for (int e = threadIdx.x; e < kMaxD * kMaxN; e += kBlock) (&L.P[0][0])[e] = (&tab->P[0][0])[e];
+    for (int e = threadIdx.x; e < kMaxG * kMaxD * 2; e += kBlock)
+        (&L.coefl[0][0][0])[e] = (&tab->coefl[0][0][0])[e];
+    for (int e = threadIdx.x; e < kMaxG * kMaxN; e += kBlock)
+        (&L.modes[0][0])[e] = (&tab->modes[0][0])[e];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ tab, int kind,
                                                     double *__restrict__ M64,
                                                     float *__restrict__ M32,
                                                     double *__restrict__ part)
 {
+    __shared__ SetupLds L;
+    setup_lds(tab, L);
     const int N = tab->N, n = tab->n, d = tab->d, g = tab->g;
-    int begin, end;
-    chunk_of_block(tab, begin, end);
+    const bool aniso = tab->aniso != 0;
+    const int D = tab->D;
     double pkmin[1] = {INFINITY};
-    for (int i = begin + threadIdx.x; i < end; i += kBlock) {
+    // a grid-stride loop over every entry: the per-entry work is arithmetic,
+    // and the launch takes as many workgroups as the partial sums allow
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < D; i += gridDim.x * kBlock) {
         int ib[kMaxN];
         digits(tab, i, ib);
         double pk[kMaxD];
         for (int l = 0; l < d; ++l) {
             double s = 0.0;
-            for (int t = 0; t < n; ++t) s += tab->P[l][t] * (double)signed_of(ib[t], N);
+            for (int t = 0; t < n; ++t) s += L.P[l][t] * (double)signed_of(ib[t], N);
             pk[l] = s;
         }
         double pk2 = 0.0;
@@ -54,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ ta
         if (i != 0) {
             pkmin[0] = fmin(pkmin[0], pk2);
             double qkk = tab->a0 * pk2;
-            if (tab->aniso) {
+            if (aniso) {
                 qkk = 0.0;
                 for (int l = 0; l < d; ++l) qkk += tab->a0l[l] * pk[l] * pk[l];
             }
@@ -63,20 +86,23 @@ __global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ ta
             } else {
                 double col = 0.0;
                 for (int r = 0; r < g; ++r) {
+                    // signed digits of rep(k + m), shared by every component l
+                    double sj[kMaxN];
+                    for (int t = 0; t < n; ++t) {
+                        int jb = ib[t] + L.modes[r][t];
+                        jb += (jb < 0) ? N : 0;
+                        jb -= (jb >= N) ? N : 0;
+                        sj[t] = (double)signed_of(jb, N);
+                    }
                     double w = 0.0, qr = 0.0, qi = 0.0;
                     for (int l = 0; l < d; ++l) {
                         double pj = 0.0;
-                        for (int t = 0; t < n; ++t) {
-                            int jb = ib[t] + tab->modes[r][t];
-                            jb += (jb < 0) ? N : 0;
-                            jb -= (jb >= N) ? N : 0;
-                            pj += tab->P[l][t] * (double)signed_of(jb, N);
-                        }
+                        for (int t = 0; t < n; ++t) pj += L.P[l][t] * sj[t];
                         w += pj * pk[l];
-                        qr += tab->coefl[r][l][0] * (pj * pk[l]);
-                        qi += tab->coefl[r][l][1] * (pj * pk[l]);
+                        qr += L.coefl[r][l][0] * (pj * pk[l]);
+                        qi += L.coefl[r][l][1] * (pj * pk[l]);
                     }
-                    if (tab->aniso) {
+                    if (aniso) {
                         col += qr * qr + qi * qi;
                     } else {
                         const double a2 = tab->coef[r][0] * tab->coef[r][0] +
@@ -95,28 +121,47 @@ __global__ __launch_bounds__(kBlock) void k_precond(const Table *__restrict__ ta
 
 // min and -max of A(y) = sum_m Ahat_m exp(i m.y) over y = 2 pi j / N (for a
 // diagonal coefficient: over every entry a_l).  The phase m.j is reduced mod N
-// exactly in integers before the sine/cosine.
+// exactly in integers before the sine/cosine; for N up to kPhaseTab the
+// sines and cosines of the N phases are computed once per workgroup (the same
+// calls on the same arguments) and looked up.
+constexpr int kPhaseTab = 2048;
 __global__ __launch_bounds__(kBlock) void k_extrema(const Table *__restrict__ tab,
                                                     double *__restrict__ part)
 {
+    __shared__ SetupLds L;
+    __shared__ double2 s_sc[kPhaseTab];
     const int N = tab->N, n = tab->n, g = tab->g;
+    const bool table = N <= kPhaseTab;
+    if (table) {
+        for (int j = threadIdx.x; j < N; j += kBlock) {
+            double sn, cs;
+            sincospi(2.0 * (double)j / (double)N, &sn, &cs);
+            s_sc[j] = make_double2(sn, cs);
+        }
+    }
+    setup_lds(tab, L);  // (its barrier also publishes the phase table)
     const int entries = tab->aniso ? tab->d : 1;
-    int begin, end;
-    chunk_of_block(tab, begin, end);
+    const int D = tab->D;
     double v[2] = {INFINITY, INFINITY};
-    for (int i = begin + threadIdx.x; i < end; i += kBlock) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < D; i += gridDim.x * kBlock) {
         int ib[kMaxN];
         digits(tab, i, ib);
         double a[kMaxD] = {0.0, 0.0, 0.0, 0.0};
         for (int r = 0; r < g; ++r) {
             long long ph = 0;
-            for (int t = 0; t < n; ++t) ph += (long long)tab->modes[r][t] * ib[t];
+            for (int t = 0; t < n; ++t) ph += (long long)L.modes[r][t] * ib[t];
             ph %= N;
             if (ph < 0) ph += N;
             double sn, cs;
-            sincospi(2.0 * (double)ph / (double)N, &sn, &cs);
+            if (table) {
+                const double2 sc = s_sc[ph];
+                sn = sc.x;
+                cs = sc.y;
+            } else {
+                sincospi(2.0 * (double)ph / (double)N, &sn, &cs);
+            }
             for (int l = 0; l < entries; ++l)
-                a[l] += tab->coefl[r][l][0] * cs - tab->coefl[r][l][1] * sn;
+                a[l] += L.coefl[r][l][0] * cs - L.coefl[r][l][1] * sn;
         }
         for (int l = 0; l < entries; ++l) {
             v[0] = fmin(v[0], a[l]);
@@ -260,25 +305,34 @@ __global__ __launch_bounds__(kBlock) void k_multi_index(const Table *__restrict_
 
 }  // namespace
 
+// Grid of the arithmetic set-up kernels: one entry per thread up to the
+// partial-sum limit (grid-stride beyond it).
+static int setup_grid(const Table &ht)
+{
+    return (int)std::min<int64_t>(kMaxBlocks, std::max<int64_t>(1, ((int64_t)ht.D + kBlock - 1) / kBlock));
+}
+
 hipError_t launch_precond(const Table *tab, const Table &ht, int kind, double *M64, float *M32,
                           const Parts &parts, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_precond, dim3(ht.nblocks), dim3(kBlock), 0, s, tab, kind, M64, M32, parts.c);
+    const int nb = setup_grid(ht);
+    hipLaunchKernelGGL(k_precond, dim3(nb), dim3(kBlock), 0, s, tab, kind, M64, M32, parts.c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_finalize<1, true>), dim3(1), dim3(kBlock), 0, s, (const double *)parts.c,
-                       ht.nblocks, out, 0);
+                       nb, out, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_extrema(const Table *tab, const Table &ht, const Parts &parts, double *out,
                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_extrema, dim3(ht.nblocks), dim3(kBlock), 0, s, tab, parts.c);
+    const int nb = setup_grid(ht);
+    hipLaunchKernelGGL(k_extrema, dim3(nb), dim3(kBlock), 0, s, tab, parts.c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_finalize<2, true>), dim3(1), dim3(kBlock), 0, s, (const double *)parts.c,
-                       ht.nblocks, out, 1);
+                       nb, out, 1);
     return hipGetLastError();
 }
 
