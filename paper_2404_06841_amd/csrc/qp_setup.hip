@@ -182,18 +182,49 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
     }
 }
 
+// The modes whose storage index lies in [begin, end), in increasing order of
+// r (at most kMaxG = 64, so wave 0 finds them with one ballot): the
+// corrector sources below test each entry against these alone.
+struct ChunkModes {
+    int r[kMaxG];
+    int idx[kMaxG];
+    int count;
+};
+static_assert(kMaxG <= kWave, "one ballot covers every mode");
+
+__device__ __forceinline__ void chunk_modes(const Table *__restrict__ tab, int begin, int end,
+                                            ChunkModes &cm)
+{
+    if (threadIdx.x < kWave) {
+        const int r = threadIdx.x;
+        const int ix = r < tab->g ? tab->midx[r] : -1;
+        const bool in = r < tab->g && ix >= begin && ix < end;
+        const unsigned long long mask = __ballot(in);
+        if (in) {
+            const int slot = __popcll(mask & ((1ull << r) - 1ull));
+            cm.r[slot] = r;
+            cm.idx[slot] = ix;
+        }
+        if (r == 0) cm.count = __popcll(mask);
+    }
+    __syncthreads();
+}
+
 // F_k = i (P k)_j Ahat_k on the modes, 0 elsewhere (each entry written once);
 // for a diagonal coefficient Ahat is a_j's (the source d a_j / d x_j, App. D).
 __global__ __launch_bounds__(kBlock) void k_corrector_rhs(const Table *__restrict__ tab, int j,
                                                           double2 *__restrict__ F)
 {
-    const int g = tab->g;
+    __shared__ ChunkModes cm;
     int begin, end;
     chunk_of_block(tab, begin, end);
+    chunk_modes(tab, begin, end, cm);
+    const int nm = cm.count;
     for (int i = begin + threadIdx.x; i < end; i += kBlock) {
         double2 v = make_double2(0.0, 0.0);
-        for (int r = 0; r < g; ++r) {
-            if (tab->midx[r] == i) {
+        for (int c = 0; c < nm; ++c) {
+            if (cm.idx[c] == i) {
+                const int r = cm.r[c];
                 const double s = tab->Pm[r][j];
                 v.x += -s * tab->coefl[r][j][1];
                 v.y += s * tab->coefl[r][j][0];
@@ -211,10 +242,12 @@ __global__ __launch_bounds__(kBlock) void k_corrector_rhs_all(const Table *__res
                                                               double2 *__restrict__ F,
                                                               double *__restrict__ part)
 {
-    const int g = tab->g;
+    __shared__ ChunkModes cm;
     const size_t D = tab->D;
     int begin, end;
     chunk_of_block(tab, begin, end);
+    chunk_modes(tab, begin, end, cm);
+    const int nm = cm.count;
     double acc[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j] = 0.0;
@@ -222,8 +255,9 @@ __global__ __launch_bounds__(kBlock) void k_corrector_rhs_all(const Table *__res
         double2 v[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) v[j] = make_double2(0.0, 0.0);
-        for (int r = 0; r < g; ++r) {
-            if (tab->midx[r] == i) {
+        for (int c = 0; c < nm; ++c) {
+            if (cm.idx[c] == i) {
+                const int r = cm.r[c];
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     const double s = tab->Pm[r][j];
