@@ -47,7 +47,19 @@ def host(t) -> np.ndarray:
     return t.detach().cpu().numpy()
 
 
+def _many_modes(N: int):
+    # 31 seeded +-mode pairs and the mean: g = 63, the largest odd mode
+    # count (the kernels' per-mode tables, set-up lists and chunk walks at
+    # their limit of 64); small amplitudes keep the field elliptic
+    rng = np.random.default_rng(2404)
+    modes, coef, amps = W.random_modes(4, 31, 2, rng, 0.05, 2.5, 3.0)
+    return W.Problem("eightfold_many_modes", 2, 4, int(N), W.eightfold_P(), modes, coef,
+                     {"amplitudes": amps.tolist()})
+
+
 PROBLEMS = {
+    "many_modes_g63_N12": lambda: _many_modes(12),
+    "many_modes_g63_N6_one_launch": lambda: _many_modes(6),
     "c1_1d_n2_N32": lambda: W.one_d_two_mode(32, 2.0),
     "ex1_N16": lambda: W.one_d_two_mode(16, 6.0, 2 * np.pi),
     "three_mode_N9": lambda: W.one_d_three_mode(9),
