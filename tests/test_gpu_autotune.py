@@ -56,8 +56,17 @@ def key64(L: dict) -> tuple:
     return L["item_tiles64"], L["workgroups64"], L["xcd_front64"]
 
 
-@pytest.mark.parametrize("make", [lambda: W.eightfold_random(16, 3), lambda: W.icosahedral(6)],
-                         ids=["eightfold_random_N16", "icosa_N6"])
+def _many_modes(N: int):
+    # 31 seeded +-mode pairs and the mean (g = 63: 64 padded mode records)
+    rng = np.random.default_rng(2404)
+    modes, coef, amps = W.random_modes(4, 31, 2, rng, 0.05, 2.5, 3.0)
+    return W.Problem("eightfold_many_modes", 2, 4, int(N), W.eightfold_P(), modes, coef,
+                     {"amplitudes": amps.tolist()})
+
+
+@pytest.mark.parametrize("make", [lambda: W.eightfold_random(16, 3), lambda: W.icosahedral(6),
+                                  lambda: _many_modes(12)],
+                         ids=["eightfold_random_N16", "icosa_N6", "many_modes_g63_N12"])
 def test_every_layout_gives_bitwise_equal_products(make):
     prob = make()
     say("[case] layouts", prob.D, prob.g)
