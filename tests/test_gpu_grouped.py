@@ -43,6 +43,14 @@ def standalone(probs, **kw):
     return out
 
 
+def _many_modes(N: int):
+    # 31 seeded +-mode pairs and the mean (g = 63: 64 padded mode records)
+    rng = np.random.default_rng(2404)
+    modes, coef, amps = W.random_modes(4, 31, 2, rng, 0.05, 2.5, 3.0)
+    return W.Problem("eightfold_many_modes", 2, 4, int(N), W.eightfold_P(), modes, coef,
+                     {"amplitudes": amps.tolist()})
+
+
 GROUPS = {
     # d = 2, real coefficients, sizes from 125 to 331,776 unknowns (grids
     # below 8 workgroups, odd N, several workgroup counts)
@@ -58,6 +66,8 @@ GROUPS = {
     # entries, so the vector steps load eight rows per thread) beside small ones
     "eightfold_N32_mixed": lambda: [W.eightfold_random(32, 0), W.eightfold_random(8, 1),
                                     W.eightfold_random(24, 2)],
+    # 63 coefficient modes beside 17 (the grouped product's records at 64)
+    "many_modes_mixed": lambda: [_many_modes(12), W.eightfold_random(8, 1), _many_modes(6)],
 }
 # groups whose problems are also created with the layout autotuner (as the
 # batch benchmark does): the grouped launches must use each problem's tuned
