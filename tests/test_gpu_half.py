@@ -134,7 +134,16 @@ def test_half_product_rejects_even_N_and_diagonal_coefficients():
 # (D+1)/2 stored entries.  Each is compared with the oracle's full-storage
 # result at the stored indices.
 
+def _many_modes(N: int):
+    # 31 seeded +-mode pairs and the mean, real (g = 63: 64 padded records)
+    rng = np.random.default_rng(2404)
+    modes, coef, amps = W.random_modes(4, 31, 2, rng, 0.05, 2.5, 3.0)
+    return W.Problem("eightfold_many_modes", 2, 4, int(N), W.eightfold_P(), modes, coef,
+                     {"amplitudes": amps.tolist()})
+
+
 REAL_CASES = {
+    "many_modes_g63_N7": lambda: _many_modes(7),
     "icosa_N5": lambda: W.icosahedral(5),
     "icosa_N7": lambda: W.icosahedral(7),
     "eightfold_random_N9": lambda: W.eightfold_random(9, 3),
