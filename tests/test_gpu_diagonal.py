@@ -40,7 +40,19 @@ def host(t) -> np.ndarray:
     return t.detach().cpu().numpy()
 
 
+def _many_modes_diag(N: int):
+    # both diagonal entries on the same 31 seeded +-mode pairs and the mean
+    # (g = 63: 64 padded records), with their own amplitudes and means
+    rng = np.random.default_rng(2405)
+    modes, coef, _ = W.random_modes(4, 31, 2, rng, 0.05, 2.5, 3.0)
+    coef2 = coef * 0.8
+    coef2[np.all(modes == 0, axis=1)] = 4.0
+    return W.diagonal("eightfold_diag_many_modes", 2, 4, int(N), W.eightfold_P(),
+                      [(modes, coef), (modes, coef2)])
+
+
 CASES = {
+    "many_modes_g63_N12": lambda: _many_modes_diag(12),
     "paper_example_N6": lambda: W.paper_homogenization(6),
     "paper_example_N18": lambda: W.paper_homogenization(18),
     "laminate_N8": lambda: W.laminate(8),
