@@ -57,7 +57,17 @@ def _many_modes(N: int):
                      {"amplitudes": amps.tolist()})
 
 
+def _d4_n8(N: int):
+    # the largest dimensions (d = 4, n = 8): a seeded Gaussian P and a cosine
+    # field over the eight parent axes (digit arrays and P at their limits)
+    rng = np.random.default_rng(2408)
+    P = rng.standard_normal((4, 8))
+    modes, coef = W.cosine_field(8, 3.0, [0.3] * 8)
+    return W.Problem("d4_n8", 4, 8, int(N), P, modes, coef, {})
+
+
 PROBLEMS = {
+    "d4_n8_N4": lambda: _d4_n8(4),
     "many_modes_g63_N12": lambda: _many_modes(12),
     "many_modes_g63_N6_one_launch": lambda: _many_modes(6),
     "c1_1d_n2_N32": lambda: W.one_d_two_mode(32, 2.0),
