@@ -2,38 +2,38 @@
 // compiled on the host by the tests).
 //
 // A product gathers the neighbour values of its g modes chunk by chunk, each
-// chunk a compile-time count of records: records [0, gp), gp = g rounded up
-// to a multiple of 4 (the records staged in LDS; the padding ones read
-// zero).  The walk takes chunks of KC records while they fit, then one chunk
-// of KC / 2 when that keeps the start a multiple of 4, then chunks of 4 up
-// to gp.  A chunk running past gp would read records that were never staged.
+// chunk a compile-time count of records, in record order: chunks of KC
+// records while they fit, then one chunk of KC / 2 (when that is at least 4
+// and fits), then chunks of 4, then one chunk of the 1 to 3 records left.
+// The walk ends exactly at record g: the records staged past g (zero-weight
+// padding up to a multiple of 4) are never gathered, and no chunk reads a
+// record that was not staged.
 #pragma once
+
+#include <type_traits>
 
 namespace qp {
 
-// whether the walk takes a chunk of KC / 2 records at record rb
-constexpr bool take_half_chunk(int KC, int rb, int gp)
+// chunk(std::integral_constant<int, C>(), rb) for each chunk [rb, rb + C)
+template <int KC, typename F>
+__attribute__((always_inline)) constexpr void walk_records(int g, F &&chunk)
 {
-    return KC / 2 >= 4 && (KC / 2) % 4 == 0 && rb + KC / 2 <= gp;
-}
-
-// where the walk over gp records ends (gp when every chunk stays inside)
-constexpr int chunk_walk_end(int KC, int gp)
-{
+    static_assert(KC >= 4 && KC % 4 == 0, "full chunks are whole groups of four records");
     int rb = 0;
-    while (rb + KC <= gp) rb += KC;
-    if (take_half_chunk(KC, rb, gp)) rb += KC / 2;
-    while (rb < gp) rb += 4;
-    return rb;
-}
-
-// whether the walk ends exactly at gp for every gp = 4, 8, ..., gpmax
-constexpr bool chunk_walk_exact(int KC, int gpmax)
-{
-    if (KC < 4 || KC % 4 != 0) return false;
-    for (int gp = 4; gp <= gpmax; gp += 4)
-        if (chunk_walk_end(KC, gp) != gp) return false;
-    return true;
+    for (; rb + KC <= g; rb += KC) chunk(std::integral_constant<int, KC>(), rb);
+    if constexpr (KC / 2 >= 4) {
+        if (rb + KC / 2 <= g) {
+            chunk(std::integral_constant<int, KC / 2>(), rb);
+            rb += KC / 2;
+        }
+    }
+    for (; rb + 4 <= g; rb += 4) chunk(std::integral_constant<int, 4>(), rb);
+    switch (g - rb) {
+    case 3: chunk(std::integral_constant<int, 3>(), rb); break;
+    case 2: chunk(std::integral_constant<int, 2>(), rb); break;
+    case 1: chunk(std::integral_constant<int, 1>(), rb); break;
+    default: break;
+    }
 }
 
 }  // namespace qp

@@ -25,7 +25,8 @@
 // whose neighbour crosses a slot-axis boundary for some lane of the tile (a
 // host-prepared mask per tile row) are corrected per lane.  Neighbour loads
 // are issued in chunks of up to Inflight<T> before the first is consumed; the
-// mode count is padded to a multiple of 4 with zero-weight copies of m = 0.
+// staged records are padded to a multiple of 4 with zero-weight copies of
+// m = 0, which the walk over the records (walk_records) never gathers.
 //
 // Unit order: each XCD owns a contiguous eighth of the units, and its
 // workgroups sweep that range together (adjacent workgroups take adjacent
@@ -61,6 +62,13 @@ template <>
 struct Inflight<double> {
     static constexpr int v = QP_INFLIGHT_F64;
 };
+
+// Fused multiply-add written out, so that every instantiation of the product
+// (all chunk sizes of the record walk, 32- and 64-bit gathers) rounds each
+// weight and each accumulation step the same way, whatever the compiler
+// would contract on its own.
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Static mode data, staged once per workgroup.
 template <typename T, int DT>
@@ -111,7 +119,6 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
     if (EPI == EPI_ALPHA && (st->done || st->pause)) return;
     if (EPI == EPI_RESID && !st->replace) return;  // replaced only once paused (fold decides)
     constexpr int KC = Inflight<T>::v;
-    static_assert(chunk_walk_exact(KC, (kMaxG + 3) & ~3), "the chunk walk must end at the last record");
     // per padded mode and lane: (wrapped column, face factor as float); gp * kWave
     // entries of dynamic LDS when N <= kWave
     extern __shared__ int2 s_geo[];
@@ -352,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                         // sum_l Ahat^l (P k)_l (P j)_l
                         T t[DT];
 #pragma unroll
-                        for (int l = 0; l < DT; ++l) t[l] = (sq[l] + c * ql[l]) - pk[l] * R.pmw[l];
+                        for (int l = 0; l < DT; ++l) t[l] = fmac(-pk[l], R.pmw[l], fmac(c, ql[l], sq[l]));
                         if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
                             const int m = R.mslot;
                             const int jb = ibs - m;
@@ -360,29 +367,29 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
                             const int kd = ks - m;
                             const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
 #pragma unroll
-                            for (int l = 0; l < DT; ++l) t[l] += cs * qs[l];
+                            for (int l = 0; l < DT; ++l) t[l] = fmac(cs, qs[l], t[l]);
                         }
                         T a = 0, b = 0;
 #pragma unroll
                         for (int l = 0; l < DT; ++l) {
-                            a += R.ar[l] * t[l];
-                            if (!REAL) b += R.ai[l] * t[l];
+                            a = fmac(R.ar[l], t[l], a);
+                            if (!REAL) b = fmac(R.ai[l], t[l], b);
                         }
                         wr[k] = a;
                         wi[k] = b;
                     } else {
                         // a W = a (|P k|^2 + c N q_last) - (P k).(a P m')
                         const T a = R.a;
-                        T wv = a * (s2 + c * cq);
+                        T wv = a * fmac(c, cq, s2);
 #pragma unroll
-                        for (int l = 0; l < DT; ++l) wv -= pk[l] * R.apm[l];
+                        for (int l = 0; l < DT; ++l) wv = fmac(-pk[l], R.apm[l], wv);
                         if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
                             const int m = R.mslot;
                             const int jb = ibs - m;
                             idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
                             const int kd = ks - m;
                             const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
-                            wv += a * cs * cqs;
+                            wv = fmac(a * cs, cqs, wv);
                         }
                         wr[k] = REAL ? wv : R.cr * wv;
                         wi[k] = REAL ? (T)0 : R.ci * wv;
@@ -392,25 +399,16 @@ __global__ __launch_bounds__(kBlock) void k_matvec(const Table *__restrict__ tab
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
                     if (REAL) {
-                        acc_re += wr[k] * u[k].x;
-                        acc_im += wr[k] * u[k].y;
+                        acc_re = fmac(wr[k], u[k].x, acc_re);
+                        acc_im = fmac(wr[k], u[k].y, acc_im);
                     } else {
-                        acc_re += wr[k] * u[k].x - wi[k] * u[k].y;
-                        acc_im += wr[k] * u[k].y + wi[k] * u[k].x;
+                        acc_re = fmac(wr[k], u[k].x, fmac(-wi[k], u[k].y, acc_re));
+                        acc_im = fmac(wr[k], u[k].y, fmac(wi[k], u[k].x, acc_im));
                     }
                 }
             };
             auto all_modes = [&](auto Gc) {
-                using std::integral_constant;
-                int rb = 0;
-                for (; rb + KC <= gp; rb += KC) chunk(integral_constant<int, KC>(), Gc, rb);
-                // a half chunk only when it keeps rb a multiple of 4 (gp is one,
-                // and the 4-chunks below must end exactly at gp)
-                if (take_half_chunk(KC, rb, gp)) {
-                    chunk(integral_constant<int, (KC / 2 >= 4 ? KC / 2 : 4)>(), Gc, rb);
-                    rb += KC / 2;
-                }
-                for (; rb < gp; rb += 4) chunk(integral_constant<int, 4>(), Gc, rb);
+                walk_records<KC>(g, [&](auto Cc, int rb) { chunk(Cc, Gc, rb); });
             };
             if (cached)
                 all_modes(std::true_type());
@@ -756,7 +754,6 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
     static_assert(!HALF || (REAL && !AN && !WIDE), "half storage: real scalar coefficient");
     // neighbour loads in flight per chunk: about Inflight<T> over all right-hand sides
     constexpr int KC = (Inflight<T>::v / KR >= 8) ? (Inflight<T>::v / KR) / 4 * 4 : 4;
-    static_assert(chunk_walk_exact(KC, (kMaxG + 3) & ~3), "the chunk walk must end at the last record");
     using Rec = TileRec<T, DT, AN, HALF>;
     // dynamic LDS: gp * kWave lane-geometry entries (column, face factor),
     // then kWaves * gp unit records
@@ -947,7 +944,7 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                         // + N c p_{n-1,l} + N cs p_{n-2,l}
                         T t[DT];
 #pragma unroll
-                        for (int l = 0; l < DT; ++l) t[l] = (sq[l] + c * ql[l]) - pk[l] * Q.pmw[l];
+                        for (int l = 0; l < DT; ++l) t[l] = fmac(-pk[l], Q.pmw[l], fmac(c, ql[l], sq[l]));
                         if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
                             const int mm = Q.mslot;
                             const int jb = ibs - mm;
@@ -955,28 +952,28 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
                             const int kd = ks - mm;
                             const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
 #pragma unroll
-                            for (int l = 0; l < DT; ++l) t[l] += cs * qs[l];
+                            for (int l = 0; l < DT; ++l) t[l] = fmac(cs, qs[l], t[l]);
                         }
                         T a = 0, b = 0;
 #pragma unroll
                         for (int l = 0; l < DT; ++l) {
-                            a += Q.ar[l] * t[l];
-                            if (!REAL) b += Q.ai[l] * t[l];
+                            a = fmac(Q.ar[l], t[l], a);
+                            if (!REAL) b = fmac(Q.ai[l], t[l], b);
                         }
                         wr[m] = a;
                         wi[m] = b;
                     } else {
                         // a W = a (|P k|^2 + c N q_last) - (P k).(a P m')
-                        T wv = Q.a * (s2 + c * cq);
+                        T wv = Q.a * fmac(c, cq, s2);
 #pragma unroll
-                        for (int l = 0; l < DT; ++l) wv -= pk[l] * Q.apm[l];
+                        for (int l = 0; l < DT; ++l) wv = fmac(-pk[l], Q.apm[l], wv);
                         if ((slow >> r) & 1ull) {  // slot-axis crossing for some lane
                             const int mm = Q.mslot;
                             const int jb = ibs - mm;
                             idx += (jb < 0) ? N * N : ((jb >= N) ? -N * N : 0);
                             const int kd = ks - mm;
                             const T cs = (kd < lo) ? (T)1 : ((kd > hi) ? (T)-1 : (T)0);
-                            wv += Q.a * cs * cqs;
+                            wv = fmac(Q.a * cs, cqs, wv);
                         }
                         wr[m] = REAL ? wv : Q.cr * wv;
                         wi[m] = REAL ? (T)0 : Q.ci * wv;
@@ -1029,27 +1026,16 @@ __device__ __forceinline__ void matvec_plane(const int vb, const int vnb,
 #pragma unroll
                     for (int k = 0; k < KR; ++k) {
                         if (REAL) {
-                            acc_re[k] += wr[m] * u[m][k].x;
-                            acc_im[k] += wr[m] * u[m][k].y;
+                            acc_re[k] = fmac(wr[m], u[m][k].x, acc_re[k]);
+                            acc_im[k] = fmac(wr[m], u[m][k].y, acc_im[k]);
                         } else {
-                            acc_re[k] += wr[m] * u[m][k].x - wi[m] * u[m][k].y;
-                            acc_im[k] += wr[m] * u[m][k].y + wi[m] * u[m][k].x;
+                            acc_re[k] = fmac(wr[m], u[m][k].x, fmac(-wi[m], u[m][k].y, acc_re[k]));
+                            acc_im[k] = fmac(wr[m], u[m][k].y, fmac(wi[m], u[m][k].x, acc_im[k]));
                         }
                     }
                 }
             };
-            {
-                using std::integral_constant;
-                int rb = 0;
-                for (; rb + KC <= gp; rb += KC) chunk(integral_constant<int, KC>(), rb);
-                // a half chunk only when it keeps rb a multiple of 4 (gp is one,
-                // and the 4-chunks below must end exactly at gp)
-                if (take_half_chunk(KC, rb, gp)) {
-                    chunk(integral_constant<int, (KC / 2 >= 4 ? KC / 2 : 4)>(), rb);
-                    rb += KC / 2;
-                }
-                for (; rb < gp; rb += 4) chunk(integral_constant<int, 4>(), rb);
-            }
+            walk_records<KC>(g, chunk);
             bool store = active;
             size_t i = (size_t)(L0 + s) * N + p;
             if constexpr (HALF) {

@@ -1,13 +1,14 @@
 """The stiffness product's walk over its mode records, compiled on the host.
 
-The product gathers its modes in chunks of a compile-time record count (a
-full chunk of KC records, one chunk of KC / 2, chunks of 4); every chunk must
-stay inside the gp records staged in LDS (gp = g rounded up to 4).  A walk
-that ran past gp read records that were never staged and gave results that
-changed from run to run; the kernels now check the walk at compile time
-(static_assert on chunk_walk_exact) for their own KC.  This test runs the
-same header on the host for every chunk size the in-flight settings can
-give, and rebuilds each walk from its chunks.
+The product gathers its g modes in chunks of a compile-time record count (full
+chunks of KC records, one chunk of KC / 2, chunks of 4, then one chunk of the
+1 to 3 records left).  Only the first g records are real: the staged records
+past g are zero-weight padding up to a multiple of 4, and a walk that ran past
+the staged records once read records that were never written and gave results
+that changed from run to run.  This test runs the kernels' own walk
+(`walk_records` in qp_chunk_walk.h) on the host for every chunk size the
+in-flight settings can give and every mode count, and rebuilds each walk from
+its chunks.
 """
 from __future__ import annotations
 
@@ -19,26 +20,24 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(os.path.dirname(HERE), "paper_2404_06841_amd", "csrc")
-GPMAX = 64  # QP_MAX_MODES, already a multiple of 4
+GMAX = 64  # QP_MAX_MODES
 
 PROGRAM = r"""
 #include <cstdio>
+#include <utility>
 #include "qp_chunk_walk.h"
-int main() {
-    for (int KC = 4; KC <= 64; KC += 4)
-        for (int gp = 4; gp <= %d; gp += 4) {
-            std::printf("%%d %%d %%d %%d", KC, gp, qp::chunk_walk_end(KC, gp),
-                        (int)qp::chunk_walk_exact(KC, gp));
-            // the chunks, as the kernels take them
-            int rb = 0;
-            for (; rb + KC <= gp; rb += KC) std::printf(" %%d:%%d", rb, KC);
-            if (qp::take_half_chunk(KC, rb, gp)) { std::printf(" %%d:%%d", rb, KC / 2); rb += KC / 2; }
-            for (; rb < gp; rb += 4) std::printf(" %%d:4", rb);
-            std::printf("\n");
-        }
-    return 0;
+template <int KC> void walks() {
+    for (int g = 0; g <= %d; ++g) {
+        std::printf("%%d %%d", KC, g);
+        qp::walk_records<KC>(g, [](auto Cc, int rb) {
+            std::printf(" %%d:%%d", rb, (int)decltype(Cc)::value);
+        });
+        std::printf("\n");
+    }
 }
-""" % GPMAX
+template <int... I> void all(std::integer_sequence<int, I...>) { (walks<4 * (I + 1)>(), ...); }
+int main() { all(std::make_integer_sequence<int, 16>()); return 0; }
+""" % GMAX
 
 
 @pytest.fixture(scope="module")
@@ -55,37 +54,43 @@ def walks(tmp_path_factory):
     table = {}
     for line in out.splitlines():
         f = line.split()
-        KC, gp, end, exact = map(int, f[:4])
-        chunks = [tuple(map(int, c.split(":"))) for c in f[4:]]
-        table[(KC, gp)] = (end, exact, chunks)
+        KC, g = int(f[0]), int(f[1])
+        table[(KC, g)] = [tuple(map(int, c.split(":"))) for c in f[2:]]
     return table
 
 
-def test_every_walk_covers_the_staged_records_exactly(walks):
-    for (KC, gp), (end, exact, chunks) in walks.items():
-        assert end == gp, (KC, gp, chunks)
+def test_every_walk_covers_the_real_records_exactly(walks):
+    assert len(walks) == 16 * (GMAX + 1)
+    for (KC, g), chunks in walks.items():
         pos = 0
         for start, size in chunks:
-            assert start == pos and start % 4 == 0 and size in (KC, KC // 2, 4), (KC, gp, chunks)
-            assert start + size <= gp, (KC, gp, chunks)
+            assert start == pos and size in (KC, KC // 2, 4, 3, 2, 1), (KC, g, chunks)
+            assert start + size <= g, (KC, g, chunks)
             pos += size
-        assert pos == gp, (KC, gp, chunks)
+        assert pos == g, (KC, g, chunks)
+        # at most one chunk of fewer than 4 records, and only at the end
+        assert all(s >= 4 for _, s in chunks[:-1]), (KC, g, chunks)
 
 
-def test_exact_for_every_in_flight_setting(walks):
+def test_in_flight_settings(walks):
     # the plane-tile product: KC = (inflight / KR) rounded down to a multiple
     # of 4 when that is at least 8, else 4; the generic product: KC = inflight
     for inflight in range(4, 65, 4):
         for KR in (1, 2, 3):
             q = inflight // KR
             KC = (q // 4) * 4 if q >= 8 else 4
-            assert walks[(KC, GPMAX)][1] == 1, (inflight, KR, KC)
-        assert walks[(inflight, GPMAX)][1] == 1, inflight
+            assert (KC, GMAX) in walks, (inflight, KR, KC)
 
 
-def test_half_chunk_case_that_once_ran_past_the_records(walks):
-    # 24 gathers in flight over two right-hand sides: KC = 12; with the 17
-    # modes of the headline problem gp = 20.  A 6-record half chunk at 12
-    # would leave the 4-chunks starting at 18 and reading records 20 and 21.
-    end, exact, chunks = walks[(12, 20)]
-    assert chunks == [(0, 12), (12, 4), (16, 4)] and end == 20
+def test_the_headline_and_icosahedral_walks(walks):
+    # 17 modes (the eightfold field with eight mode pairs): two right-hand
+    # sides keep KC = 8; the last chunk is the one real record past 16
+    assert walks[(8, 17)] == [(0, 8), (8, 8), (16, 1)]
+    # 13 icosahedral modes with KC = 8 (FP64, one right-hand side) and 16
+    assert walks[(8, 13)] == [(0, 8), (8, 4), (12, 1)]
+    assert walks[(16, 13)] == [(0, 8), (8, 4), (12, 1)]
+    # 24 gathers in flight over two right-hand sides: KC = 12, and a half
+    # chunk of 6 is now allowed, since no later chunk has to end at a
+    # multiple of 4
+    assert walks[(12, 17)] == [(0, 12), (12, 4), (16, 1)]
+    assert walks[(12, 20)] == [(0, 12), (12, 6), (18, 2)]
